@@ -1,0 +1,42 @@
+"""Plain FP64 CPU oracle for the staggered-grid pressure Poisson solve.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, calls or
+links this package: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` use it.  It shares no code with the HIP
+library (no kernels, headers, tables or helpers); the two meet only through
+the seeded input generators in ``paper_2609_19130_amd.synth``.
+
+What it computes (paper: "Fluid Mechanics" subsection, eqs. ``velsolen``,
+``elliptic`` and the boundary-condition paragraph after eq. ``pressure``;
+"Fluid domain" parallelisation subsection for the FFT/tridiagonal method):
+
+* the second-order staggered discrete operators D (divergence), G (gradient)
+  and L_h = D G on a grid uniform and periodic in x and z and non-uniform in
+  y, with homogeneous Neumann conditions for the pressure correction at the
+  two y walls (``operators``);
+* the unique discrete solution of L_h phi = f - m with volume-weighted mean
+  zero, where m is the volume-weighted mean of f, computed by real FFT in x,
+  complex FFT in z, one tridiagonal system per horizontal Fourier mode along y,
+  flux integration for the singular (0,0) mode, and the inverse FFTs
+  (``poisson``);
+* independent pins: a dense bordered solve (``dense``), an exact rational
+  bordered solve (``exact``) and manufactured solutions built from the
+  discrete y eigenvectors (``manufactured``).
+
+Parity status: the paper prints no worked example, no error table and no
+Poisson-only numbers, so none of these functions is pinned to a printed
+value; every function is pinned instead to closed forms, invariants, dense
+and exact-rational solves (see ``tests/test_oracle_pins.py``).
+"""
+
+from .grid import Geometry, geometry
+from .operators import divergence, gradient, laplacian
+from .poisson import solve, solve_modes, thomas_modes, zero_mode_flux_integration
+from .dense import bordered_matrix, dense_solve
+from .manufactured import y_eigenpairs, manufactured_field
+
+__all__ = [
+    "Geometry", "geometry", "divergence", "gradient", "laplacian", "solve",
+    "solve_modes", "thomas_modes", "zero_mode_flux_integration",
+    "bordered_matrix", "dense_solve", "y_eigenpairs", "manufactured_field",
+]
