@@ -44,19 +44,20 @@ def gradient(phi, g):
 def laplacian(phi, g):
     """7-point staggered Laplacian L_h phi, written out stencil by stencil.
 
-    x and z: periodic second differences; y: a[j] phi[j-1] + b[j] phi[j]
-    + c[j] phi[j+1] with a[0] = c[ny-1] = 0.  Works in any float dtype
+    x and z: periodic second differences; y: the difference of the two face
+    fluxes, a[j] (phi[j-1] - phi[j]) + c[j] (phi[j+1] - phi[j]), with
+    a[0] = c[ny-1] = 0 (the diagonal b = -(a + c) is not formed, so no
+    rounding of it enters the operator).  Works in any float dtype
     (``numpy.longdouble`` for manufactured right-hand sides) provided the
     geometry was built in that dtype.
     """
     out = (np.roll(phi, -1, axis=2) - 2 * phi + np.roll(phi, 1, axis=2)) / (g.dx * g.dx)
     out = out + (np.roll(phi, -1, axis=1) - 2 * phi + np.roll(phi, 1, axis=1)) / (g.dz * g.dz)
     a = g.a.reshape(-1, 1, 1)
-    b = g.b.reshape(-1, 1, 1)
     c = g.c.reshape(-1, 1, 1)
-    ylap = b * phi
-    ylap[1:] += a[1:] * phi[:-1]
-    ylap[:-1] += c[:-1] * phi[1:]
+    ylap = np.zeros_like(phi)
+    ylap[1:] += a[1:] * (phi[:-1] - phi[1:])
+    ylap[:-1] += c[:-1] * (phi[1:] - phi[:-1])
     return out + ylap
 
 

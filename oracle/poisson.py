@@ -18,7 +18,8 @@ with V = dx dz dyf[j] the cell volume.  Steps, in order:
      problem compatible; the paper is silent on incompatible data);
   2. F = FFT_z(RFFT_x(f)), unnormalised;
   3. for every (kx, kz) != (0, 0): Thomas elimination of
-     a_j X_{j-1} + (b_j + lx(kx) + lz(kz)) X_j + c_j X_{j+1} = F_j;
+     a_j X_{j-1} + (b_j + lx(kx) + lz(kz)) X_j + c_j X_{j+1} = F_j,
+     b_j = -(a_j + c_j) (see ``thomas_modes`` for the pivot form);
   4. for (0, 0): integrate the face flux from the lower wall, then the
      potential, then remove its weighted mean;
   5. phi = IRFFT_x(IFFT_z(X)).
@@ -29,23 +30,37 @@ import numpy as np
 from .grid import geometry, lambda_x, lambda_z
 
 
-def thomas_modes(a, b, c, lam, F):
-    """Thomas elimination for many systems sharing a, b, c but with diagonal
-    shifts ``lam`` (broadcast against F[0]).  F has shape (ny, ...)."""
+def thomas_modes(a, c, L, F):
+    """Thomas elimination for many systems sharing the face coefficients a, c,
+    each with its own shift L = -lambda >= 0 (broadcast against F[0]):
+
+        a_j X_{j-1} - (a_j + c_j + L) X_j + c_j X_{j+1} = F_j,   a_0 = c_{ny-1} = 0.
+
+    The diagonal of the y operator is minus the sum of the two face
+    coefficients (the operator is a difference of face fluxes), so the
+    elimination is written with eps_j = 1 + c'_j, where c'_j is the usual
+    Thomas multiplier: the pivot is -(c_j + L + a_j eps_{j-1}), a sum of
+    non-negative terms, and the diagonal is never formed or rounded.  In
+    exact arithmetic this is the textbook Thomas algorithm; in floating point
+    it avoids the cancellation that costs plain Thomas up to ~1e-11 relative
+    accuracy on the near-singular low modes of stretched grids.
+    """
     ny = F.shape[0]
-    cp = np.empty((ny,) + np.shape(lam), dtype=np.float64)
+    L = np.asarray(L, dtype=np.float64)
+    D = np.empty((ny,) + L.shape, dtype=np.float64)     # minus the pivots
     dp = np.empty(F.shape, dtype=F.dtype)
-    den = b[0] + lam
-    cp[0] = c[0] / den
-    dp[0] = F[0] / den
-    for j in range(1, ny):
-        den = b[j] + lam - a[j] * cp[j - 1]
-        cp[j] = c[j] / den
-        dp[j] = (F[j] - a[j] * dp[j - 1]) / den
+    eps = np.zeros(L.shape, dtype=np.float64)
+    prev = np.zeros(F.shape[1:], dtype=F.dtype)
+    for j in range(ny):
+        n = L + a[j] * eps
+        D[j] = c[j] + n
+        eps = n / D[j]
+        dp[j] = (a[j] * prev - F[j]) / D[j]
+        prev = dp[j]
     X = np.empty_like(dp)
     X[ny - 1] = dp[ny - 1]
     for j in range(ny - 2, -1, -1):
-        X[j] = dp[j] - cp[j] * X[j + 1]
+        X[j] = dp[j] + (c[j] / D[j]) * X[j + 1]
     return X
 
 
@@ -70,10 +85,9 @@ def zero_mode_flux_integration(g, ghat):
 def solve_modes(g, F):
     """Step 3 and 4 on the spectral array F[ny, nz, nx//2+1] (unnormalised
     DFT coefficients of a compatible right-hand side)."""
-    lam = lambda_z(g).reshape(-1, 1) + lambda_x(g).reshape(1, -1)
-    lam_safe = lam.copy()
-    lam_safe[0, 0] = -1.0          # placeholder; the (0,0) column is replaced below
-    X = thomas_modes(g.a, g.b, g.c, lam_safe, F)
+    L = -(lambda_z(g).reshape(-1, 1) + lambda_x(g).reshape(1, -1))
+    L[0, 0] = 1.0                  # placeholder; the singular (0,0) column is replaced below
+    X = thomas_modes(g.a, g.c, L, F)
     X00, _ = zero_mode_flux_integration(g, F[:, 0, 0].real)
     X[:, 0, 0] = X00
     return X
