@@ -1,0 +1,210 @@
+"""Throughput of the staggered-grid pressure Poisson solve on one MI355X.
+
+Workload: 512 x 384 x 512 cells, x and z periodic (Lx = Lz = 2 pi), y on
+[-1, 1] with tanh stretching beta = 2 and Neumann walls; right-hand side =
+discrete divergence (computed by the library's divergence kernel) of a seeded
+staggered velocity field whose components have a k^-5/3 spectrum up to k = 64
+(inputs resident in HBM before timing).  One step = one complete solve.
+
+    python bench.py [--steps K] [--warmup W] [--precision fp64|mixed|mixed_f64sweep]
+
+Prints one JSON line.  `value` is FP64 solves/s (the direct solve); the mixed
+forms (FP32 transforms and line solves wrapped in FP64 iterative refinement
+to a 1e-10 relative residual) are timed beside it on the same input and
+reported under "mixed".  The roofline entry is the dominant kernel of the
+FP64 solve, its duration taken from HIP events recorded around every launch
+inside the timed region.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Poisson solves/s + HBM GB/s at 512x384x512, mixed vs FP64 at 1e-10 resid"
+HBM_PEAK_GBS = 8000.0
+SOURCES = ["ibp_api.cpp", "ibp_xz.hip", "ibp_ytri.hip", "ibp_misc.hip", "ibp_device.hpp", "ibp_internal.hpp"]
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for name in SOURCES:
+        with open(os.path.join(ROOT, "paper_2609_19130_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def timed_solves(plan, f, phi, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        plan.solve(f, phi)
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        plan.solve(f, phi)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = plan.profile()
+    plan.set_profiling(False)
+    return start.elapsed_time(stop) / steps, wall, prof
+
+
+def traffic_for(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries, when they
+    were taken on the current kernel sources; otherwise None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(args):
+    """The oracle as it stands, on the host cores, on one full solve of the
+    same workload (numpy FFTs and a numpy Thomas sweep: one thread)."""
+    import numpy as np
+
+    import oracle
+    from oracle.grid import geometry
+    from oracle.operators import divergence
+    from paper_2609_19130_amd import synth
+
+    nx, ny, nz = args.nx, args.ny, args.nz
+    if args.cpu_sample == "quarter":
+        nx, nz = nx // 2, nz // 2
+    yf = synth.tanh_faces(ny, args.beta)
+    g = geometry(nx, ny, nz, 2 * np.pi, 2 * np.pi, yf)
+    u, v, w = synth.kolmogorov_velocity(nx, ny, nz, seed=3, kmax=64)
+    f = divergence(u, v, w, g)
+    del u, v, w
+    times = []
+    while len(times) < 3 and sum(times) < 30.0:
+        t0 = time.perf_counter()
+        oracle.solve(f, 2 * np.pi, 2 * np.pi, yf)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
+    scale = (nx * ny * nz) / float(args.nx * args.ny * args.nz)
+    return {"value": scale / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"median of {len(times)} full oracle solves at {nx}x{ny}x{nz}: {dt:.2f} s each"
+                      + ("" if scale == 1.0 else f"; rate scaled by the cell ratio {scale:.3f}")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--nx", type=int, default=512)
+    ap.add_argument("--ny", type=int, default=384)
+    ap.add_argument("--nz", type=int, default=512)
+    ap.add_argument("--beta", type=float, default=2.0)
+    ap.add_argument("--mixed-iters", type=int, default=6)
+    ap.add_argument("--forms", default="fp64,mixed,mixed_f64sweep")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", choices=["full", "quarter"], default="full")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2609_19130_amd import ibpoisson as ibp
+    from paper_2609_19130_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    nx, ny, nz = args.nx, args.ny, args.nz
+    workload = f"poisson_{nx}x{ny}x{nz}_beta{args.beta:g}_kolmogorov"
+    Lx = Lz = 2 * np.pi
+    yf = synth.tanh_faces(ny, args.beta)
+    log(f"[bench] generating k^-5/3 velocity {nx}x{ny}x{nz}")
+    t0 = time.perf_counter()
+    u, v, w = synth.kolmogorov_velocity(nx, ny, nz, seed=3, kmax=64)
+    log(f"[bench] generated in {time.perf_counter() - t0:.1f} s; uploading")
+    plan = ibp.Plan(nx, ny, nz, Lx, Lz, yf)
+    ud, vd, wd = (torch.from_numpy(a).cuda() for a in (u, v, w))
+    del u, v, w
+    f = plan.divergence(ud, vd, wd)
+    del ud, vd, wd
+    phi = torch.empty_like(f)
+    torch.cuda.synchronize()
+
+    forms = [s for s in args.forms.split(",") if s]
+    results = {}
+    for form in forms:
+        plan.set_precision(form, 1e-10, args.mixed_iters)
+        log(f"[bench] timing {form}: {args.warmup} warmup + {args.steps} steps")
+        ms, wall, prof = timed_solves(plan, f, phi, args.steps, args.warmup)
+        info = plan.info()
+        results[form] = dict(ms=ms, wall=wall, prof=prof, info=info)
+        log(f"[bench] {form}: {ms:.3f} ms/solve, info {info}")
+
+    N = nx * ny * nz
+    Nh = (nx // 2 + 1) * ny * nz
+    stage_bytes = 16.0 * N + 8 * 16.0 * Nh      # five passes, each a full read + write (FP64)
+    r64 = results.get("fp64")
+    out = {"metric": METRIC, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic: seeded k^-5/3 staggered velocity, rhs = its discrete divergence",
+           "config": {"workload": workload, "nx": nx, "ny": ny, "nz": nz, "beta": args.beta,
+                      "Lx": "2pi", "Lz": "2pi", "form": "fp64 direct solve"}}
+    if r64 is not None:
+        out["value"] = 1000.0 / r64["ms"]
+        out["ms_per_step"] = r64["ms"]
+        out["hbm_gbs_stage_model"] = stage_bytes / (r64["ms"] * 1e-3) / 1e9
+        out["stage_model_bytes"] = stage_bytes
+        out["roofline_frac_stage_model"] = out["hbm_gbs_stage_model"] / HBM_PEAK_GBS
+        passes = {}
+        for name, p in r64["prof"].items():
+            avg = p["total_ms"] / p["launches"]
+            passes[name] = {"avg_ms": avg, "launches": p["launches"],
+                            "gbs": p["bytes_per_launch"] / (avg * 1e-3) / 1e9}
+        out["passes_fp64"] = passes
+        dom = max(r64["prof"].items(), key=lambda kv: kv[1]["total_ms"])
+        name, p = dom
+        avg = p["total_ms"] / p["launches"]
+        ach = p["bytes_per_launch"] / (avg * 1e-3) / 1e9
+        out["roofline"] = {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                           "bytes_per_launch": p["bytes_per_launch"], "avg_launch_ms": avg,
+                           "traffic": traffic_for(name, workload)}
+    mixed = {}
+    for form in forms:
+        if form == "fp64":
+            continue
+        r = results[form]
+        mixed[form] = {"solves_per_s": 1000.0 / r["ms"], "ms_per_step": r["ms"],
+                       "iterations": r["info"]["iterations"], "converged": r["info"]["converged"],
+                       "rel_residual": r["info"]["rel_residual"],
+                       "vs_fp64": (r64["ms"] / r["ms"]) if r64 else None}
+    out["mixed"] = mixed
+    out["source_hash"] = source_hash()
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline: oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,170 @@
+/*
+ * libibpoisson -- staggered-grid pressure Poisson solver for AMD Instinct
+ * MI355X (gfx950).  C ABI: plain pointers and sizes only.
+ *
+ * The problem (paper: eq. ``elliptic`` of the fractional-step method, its
+ * boundary-condition paragraph after eq. ``pressure``, and the FFT solver of
+ * the "Fluid domain" parallelisation subsection): on a grid of nx * ny * nz
+ * pressure cells, periodic and uniform in x (length Lx) and z (length Lz) and
+ * wall-bounded with arbitrary spacing in y, find phi with
+ *
+ *     L_h phi = rhs - m,      sum_cells V phi = 0,
+ *
+ * where L_h = D G is the second-order staggered 7-point Laplacian with
+ * homogeneous Neumann conditions at the two y walls, V = dx dz dyf_j is the
+ * cell volume and m = sum V rhs / sum V is the volume-weighted mean of rhs
+ * (zero for a right-hand side that is the divergence of a velocity field
+ * with zero wall-normal velocity at the walls; otherwise it is removed and
+ * reported).  The caller applies the 1/(alpha dt) scale and any mass source
+ * q of eq. ``elliptic``: the library solves exactly what it is given.
+ *
+ * Method: real FFT along x, complex FFT along z, one tridiagonal system per
+ * horizontal wavenumber pair along y (the (0,0) mode by FP64 flux
+ * integration), inverse FFTs.
+ *
+ * Layout: every field is C-ordered [ny][nz][nx] (x fastest, y slowest), FP64,
+ * device memory, 16-byte aligned.  x and z cell centres are at (i + 1/2) dx
+ * and (k + 1/2) dz; y pressure points are the midpoints of the ny + 1 face
+ * coordinates passed to ibp_plan_create.
+ *
+ * Execution: argument checks are synchronous and happen before anything is
+ * enqueued.  Solves are asynchronous on the given stream (a hipStream_t;
+ * NULL = the device's default stream); they never synchronise, allocate or
+ * copy to the host, so a solve sequence can be captured in a hipGraph.  A
+ * plan owns one workspace: solves with one plan must not overlap on two
+ * streams.  Nothing aborts, exits or throws across this interface.
+ */
+#ifndef IBPOISSON_H
+#define IBPOISSON_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ibp_plan_s* ibp_plan_t;
+
+typedef enum {
+  IBP_SUCCESS = 0,
+  IBP_ERROR_INVALID_VALUE = 1,    /* null pointer, bad geometry, misaligned or aliased buffers */
+  IBP_ERROR_UNSUPPORTED_SIZE = 2, /* grid size outside what the kernels support (see ibp_check_dims) */
+  IBP_ERROR_OUT_OF_MEMORY = 3,    /* device allocation failed, or caller workspace too small */
+  IBP_ERROR_HIP = 4,              /* a HIP runtime call failed (no device, launch failure, ...) */
+  IBP_ERROR_INTERNAL = 5          /* unexpected internal failure (C++ exception caught) */
+} ibp_status_t;
+
+typedef enum {
+  IBP_FP64 = 0,            /* FP64 transforms and line solves: the direct solve */
+  IBP_MIXED = 1,           /* FP32 transforms and FP32 line solves, FP64 (0,0) mode, FP64
+                              residual and update, iterative refinement to rtol */
+  IBP_MIXED_F64SWEEP = 2   /* as IBP_MIXED, but the line-solve arithmetic is FP64 on the
+                              FP32 spectral data (storage and transforms stay FP32) */
+} ibp_precision_t;
+
+typedef struct {
+  int iterations;       /* refinement corrections applied after the initial solve (0 for FP64) */
+  int converged;        /* FP64: 1; mixed: rel_residual <= rtol was reached */
+  int nonfinite_input;  /* a NaN/Inf (or FP64 overflow) was met in rhs or in a residual */
+  int reserved;
+  double rel_residual;  /* ||rhs - m - L_h phi||_2 / ||rhs - m||_2 in FP64 (NaN for FP64 solves) */
+  double removed_mean;  /* m, the removed volume-weighted mean of rhs */
+  double rhs_norm;      /* ||rhs - m||_2 (mixed) */
+  double residual_norm; /* ||rhs - m - L_h phi||_2 (mixed) */
+} ibp_info_t;
+
+/* Host-only size check (touches no GPU).  nx must be even with nx/2 having
+ * no prime factor above 11 and nx <= 4096; nz must have no prime factor above
+ * 11 and nz <= 4096; 2 <= ny <= 1536.  Returns IBP_SUCCESS or
+ * IBP_ERROR_UNSUPPORTED_SIZE (IBP_ERROR_INVALID_VALUE for nx, nz < 1). */
+ibp_status_t ibp_check_dims(int nx, int ny, int nz);
+
+/* Create a plan for one grid.  y_nodes: HOST pointer to ny + 1 finite,
+ * strictly increasing wall-normal face coordinates (walls at y_nodes[0] and
+ * y_nodes[ny]); copied, the caller keeps ownership.  Lx, Lz: finite, > 0.
+ * Builds the FP64 y-operator coefficients, the closed-form eigenvalues
+ * lambda_x(kx) = -(4/dx^2) sin^2(pi kx/nx), lambda_z(kz) likewise, the FFT
+ * twiddles, and allocates the device tables and the default workspace on
+ * the current device.  Precision defaults to IBP_FP64.  On failure *plan is
+ * set to NULL. */
+ibp_status_t ibp_plan_create(ibp_plan_t* plan, int nx, int ny, int nz, double Lx, double Lz,
+                             const double* y_nodes);
+
+/* Free the plan's device tables and owned workspace (not a caller workspace).
+ * NULL is accepted.  Waits for nothing: the caller must make sure no solve
+ * with this plan is still running. */
+ibp_status_t ibp_plan_destroy(ibp_plan_t plan);
+
+/* Select the precision form.  rtol: relative residual target of the mixed
+ * forms (> 0, e.g. 1e-10); max_iters: maximum refinement corrections after
+ * the initial FP32 solve, 0..64.  Both are ignored for IBP_FP64. */
+ibp_status_t ibp_plan_set_precision(ibp_plan_t plan, ibp_precision_t precision, double rtol,
+                                    int max_iters);
+
+/* Bytes of device workspace a solve with this plan needs (any precision). */
+ibp_status_t ibp_plan_workspace_size(ibp_plan_t plan, size_t* bytes);
+
+/* Hand the plan a caller-owned device workspace of at least
+ * ibp_plan_workspace_size bytes, 256-byte aligned (e.g. from PyTorch's
+ * allocator); the plan frees its own workspace and uses this one until the
+ * plan is destroyed or another workspace is set.  Passing NULL re-allocates
+ * an owned workspace.  Too small -> IBP_ERROR_OUT_OF_MEMORY. */
+ibp_status_t ibp_plan_set_workspace(ibp_plan_t plan, void* device_ptr, size_t bytes);
+
+/* Solve L_h phi = rhs - m (see top).  rhs, phi: device pointers to
+ * nx*ny*nz doubles, [ny][nz][nx], 16-byte aligned.  rhs is read-only.
+ * phi may alias rhs (in-place) for IBP_FP64 only; in the mixed forms rhs is
+ * read again by every refinement pass, so any overlap returns
+ * IBP_ERROR_INVALID_VALUE.  Enqueued on `stream` (hipStream_t or NULL); call
+ * on the device the plan was created on. */
+ibp_status_t ibp_solve(ibp_plan_t plan, const double* rhs, double* phi, void* stream);
+
+/* Solve `count` independent problems, problem i with plans[i], rhs[i],
+ * phi[i] (each as in ibp_solve; HOST arrays of plans and device pointers).
+ * The plans must be distinct (each owns its workspace).  All work is
+ * enqueued on `stream`. */
+ibp_status_t ibp_solve_batched(const ibp_plan_t* plans, int count, const double* const* rhs,
+                               double* const* phi, void* stream);
+
+/* Wait for the plan's last solve and report its state (iterations,
+ * convergence, non-finite flag, residuals, removed mean). */
+ibp_status_t ibp_get_info(ibp_plan_t plan, ibp_info_t* out);
+
+/* Discrete divergence of a staggered velocity field on the plan's grid (the
+ * div u* of eq. ``elliptic``): f[j][k][i] = (u[j][k][i+1]-u[j][k][i])/dx +
+ * (v[j+1][k][i]-v[j][k][i])/dyf_j + (w[j][k+1][i]-w[j][k][i])/dz, periodic in
+ * x and z.  u, w: [ny][nz][nx] on the x and z faces at x = i dx, z = k dz;
+ * v: [ny+1][nz][nx] on the y faces (rows 0 and ny are the walls); f:
+ * [ny][nz][nx].  Device pointers, asynchronous on `stream`. */
+ibp_status_t ibp_divergence(ibp_plan_t plan, const double* u, const double* v, const double* w,
+                            double* f, void* stream);
+
+/* Per-pass timing.  While enabled, every kernel launch of ibp_solve is
+ * bracketed by two HIP events recorded on the solve's stream (a few
+ * microseconds of overhead per launch; not for graph capture). */
+typedef struct {
+  char name[32];           /* pass name, e.g. "x_r2c", "z_fwd", "y_solve", "z_inv", "x_c2r" */
+  int launches;            /* launches since profiling was enabled or last queried */
+  int reserved;
+  double total_ms;         /* summed event-measured duration of those launches */
+  double bytes_per_launch; /* algorithmic HBM bytes of one launch: every input element
+                              read once and every output element written once */
+} ibp_pass_stat_t;
+
+ibp_status_t ibp_plan_set_profiling(ibp_plan_t plan, int enable);
+
+/* Waits for the recorded events, writes up to `max` pass entries to `stats`
+ * (HOST array) and their number to *count, and resets the counters. */
+ibp_status_t ibp_plan_get_profile(ibp_plan_t plan, int max, int* count, ibp_pass_stat_t* stats);
+
+/* Static, never NULL. */
+const char* ibp_status_string(ibp_status_t status);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int ibp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBPOISSON_H */

@@ -1,0 +1,680 @@
+// Host side of libibpoisson: argument validation, FP64 geometry and tables,
+// workspace management and the enqueue order of the solve passes.  Every
+// entry point is extern "C", returns a status and catches C++ exceptions.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/ibpoisson.h"
+#include "ibp_internal.hpp"
+
+using namespace ibp;
+
+namespace {
+
+constexpr int kVersion = 100;  // 0.1.0
+
+// Radix factorisation for the LDS FFT: eights first, then fours, twos and the
+// odd primes.  Returns false if n has a prime factor above 11.
+bool factorize(int n, FftPlan* fp) {
+  fp->n = n;
+  fp->nst = 0;
+  int m = n;
+  auto push = [&](int r) {
+    if (fp->nst >= 16) return false;
+    fp->radix[fp->nst++] = r;
+    m /= r;
+    return true;
+  };
+  while (m % 8 == 0)
+    if (!push(8)) return false;
+  while (m % 4 == 0)
+    if (!push(4)) return false;
+  while (m % 2 == 0)
+    if (!push(2)) return false;
+  for (int p : {3, 5, 7, 11})
+    while (m % p == 0)
+      if (!push(p)) return false;
+  return m == 1;
+}
+
+// W_n^e = exp(-2 pi i e / n), e = 0..n-1, evaluated in long double and rounded.
+void twiddles(int n, std::vector<double>& re, std::vector<double>& im) {
+  re.resize(n);
+  im.resize(n);
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int e = 0; e < n; ++e) {
+    const long double a = two_pi * (long double)e / (long double)n;
+    re[e] = (double)cosl(a);
+    im[e] = (double)-sinl(a);
+  }
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+ibp_status_t from_hip(hipError_t e) {
+  if (e == hipSuccess) return IBP_SUCCESS;
+  if (e == hipErrorOutOfMemory) return IBP_ERROR_OUT_OF_MEMORY;
+  return IBP_ERROR_HIP;
+}
+
+}  // namespace
+
+struct ibp_plan_s {
+  int nx = 0, ny = 0, nz = 0, h = 0, hp = 0;
+  double Lx = 0, Lz = 0, dx = 0, dz = 0;
+  int device = 0;
+  ibp_precision_t prec = IBP_FP64;
+  double rtol = 1e-10;
+  int max_iters = 4;
+  FftPlan fpx{}, fpz{};
+  int yM = 16, yK = 2;
+  int zc64 = 1, zc32 = 1;   // z-pass kx columns per block
+  int rb64 = 1, rb32 = 1;   // x-pass rows per block
+  long nb64 = 1, nb32 = 1;  // x-pass blocks
+  // device tables
+  void* tables = nullptr;
+  const double *ya = nullptr, *yc = nullptr, *dyf = nullptr, *dyc = nullptr;
+  const double *lamx = nullptr, *lamz = nullptr;
+  const float *ya32 = nullptr, *yc32 = nullptr, *lamx32 = nullptr, *lamz32 = nullptr;
+  const Cx<double>*twx = nullptr, *twz = nullptr;
+  const Cx<float>*twx32 = nullptr, *twz32 = nullptr;
+  // workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  Cx<double>* spec64 = nullptr;
+  Cx<float>* spec32 = nullptr;
+  double* rowsum = nullptr;
+  double* phi00 = nullptr;
+  double* part = nullptr;
+  Ctl* ctl = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool solved = false;
+  // profiling: event pairs around launches, per pass id
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_pass;       // pass id of pair i (events 2i, 2i+1)
+  size_t ev_used = 0;
+};
+
+namespace {
+
+size_t workspace_bytes(const ibp_plan_s* p) {
+  const size_t nh = (size_t)p->ny * p->nz * p->hp;
+  size_t b = align256(nh * sizeof(Cx<double>));
+  b += align256((size_t)p->ny * p->nz * sizeof(double));
+  b += align256((size_t)p->ny * sizeof(double));
+  const long nb = p->nb64 > p->nb32 ? p->nb64 : p->nb32;
+  b += align256((size_t)nb * kPartStride * sizeof(double));
+  b += align256(sizeof(Ctl));
+  return b;
+}
+
+void carve_workspace(ibp_plan_s* p) {
+  char* c = static_cast<char*>(p->ws);
+  const size_t nh = (size_t)p->ny * p->nz * p->hp;
+  p->spec64 = reinterpret_cast<Cx<double>*>(c);
+  p->spec32 = reinterpret_cast<Cx<float>*>(c);
+  c += align256(nh * sizeof(Cx<double>));
+  p->rowsum = reinterpret_cast<double*>(c);
+  c += align256((size_t)p->ny * p->nz * sizeof(double));
+  p->phi00 = reinterpret_cast<double*>(c);
+  c += align256((size_t)p->ny * sizeof(double));
+  p->part = reinterpret_cast<double*>(c);
+  const long nb = p->nb64 > p->nb32 ? p->nb64 : p->nb32;
+  c += align256((size_t)nb * kPartStride * sizeof(double));
+  p->ctl = reinterpret_cast<Ctl*>(c);
+}
+
+ibp_status_t check_dims(int nx, int ny, int nz, FftPlan* fpx, FftPlan* fpz) {
+  if (nx < 1 || nz < 1 || ny < 1) return IBP_ERROR_INVALID_VALUE;
+  if (nx % 2 != 0 || nx > 2 * kTileX64) return IBP_ERROR_UNSUPPORTED_SIZE;
+  if (nz > kTileZ64) return IBP_ERROR_UNSUPPORTED_SIZE;
+  if (ny < 2 || ny > kMaxNy) return IBP_ERROR_UNSUPPORTED_SIZE;
+  FftPlan a{}, b{};
+  if (!factorize(nx / 2, &a) || !factorize(nz, &b)) return IBP_ERROR_UNSUPPORTED_SIZE;
+  int M, K;
+  if (!ytri_shape(ny, &M, &K)) return IBP_ERROR_UNSUPPORTED_SIZE;
+  if (fpx) *fpx = a;
+  if (fpz) *fpz = b;
+  return IBP_SUCCESS;
+}
+
+bool valid_plan(const ibp_plan_s* p) { return p != nullptr && p->tables != nullptr && p->ws != nullptr; }
+
+ibp_status_t enqueue_solve(ibp_plan_s* p, const double* rhs, double* phi, hipStream_t s);
+
+enum Pass { P_XR2C, P_ZFWD, P_Y, P_ZINV, P_XC2R, P_XRES, P_CHECK, P_XRESONLY, P_XC2R_ADD, P_DIV, P_COUNT };
+const char* const kPassName[P_COUNT] = {"x_r2c", "z_fwd", "y_solve", "z_inv", "x_c2r", "x_resid_r2c",
+                                        "check", "x_resid_only", "x_c2r_add", "divergence"};
+
+// Algorithmic bytes of one launch of each pass (each input element read
+// once, each output element written once).  N = nx ny nz cells, Nh =
+// (nx/2+1) ny nz half-spectrum coefficients of `cb` bytes.
+double pass_bytes(const ibp_plan_s* p, int pass) {
+  const double N = (double)p->nx * p->ny * p->nz;
+  const double Nh = (double)p->hp * p->ny * p->nz;
+  const double cb = (p->prec == IBP_FP64) ? 16.0 : 8.0;
+  switch (pass) {
+    case P_XR2C: return 8.0 * N + cb * Nh;
+    case P_ZFWD:
+    case P_ZINV:
+    case P_Y: return 2.0 * cb * Nh;
+    case P_XC2R: return cb * Nh + 8.0 * N;
+    case P_XRES: return 16.0 * N + cb * Nh;        // f and phi in, spectrum out
+    case P_XRESONLY: return 16.0 * N;
+    case P_XC2R_ADD: return cb * Nh + 16.0 * N;    // spectrum and phi in, phi out
+    case P_DIV: return 32.0 * N;                   // u, v, w in, f out
+    default: return 0.0;
+  }
+}
+
+hipError_t prof_mark(ibp_plan_s* p, int pass, hipStream_t s, bool begin) {
+  if (!p->profiling) return hipSuccess;
+  if (begin) {
+    const size_t need = 2 * (p->ev_used + 1);
+    while (p->ev_pool.size() < need) {
+      hipEvent_t e;
+      hipError_t err = hipEventCreate(&e);
+      if (err != hipSuccess) return err;
+      p->ev_pool.push_back(e);
+    }
+    if (p->ev_pass.size() < p->ev_used + 1) p->ev_pass.resize(p->ev_used + 1);
+    p->ev_pass[p->ev_used] = pass;
+    return hipEventRecord(p->ev_pool[2 * p->ev_used], s);
+  }
+  hipError_t err = hipEventRecord(p->ev_pool[2 * p->ev_used + 1], s);
+  p->ev_used++;
+  return err;
+}
+
+}  // namespace
+
+extern "C" {
+
+ibp_status_t ibp_check_dims(int nx, int ny, int nz) {
+  try {
+    return check_dims(nx, ny, nz, nullptr, nullptr);
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+const char* ibp_status_string(ibp_status_t s) {
+  switch (s) {
+    case IBP_SUCCESS: return "IBP_SUCCESS";
+    case IBP_ERROR_INVALID_VALUE: return "IBP_ERROR_INVALID_VALUE";
+    case IBP_ERROR_UNSUPPORTED_SIZE: return "IBP_ERROR_UNSUPPORTED_SIZE";
+    case IBP_ERROR_OUT_OF_MEMORY: return "IBP_ERROR_OUT_OF_MEMORY";
+    case IBP_ERROR_HIP: return "IBP_ERROR_HIP";
+    case IBP_ERROR_INTERNAL: return "IBP_ERROR_INTERNAL";
+  }
+  return "IBP_UNKNOWN_STATUS";
+}
+
+int ibp_version(void) { return kVersion; }
+
+ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx, double Lz,
+                             const double* y) {
+  if (out == nullptr) return IBP_ERROR_INVALID_VALUE;
+  *out = nullptr;
+  try {
+    FftPlan fpx{}, fpz{};
+    ibp_status_t st = check_dims(nx, ny, nz, &fpx, &fpz);
+    if (st != IBP_SUCCESS) return st;
+    if (!(std::isfinite(Lx) && Lx > 0.0 && std::isfinite(Lz) && Lz > 0.0)) return IBP_ERROR_INVALID_VALUE;
+    if (y == nullptr) return IBP_ERROR_INVALID_VALUE;
+    for (int j = 0; j <= ny; ++j)
+      if (!std::isfinite(y[j])) return IBP_ERROR_INVALID_VALUE;
+    for (int j = 0; j < ny; ++j)
+      if (!(y[j + 1] > y[j])) return IBP_ERROR_INVALID_VALUE;
+
+    ibp_plan_s* p = new (std::nothrow) ibp_plan_s;
+    if (!p) return IBP_ERROR_OUT_OF_MEMORY;
+    p->nx = nx;
+    p->ny = ny;
+    p->nz = nz;
+    p->h = nx / 2;
+    p->hp = nx / 2 + 1;
+    p->Lx = Lx;
+    p->Lz = Lz;
+    p->dx = Lx / nx;
+    p->dz = Lz / nz;
+    p->fpx = fpx;
+    p->fpz = fpz;
+    ytri_shape(ny, &p->yM, &p->yK);
+    p->rb64 = kTileX64 / p->h;
+    p->rb32 = kTileX32 / p->h;
+    const long nrows = (long)ny * nz;
+    p->nb64 = (nrows + p->rb64 - 1) / p->rb64;
+    p->nb32 = (nrows + p->rb32 - 1) / p->rb32;
+    p->zc64 = kTileZ64 / nz;
+    p->zc32 = kTileZ32 / nz;
+    if (p->zc64 > 64) p->zc64 = 64;
+    if (p->zc32 > 64) p->zc32 = 64;
+    if (p->zc64 > p->hp) p->zc64 = p->hp;
+    if (p->zc32 > p->hp) p->zc32 = p->hp;
+
+    // ---- FP64 geometry of the y operator (staggered, Neumann walls)
+    // face coefficients a_j, c_j; the diagonal -(a_j + c_j) is never formed:
+    // the kernels use the flux-difference form of the operator.
+    std::vector<double> dyf(ny), yc(ny), dyc(ny + 1, 0.0), a(ny, 0.0), c(ny, 0.0);
+    for (int j = 0; j < ny; ++j) {
+      dyf[j] = y[j + 1] - y[j];
+      yc[j] = 0.5 * (y[j] + y[j + 1]);
+    }
+    for (int j = 1; j < ny; ++j) dyc[j] = yc[j] - yc[j - 1];
+    for (int j = 0; j < ny; ++j) {
+      if (j > 0) a[j] = 1.0 / (dyf[j] * dyc[j]);
+      if (j < ny - 1) c[j] = 1.0 / (dyf[j] * dyc[j + 1]);
+    }
+    // ---- closed-form eigenvalues of the periodic second differences
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<double> lx(p->hp), lz(nz);
+    for (int k = 0; k < p->hp; ++k) {
+      const long double sn = sinl(pi * k / nx);
+      lx[k] = (double)(-4.0L * sn * sn / ((long double)p->dx * p->dx));
+    }
+    for (int k = 0; k < nz; ++k) {
+      const long double sn = sinl(pi * k / nz);
+      lz[k] = (double)(-4.0L * sn * sn / ((long double)p->dz * p->dz));
+    }
+    std::vector<double> twxr, twxi, twzr, twzi;
+    twiddles(nx, twxr, twxi);
+    twiddles(nz, twzr, twzi);
+
+    // ---- one device allocation for all tables
+    std::vector<char> host;
+    auto put = [&](const void* src, size_t bytes) {
+      const size_t off = host.size();
+      host.resize(off + align256(bytes), 0);
+      std::memcpy(host.data() + off, src, bytes);
+      return off;
+    };
+    std::vector<float> f32;
+    auto tof = [&](const std::vector<double>& v) {
+      f32.assign(v.begin(), v.end());
+      return put(f32.data(), f32.size() * sizeof(float));
+    };
+    std::vector<double> cx64(2 * (size_t)nx), cz64(2 * (size_t)nz);
+    std::vector<float> cx32(2 * (size_t)nx), cz32(2 * (size_t)nz);
+    for (int e = 0; e < nx; ++e) {
+      cx64[2 * e] = twxr[e];
+      cx64[2 * e + 1] = twxi[e];
+      cx32[2 * e] = (float)twxr[e];
+      cx32[2 * e + 1] = (float)twxi[e];
+    }
+    for (int e = 0; e < nz; ++e) {
+      cz64[2 * e] = twzr[e];
+      cz64[2 * e + 1] = twzi[e];
+      cz32[2 * e] = (float)twzr[e];
+      cz32[2 * e + 1] = (float)twzi[e];
+    }
+    const size_t o_ya = put(a.data(), ny * sizeof(double));
+    const size_t o_yc = put(c.data(), ny * sizeof(double));
+    const size_t o_dyf = put(dyf.data(), ny * sizeof(double));
+    const size_t o_dyc = put(dyc.data(), (ny + 1) * sizeof(double));
+    const size_t o_lx = put(lx.data(), lx.size() * sizeof(double));
+    const size_t o_lz = put(lz.data(), lz.size() * sizeof(double));
+    const size_t o_twx = put(cx64.data(), cx64.size() * sizeof(double));
+    const size_t o_twz = put(cz64.data(), cz64.size() * sizeof(double));
+    const size_t o_ya32 = tof(a);
+    const size_t o_yc32 = tof(c);
+    const size_t o_lx32 = tof(lx);
+    const size_t o_lz32 = tof(lz);
+    const size_t o_twx32 = put(cx32.data(), cx32.size() * sizeof(float));
+    const size_t o_twz32 = put(cz32.data(), cz32.size() * sizeof(float));
+
+    hipError_t e = hipGetDevice(&p->device);
+    if (e == hipSuccess) e = hipMalloc(&p->tables, host.size());
+    if (e == hipSuccess) e = hipMemcpy(p->tables, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      if (p->tables) hipFree(p->tables);
+      delete p;
+      return from_hip(e);
+    }
+    char* d = static_cast<char*>(p->tables);
+    p->ya = reinterpret_cast<const double*>(d + o_ya);
+    p->yc = reinterpret_cast<const double*>(d + o_yc);
+    p->dyf = reinterpret_cast<const double*>(d + o_dyf);
+    p->dyc = reinterpret_cast<const double*>(d + o_dyc);
+    p->lamx = reinterpret_cast<const double*>(d + o_lx);
+    p->lamz = reinterpret_cast<const double*>(d + o_lz);
+    p->twx = reinterpret_cast<const Cx<double>*>(d + o_twx);
+    p->twz = reinterpret_cast<const Cx<double>*>(d + o_twz);
+    p->ya32 = reinterpret_cast<const float*>(d + o_ya32);
+    p->yc32 = reinterpret_cast<const float*>(d + o_yc32);
+    p->lamx32 = reinterpret_cast<const float*>(d + o_lx32);
+    p->lamz32 = reinterpret_cast<const float*>(d + o_lz32);
+    p->twx32 = reinterpret_cast<const Cx<float>*>(d + o_twx32);
+    p->twz32 = reinterpret_cast<const Cx<float>*>(d + o_twz32);
+
+    p->ws_bytes = workspace_bytes(p);
+    e = hipMalloc(&p->ws, p->ws_bytes);
+    if (e != hipSuccess) {
+      hipFree(p->tables);
+      delete p;
+      return from_hip(e);
+    }
+    p->ws_owned = true;
+    carve_workspace(p);
+    *out = p;
+    return IBP_SUCCESS;
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+ibp_status_t ibp_plan_destroy(ibp_plan_t p) {
+  if (p == nullptr) return IBP_SUCCESS;
+  try {
+    for (hipEvent_t e : p->ev_pool) hipEventDestroy(e);
+    if (p->ws_owned && p->ws) hipFree(p->ws);
+    if (p->tables) hipFree(p->tables);
+    delete p;
+    return IBP_SUCCESS;
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+ibp_status_t ibp_plan_set_precision(ibp_plan_t p, ibp_precision_t prec, double rtol, int max_iters) {
+  if (!valid_plan(p)) return IBP_ERROR_INVALID_VALUE;
+  if (prec != IBP_FP64 && prec != IBP_MIXED && prec != IBP_MIXED_F64SWEEP) return IBP_ERROR_INVALID_VALUE;
+  if (prec != IBP_FP64) {
+    if (!(rtol > 0.0) || !std::isfinite(rtol)) return IBP_ERROR_INVALID_VALUE;
+    if (max_iters < 0 || max_iters > 64) return IBP_ERROR_INVALID_VALUE;
+    p->rtol = rtol;
+    p->max_iters = max_iters;
+  }
+  p->prec = prec;
+  return IBP_SUCCESS;
+}
+
+ibp_status_t ibp_plan_workspace_size(ibp_plan_t p, size_t* bytes) {
+  if (!valid_plan(p) || bytes == nullptr) return IBP_ERROR_INVALID_VALUE;
+  *bytes = workspace_bytes(p);
+  return IBP_SUCCESS;
+}
+
+ibp_status_t ibp_plan_set_workspace(ibp_plan_t p, void* ptr, size_t bytes) {
+  if (!valid_plan(p)) return IBP_ERROR_INVALID_VALUE;
+  try {
+    const size_t need = workspace_bytes(p);
+    if (ptr != nullptr) {
+      if ((reinterpret_cast<uintptr_t>(ptr) & 255) != 0) return IBP_ERROR_INVALID_VALUE;
+      if (bytes < need) return IBP_ERROR_OUT_OF_MEMORY;
+      if (p->ws_owned) hipFree(p->ws);
+      p->ws = ptr;
+      p->ws_bytes = bytes;
+      p->ws_owned = false;
+    } else {
+      void* w = nullptr;
+      hipError_t e = hipMalloc(&w, need);
+      if (e != hipSuccess) return from_hip(e);
+      if (p->ws_owned) hipFree(p->ws);
+      p->ws = w;
+      p->ws_bytes = need;
+      p->ws_owned = true;
+    }
+    carve_workspace(p);
+    return IBP_SUCCESS;
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+ibp_status_t ibp_solve(ibp_plan_t p, const double* rhs, double* phi, void* stream) {
+  if (!valid_plan(p) || rhs == nullptr || phi == nullptr) return IBP_ERROR_INVALID_VALUE;
+  if ((reinterpret_cast<uintptr_t>(rhs) & 15) != 0 || (reinterpret_cast<uintptr_t>(phi) & 15) != 0)
+    return IBP_ERROR_INVALID_VALUE;
+  const size_t n = (size_t)p->nx * p->ny * p->nz;
+  if (p->prec != IBP_FP64) {
+    const uintptr_t r0 = reinterpret_cast<uintptr_t>(rhs), r1 = r0 + n * sizeof(double);
+    const uintptr_t q0 = reinterpret_cast<uintptr_t>(phi), q1 = q0 + n * sizeof(double);
+    if (r0 < q1 && q0 < r1) return IBP_ERROR_INVALID_VALUE;
+  }
+  try {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return from_hip(e);
+    if (dev != p->device) return IBP_ERROR_INVALID_VALUE;
+    return enqueue_solve(p, rhs, phi, static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+ibp_status_t ibp_solve_batched(const ibp_plan_t* plans, int count, const double* const* rhs,
+                               double* const* phi, void* stream) {
+  if (count < 0) return IBP_ERROR_INVALID_VALUE;
+  if (count == 0) return IBP_SUCCESS;
+  if (plans == nullptr || rhs == nullptr || phi == nullptr) return IBP_ERROR_INVALID_VALUE;
+  for (int i = 0; i < count; ++i) {
+    if (!valid_plan(plans[i]) || rhs[i] == nullptr || phi[i] == nullptr) return IBP_ERROR_INVALID_VALUE;
+    for (int k = 0; k < i; ++k)
+      if (plans[k] == plans[i]) return IBP_ERROR_INVALID_VALUE;
+  }
+  for (int i = 0; i < count; ++i) {
+    ibp_status_t st = ibp_solve(plans[i], rhs[i], phi[i], stream);
+    if (st != IBP_SUCCESS) return st;
+  }
+  return IBP_SUCCESS;
+}
+
+ibp_status_t ibp_get_info(ibp_plan_t p, ibp_info_t* out) {
+  if (!valid_plan(p) || out == nullptr) return IBP_ERROR_INVALID_VALUE;
+  try {
+    std::memset(out, 0, sizeof(*out));
+    if (!p->solved) {
+      out->rel_residual = NAN;
+      return IBP_SUCCESS;
+    }
+    hipError_t e = hipStreamSynchronize(p->last_stream);
+    Ctl c{};
+    if (e == hipSuccess) e = hipMemcpy(&c, p->ctl, sizeof(Ctl), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return from_hip(e);
+    out->iterations = c.iters;
+    out->converged = c.converged;
+    out->nonfinite_input = c.nonfinite;
+    out->rel_residual = c.rel_residual;
+    out->removed_mean = c.removed_mean;
+    out->rhs_norm = std::sqrt(c.fnorm2);
+    out->residual_norm = std::sqrt(c.rnorm2);
+    return IBP_SUCCESS;
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+ibp_status_t ibp_plan_set_profiling(ibp_plan_t p, int enable) {
+  if (!valid_plan(p)) return IBP_ERROR_INVALID_VALUE;
+  p->profiling = enable != 0;
+  p->ev_used = 0;
+  return IBP_SUCCESS;
+}
+
+ibp_status_t ibp_plan_get_profile(ibp_plan_t p, int max, int* count, ibp_pass_stat_t* stats) {
+  if (!valid_plan(p) || count == nullptr || (max > 0 && stats == nullptr) || max < 0) return IBP_ERROR_INVALID_VALUE;
+  try {
+    double ms[P_COUNT] = {0};
+    int n[P_COUNT] = {0};
+    for (size_t i = 0; i < p->ev_used; ++i) {
+      hipError_t e = hipEventSynchronize(p->ev_pool[2 * i + 1]);
+      float t = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, p->ev_pool[2 * i], p->ev_pool[2 * i + 1]);
+      if (e != hipSuccess) return from_hip(e);
+      ms[p->ev_pass[i]] += t;
+      n[p->ev_pass[i]] += 1;
+    }
+    p->ev_used = 0;
+    int c = 0;
+    for (int k = 0; k < P_COUNT; ++k) {
+      if (n[k] == 0) continue;
+      if (c < max) {
+        std::memset(&stats[c], 0, sizeof(ibp_pass_stat_t));
+        std::strncpy(stats[c].name, kPassName[k], sizeof(stats[c].name) - 1);
+        stats[c].launches = n[k];
+        stats[c].total_ms = ms[k];
+        stats[c].bytes_per_launch = pass_bytes(p, k);
+      }
+      ++c;
+    }
+    *count = c < max ? c : max;
+    return IBP_SUCCESS;
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+ibp_status_t ibp_divergence(ibp_plan_t p, const double* u, const double* v, const double* w, double* f,
+                            void* stream) {
+  if (!valid_plan(p) || !u || !v || !w || !f) return IBP_ERROR_INVALID_VALUE;
+  try {
+    DivArgs a{u, v, w, f, p->dyf, p->nx, p->ny, p->nz, 1.0 / p->dx, 1.0 / p->dz};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = prof_mark(p, P_DIV, s, true);
+    if (e == hipSuccess) e = launch_divergence(a, s);
+    if (e == hipSuccess) e = prof_mark(p, P_DIV, s, false);
+    return from_hip(e);
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+XArgs<T> xargs(ibp_plan_s* p, const double* rhs, const double* phi_in, double* phi_out, Cx<T>* spec,
+               const Cx<T>* twx, int rb, int iter) {
+  XArgs<T> a{};
+  a.f = rhs;
+  a.phi = phi_in;
+  a.out = phi_out;
+  a.spec = spec;
+  a.rowsum = p->rowsum;
+  a.part = p->part;
+  a.phi00 = p->phi00;
+  a.ctl = p->ctl;
+  a.twx = twx;
+  a.ya = p->ya;
+  a.yc = p->yc;
+  a.fp = p->fpx;
+  a.nx = p->nx;
+  a.ny = p->ny;
+  a.nz = p->nz;
+  a.h = p->h;
+  a.hp = p->hp;
+  a.rows_per_block = rb;
+  a.nrows = (long)p->ny * p->nz;
+  a.idx2 = 1.0 / (p->dx * p->dx);
+  a.idz2 = 1.0 / (p->dz * p->dz);
+  a.out_scale = 1.0 / ((double)p->h * (double)p->nz);
+  a.inv_nxnz = 1.0 / ((double)p->nx * (double)p->nz);
+  a.iter = iter;
+  return a;
+}
+
+ZeroArgs zargs(ibp_plan_s* p, long nparts, int init, int mixed, int iter, int final_pass) {
+  ZeroArgs z{};
+  z.rowsum = p->rowsum;
+  z.phi00 = p->phi00;
+  z.dyf = p->dyf;
+  z.dyc = p->dyc;
+  z.part = p->part;
+  z.nparts = nparts;
+  z.ctl = p->ctl;
+  z.nx = p->nx;
+  z.ny = p->ny;
+  z.nz = p->nz;
+  z.init = init;
+  z.mixed = mixed;
+  z.iter = iter;
+  z.final_pass = final_pass;
+  z.rtol = p->rtol;
+  return z;
+}
+
+// Launch with optional profiling events around it.
+#define IBP_LAUNCH(pass, ...)                              \
+  do {                                                     \
+    hipError_t e_ = prof_mark(p, (pass), s, true);         \
+    if (e_ == hipSuccess) e_ = (__VA_ARGS__);              \
+    if (e_ == hipSuccess) e_ = prof_mark(p, (pass), s, false); \
+    if (e_ != hipSuccess) return from_hip(e_);             \
+  } while (0)
+
+template <typename U>
+ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStream_t s);
+
+ibp_status_t enqueue_solve(ibp_plan_s* p, const double* rhs, double* phi, hipStream_t s) {
+  p->last_stream = s;
+  p->solved = true;
+  if (p->prec == IBP_MIXED) return enqueue_mixed<float>(p, rhs, phi, s);
+  if (p->prec == IBP_MIXED_F64SWEEP) return enqueue_mixed<double>(p, rhs, phi, s);
+  // FP64 direct solve: x R2C, z FFT, y line solves + FP64 (0,0), z inverse, x C2R
+  XArgs<double> xa = xargs<double>(p, rhs, nullptr, phi, p->spec64, p->twx, p->rb64, 0);
+  IBP_LAUNCH(P_XR2C, launch_xr2c<double>(XM_PLAIN, xa, p->nb64, s));
+  ZfArgs<double> za{p->spec64, p->twz, p->ctl, p->fpz, p->nz, p->hp, p->zc64, 0};
+  if (p->nz > 1) IBP_LAUNCH(P_ZFWD, launch_zfft<double>(false, za, p->ny, s));
+  YArgs<double, double> ya{p->spec64, p->lamx, p->lamz, p->ya, p->yc, p->ctl,
+                           (long)p->nz * p->hp, p->ny, p->hp, 0};
+  IBP_LAUNCH(P_Y, launch_ytri<double, double>(p->yM, p->yK, ya, zargs(p, p->nb64, 1, 0, 0, 0), s));
+  if (p->nz > 1) IBP_LAUNCH(P_ZINV, launch_zfft<double>(true, za, p->ny, s));
+  IBP_LAUNCH(P_XC2R, launch_xc2r<double>(CM_SET, xa, p->nb64, s));
+  return IBP_SUCCESS;
+}
+
+// Mixed forms: FP32 spectral passes wrapped in FP64 iterative refinement.
+//   pass 0: phi = solve32(f)                      (rows summed in FP64 for (0,0))
+//   pass k: r = f - m - L_h phi (FP64), stop if ||r|| <= rtol ||f - m||,
+//           else phi += solve32(r * s_k) / s_k   (s_k a power of two)
+//   final : residual of the last iterate.
+// Every pass is enqueued; once the control block marks the solve done the
+// remaining kernels return immediately.
+template <typename U>
+ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStream_t s) {
+  const U* lx = nullptr;
+  const U* lz = nullptr;
+  const U *ca = nullptr, *cc = nullptr;
+  if constexpr (sizeof(U) == 8) {
+    lx = p->lamx; lz = p->lamz; ca = p->ya; cc = p->yc;
+  } else {
+    lx = p->lamx32; lz = p->lamz32; ca = p->ya32; cc = p->yc32;
+  }
+  const long Q = (long)p->nz * p->hp;
+  ZfArgs<float> za{p->spec32, p->twz32, p->ctl, p->fpz, p->nz, p->hp, p->zc32, 0};
+  YArgs<float, U> ya{p->spec32, lx, lz, ca, cc, p->ctl, Q, p->ny, p->hp, 0};
+
+  XArgs<float> xa = xargs<float>(p, rhs, phi, phi, p->spec32, p->twx32, p->rb32, 0);
+  IBP_LAUNCH(P_XR2C, launch_xr2c<float>(XM_PLAIN, xa, p->nb32, s));
+  if (p->nz > 1) IBP_LAUNCH(P_ZFWD, launch_zfft<float>(false, za, p->ny, s));
+  IBP_LAUNCH(P_Y, launch_ytri<float, U>(p->yM, p->yK, ya, zargs(p, p->nb32, 1, 1, 0, 0), s));
+  if (p->nz > 1) IBP_LAUNCH(P_ZINV, launch_zfft<float>(true, za, p->ny, s));
+  IBP_LAUNCH(P_XC2R, launch_xc2r<float>(CM_SET, xa, p->nb32, s));
+
+  za.check_done = 1;
+  ya.check_done = 1;
+  for (int k = 1; k <= p->max_iters; ++k) {
+    xa.iter = k;
+    IBP_LAUNCH(P_XRES, launch_xr2c<float>(XM_RESID, xa, p->nb32, s));
+    IBP_LAUNCH(P_CHECK, launch_check(zargs(p, p->nb32, 0, 1, k, 0), s));
+    if (p->nz > 1) IBP_LAUNCH(P_ZFWD, launch_zfft<float>(false, za, p->ny, s));
+    IBP_LAUNCH(P_Y, launch_ytri<float, U>(p->yM, p->yK, ya, zargs(p, p->nb32, 0, 1, k, 0), s));
+    if (p->nz > 1) IBP_LAUNCH(P_ZINV, launch_zfft<float>(true, za, p->ny, s));
+    IBP_LAUNCH(P_XC2R_ADD, launch_xc2r<float>(CM_ADD, xa, p->nb32, s));
+  }
+  xa.iter = p->max_iters + 1;
+  IBP_LAUNCH(P_XRESONLY, launch_xr2c<float>(XM_RESID_ONLY, xa, p->nb32, s));
+  IBP_LAUNCH(P_CHECK, launch_check(zargs(p, p->nb32, 0, 1, p->max_iters + 1, 1), s));
+  return IBP_SUCCESS;
+}
+
+}  // namespace

@@ -1,0 +1,295 @@
+// Device-side building blocks for libibpoisson (gfx950, wave64).
+//
+// * Cx<T>: interleaved complex value (T = double or float), aligned so a
+//   whole value moves in one 16-byte (double) or 8-byte (float) access.
+// * Radix-2/3/4/5/7/8/11 DFT butterflies.
+// * lds_fft: mixed-radix Stockham autosort FFT of `nb` sequences of length
+//   `n` that sit in LDS, all threads of the block cooperating.  Stage with
+//   radix R and span Ns (product of the radices before it): butterfly j of a
+//   sequence reads elements j + r*(n/R), multiplies input r by W_{Ns*R}^{r*(j%Ns)},
+//   and writes output r to (j - j%Ns)*R + j%Ns + r*Ns.  Output is in natural
+//   order.  Twiddles come from a host-computed FP64 table of W_N^e.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ibp {
+
+constexpr int kThreads = 256;   // every kernel uses 256-thread blocks (4 waves)
+constexpr int kWave = 64;
+
+template <typename T>
+struct alignas(2 * sizeof(T)) Cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
+  return Cx<T>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) { return Cx<T>{a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> csub(Cx<T> a, Cx<T> b) { return Cx<T>{a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> cscale(Cx<T> a, T s) { return Cx<T>{a.x * s, a.y * s}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> cconj(Cx<T> a) { return Cx<T>{a.x, -a.y}; }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename T>
+__device__ __forceinline__ Cx<T> mul_mi(Cx<T> a) {
+  return INV ? Cx<T>{-a.y, a.x} : Cx<T>{a.y, -a.x};
+}
+
+// FFT factorisation handed to kernels by value.
+struct FftPlan {
+  int n;          // sequence length
+  int nst;        // number of stages
+  int radix[16];  // radices in stage order
+};
+
+// ---------------------------------------------------------------- butterflies
+template <int R, bool INV, typename T>
+struct Bfly;
+
+template <bool INV, typename T>
+struct Bfly<2, INV, T> {
+  __device__ __forceinline__ static void run(Cx<T>* v) {
+    Cx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <bool INV, typename T>
+struct Bfly<4, INV, T> {
+  __device__ __forceinline__ static void run(Cx<T>* v) {
+    Cx<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    Cx<T> t2 = cadd(v[1], v[3]), t3 = mul_mi<INV>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  }
+};
+
+template <bool INV, typename T>
+struct Bfly<8, INV, T> {
+  __device__ __forceinline__ static void run(Cx<T>* v) {
+    const T h = T(0.7071067811865476);
+    Cx<T> a[4], b[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      a[r] = cadd(v[r], v[r + 4]);
+      b[r] = csub(v[r], v[r + 4]);
+    }
+    // b[r] *= W_8^r (forward) or its conjugate (inverse)
+    b[1] = INV ? Cx<T>{h * (b[1].x - b[1].y), h * (b[1].x + b[1].y)}
+               : Cx<T>{h * (b[1].x + b[1].y), h * (b[1].y - b[1].x)};
+    b[2] = mul_mi<INV>(b[2]);
+    b[3] = INV ? Cx<T>{-h * (b[3].x + b[3].y), h * (b[3].x - b[3].y)}
+               : Cx<T>{h * (b[3].y - b[3].x), -h * (b[3].x + b[3].y)};
+    Bfly<4, INV, T>::run(a);
+    Bfly<4, INV, T>::run(b);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[2 * q] = a[q];
+      v[2 * q + 1] = b[q];
+    }
+  }
+};
+
+// Odd prime radix: y_q = v_0 + sum_r (v_r + v_{R-r}) cos(2 pi q r / R)
+//                        -/+ i sum_r (v_r - v_{R-r}) sin(2 pi q r / R)
+template <int R>
+struct OddConst;
+template <>
+struct OddConst<3> {
+  __device__ static constexpr double c(int k) { return -0.5; }
+  __device__ static constexpr double s(int k) { return 0.8660254037844386; }
+};
+template <>
+struct OddConst<5> {
+  __device__ static constexpr double c(int k) { return k == 1 ? 0.30901699437494745 : -0.8090169943749475; }
+  __device__ static constexpr double s(int k) { return k == 1 ? 0.9510565162951535 : 0.5877852522924731; }
+};
+template <>
+struct OddConst<7> {
+  __device__ static constexpr double c(int k) {
+    return k == 1 ? 0.6234898018587335 : (k == 2 ? -0.2225209339563144 : -0.9009688679024191);
+  }
+  __device__ static constexpr double s(int k) {
+    return k == 1 ? 0.7818314824680298 : (k == 2 ? 0.9749279121818236 : 0.4338837391175581);
+  }
+};
+template <>
+struct OddConst<11> {
+  __device__ static constexpr double c(int k) {
+    return k == 1 ? 0.8412535328311812
+         : k == 2 ? 0.41541501300188644
+         : k == 3 ? -0.14231483827328514
+         : k == 4 ? -0.6548607339452851
+                  : -0.9594929736144974;
+  }
+  __device__ static constexpr double s(int k) {
+    return k == 1 ? 0.5406408174555976
+         : k == 2 ? 0.9096319953545183
+         : k == 3 ? 0.9898214418809327
+         : k == 4 ? 0.7557495743542583
+                  : 0.28173255684142967;
+  }
+};
+
+template <int R, bool INV, typename T>
+struct BflyOdd {
+  __device__ __forceinline__ static void run(Cx<T>* v) {
+    constexpr int H = (R - 1) / 2;
+    Cx<T> sp[H], sm[H];
+    Cx<T> y0 = v[0];
+#pragma unroll
+    for (int r = 1; r <= H; ++r) {
+      sp[r - 1] = cadd(v[r], v[R - r]);
+      sm[r - 1] = csub(v[r], v[R - r]);
+      y0 = cadd(y0, sp[r - 1]);
+    }
+    Cx<T> out[R];
+    out[0] = y0;
+#pragma unroll
+    for (int q = 1; q <= H; ++q) {
+      Cx<T> A = v[0], B = Cx<T>{T(0), T(0)};
+#pragma unroll
+      for (int r = 1; r <= H; ++r) {
+        int k = (q * r) % R;
+        // cos(2 pi k / R) = cos(2 pi (R-k) / R); sin(2 pi k / R) = -sin(2 pi (R-k)/R)
+        const T cv = T(OddConst<R>::c(k <= H ? k : R - k));
+        const T sv = T(k <= H ? OddConst<R>::s(k) : -OddConst<R>::s(R - k));
+        A.x += cv * sp[r - 1].x;
+        A.y += cv * sp[r - 1].y;
+        B.x += sv * sm[r - 1].x;
+        B.y += sv * sm[r - 1].y;
+      }
+      Cx<T> iB = mul_mi<INV>(B);      // -i B forward, +i B inverse
+      out[q] = cadd(A, iB);
+      out[R - q] = csub(A, iB);
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = out[q];
+  }
+};
+template <bool INV, typename T>
+struct Bfly<3, INV, T> : BflyOdd<3, INV, T> {};
+template <bool INV, typename T>
+struct Bfly<5, INV, T> : BflyOdd<5, INV, T> {};
+template <bool INV, typename T>
+struct Bfly<7, INV, T> : BflyOdd<7, INV, T> {};
+template <bool INV, typename T>
+struct Bfly<11, INV, T> : BflyOdd<11, INV, T> {};
+
+// ---------------------------------------------------------------- LDS FFT
+// One Stockham stage over all sequences.  Every thread first reads and
+// transforms all its butterflies into registers, then the block syncs, then
+// the results are written back in place.  MAXB bounds butterflies per thread:
+// the host guarantees nb * n <= MAXB * R * kThreads.
+template <int R, int MAXB, bool INV, typename T>
+__device__ __forceinline__ void fft_stage(Cx<T>* buf, int n, int nb, int ss, int Ns,
+                                          const Cx<T>* __restrict__ tw, int twstride) {
+  const int m = n / R;
+  const int nbf = nb * m;
+  const int twmul = (n / (Ns * R)) * twstride;
+  Cx<T> v[MAXB][R];
+  int dst[MAXB];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int t = threadIdx.x + q * kThreads;
+    dst[q] = -1;
+    if (t < nbf) {
+      const int b = t / m;
+      const int j = t - b * m;
+      const int k = j % Ns;
+      const Cx<T>* base = buf + b * ss;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = base[j + r * m];
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          Cx<T> w = tw[r * k * twmul];
+          if (INV) w.y = -w.y;
+          v[q][r] = cmul(v[q][r], w);
+        }
+      }
+      Bfly<R, INV, T>::run(v[q]);
+      dst[q] = b * ss + (j - k) * R + k;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    if (dst[q] >= 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[dst[q] + r * Ns] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// nb sequences of length fp.n; sequence b starts at buf + b*ss.
+// TILE is the compile-time bound on nb * n.
+template <int TILE, bool INV, typename T>
+__device__ void lds_fft(Cx<T>* buf, int nb, int ss, const FftPlan& fp,
+                        const Cx<T>* __restrict__ tw, int twstride) {
+  const int n = fp.n;
+  int Ns = 1;
+  for (int s = 0; s < fp.nst; ++s) {
+    const int R = fp.radix[s];
+    switch (R) {
+      case 8: fft_stage<8, cdiv(TILE, 8 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride); break;
+      case 4: fft_stage<4, cdiv(TILE, 4 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride); break;
+      case 2: fft_stage<2, cdiv(TILE, 2 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride); break;
+      case 3: fft_stage<3, cdiv(TILE, 3 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride); break;
+      case 5: fft_stage<5, cdiv(TILE, 5 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride); break;
+      case 7: fft_stage<7, cdiv(TILE, 7 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride); break;
+      case 11: fft_stage<11, cdiv(TILE, 11 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride); break;
+      default: break;
+    }
+    Ns *= R;
+  }
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+// Deterministic block reduction of NV values per thread (fixed order):
+// wave butterflies, then the 4 wave results summed in wave order.
+template <int NV>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], const bool (&is_max)[NV], double* sh) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = is_max[i] ? wave_max(v[i]) : wave_sum(v[i]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) sh[wave * NV + i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double r = sh[i];
+    for (int w = 1; w < kThreads / kWave; ++w) r = is_max[i] ? fmax(r, sh[w * NV + i]) : r + sh[w * NV + i];
+    v[i] = r;
+  }
+  __syncthreads();
+}
+
+}  // namespace ibp

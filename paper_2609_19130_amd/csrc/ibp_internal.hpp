@@ -1,0 +1,133 @@
+// Internal declarations shared by the kernel translation units and the host
+// side of libibpoisson.  Not part of the public C ABI (include/ibpoisson.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "ibp_device.hpp"
+
+namespace ibp {
+
+// Solve state kept in device memory.  The iteration-0 (0,0)-mode block
+// re-initialises it at the start of every solve, before any kernel reads it,
+// so no memset is ever enqueued (solves stay graph-capturable).
+struct alignas(64) Ctl {
+  int done;           // refinement finished: later kernels of the solve return at once
+  int iters;          // refinement corrections applied after the initial solve
+  int converged;
+  int nonfinite;      // non-finite value met in the right-hand side (or residual)
+  double scale[2];    // FP32 input scale of refinement pass k is scale[k & 1]
+  double fnorm2;      // ||f - m||_2^2
+  double rnorm2;      // ||r||_2^2 of the latest residual
+  double rmax;        // max |r| of the latest residual
+  double removed_mean;
+  double rel_residual;
+  double pad[1];
+};
+
+enum XMode { XM_PLAIN = 0, XM_RESID = 1, XM_RESID_ONLY = 2 };
+enum CMode { CM_SET = 0, CM_ADD = 1 };
+
+constexpr int kPartStride = 4;  // per-block partials: sum in^2, sum (f-m)^2, max |in|, #non-finite
+
+template <typename T>
+struct XArgs {
+  const double* f;       // right-hand side [ny][nz][nx]
+  const double* phi;     // current iterate (residual modes)
+  double* out;           // solution [ny][nz][nx] (C2R)
+  Cx<T>* spec;           // half spectrum [ny][nz][hp]
+  double* rowsum;        // [ny*nz] FP64 sums of each transformed row
+  double* part;          // [nblocks][kPartStride]
+  const double* phi00;   // [ny] (0,0)-mode solution (C2R)
+  Ctl* ctl;
+  const Cx<T>* twx;      // W_nx^e, e < nx
+  const double* ya;      // FP64 face coefficients of the y operator (residual)
+  const double* yc;
+  FftPlan fp;            // length h = nx/2
+  int nx, ny, nz, h, hp;
+  int rows_per_block;
+  long nrows;            // ny * nz
+  double idx2, idz2;     // 1/dx^2, 1/dz^2
+  double out_scale;      // 1/(h nz): normalisation of the two inverse transforms
+  double inv_nxnz;
+  int iter;              // refinement pass (selects ctl->scale slot)
+};
+
+template <typename T>
+struct ZfArgs {
+  Cx<T>* spec;
+  const Cx<T>* twz;      // W_nz^e, e < nz
+  Ctl* ctl;
+  FftPlan fp;            // length nz
+  int nz, hp, cols;      // cols: kx columns per block
+  int check_done;
+};
+
+template <typename T, typename U>   // T: spectral storage, U: line-solve arithmetic
+struct YArgs {
+  Cx<T>* spec;
+  const U* lamx;         // [hp]
+  const U* lamz;         // [nz]
+  const U* ya;           // [ny] face coefficients: sub- and super-diagonal of the y operator
+  const U* yc;
+  Ctl* ctl;
+  long Q;                // nz * hp spectral columns
+  int ny, hp, check_done;
+};
+
+struct ZeroArgs {        // FP64 (0,0) mode and solve control
+  const double* rowsum;
+  double* phi00;
+  const double* dyf;     // [ny]
+  const double* dyc;     // [ny+1], entries 1..ny-1 used
+  const double* part;
+  long nparts;
+  Ctl* ctl;
+  int nx, ny, nz;
+  int init;              // first (0,0) solve of a solve call: re-initialise ctl
+  int mixed;
+  int iter;
+  int final_pass;
+  double rtol;
+};
+
+struct DivArgs {
+  const double* u;
+  const double* v;
+  const double* w;
+  double* f;
+  const double* dyf;
+  int nx, ny, nz;
+  double idx, idz;
+};
+
+// ---------------------------------------------------------------- launchers
+constexpr int kTileX64 = 2048, kTileX32 = 4096;   // complex elements per x-pass block
+constexpr int kTileZ64 = 4096, kTileZ32 = 8192;   // complex elements per z-pass block
+constexpr int kMaxYChunk = 32;                    // (0,0) block: rows per thread
+constexpr int kMaxNy = 1536;
+
+template <typename T> int tile_x();
+template <typename T> int tile_z();
+template <> inline int tile_x<double>() { return kTileX64; }
+template <> inline int tile_x<float>() { return kTileX32; }
+template <> inline int tile_z<double>() { return kTileZ64; }
+template <> inline int tile_z<float>() { return kTileZ32; }
+
+template <typename T>
+hipError_t launch_xr2c(int mode, const XArgs<T>& a, long nblocks, hipStream_t s);
+template <typename T>
+hipError_t launch_xc2r(int mode, const XArgs<T>& a, long nblocks, hipStream_t s);
+template <typename T>
+hipError_t launch_zfft(bool inverse, const ZfArgs<T>& a, int ny, hipStream_t s);
+template <typename T, typename U>
+hipError_t launch_ytri(int M, int K, const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s);
+hipError_t launch_check(const ZeroArgs& z, hipStream_t s);
+hipError_t launch_divergence(const DivArgs& a, hipStream_t s);
+
+// Host-side choice of the y-pass shape: modes per block M and rows per
+// thread K with (256/M) * K >= ny.  Returns false when ny is too large.
+bool ytri_shape(int ny, int* M, int* K);
+
+}  // namespace ibp

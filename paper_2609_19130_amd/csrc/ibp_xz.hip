@@ -1,0 +1,231 @@
+// Transforms along the two periodic directions (paper: batched 2-D real FFTs
+// on the x1-x2 planes diagonalise the periodic directions of the elliptic
+// problem; "Fluid domain" parallelisation subsection).
+//
+// x pass: each row of nx reals is read as h = nx/2 complex pairs
+// (x[2m], x[2m+1]), transformed by an h-point complex FFT in LDS, and split
+// into the nx/2+1 half-spectrum coefficients X[k] = E[k] + W_nx^k O[k] with
+// E = (Z[k] + conj Z[h-k]) / 2 and O = (Z[k] - conj Z[h-k]) / 2i.  The inverse
+// reverses both steps.  One block owns `rows_per_block` whole rows; each wave
+// loads whole rows with 16-byte coalesced accesses and sums them in FP64 for
+// the (0,0) mode.
+//
+// z pass: one block owns one y plane and `cols` consecutive kx columns of
+// the half spectrum; consecutive threads read consecutive kx (contiguous
+// segments), the tile is transposed into LDS as one sequence per column and
+// transformed along z, then written back in place.
+#include "ibp_internal.hpp"
+
+namespace ibp {
+
+template <typename T, int MODE, int TILE>
+__global__ __launch_bounds__(kThreads) void k_xr2c(XArgs<T> A) {
+  __shared__ Cx<T> buf[TILE];
+  __shared__ double sh[4 * 4];
+  if (MODE != XM_PLAIN && A.ctl->done) return;
+  const int h = A.h, RB = A.rows_per_block, nx = A.nx, nz = A.nz, ny = A.ny;
+  const long row0 = (long)blockIdx.x * RB;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  double acc_in2 = 0.0, acc_f2 = 0.0, acc_max = 0.0, acc_bad = 0.0;
+  double mean = 0.0, s = 1.0;
+  if (MODE != XM_PLAIN) mean = A.ctl->removed_mean;
+  if (MODE == XM_RESID) s = A.ctl->scale[A.iter & 1];
+
+  for (int lr = wave; lr < RB; lr += kThreads / kWave) {
+    const long row = row0 + lr;
+    if (row >= A.nrows) {
+      if (MODE != XM_RESID_ONLY)
+        for (int m = lane; m < h; m += kWave) buf[lr * h + m] = Cx<T>{T(0), T(0)};
+      continue;
+    }
+    const double* frow = A.f + row * nx;
+    double rs = 0.0;
+    const int j = (int)(row / nz);
+    const int k = (int)(row - (long)j * nz);
+    for (int m = lane; m < h; m += kWave) {
+      const double2 fv = *reinterpret_cast<const double2*>(frow + 2 * m);
+      double v0, v1;
+      if (MODE == XM_PLAIN) {
+        v0 = fv.x;
+        v1 = fv.y;
+        acc_f2 += v0 * v0 + v1 * v1;
+      } else {
+        // r = (f - m) - L_h phi, 7-point staggered stencil, FP64
+        const double* prow = A.phi + row * nx;
+        const double2 pc = *reinterpret_cast<const double2*>(prow + 2 * m);
+        const double pl = prow[m == 0 ? nx - 1 : 2 * m - 1];
+        const double pr = prow[2 * m + 2 == nx ? 0 : 2 * m + 2];
+        const int kp = k + 1 == nz ? 0 : k + 1, km = k == 0 ? nz - 1 : k - 1;
+        const double2 zp = *reinterpret_cast<const double2*>(A.phi + ((long)j * nz + kp) * nx + 2 * m);
+        const double2 zm = *reinterpret_cast<const double2*>(A.phi + ((long)j * nz + km) * nx + 2 * m);
+        double2 yp = make_double2(0.0, 0.0), ym = make_double2(0.0, 0.0);
+        if (j + 1 < ny) yp = *reinterpret_cast<const double2*>(A.phi + ((long)(j + 1) * nz + k) * nx + 2 * m);
+        if (j > 0) ym = *reinterpret_cast<const double2*>(A.phi + ((long)(j - 1) * nz + k) * nx + 2 * m);
+        // y part as a difference of face fluxes (a_0 = c_{ny-1} = 0)
+        const double ca = A.ya[j], cc = A.yc[j];
+        const double L0 = (pc.y - 2.0 * pc.x + pl) * A.idx2 + (zp.x + zm.x - 2.0 * pc.x) * A.idz2 +
+                          ca * (ym.x - pc.x) + cc * (yp.x - pc.x);
+        const double L1 = (pr - 2.0 * pc.y + pc.x) * A.idx2 + (zp.y + zm.y - 2.0 * pc.y) * A.idz2 +
+                          ca * (ym.y - pc.y) + cc * (yp.y - pc.y);
+        const double f0 = fv.x - mean, f1 = fv.y - mean;
+        v0 = f0 - L0;
+        v1 = f1 - L1;
+        acc_f2 += f0 * f0 + f1 * f1;
+      }
+      rs += v0 + v1;
+      acc_in2 += v0 * v0 + v1 * v1;
+      acc_max = fmax(acc_max, fmax(fabs(v0), fabs(v1)));
+      if (!isfinite(v0) || !isfinite(v1)) acc_bad += 1.0;
+      if (MODE != XM_RESID_ONLY) buf[lr * h + m] = Cx<T>{T(v0 * s), T(v1 * s)};
+    }
+    rs = wave_sum(rs);
+    if (MODE != XM_RESID_ONLY && lane == 0) A.rowsum[row] = rs;
+  }
+  {
+    double vals[4] = {acc_in2, acc_f2, acc_max, acc_bad};
+    const bool ismax[4] = {false, false, true, false};
+    block_reduce<4>(vals, ismax, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) A.part[(long)blockIdx.x * kPartStride + i] = vals[i];
+    }
+  }
+  if (MODE == XM_RESID_ONLY) return;
+  __syncthreads();
+  lds_fft<TILE, false, T>(buf, RB, h, A.fp, A.twx, 2);
+
+  const int hh = h / 2 + 1;
+  for (int e = threadIdx.x; e < RB * hh; e += kThreads) {
+    const int lr = e / hh, k = e - lr * hh;
+    const long row = row0 + lr;
+    if (row >= A.nrows) continue;
+    const Cx<T> Zk = buf[lr * h + k % h];
+    const Cx<T> Zc = cconj(buf[lr * h + (h - k) % h]);
+    const Cx<T> E = cscale(cadd(Zk, Zc), T(0.5));
+    const Cx<T> D = csub(Zk, Zc);
+    const Cx<T> O = Cx<T>{T(0.5) * D.y, T(-0.5) * D.x};     // D / 2i
+    const Cx<T> WO = cmul(A.twx[k], O);
+    Cx<T>* srow = A.spec + row * A.hp;
+    srow[k] = cadd(E, WO);
+    if (h - k != k) srow[h - k] = cconj(csub(E, WO));
+  }
+}
+
+template <typename T, int MODE, int TILE>
+__global__ __launch_bounds__(kThreads) void k_xc2r(XArgs<T> A) {
+  __shared__ Cx<T> buf[TILE];
+  if (MODE == CM_ADD && A.ctl->done) return;
+  const int h = A.h, RB = A.rows_per_block, nx = A.nx, nz = A.nz;
+  const long row0 = (long)blockIdx.x * RB;
+  const int hh = h / 2 + 1;
+  for (int e = threadIdx.x; e < RB * hh; e += kThreads) {
+    const int lr = e / hh, k = e - lr * hh;
+    const long row = row0 + lr;
+    Cx<T> Xk{T(0), T(0)}, Xm{T(0), T(0)};
+    if (row < A.nrows) {
+      const Cx<T>* srow = A.spec + row * A.hp;
+      Xk = srow[k];
+      Xm = srow[h - k];
+    }
+    if (k == 0) {           // X[0] and X[h] of a real sequence are real
+      Xk.y = T(0);
+      Xm.y = T(0);
+    }
+    const Cx<T> Xmc = cconj(Xm);
+    const Cx<T> E = cscale(cadd(Xk, Xmc), T(0.5));
+    const Cx<T> D = cscale(csub(Xk, Xmc), T(0.5));
+    const Cx<T> O = cmul(cconj(A.twx[k]), D);
+    buf[lr * h + k] = Cx<T>{E.x - O.y, E.y + O.x};               // E + i O
+    const int km = (h - k) % h;
+    if (km != k) buf[lr * h + km] = Cx<T>{E.x + O.y, O.x - E.y};   // conj(E) + i conj(O)
+  }
+  __syncthreads();
+  lds_fft<TILE, true, T>(buf, RB, h, A.fp, A.twx, 2);
+
+  double cs = A.out_scale;
+  if (MODE == CM_ADD) cs = cs / A.ctl->scale[A.iter & 1];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  for (int lr = wave; lr < RB; lr += kThreads / kWave) {
+    const long row = row0 + lr;
+    if (row >= A.nrows) break;
+    const int j = (int)(row / nz);
+    const double c00 = A.phi00[j] * A.inv_nxnz;
+    double* orow = A.out + row * nx;
+    for (int m = lane; m < h; m += kWave) {
+      const Cx<T> z = buf[lr * h + m];
+      double v0 = double(z.x) * cs + c00, v1 = double(z.y) * cs + c00;
+      double2* o = reinterpret_cast<double2*>(orow + 2 * m);
+      if (MODE == CM_ADD) {
+        const double2 old = *o;
+        v0 += old.x;
+        v1 += old.y;
+      }
+      *o = make_double2(v0, v1);
+    }
+  }
+}
+
+template <typename T, bool INV, int TILE>
+__global__ __launch_bounds__(kThreads) void k_zfft(ZfArgs<T> A) {
+  __shared__ Cx<T> buf[TILE + 64];
+  if (A.check_done && A.ctl->done) return;
+  const int nz = A.nz, C = A.cols, hp = A.hp, ss = nz + 1;
+  const int c0 = blockIdx.x * C;
+  Cx<T>* plane = A.spec + (size_t)blockIdx.y * nz * hp;
+  for (int e = threadIdx.x; e < C * nz; e += kThreads) {
+    const int z = e / C, c = e - z * C;
+    buf[c * ss + z] = (c0 + c < hp) ? plane[(size_t)z * hp + c0 + c] : Cx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  lds_fft<TILE, INV, T>(buf, C, ss, A.fp, A.twz, 1);
+  for (int e = threadIdx.x; e < C * nz; e += kThreads) {
+    const int z = e / C, c = e - z * C;
+    if (c0 + c < hp) plane[(size_t)z * hp + c0 + c] = buf[c * ss + z];
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename T>
+hipError_t launch_xr2c(int mode, const XArgs<T>& a, long nblocks, hipStream_t s) {
+  constexpr int TL = (sizeof(T) == 8) ? kTileX64 : kTileX32;
+  dim3 grid((unsigned)nblocks), block(kThreads);
+  switch (mode) {
+    case XM_PLAIN: hipLaunchKernelGGL((k_xr2c<T, XM_PLAIN, TL>), grid, block, 0, s, a); break;
+    case XM_RESID: hipLaunchKernelGGL((k_xr2c<T, XM_RESID, TL>), grid, block, 0, s, a); break;
+    case XM_RESID_ONLY: hipLaunchKernelGGL((k_xr2c<T, XM_RESID_ONLY, TL>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xc2r(int mode, const XArgs<T>& a, long nblocks, hipStream_t s) {
+  constexpr int TL = (sizeof(T) == 8) ? kTileX64 : kTileX32;
+  dim3 grid((unsigned)nblocks), block(kThreads);
+  switch (mode) {
+    case CM_SET: hipLaunchKernelGGL((k_xc2r<T, CM_SET, TL>), grid, block, 0, s, a); break;
+    case CM_ADD: hipLaunchKernelGGL((k_xc2r<T, CM_ADD, TL>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zfft(bool inverse, const ZfArgs<T>& a, int ny, hipStream_t s) {
+  constexpr int TL = (sizeof(T) == 8) ? kTileZ64 : kTileZ32;
+  dim3 grid((unsigned)((a.hp + a.cols - 1) / a.cols), (unsigned)ny), block(kThreads);
+  if (inverse)
+    hipLaunchKernelGGL((k_zfft<T, true, TL>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_zfft<T, false, TL>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_xr2c<double>(int, const XArgs<double>&, long, hipStream_t);
+template hipError_t launch_xr2c<float>(int, const XArgs<float>&, long, hipStream_t);
+template hipError_t launch_xc2r<double>(int, const XArgs<double>&, long, hipStream_t);
+template hipError_t launch_xc2r<float>(int, const XArgs<float>&, long, hipStream_t);
+template hipError_t launch_zfft<double>(bool, const ZfArgs<double>&, int, hipStream_t);
+template hipError_t launch_zfft<float>(bool, const ZfArgs<float>&, int, hipStream_t);
+
+}  // namespace ibp

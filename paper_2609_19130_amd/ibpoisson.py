@@ -1,0 +1,216 @@
+"""ctypes binding of libibpoisson (argument marshalling only).
+
+Every step of the solve runs in the HIP kernels of ``libibpoisson.so``; this
+module checks tensor shapes, dtypes and devices, passes raw device pointers
+and the current HIP stream, and maps status codes to exceptions.  PyTorch
+provides device memory and streams.  If the shared library is missing the
+first call raises: there is no fallback implementation.
+"""
+
+import ctypes
+import os
+
+FP64, MIXED, MIXED_F64SWEEP = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "mixed": MIXED, "mixed_f64sweep": MIXED_F64SWEEP}
+
+SUCCESS, INVALID_VALUE, UNSUPPORTED_SIZE, OUT_OF_MEMORY, HIP_ERROR, INTERNAL = range(6)
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libibpoisson.so")
+
+_lib = None
+
+
+class IbpError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int),
+                ("nonfinite_input", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("removed_mean", ctypes.c_double),
+                ("rhs_norm", ctypes.c_double), ("residual_norm", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+class PassStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("total_ms", ctypes.c_double), ("bytes_per_launch", ctypes.c_double)]
+
+
+def lib():
+    """Load libibpoisson.so (once) and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2609_19130_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, ci, cd, cs = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "ibp_check_dims": (ci, [ci, ci, ci]),
+        "ibp_plan_create": (ci, [ctypes.POINTER(vp), ci, ci, ci, cd, cd, ctypes.POINTER(cd)]),
+        "ibp_plan_destroy": (ci, [vp]),
+        "ibp_plan_set_precision": (ci, [vp, ci, cd, ci]),
+        "ibp_plan_workspace_size": (ci, [vp, ctypes.POINTER(cs)]),
+        "ibp_plan_set_workspace": (ci, [vp, vp, cs]),
+        "ibp_solve": (ci, [vp, vp, vp, vp]),
+        "ibp_solve_batched": (ci, [ctypes.POINTER(vp), ci, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]),
+        "ibp_get_info": (ci, [vp, ctypes.POINTER(Info)]),
+        "ibp_divergence": (ci, [vp, vp, vp, vp, vp, vp]),
+        "ibp_plan_set_profiling": (ci, [vp, ci]),
+        "ibp_plan_get_profile": (ci, [vp, ci, ctypes.POINTER(ci), ctypes.POINTER(PassStat)]),
+        "ibp_status_string": (ctypes.c_char_p, [ci]),
+        "ibp_version": (ci, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def status_string(status):
+    return lib().ibp_status_string(int(status)).decode()
+
+
+def check_dims(nx, ny, nz):
+    """Host-only size check; returns a status code."""
+    return lib().ibp_check_dims(int(nx), int(ny), int(nz))
+
+
+def _check(status, what):
+    if status != SUCCESS:
+        raise IbpError(status, what)
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _field(t, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """One grid: nx, ny, nz pressure cells, periodic lengths Lx, Lz and the
+    ny+1 wall-normal face coordinates ``y_nodes`` (host array)."""
+
+    def __init__(self, nx, ny, nz, Lx, Lz, y_nodes, precision="fp64", rtol=1e-10, max_iters=4):
+        L = lib()
+        y = [float(v) for v in y_nodes]
+        if len(y) != ny + 1:
+            raise ValueError(f"y_nodes must have ny+1 = {ny + 1} entries")
+        arr = (ctypes.c_double * len(y))(*y)
+        h = ctypes.c_void_p()
+        _check(L.ibp_plan_create(ctypes.byref(h), int(nx), int(ny), int(nz), float(Lx), float(Lz), arr),
+               "ibp_plan_create")
+        self._h = h
+        self.shape = (int(ny), int(nz), int(nx))
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.set_precision(precision, rtol, max_iters)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("plan destroyed")
+        return self._h
+
+    def set_precision(self, precision, rtol=1e-10, max_iters=4):
+        code = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        _check(lib().ibp_plan_set_precision(self.handle, code, float(rtol), int(max_iters)),
+               "ibp_plan_set_precision")
+        self.precision = code
+
+    def workspace_size(self):
+        n = ctypes.c_size_t()
+        _check(lib().ibp_plan_workspace_size(self.handle, ctypes.byref(n)), "ibp_plan_workspace_size")
+        return n.value
+
+    def set_workspace(self, tensor):
+        """Use a caller-owned device buffer (e.g. a torch uint8 tensor) as workspace;
+        the tensor must stay alive while the plan uses it.  None re-allocates."""
+        if tensor is None:
+            _check(lib().ibp_plan_set_workspace(self.handle, None, 0), "ibp_plan_set_workspace")
+            self._ws = None
+            return
+        nbytes = tensor.numel() * tensor.element_size()
+        _check(lib().ibp_plan_set_workspace(self.handle, ctypes.c_void_p(tensor.data_ptr()), nbytes),
+               "ibp_plan_set_workspace")
+        self._ws = tensor
+
+    def solve(self, rhs, phi=None, stream=None):
+        """Enqueue a solve; returns phi (allocated if not given)."""
+        import torch
+        r = _field(rhs, self.shape, "rhs")
+        if phi is None:
+            phi = torch.empty(self.shape, dtype=torch.float64, device=rhs.device)
+        p = _field(phi, self.shape, "phi")
+        _check(lib().ibp_solve(self.handle, r, p, _stream_ptr(stream)), "ibp_solve")
+        return phi
+
+    def info(self):
+        inf = Info()
+        _check(lib().ibp_get_info(self.handle, ctypes.byref(inf)), "ibp_get_info")
+        return inf.as_dict()
+
+    def set_profiling(self, enable=True):
+        _check(lib().ibp_plan_set_profiling(self.handle, 1 if enable else 0), "ibp_plan_set_profiling")
+
+    def profile(self):
+        """Per-pass launch counts, summed event times and algorithmic bytes
+        since profiling was enabled or last queried (synchronises)."""
+        arr = (PassStat * 16)()
+        n = ctypes.c_int()
+        _check(lib().ibp_plan_get_profile(self.handle, 16, ctypes.byref(n), arr), "ibp_plan_get_profile")
+        return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms,
+                                           bytes_per_launch=arr[i].bytes_per_launch) for i in range(n.value)}
+
+    def divergence(self, u, v, w, f=None, stream=None):
+        import torch
+        ny, nz, nx = self.shape
+        pu = _field(u, self.shape, "u")
+        pv = _field(v, (ny + 1, nz, nx), "v")
+        pw = _field(w, self.shape, "w")
+        if f is None:
+            f = torch.empty(self.shape, dtype=torch.float64, device=u.device)
+        pf = _field(f, self.shape, "f")
+        _check(lib().ibp_divergence(self.handle, pu, pv, pw, pf, _stream_ptr(stream)), "ibp_divergence")
+        return f
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().ibp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batched(plans, rhs, phi, stream=None):
+    """Enqueue len(plans) independent solves in one call."""
+    n = len(plans)
+    if len(rhs) != n or len(phi) != n:
+        raise ValueError("plans, rhs and phi must have the same length")
+    H = (ctypes.c_void_p * n)(*[p.handle for p in plans])
+    R = (ctypes.c_void_p * n)(*[_field(r, p.shape, "rhs").value for r, p in zip(rhs, plans)])
+    P = (ctypes.c_void_p * n)(*[_field(q, p.shape, "phi").value for q, p in zip(phi, plans)])
+    _check(lib().ibp_solve_batched(H, n, R, P, _stream_ptr(stream)), "ibp_solve_batched")
+    return phi
