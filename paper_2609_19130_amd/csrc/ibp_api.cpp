@@ -11,6 +11,7 @@
 
 #include "../../include/ibpoisson.h"
 #include "ibp_internal.hpp"
+#include "ibp_regfft.hpp"
 
 using namespace ibp;
 
@@ -66,16 +67,18 @@ ibp_status_t from_hip(hipError_t e) {
 
 struct ibp_plan_s {
   int nx = 0, ny = 0, nz = 0, h = 0, hp = 0;
-  double Lx = 0, Lz = 0, dx = 0, dz = 0;
+  double Lx = 0, Lz = 0, dx = 0, dz = 0, dyf_sum = 0;
   int device = 0;
   ibp_precision_t prec = IBP_FP64;
   double rtol = 1e-10;
   int max_iters = 4;
   FftPlan fpx{}, fpz{};
-  int yM = 16, yK = 2;
+  int yP = 32, yK = 2;   // line solve: lanes per column, rows per lane
   int zc64 = 1, zc32 = 1;   // z-pass kx columns per block
   int rb64 = 1, rb32 = 1;   // x-pass rows per block
-  long nb64 = 1, nb32 = 1;  // x-pass blocks
+  long nb64 = 1, nb32 = 1;  // x-pass blocks (transform passes)
+  long nbro = 1;            // blocks of the residual-only pass
+  bool xfast = false, zfast = false;   // register-FFT kernels for power-of-two lengths
   // device tables
   void* tables = nullptr;
   const double *ya = nullptr, *yc = nullptr, *dyf = nullptr, *dyc = nullptr;
@@ -104,13 +107,17 @@ struct ibp_plan_s {
 
 namespace {
 
+long max_parts(const ibp_plan_s* p) {
+  long nb = p->nb64 > p->nb32 ? p->nb64 : p->nb32;
+  return nb > p->nbro ? nb : p->nbro;
+}
+
 size_t workspace_bytes(const ibp_plan_s* p) {
   const size_t nh = (size_t)p->ny * p->nz * p->hp;
   size_t b = align256(nh * sizeof(Cx<double>));
   b += align256((size_t)p->ny * p->nz * sizeof(double));
   b += align256((size_t)p->ny * sizeof(double));
-  const long nb = p->nb64 > p->nb32 ? p->nb64 : p->nb32;
-  b += align256((size_t)nb * kPartStride * sizeof(double));
+  b += align256((size_t)max_parts(p) * kPartStride * sizeof(double));
   b += align256(sizeof(Ctl));
   return b;
 }
@@ -126,8 +133,7 @@ void carve_workspace(ibp_plan_s* p) {
   p->phi00 = reinterpret_cast<double*>(c);
   c += align256((size_t)p->ny * sizeof(double));
   p->part = reinterpret_cast<double*>(c);
-  const long nb = p->nb64 > p->nb32 ? p->nb64 : p->nb32;
-  c += align256((size_t)nb * kPartStride * sizeof(double));
+  c += align256((size_t)max_parts(p) * kPartStride * sizeof(double));
   p->ctl = reinterpret_cast<Ctl*>(c);
 }
 
@@ -247,10 +253,17 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     p->dz = Lz / nz;
     p->fpx = fpx;
     p->fpz = fpz;
-    ytri_shape(ny, &p->yM, &p->yK);
-    p->rb64 = kTileX64 / p->h;
-    p->rb32 = kTileX32 / p->h;
+    ytri_shape(ny, &p->yP, &p->yK);
+    p->xfast = rfft::supported(p->h);
+    p->zfast = rfft::supported(nz);
     const long nrows = (long)ny * nz;
+    p->nbro = (nrows + kTileX32 / p->h - 1) / (kTileX32 / p->h);
+    if (p->xfast) {
+      p->rb64 = p->rb32 = (int)fast_x_rows_per_block(p->h);
+    } else {
+      p->rb64 = kTileX64 / p->h;
+      p->rb32 = kTileX32 / p->h;
+    }
     p->nb64 = (nrows + p->rb64 - 1) / p->rb64;
     p->nb32 = (nrows + p->rb32 - 1) / p->rb32;
     p->zc64 = kTileZ64 / nz;
@@ -269,6 +282,7 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
       yc[j] = 0.5 * (y[j] + y[j + 1]);
     }
     for (int j = 1; j < ny; ++j) dyc[j] = yc[j] - yc[j - 1];
+    for (int j = 0; j < ny; ++j) p->dyf_sum += dyf[j];
     for (int j = 0; j < ny; ++j) {
       if (j > 0) a[j] = 1.0 / (dyf[j] * dyc[j]);
       if (j < ny - 1) c[j] = 1.0 / (dyf[j] * dyc[j + 1]);
@@ -315,8 +329,12 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
       cz32[2 * e] = (float)twzr[e];
       cz32[2 * e + 1] = (float)twzi[e];
     }
-    const size_t o_ya = put(a.data(), ny * sizeof(double));
-    const size_t o_yc = put(c.data(), ny * sizeof(double));
+    // face coefficients zero-padded to the line solve's P*K rows
+    const int ypad = p->yP * p->yK > ny ? p->yP * p->yK : ny;
+    a.resize(ypad, 0.0);
+    c.resize(ypad, 0.0);
+    const size_t o_ya = put(a.data(), ypad * sizeof(double));
+    const size_t o_yc = put(c.data(), ypad * sizeof(double));
     const size_t o_dyf = put(dyf.data(), ny * sizeof(double));
     const size_t o_dyc = put(dyc.data(), (ny + 1) * sizeof(double));
     const size_t o_lx = put(lx.data(), lx.size() * sizeof(double));
@@ -566,6 +584,7 @@ XArgs<T> xargs(ibp_plan_s* p, const double* rhs, const double* phi_in, double* p
   a.twx = twx;
   a.ya = p->ya;
   a.yc = p->yc;
+  a.dyf = p->dyf;
   a.fp = p->fpx;
   a.nx = p->nx;
   a.ny = p->ny;
@@ -599,6 +618,7 @@ ZeroArgs zargs(ibp_plan_s* p, long nparts, int init, int mixed, int iter, int fi
   z.iter = iter;
   z.final_pass = final_pass;
   z.rtol = p->rtol;
+  z.dyf_sum = p->dyf_sum;
   return z;
 }
 
@@ -611,6 +631,29 @@ ZeroArgs zargs(ibp_plan_s* p, long nparts, int init, int mixed, int iter, int fi
     if (e_ != hipSuccess) return from_hip(e_);             \
   } while (0)
 
+template <typename T>
+hipError_t run_xr2c(const ibp_plan_s* p, int mode, const XArgs<T>& a, hipStream_t s) {
+  if (p->xfast && mode != XM_RESID_ONLY) return launch_xr2c_fast<T>(mode, a, s);
+  if (mode == XM_RESID_ONLY) {
+    XArgs<T> b = a;
+    b.rows_per_block = kTileX32 / p->h;
+    return launch_xr2c<T>(mode, b, p->nbro, s);
+  }
+  return launch_xr2c<T>(mode, a, sizeof(T) == 8 ? p->nb64 : p->nb32, s);
+}
+
+template <typename T>
+hipError_t run_xc2r(const ibp_plan_s* p, int mode, const XArgs<T>& a, hipStream_t s) {
+  if (p->xfast) return launch_xc2r_fast<T>(mode, a, s);
+  return launch_xc2r<T>(mode, a, sizeof(T) == 8 ? p->nb64 : p->nb32, s);
+}
+
+template <typename T>
+hipError_t run_zfft(const ibp_plan_s* p, bool inverse, const ZfArgs<T>& a, hipStream_t s) {
+  if (p->zfast) return launch_zfft_fast<T>(inverse, a, p->ny, s);
+  return launch_zfft<T>(inverse, a, p->ny, s);
+}
+
 template <typename U>
 ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStream_t s);
 
@@ -621,14 +664,14 @@ ibp_status_t enqueue_solve(ibp_plan_s* p, const double* rhs, double* phi, hipStr
   if (p->prec == IBP_MIXED_F64SWEEP) return enqueue_mixed<double>(p, rhs, phi, s);
   // FP64 direct solve: x R2C, z FFT, y line solves + FP64 (0,0), z inverse, x C2R
   XArgs<double> xa = xargs<double>(p, rhs, nullptr, phi, p->spec64, p->twx, p->rb64, 0);
-  IBP_LAUNCH(P_XR2C, launch_xr2c<double>(XM_PLAIN, xa, p->nb64, s));
+  IBP_LAUNCH(P_XR2C, run_xr2c<double>(p, XM_PLAIN, xa, s));
   ZfArgs<double> za{p->spec64, p->twz, p->ctl, p->fpz, p->nz, p->hp, p->zc64, 0};
-  if (p->nz > 1) IBP_LAUNCH(P_ZFWD, launch_zfft<double>(false, za, p->ny, s));
+  if (p->nz > 1) IBP_LAUNCH(P_ZFWD, run_zfft<double>(p, false, za, s));
   YArgs<double, double> ya{p->spec64, p->lamx, p->lamz, p->ya, p->yc, p->ctl,
                            (long)p->nz * p->hp, p->ny, p->hp, 0};
-  IBP_LAUNCH(P_Y, launch_ytri<double, double>(p->yM, p->yK, ya, zargs(p, p->nb64, 1, 0, 0, 0), s));
-  if (p->nz > 1) IBP_LAUNCH(P_ZINV, launch_zfft<double>(true, za, p->ny, s));
-  IBP_LAUNCH(P_XC2R, launch_xc2r<double>(CM_SET, xa, p->nb64, s));
+  IBP_LAUNCH(P_Y, launch_ytri<double, double>(p->yP, p->yK, ya, zargs(p, p->nb64, 1, 0, 0, 0), s));
+  if (p->nz > 1) IBP_LAUNCH(P_ZINV, run_zfft<double>(p, true, za, s));
+  IBP_LAUNCH(P_XC2R, run_xc2r<double>(p, CM_SET, xa, s));
   return IBP_SUCCESS;
 }
 
@@ -654,26 +697,26 @@ ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStr
   YArgs<float, U> ya{p->spec32, lx, lz, ca, cc, p->ctl, Q, p->ny, p->hp, 0};
 
   XArgs<float> xa = xargs<float>(p, rhs, phi, phi, p->spec32, p->twx32, p->rb32, 0);
-  IBP_LAUNCH(P_XR2C, launch_xr2c<float>(XM_PLAIN, xa, p->nb32, s));
-  if (p->nz > 1) IBP_LAUNCH(P_ZFWD, launch_zfft<float>(false, za, p->ny, s));
-  IBP_LAUNCH(P_Y, launch_ytri<float, U>(p->yM, p->yK, ya, zargs(p, p->nb32, 1, 1, 0, 0), s));
-  if (p->nz > 1) IBP_LAUNCH(P_ZINV, launch_zfft<float>(true, za, p->ny, s));
-  IBP_LAUNCH(P_XC2R, launch_xc2r<float>(CM_SET, xa, p->nb32, s));
+  IBP_LAUNCH(P_XR2C, run_xr2c<float>(p, XM_PLAIN, xa, s));
+  if (p->nz > 1) IBP_LAUNCH(P_ZFWD, run_zfft<float>(p, false, za, s));
+  IBP_LAUNCH(P_Y, launch_ytri<float, U>(p->yP, p->yK, ya, zargs(p, p->nb32, 1, 1, 0, 0), s));
+  if (p->nz > 1) IBP_LAUNCH(P_ZINV, run_zfft<float>(p, true, za, s));
+  IBP_LAUNCH(P_XC2R, run_xc2r<float>(p, CM_SET, xa, s));
 
   za.check_done = 1;
   ya.check_done = 1;
   for (int k = 1; k <= p->max_iters; ++k) {
     xa.iter = k;
-    IBP_LAUNCH(P_XRES, launch_xr2c<float>(XM_RESID, xa, p->nb32, s));
+    IBP_LAUNCH(P_XRES, run_xr2c<float>(p, XM_RESID, xa, s));
     IBP_LAUNCH(P_CHECK, launch_check(zargs(p, p->nb32, 0, 1, k, 0), s));
-    if (p->nz > 1) IBP_LAUNCH(P_ZFWD, launch_zfft<float>(false, za, p->ny, s));
-    IBP_LAUNCH(P_Y, launch_ytri<float, U>(p->yM, p->yK, ya, zargs(p, p->nb32, 0, 1, k, 0), s));
-    if (p->nz > 1) IBP_LAUNCH(P_ZINV, launch_zfft<float>(true, za, p->ny, s));
-    IBP_LAUNCH(P_XC2R_ADD, launch_xc2r<float>(CM_ADD, xa, p->nb32, s));
+    if (p->nz > 1) IBP_LAUNCH(P_ZFWD, run_zfft<float>(p, false, za, s));
+    IBP_LAUNCH(P_Y, launch_ytri<float, U>(p->yP, p->yK, ya, zargs(p, p->nb32, 0, 1, k, 0), s));
+    if (p->nz > 1) IBP_LAUNCH(P_ZINV, run_zfft<float>(p, true, za, s));
+    IBP_LAUNCH(P_XC2R_ADD, run_xc2r<float>(p, CM_ADD, xa, s));
   }
   xa.iter = p->max_iters + 1;
-  IBP_LAUNCH(P_XRESONLY, launch_xr2c<float>(XM_RESID_ONLY, xa, p->nb32, s));
-  IBP_LAUNCH(P_CHECK, launch_check(zargs(p, p->nb32, 0, 1, p->max_iters + 1, 1), s));
+  IBP_LAUNCH(P_XRESONLY, run_xr2c<float>(p, XM_RESID_ONLY, xa, s));
+  IBP_LAUNCH(P_CHECK, launch_check(zargs(p, p->nbro, 0, 1, p->max_iters + 1, 1), s));
   return IBP_SUCCESS;
 }
 

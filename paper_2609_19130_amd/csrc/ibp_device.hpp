@@ -271,8 +271,9 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // Deterministic block reduction of NV values per thread (fixed order):
-// wave butterflies, then the 4 wave results summed in wave order.
-template <int NV>
+// wave butterflies, then the NT/64 wave results combined in wave order.
+// sh must hold NV * NT/64 doubles.
+template <int NV, int NT = kThreads>
 __device__ __forceinline__ void block_reduce(double (&v)[NV], const bool (&is_max)[NV], double* sh) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
 #pragma unroll
@@ -286,7 +287,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], const bool (&is_ma
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     double r = sh[i];
-    for (int w = 1; w < kThreads / kWave; ++w) r = is_max[i] ? fmax(r, sh[w * NV + i]) : r + sh[w * NV + i];
+    for (int w = 1; w < NT / kWave; ++w) r = is_max[i] ? fmax(r, sh[w * NV + i]) : r + sh[w * NV + i];
     v[i] = r;
   }
   __syncthreads();

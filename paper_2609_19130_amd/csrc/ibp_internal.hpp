@@ -23,13 +23,14 @@ struct alignas(64) Ctl {
   double rmax;        // max |r| of the latest residual
   double removed_mean;
   double rel_residual;
-  double pad[1];
+  double phimean;     // volume-weighted mean of the iterate read by the latest residual pass
 };
 
 enum XMode { XM_PLAIN = 0, XM_RESID = 1, XM_RESID_ONLY = 2 };
 enum CMode { CM_SET = 0, CM_ADD = 1 };
 
-constexpr int kPartStride = 4;  // per-block partials: sum in^2, sum (f-m)^2, max |in|, #non-finite
+// per-block partials: sum in^2, sum (f-m)^2, max |in|, #non-finite, sum_j dyf_j * (row sums of phi)
+constexpr int kPartStride = 5;
 
 template <typename T>
 struct XArgs {
@@ -44,6 +45,7 @@ struct XArgs {
   const Cx<T>* twx;      // W_nx^e, e < nx
   const double* ya;      // FP64 face coefficients of the y operator (residual)
   const double* yc;
+  const double* dyf;     // cell widths (volume weights of the mean of phi)
   FftPlan fp;            // length h = nx/2
   int nx, ny, nz, h, hp;
   int rows_per_block;
@@ -90,6 +92,7 @@ struct ZeroArgs {        // FP64 (0,0) mode and solve control
   int iter;
   int final_pass;
   double rtol;
+  double dyf_sum;        // sum_j dyf_j
 };
 
 struct DivArgs {
@@ -105,8 +108,8 @@ struct DivArgs {
 // ---------------------------------------------------------------- launchers
 constexpr int kTileX64 = 2048, kTileX32 = 4096;   // complex elements per x-pass block
 constexpr int kTileZ64 = 4096, kTileZ32 = 8192;   // complex elements per z-pass block
-constexpr int kMaxYChunk = 32;                    // (0,0) block: rows per thread
 constexpr int kMaxNy = 1536;
+constexpr long kYTileBytes = 72 * 1024;           // staged line-solve tile per block
 
 template <typename T> int tile_x();
 template <typename T> int tile_z();
@@ -122,12 +125,23 @@ hipError_t launch_xc2r(int mode, const XArgs<T>& a, long nblocks, hipStream_t s)
 template <typename T>
 hipError_t launch_zfft(bool inverse, const ZfArgs<T>& a, int ny, hipStream_t s);
 template <typename T, typename U>
-hipError_t launch_ytri(int M, int K, const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s);
+hipError_t launch_ytri(int P, int K, const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s);
 hipError_t launch_check(const ZeroArgs& z, hipStream_t s);
+
+// Register-FFT kernels for power-of-two lengths 32..1024 (ibp_fastxz.hip).
+template <typename T>
+hipError_t launch_xr2c_fast(int mode, const XArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_xc2r_fast(int mode, const XArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_zfft_fast(bool inverse, const ZfArgs<T>& a, int ny, hipStream_t s);
+long fast_x_rows_per_block(int h);
+template <typename T>
+int fast_z_cols(int nz);
 hipError_t launch_divergence(const DivArgs& a, hipStream_t s);
 
-// Host-side choice of the y-pass shape: modes per block M and rows per
-// thread K with (256/M) * K >= ny.  Returns false when ny is too large.
-bool ytri_shape(int ny, int* M, int* K);
+// Host-side choice of the y-pass shape: lanes per column P and rows per
+// lane K with P * K >= ny.  Returns false when ny is too large.
+bool ytri_shape(int ny, int* P, int* K);
 
 }  // namespace ibp

@@ -1,0 +1,125 @@
+// Register-resident Stockham FFT for compile-time lengths (gfx950).
+//
+// A sequence of N complex values is spread over TT = N / 8 threads, each
+// holding 8 values in registers.  Stage s (radix R, span Ns) works on the
+// "stage-input layout" v[u*R + r] = x[b + r*(N/R)], b = t + TT*u, u < 8/R:
+// every input r is multiplied by W_{Ns*R}^{r*(b % Ns)}, a radix-R DFT is
+// applied, and output r belongs at index (b - b % Ns)*R + b % Ns + r*Ns.
+// Between stages the values are exchanged through LDS (padded by one
+// element every eight to spread banks); after the last stage (radix RL) the
+// slot u*RL + r of thread t holds X[t + TT*(u + r*8/RL)] in natural order.
+// The first stage reads the natural layout x[t + TT*i] directly when its
+// radix is 8, so callers load and store global memory with consecutive
+// threads on consecutive elements.
+#pragma once
+
+#include "ibp_device.hpp"
+
+namespace ibp {
+namespace rfft {
+
+constexpr int kE = 8;   // values per thread
+
+__device__ __forceinline__ constexpr int pad8(int o) { return o + (o >> 3); }
+
+// LDS elements reserved per sequence: padded length plus one, so that
+// consecutive sequences start in different banks.
+template <int N>
+struct Seq {
+  static constexpr int stride = N + N / 8 + 1;
+};
+
+template <int N, int R, int Ns, bool INV, typename T>
+__device__ __forceinline__ void stage_compute(Cx<T> (&v)[kE], int t, const Cx<T>* __restrict__ tw,
+                                              int twstride) {
+  constexpr int TT = N / kE;
+#pragma unroll
+  for (int u = 0; u < kE / R; ++u) {
+    if constexpr (Ns > 1) {
+      const int b = t + TT * u;
+      const int k = b % Ns;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        Cx<T> w = tw[(r * k * (N / (Ns * R))) * twstride];
+        if (INV) w.y = -w.y;
+        v[u * R + r] = cmul(v[u * R + r], w);
+      }
+    }
+    Bfly<R, INV, T>::run(&v[u * R]);
+  }
+}
+
+template <int N, int R, int Ns, typename T>
+__device__ __forceinline__ void stage_store(const Cx<T> (&v)[kE], int t, Cx<T>* lds) {
+  constexpr int TT = N / kE;
+#pragma unroll
+  for (int u = 0; u < kE / R; ++u) {
+    const int b = t + TT * u;
+    const int k = b % Ns;
+    const int base = (b - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) lds[pad8(base + r * Ns)] = v[u * R + r];
+  }
+}
+
+template <int N, int R, typename T>
+__device__ __forceinline__ void stage_load(Cx<T> (&v)[kE], int t, const Cx<T>* lds) {
+  constexpr int TT = N / kE;
+#pragma unroll
+  for (int u = 0; u < kE / R; ++u)
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[u * R + r] = lds[pad8(t + TT * u + r * (N / R))];
+}
+
+// Natural sub-index of register slot s after a last stage of radix RL.
+template <int RL>
+__device__ __forceinline__ constexpr int final_index(int s) {
+  return (s / RL) + (s % RL) * (kE / RL);
+}
+
+template <int N, int Ns, bool INV, typename T, int R, int... Rest>
+struct Stages {
+  static constexpr int last_radix() {
+    if constexpr (sizeof...(Rest) == 0)
+      return R;
+    else
+      return Stages<N, Ns * R, INV, T, Rest...>::last_radix();
+  }
+  // Every thread of the block must call this (it contains __syncthreads).
+  __device__ __forceinline__ static void run(Cx<T> (&v)[kE], int t, Cx<T>* lds, const Cx<T>* __restrict__ tw,
+                                             int twstride) {
+    stage_compute<N, R, Ns, INV, T>(v, t, tw, twstride);
+    if constexpr (sizeof...(Rest) > 0) {
+      constexpr int R2 = Stages<N, Ns * R, INV, T, Rest...>::first_radix();
+      stage_store<N, R, Ns, T>(v, t, lds);
+      __syncthreads();
+      stage_load<N, R2, T>(v, t, lds);
+      __syncthreads();
+      Stages<N, Ns * R, INV, T, Rest...>::run(v, t, lds, tw, twstride);
+    }
+  }
+  static constexpr int first_radix() { return R; }
+};
+
+// Radix plans of the supported lengths (first radix 8: natural input layout).
+template <int N, bool INV, typename T>
+struct Plan;
+template <bool INV, typename T>
+struct Plan<32, INV, T> : Stages<32, 1, INV, T, 8, 4> {};
+template <bool INV, typename T>
+struct Plan<64, INV, T> : Stages<64, 1, INV, T, 8, 8> {};
+template <bool INV, typename T>
+struct Plan<128, INV, T> : Stages<128, 1, INV, T, 8, 4, 4> {};
+template <bool INV, typename T>
+struct Plan<256, INV, T> : Stages<256, 1, INV, T, 8, 8, 4> {};
+template <bool INV, typename T>
+struct Plan<512, INV, T> : Stages<512, 1, INV, T, 8, 8, 8> {};
+template <bool INV, typename T>
+struct Plan<1024, INV, T> : Stages<1024, 1, INV, T, 8, 8, 4, 4> {};
+
+__host__ __device__ constexpr bool supported(int n) {
+  return n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024;
+}
+
+}  // namespace rfft
+}  // namespace ibp

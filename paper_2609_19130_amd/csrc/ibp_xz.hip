@@ -21,12 +21,12 @@ namespace ibp {
 template <typename T, int MODE, int TILE>
 __global__ __launch_bounds__(kThreads) void k_xr2c(XArgs<T> A) {
   __shared__ Cx<T> buf[TILE];
-  __shared__ double sh[4 * 4];
+  __shared__ double sh[4 * 5];
   if (MODE != XM_PLAIN && A.ctl->done) return;
   const int h = A.h, RB = A.rows_per_block, nx = A.nx, nz = A.nz, ny = A.ny;
   const long row0 = (long)blockIdx.x * RB;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  double acc_in2 = 0.0, acc_f2 = 0.0, acc_max = 0.0, acc_bad = 0.0;
+  double acc_in2 = 0.0, acc_f2 = 0.0, acc_max = 0.0, acc_bad = 0.0, acc_wphi = 0.0;
   double mean = 0.0, s = 1.0;
   if (MODE != XM_PLAIN) mean = A.ctl->removed_mean;
   if (MODE == XM_RESID) s = A.ctl->scale[A.iter & 1];
@@ -71,6 +71,7 @@ __global__ __launch_bounds__(kThreads) void k_xr2c(XArgs<T> A) {
         v0 = f0 - L0;
         v1 = f1 - L1;
         acc_f2 += f0 * f0 + f1 * f1;
+        acc_wphi += A.dyf[j] * (pc.x + pc.y);
       }
       rs += v0 + v1;
       acc_in2 += v0 * v0 + v1 * v1;
@@ -82,12 +83,12 @@ __global__ __launch_bounds__(kThreads) void k_xr2c(XArgs<T> A) {
     if (MODE != XM_RESID_ONLY && lane == 0) A.rowsum[row] = rs;
   }
   {
-    double vals[4] = {acc_in2, acc_f2, acc_max, acc_bad};
-    const bool ismax[4] = {false, false, true, false};
-    block_reduce<4>(vals, ismax, sh);
+    double vals[5] = {acc_in2, acc_f2, acc_max, acc_bad, acc_wphi};
+    const bool ismax[5] = {false, false, true, false, false};
+    block_reduce<5>(vals, ismax, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) A.part[(long)blockIdx.x * kPartStride + i] = vals[i];
+      for (int i = 0; i < kPartStride; ++i) A.part[(long)blockIdx.x * kPartStride + i] = vals[i];
     }
   }
   if (MODE == XM_RESID_ONLY) return;
@@ -149,7 +150,8 @@ __global__ __launch_bounds__(kThreads) void k_xc2r(XArgs<T> A) {
     const long row = row0 + lr;
     if (row >= A.nrows) break;
     const int j = (int)(row / nz);
-    const double c00 = A.phi00[j] * A.inv_nxnz;
+    double c00 = A.phi00[j] * A.inv_nxnz;
+    if (MODE == CM_ADD) c00 -= A.ctl->phimean;
     double* orow = A.out + row * nx;
     for (int m = lane; m < h; m += kWave) {
       const Cx<T> z = buf[lr * h + m];

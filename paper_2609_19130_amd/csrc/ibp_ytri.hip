@@ -7,11 +7,11 @@
 // j = 0..ny-1, real coefficients, complex right-hand side, a_0 = c_{ny-1} = 0
 // (homogeneous Neumann walls).
 //
-// Block decomposition: a block owns M consecutive spectral columns; the
-// P = 256/M threads of one column each own K consecutive rows (rows past ny
-// are decoupled padding).  All K rows are loaded before any arithmetic, so
-// every thread keeps K loads in flight, and consecutive threads read
-// consecutive columns (16*M-byte segments in FP64).
+// A block owns M consecutive spectral columns, staged through LDS; P lanes of
+// one wave own one column, K consecutive rows each (rows past ny are
+// decoupled padding).
+#include <cstdlib>
+
 #include "ibp_internal.hpp"
 
 namespace ibp {
@@ -23,11 +23,12 @@ namespace ibp {
 //   flux_0 = 0, flux_{j+1} = flux_j + dyf_j g_j,  X_0 = 0, X_j = X_{j-1} + dyc_j flux_j,
 // and X shifted to zero weighted mean.  Deterministic: fixed-order sums and
 // a Hillis-Steele scan over the 256 thread chunks.
+template <int NT>
 __device__ double block_excl_scan(double v, double* sc) {
   const int t = threadIdx.x;
   sc[t] = v;
   __syncthreads();
-  for (int off = 1; off < kThreads; off <<= 1) {
+  for (int off = 1; off < NT; off <<= 1) {
     const double add = t >= off ? sc[t - off] : 0.0;
     __syncthreads();
     sc[t] += add;
@@ -38,25 +39,28 @@ __device__ double block_excl_scan(double v, double* sc) {
   return r;
 }
 
+template <int NT>
 __device__ double block_sum_det(double v, double* sh) {
   bool ism[1] = {false};
   double a[1] = {v};
-  block_reduce<1>(a, ism, sh);
+  block_reduce<1, NT>(a, ism, sh);
   return a[0];
 }
 
-__device__ void reduce_parts(const ZeroArgs& Z, double* sh, double out[4]) {
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (long b = threadIdx.x; b < Z.nparts; b += kThreads) {
+template <int NT>
+__device__ void reduce_parts(const ZeroArgs& Z, double* sh, double out[kPartStride]) {
+  double v[kPartStride] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (long b = threadIdx.x; b < Z.nparts; b += NT) {
     const double* p = Z.part + b * kPartStride;
     v[0] += p[0];
     v[1] += p[1];
     v[2] = fmax(v[2], p[2]);
     v[3] += p[3];
+    v[4] += p[4];
   }
-  const bool ism[4] = {false, false, true, false};
-  block_reduce<4>(v, ism, sh);
-  for (int i = 0; i < 4; ++i) out[i] = v[i];
+  const bool ism[kPartStride] = {false, false, true, false, false};
+  block_reduce<kPartStride, NT>(v, ism, sh);
+  for (int i = 0; i < kPartStride; ++i) out[i] = v[i];
 }
 
 __device__ double next_scale(double rmax) {
@@ -64,16 +68,18 @@ __device__ double next_scale(double rmax) {
   return ldexp(1.0, 20 - ilogb(rmax));
 }
 
+template <int NT>
 __device__ void zero_mode_block(const ZeroArgs& Z) {
-  __shared__ double sc[kThreads];
-  __shared__ double sh[16];
+  __shared__ double sc[NT];
+  __shared__ double sh[(NT / kWave) * kPartStride];
   const int t = threadIdx.x, ny = Z.ny, nz = Z.nz;
-  const int CH = (ny + kThreads - 1) / kThreads;
+  constexpr int CHM = (kMaxNy + NT - 1) / NT;   // rows per thread at the largest ny
+  const int CH = (ny + NT - 1) / NT;
   const int j0 = t * CH;
-  double g[kMaxYChunk];
+  double g[CHM];
   double wsum = 0.0, dsum = 0.0, bad = 0.0;
 #pragma unroll
-  for (int c = 0; c < kMaxYChunk; ++c) {
+  for (int c = 0; c < CHM; ++c) {
     g[c] = 0.0;
     const int j = j0 + c;
     if (c < CH && j < ny) {
@@ -86,25 +92,25 @@ __device__ void zero_mode_block(const ZeroArgs& Z) {
       if (!isfinite(s)) bad += 1.0;
     }
   }
-  wsum = block_sum_det(wsum, sh);
-  dsum = block_sum_det(dsum, sh);
-  bad = block_sum_det(bad, sh);
+  wsum = block_sum_det<NT>(wsum, sh);
+  dsum = block_sum_det<NT>(dsum, sh);
+  bad = block_sum_det<NT>(bad, sh);
   const double nxnz = double(Z.nx) * double(Z.nz);
   const double m = wsum / (dsum * nxnz);
   // flux at the lower face of every cell of the chunk
   double loc = 0.0;
 #pragma unroll
-  for (int c = 0; c < kMaxYChunk; ++c) {
+  for (int c = 0; c < CHM; ++c) {
     const int j = j0 + c;
     if (c < CH && j < ny) {
       g[c] -= m * nxnz;
       loc += Z.dyf[j] * g[c];
     }
   }
-  double flux = block_excl_scan(loc, sc);
+  double flux = block_excl_scan<NT>(loc, sc);
   double tl = 0.0;
 #pragma unroll
-  for (int c = 0; c < kMaxYChunk; ++c) {      // g[c] <- dyc_j flux_j
+  for (int c = 0; c < CHM; ++c) {      // g[c] <- dyc_j flux_j
     const int j = j0 + c;
     if (c < CH && j < ny) {
       const double fj = flux;
@@ -113,10 +119,10 @@ __device__ void zero_mode_block(const ZeroArgs& Z) {
       tl += g[c];
     }
   }
-  double X = block_excl_scan(tl, sc);
+  double X = block_excl_scan<NT>(tl, sc);
   double xw = 0.0;
 #pragma unroll
-  for (int c = 0; c < kMaxYChunk; ++c) {      // g[c] <- X_j
+  for (int c = 0; c < CHM; ++c) {      // g[c] <- X_j
     const int j = j0 + c;
     if (c < CH && j < ny) {
       X += g[c];
@@ -124,16 +130,16 @@ __device__ void zero_mode_block(const ZeroArgs& Z) {
       xw += Z.dyf[j] * X;
     }
   }
-  xw = block_sum_det(xw, sh);
+  xw = block_sum_det<NT>(xw, sh);
   const double xbar = xw / dsum;
 #pragma unroll
-  for (int c = 0; c < kMaxYChunk; ++c) {
+  for (int c = 0; c < CHM; ++c) {
     const int j = j0 + c;
     if (c < CH && j < ny) Z.phi00[j] = g[c] - xbar;
   }
   if (Z.init) {
-    double p[4];
-    reduce_parts(Z, sh, p);
+    double p[kPartStride];
+    reduce_parts<NT>(Z, sh, p);
     if (t == 0) {
       Ctl* c = Z.ctl;
       c->done = 0;
@@ -147,6 +153,7 @@ __device__ void zero_mode_block(const ZeroArgs& Z) {
       c->rmax = __builtin_nan("");
       c->removed_mean = m;
       c->rel_residual = __builtin_nan("");
+      c->phimean = 0.0;
     }
   }
 }
@@ -158,48 +165,91 @@ __device__ void zero_mode_block(const ZeroArgs& Z) {
 //   n_j = L + a_j eps_{j-1},  D_j = c_j + n_j,  eps_j = n_j / D_j,
 //   d'_j = (a_j d'_{j-1} - F_j) / D_j,  X_j = d'_j + (c_j / D_j) X_{j+1},
 // so every pivot D_j is a sum of non-negative terms (no cancellation, also in
-// FP32).  Across the P row blocks of a column the three recurrences are
-// composed: eps by 2x2 Moebius matrices with non-negative entries, d' and X
-// by affine maps with coefficients in [0, 1]; one thread per column chains
-// the P block composites in LDS, then every thread re-sweeps its K rows.
-template <typename T, typename U, int K, int M>
-__global__ __launch_bounds__(kThreads) void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
-  constexpr int P = kThreads / M;
-  __shared__ U sA[M][P + 1], sB[M][P + 1], sC[M][P + 1];
-  __shared__ Cx<U> sD[M][P + 1];
+// FP32).  A column's rows are split into P partitions of K rows, one per
+// lane of a P-lane group inside one wave; the three recurrences are composed
+// per partition (eps by 2x2 Moebius matrices with non-negative entries, d'
+// and X by affine maps with coefficients in [0, 1]), chained across the
+// partitions with wave shuffles (Hillis-Steele), and each lane re-sweeps its
+// K rows.  The block's M columns are staged through LDS so that global loads
+// and stores are M * element-size contiguous bytes per row.
+
+// Column stride of the staged tile, = 2 (mod 32) elements: the coalesced
+// load/store mapping (consecutive lanes on consecutive columns, then rows)
+// then falls on distinct banks within each 16-lane (FP64) or 32-lane (FP32)
+// LDS pass.
+template <int K, int P>
+__host__ __device__ constexpr int ytile_col() {
+  return P * (K + 1) + ((2 - (P * (K + 1)) % 32) + 32) % 32;
+}
+
+template <typename U>
+__device__ __forceinline__ U shfl_up_w(U v, int d, int w) { return __shfl_up(v, d, w); }
+template <typename U>
+__device__ __forceinline__ U shfl_down_w(U v, int d, int w) { return __shfl_down(v, d, w); }
+
+template <typename T, typename U, int M, int P, int K>
+__global__ __launch_bounds__(M * P) void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
+  constexpr int NT = M * P;
+  constexpr int KS = K + 1;     // LDS slots per partition: odd, so lanes spread over banks
+  constexpr int LS = ytile_col<K, P>();   // LDS slots per column
+  __shared__ Cx<T> tile[M * LS];
   if (blockIdx.x == gridDim.x - 1) {
-    if (!(A.check_done && A.ctl->done)) zero_mode_block(Z);
+    if (!(A.check_done && A.ctl->done)) zero_mode_block<NT>(Z);
     return;
   }
   if (A.check_done && A.ctl->done) return;
-  const int m = threadIdx.x % M, p = threadIdx.x / M;
-  const long q = (long)blockIdx.x * M + m;
-  const bool valid = q < A.Q;
+  const int ny = A.ny;
+  const long Q = A.Q;
+  const long q0 = (long)blockIdx.x * M;
+  // ---- coalesced load of the [ny][M] tile into per-column partition slots:
+  // thread (row0 = tid / M, m = tid % M) moves rows row0 + P*i, i < K; all K
+  // loads are issued before the first LDS write (rows and columns past the
+  // end are clamped to valid addresses and their values discarded)
+  {
+    const int m = threadIdx.x % M, row0 = threadIdx.x / M;
+    const long qc = (q0 + m < Q) ? q0 + m : Q - 1;
+    Cx<T> ld[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int row = row0 + P * i;
+      ld[i] = A.spec[(long)(row < ny ? row : ny - 1) * Q + qc];
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int row = row0 + P * i;
+      const int pp = row / K;
+      tile[m * LS + pp * KS + (row - pp * K)] = row < ny ? ld[i] : Cx<T>{T(0), T(0)};
+    }
+  }
+  __syncthreads();
+  const int p = threadIdx.x % P, m = threadIdx.x / P;
+  const long q = q0 + m;
+  const bool valid = q < Q;
   const int kz = valid ? (int)(q / A.hp) : 0;
   const int kx = valid ? (int)(q - (long)kz * A.hp) : 0;
   U L = valid ? -(A.lamx[kx] + A.lamz[kz]) : U(1);
   if (q == 0) L = U(1);   // (0,0) is singular: solved in FP64 by the last block, zeroed here
-  const int s = p * K, ny = A.ny;
-  const long Q = A.Q;
-  const U* __restrict__ ya = A.ya;
-  const U* __restrict__ yc = A.yc;
+  const int s = p * K;
+  Cx<T>* my = tile + m * LS + p * KS;
 
-  Cx<U> d[K];
+  // face coefficients of this lane's rows: the tables are zero-padded to
+  // P*K rows, so rows past ny are decoupled (a = c = 0) and get shift 1
+  U ca[K], cc[K], cl[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    const int row = s + i;
-    Cx<T> v{T(0), T(0)};
-    if (valid && row < ny) v = A.spec[(long)row * Q + q];
-    d[i] = Cx<U>{U(v.x), U(v.y)};
+    ca[i] = A.ya[s + i];
+    cc[i] = A.yc[s + i];
+    cl[i] = (s + i < ny) ? L : U(1);
   }
-  // rows past ny are decoupled padding: a = c = 0, shift 1
-#define IBP_COEF(i, a_, c_, l_)           \
-  const bool in_ = (s + (i)) < ny;        \
-  const U a_ = in_ ? ya[s + (i)] : U(0);  \
-  const U c_ = in_ ? yc[s + (i)] : U(0);  \
-  const U l_ = in_ ? L : U(1);
+  Cx<U> d[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) d[i] = Cx<U>{U(my[i].x), U(my[i].y)};
+#define IBP_COEF(i, a_, c_, l_) \
+  const U a_ = ca[i];           \
+  const U c_ = cc[i];           \
+  const U l_ = cl[i];
 
-  // ---- scan 1: eps_out = (mA eps_in + mB) / (mC eps_in + 1) over the block
+  // ---- scan 1: eps_out = (mA eps_in + mB) / (mC eps_in + 1) over the partition
   U mA = U(1), mB = U(0), mC = U(0);
 #pragma unroll
   for (int i = 0; i < K; ++i) {
@@ -211,22 +261,22 @@ __global__ __launch_bounds__(kThreads) void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
     mB = n01 * inv;
     mC = n10 * inv;
   }
-  sA[m][p] = mA;
-  sB[m][p] = mB;
-  sC[m][p] = mC;
-  __syncthreads();
-  if (p == 0) {
-    U e = U(0);
-    for (int pp = 0; pp < P; ++pp) {
-      const U a_ = sA[m][pp], b_ = sB[m][pp], c_ = sC[m][pp];
-      sA[m][pp] = e;
-      e = (a_ * e + b_) / (c_ * e + U(1));
+#pragma unroll
+  for (int off = 1; off < P; off <<= 1) {   // inclusive prefix: mine after the earlier ones
+    const U pA = shfl_up_w(mA, off, P), pB = shfl_up_w(mB, off, P), pC = shfl_up_w(mC, off, P);
+    if (p >= off) {
+      const U n00 = mA * pA + mB * pC, n01 = mA * pB + mB;
+      const U n10 = mC * pA + pC, n11 = mC * pB + U(1);
+      const U inv = U(1) / n11;
+      mA = n00 * inv;
+      mB = n01 * inv;
+      mC = n10 * inv;
     }
   }
-  __syncthreads();
   U rD[K];
   {
-    U e = sA[m][p];
+    U e = shfl_up_w(mB, 1, P);     // eps entering the partition: earlier composite applied to 0
+    if (p == 0) e = U(0);
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       IBP_COEF(i, a, c, l)
@@ -235,8 +285,7 @@ __global__ __launch_bounds__(kThreads) void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
       e = n * rD[i];
     }
   }
-  __syncthreads();
-  // ---- scan 2: d'_out = mu d'_in + nu over the block
+  // ---- scan 2: d'_out = mu d'_in + nu over the partition
   {
     U mu = U(1);
     Cx<U> nu{U(0), U(0)};
@@ -249,22 +298,17 @@ __global__ __launch_bounds__(kThreads) void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
       mu = mi * mu;
       nu = csub(cscale(nu, mi), cscale(d[i], rD[i]));
     }
-    sA[m][p] = mu;
-    sD[m][p] = nu;
-  }
-  __syncthreads();
-  if (p == 0) {
-    Cx<U> x{U(0), U(0)};
-    for (int pp = 0; pp < P; ++pp) {
-      const U mu_ = sA[m][pp];
-      const Cx<U> nu_ = sD[m][pp];
-      sD[m][pp] = x;
-      x = cadd(cscale(x, mu_), nu_);
+#pragma unroll
+    for (int off = 1; off < P; off <<= 1) {
+      const U pm = shfl_up_w(mu, off, P);
+      const U px = shfl_up_w(nu.x, off, P), py = shfl_up_w(nu.y, off, P);
+      if (p >= off) {
+        nu = Cx<U>{mu * px + nu.x, mu * py + nu.y};
+        mu = mu * pm;
+      }
     }
-  }
-  __syncthreads();
-  {
-    Cx<U> prev = sD[m][p];
+    Cx<U> prev{shfl_up_w(nu.x, 1, P), shfl_up_w(nu.y, 1, P)};
+    if (p == 0) prev = Cx<U>{U(0), U(0)};
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       IBP_COEF(i, a, c, l)
@@ -274,8 +318,7 @@ __global__ __launch_bounds__(kThreads) void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
       prev = d[i];
     }
   }
-  __syncthreads();
-  // ---- scan 3 (upwards): X_first = T X_below + S over the block
+  // ---- scan 3 (upwards): X_first = T X_below + S over the partition
   {
     U Tt = U(1);
     Cx<U> S{U(0), U(0)};
@@ -288,23 +331,17 @@ __global__ __launch_bounds__(kThreads) void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
       Tt = tau * Tt;
       S = cadd(d[i], cscale(S, tau));
     }
-    sA[m][p] = Tt;
-    sD[m][p] = S;
-  }
-  __syncthreads();
-  if (p == 0) {
-    Cx<U> x{U(0), U(0)};
-    for (int pp = P - 1; pp >= 0; --pp) {
-      const U T_ = sA[m][pp];
-      const Cx<U> S_ = sD[m][pp];
-      sD[m][pp] = x;
-      x = cadd(cscale(x, T_), S_);
+#pragma unroll
+    for (int off = 1; off < P; off <<= 1) {   // inclusive suffix: mine before the later ones
+      const U nT = shfl_down_w(Tt, off, P);
+      const U sx = shfl_down_w(S.x, off, P), sy = shfl_down_w(S.y, off, P);
+      if (p + off < P) {
+        S = Cx<U>{Tt * sx + S.x, Tt * sy + S.y};
+        Tt = Tt * nT;
+      }
     }
-  }
-  __syncthreads();
-  if (!valid) return;
-  {
-    Cx<U> nxt = sD[m][p];
+    Cx<U> nxt{shfl_down_w(S.x, 1, P), shfl_down_w(S.y, 1, P)};
+    if (p == P - 1) nxt = Cx<U>{U(0), U(0)};
 #pragma unroll
     for (int i = K - 1; i >= 0; --i) {
       IBP_COEF(i, a, c, l)
@@ -317,11 +354,23 @@ __global__ __launch_bounds__(kThreads) void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
 #undef IBP_COEF
   const bool zero = (q == 0);
 #pragma unroll
-  for (int i = 0; i < K; ++i) {
-    const int row = s + i;
-    if (row < ny) {
-      const Cx<U> x = zero ? Cx<U>{U(0), U(0)} : d[i];
-      A.spec[(long)row * Q + q] = Cx<T>{T(x.x), T(x.y)};
+  for (int i = 0; i < K; ++i) my[i] = zero ? Cx<T>{T(0), T(0)} : Cx<T>{T(d[i].x), T(d[i].y)};
+  __syncthreads();
+  {
+    const int mm = threadIdx.x % M, row0 = threadIdx.x / M;
+    if (q0 + mm < Q) {
+      Cx<T> st[K];
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const int row = row0 + P * i;
+        const int pp = row / K;
+        st[i] = tile[mm * LS + pp * KS + (row - pp * K)];
+      }
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const int row = row0 + P * i;
+        if (row < ny) A.spec[(long)row * Q + q0 + mm] = st[i];
+      }
     }
   }
 }
@@ -331,10 +380,10 @@ __global__ __launch_bounds__(kThreads) void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
 // the residual pass, record ||r||/||f - m||, and either stop the refinement or
 // set the FP32 input scale of the next pass.
 __global__ __launch_bounds__(kThreads) void k_check(ZeroArgs Z) {
-  __shared__ double sh[16];
+  __shared__ double sh[4 * kPartStride];
   if (Z.ctl->done) return;
-  double p[4];
-  reduce_parts(Z, sh, p);
+  double p[kPartStride];
+  reduce_parts<kThreads>(Z, sh, p);
   if (threadIdx.x != 0) return;
   Ctl* c = Z.ctl;
   double rel;
@@ -346,6 +395,7 @@ __global__ __launch_bounds__(kThreads) void k_check(ZeroArgs Z) {
   c->fnorm2 = p[1];
   c->rmax = p[2];
   c->rel_residual = rel;
+  c->phimean = p[4] / (Z.dyf_sum * double(Z.nx) * double(Z.nz));
   if (p[3] > 0.0) c->nonfinite = 1;
   if (Z.final_pass || !(rel > Z.rtol)) {
     c->done = 1;
@@ -362,17 +412,18 @@ hipError_t launch_check(const ZeroArgs& z, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- dispatch
-static constexpr int kKs[] = {2, 4, 6, 8, 12, 16, 24};
+// Shapes: P = 32 lanes per column (P = 64 when ny > 768), K rows per lane
+// from {2, 4, 8, 12, 16, 24}; M columns per block so that a row segment is
+// 128 bytes, reduced while the staged tile would exceed 64 KB.
+static constexpr int kKs[] = {2, 4, 8, 12, 16, 24};
 
-bool ytri_shape(int ny, int* M, int* K) {
+bool ytri_shape(int ny, int* P, int* K) {
   if (ny < 2 || ny > kMaxNy) return false;
-  int m = 16;
-  while (m > 1 && (kThreads / m) * 24 < ny) m /= 2;
-  const int P = kThreads / m;
-  const int need = (ny + P - 1) / P;
+  const int p = ny > 32 * 24 ? 64 : 32;
+  const int need = (ny + p - 1) / p;
   for (int k : kKs) {
     if (k >= need) {
-      *M = m;
+      *P = p;
       *K = k;
       return true;
     }
@@ -380,32 +431,72 @@ bool ytri_shape(int ny, int* M, int* K) {
   return false;
 }
 
-template <typename T, typename U, int M>
-static hipError_t launch_ytri_m(int K, const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s, dim3 grid) {
-  dim3 block(kThreads);
+static int ycol_override() {
+  const char* e = getenv("IBP_YCOLS");   // tuning knob: columns per line-solve block
+  return e ? atoi(e) : 0;
+}
+
+template <typename T>
+static int ytri_cols(int P, int K) {
+  auto tile = [&](int M) {
+    const int col = P * (K + 1) + ((2 - (P * (K + 1)) % 32) + 32) % 32;
+    return (long)M * col * (long)sizeof(Cx<T>);
+  };
+  int M = 128 / (int)sizeof(Cx<T>);
+  const int o = ycol_override();
+  if (o == 2 || o == 4 || o == 8 || o == 16) M = o;
+  while (M > 2 && tile(M) > kYTileBytes) M /= 2;
+  while (M * P > 1024) M /= 2;
+  return M;
+}
+
+template <typename T, typename U, int M, int P, int K>
+static hipError_t launch_ytri_mpk(const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s) {
+  // only shapes ytri_cols can select are instantiated (staged tile <= 72 KB)
+  if constexpr ((long)M * ytile_col<K, P>() * (long)sizeof(Cx<T>) <= kYTileBytes && M * P <= 1024) {
+    const long nb = (a.Q + M - 1) / M + 1;   // + the (0,0)-mode block
+    hipLaunchKernelGGL((k_ytri<T, U, M, P, K>), dim3((unsigned)nb), dim3(M * P), 0, s, a, z);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, typename U, int M, int P>
+static hipError_t launch_ytri_mp(int K, const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s) {
   switch (K) {
-    case 2: hipLaunchKernelGGL((k_ytri<T, U, 2, M>), grid, block, 0, s, a, z); break;
-    case 4: hipLaunchKernelGGL((k_ytri<T, U, 4, M>), grid, block, 0, s, a, z); break;
-    case 6: hipLaunchKernelGGL((k_ytri<T, U, 6, M>), grid, block, 0, s, a, z); break;
-    case 8: hipLaunchKernelGGL((k_ytri<T, U, 8, M>), grid, block, 0, s, a, z); break;
-    case 12: hipLaunchKernelGGL((k_ytri<T, U, 12, M>), grid, block, 0, s, a, z); break;
-    case 16: hipLaunchKernelGGL((k_ytri<T, U, 16, M>), grid, block, 0, s, a, z); break;
-    case 24: hipLaunchKernelGGL((k_ytri<T, U, 24, M>), grid, block, 0, s, a, z); break;
+    case 2: return launch_ytri_mpk<T, U, M, P, 2>(a, z, s);
+    case 4: return launch_ytri_mpk<T, U, M, P, 4>(a, z, s);
+    case 8: return launch_ytri_mpk<T, U, M, P, 8>(a, z, s);
+    case 12: return launch_ytri_mpk<T, U, M, P, 12>(a, z, s);
+    case 16: return launch_ytri_mpk<T, U, M, P, 16>(a, z, s);
+    case 24: return launch_ytri_mpk<T, U, M, P, 24>(a, z, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 template <typename T, typename U>
-hipError_t launch_ytri(int M, int K, const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s) {
-  const long nb = (a.Q + M - 1) / M + 1;   // + the (0,0)-mode block
-  dim3 grid((unsigned)nb);
-  switch (M) {
-    case 16: return launch_ytri_m<T, U, 16>(K, a, z, s, grid);
-    case 8: return launch_ytri_m<T, U, 8>(K, a, z, s, grid);
-    case 4: return launch_ytri_m<T, U, 4>(K, a, z, s, grid);
-    default: return hipErrorInvalidValue;
+hipError_t launch_ytri(int P, int K, const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s) {
+  const int M = ytri_cols<T>(P, K);
+  if (P == 32) {
+    switch (M) {
+      case 16: return launch_ytri_mp<T, U, 16, 32>(K, a, z, s);
+      case 8: return launch_ytri_mp<T, U, 8, 32>(K, a, z, s);
+      case 4: return launch_ytri_mp<T, U, 4, 32>(K, a, z, s);
+      case 2: return launch_ytri_mp<T, U, 2, 32>(K, a, z, s);
+      default: return hipErrorInvalidValue;
+    }
   }
+  if (P == 64) {
+    switch (M) {
+      case 16: return launch_ytri_mp<T, U, 16, 64>(K, a, z, s);
+      case 8: return launch_ytri_mp<T, U, 8, 64>(K, a, z, s);
+      case 4: return launch_ytri_mp<T, U, 4, 64>(K, a, z, s);
+      case 2: return launch_ytri_mp<T, U, 2, 64>(K, a, z, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 template hipError_t launch_ytri<double, double>(int, int, const YArgs<double, double>&, const ZeroArgs&, hipStream_t);

@@ -43,6 +43,9 @@ SHAPES = [  # (nx, ny, nz, beta): several tiles, ragged tails, every radix
     (16, 17, 10, 2.0), (22, 33, 11, 2.0), (32, 40, 24, 1.5), (40, 100, 14, 2.5),
     (176, 20, 30, 2.0), (112, 45, 7, 3.0), (96, 130, 9, 2.0), (30, 400, 18, 3.0),
     (20, 777, 4, 3.0),
+    # power-of-two lengths take the register-FFT kernels (x, z or both)
+    (64, 20, 32, 2.0), (128, 33, 64, 2.5), (256, 17, 128, 2.0), (512, 9, 512, 3.0),
+    (1024, 6, 1024, 2.0), (32, 50, 20, 2.0), (48, 30, 256, 2.0), (64, 3, 1024, 1.0),
 ]
 
 
