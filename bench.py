@@ -45,12 +45,12 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def timed_solves(plan, f, phi, steps, warmup):
+def timed_solves(plan, f, phi, steps, warmup, profile=True):
     import torch
     for _ in range(warmup):
         plan.solve(f, phi)
     torch.cuda.synchronize()
-    plan.set_profiling(True)
+    plan.set_profiling(profile)
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -61,7 +61,7 @@ def timed_solves(plan, f, phi, steps, warmup):
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    prof = plan.profile()
+    prof = plan.profile() if profile else {}
     plan.set_profiling(False)
     return start.elapsed_time(stop) / steps, wall, prof
 
@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--mixed-iters", type=int, default=6)
     ap.add_argument("--forms", default="fp64,mixed,mixed_f64sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time without the per-launch events (no per-pass breakdown or roofline)")
     ap.add_argument("--cpu-sample", choices=["full", "quarter"], default="full")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -156,7 +158,7 @@ def main():
     for form in forms:
         plan.set_precision(form, 1e-10, args.mixed_iters)
         log(f"[bench] timing {form}: {args.warmup} warmup + {args.steps} steps")
-        ms, wall, prof = timed_solves(plan, f, phi, args.steps, args.warmup)
+        ms, wall, prof = timed_solves(plan, f, phi, args.steps, args.warmup, not args.no_profile)
         info = plan.info()
         results[form] = dict(ms=ms, wall=wall, prof=prof, info=info)
         log(f"[bench] {form}: {ms:.3f} ms/solve, info {info}")
@@ -182,6 +184,7 @@ def main():
             passes[name] = {"avg_ms": avg, "launches": p["launches"],
                             "gbs": p["bytes_per_launch"] / (avg * 1e-3) / 1e9}
         out["passes_fp64"] = passes
+    if r64 is not None and r64["prof"]:
         dom = max(r64["prof"].items(), key=lambda kv: kv[1]["total_ms"])
         name, p = dom
         avg = p["total_ms"] / p["launches"]

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -94,10 +95,17 @@ struct ibp_plan_s {
   Cx<float>* spec32 = nullptr;
   double* rowsum = nullptr;
   double* phi00 = nullptr;
+  double* ghat = nullptr;
+  int* ticket = nullptr;
   double* part = nullptr;
   Ctl* ctl = nullptr;
   hipStream_t last_stream = nullptr;
   bool solved = false;
+  // chunked x/z passes: second stream and dependency events
+  int chunk = 0;                   // y planes per chunk (0: whole grid per launch)
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_a, ev_b;
   // profiling: event pairs around launches, per pass id
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -112,11 +120,18 @@ long max_parts(const ibp_plan_s* p) {
   return nb > p->nbro ? nb : p->nbro;
 }
 
+size_t spec_bytes(const ibp_plan_s* p) {
+  const size_t b64 = (size_t)p->ny * spec_plane_stride<double>(p->hp, p->nz) * sizeof(Cx<double>);
+  const size_t b32 = (size_t)p->ny * spec_plane_stride<float>(p->hp, p->nz) * sizeof(Cx<float>);
+  return b64 > b32 ? b64 : b32;
+}
+
 size_t workspace_bytes(const ibp_plan_s* p) {
-  const size_t nh = (size_t)p->ny * p->nz * p->hp;
-  size_t b = align256(nh * sizeof(Cx<double>));
+  size_t b = align256(spec_bytes(p));
   b += align256((size_t)p->ny * p->nz * sizeof(double));
-  b += align256((size_t)p->ny * sizeof(double));
+  b += align256((size_t)p->ny * sizeof(double));   // phi00
+  b += align256((size_t)p->ny * sizeof(double));   // ghat
+  b += align256(sizeof(int));                      // ticket
   b += align256((size_t)max_parts(p) * kPartStride * sizeof(double));
   b += align256(sizeof(Ctl));
   return b;
@@ -124,14 +139,17 @@ size_t workspace_bytes(const ibp_plan_s* p) {
 
 void carve_workspace(ibp_plan_s* p) {
   char* c = static_cast<char*>(p->ws);
-  const size_t nh = (size_t)p->ny * p->nz * p->hp;
   p->spec64 = reinterpret_cast<Cx<double>*>(c);
   p->spec32 = reinterpret_cast<Cx<float>*>(c);
-  c += align256(nh * sizeof(Cx<double>));
+  c += align256(spec_bytes(p));
   p->rowsum = reinterpret_cast<double*>(c);
   c += align256((size_t)p->ny * p->nz * sizeof(double));
   p->phi00 = reinterpret_cast<double*>(c);
   c += align256((size_t)p->ny * sizeof(double));
+  p->ghat = reinterpret_cast<double*>(c);
+  c += align256((size_t)p->ny * sizeof(double));
+  p->ticket = reinterpret_cast<int*>(c);
+  c += align256(sizeof(int));
   p->part = reinterpret_cast<double*>(c);
   c += align256((size_t)max_parts(p) * kPartStride * sizeof(double));
   p->ctl = reinterpret_cast<Ctl*>(c);
@@ -154,6 +172,46 @@ ibp_status_t check_dims(int nx, int ny, int nz, FftPlan* fpx, FftPlan* fpz) {
 bool valid_plan(const ibp_plan_s* p) { return p != nullptr && p->tables != nullptr && p->ws != nullptr; }
 
 ibp_status_t enqueue_solve(ibp_plan_s* p, const double* rhs, double* phi, hipStream_t s);
+
+// y planes per chunk when the x/z passes run chunk by chunk on two streams
+// (IBP_CHUNK planes, rounded up to whole x-pass blocks; off by default and
+// for grids of fewer than three chunks).  Measured on MI355X at 512x384x512
+// the chunked form is slower at every chunk size (launch granularity), so it
+// is an opt-in for experiments on other shapes.
+int chunk_planes(const ibp_plan_s* p) {
+  int S = 0;
+  if (const char* e = getenv("IBP_CHUNK")) S = atoi(e);
+  if (S <= 0 || p->nz == 1) return 0;
+  while (((long)S * p->nz) % p->rb64 != 0 || ((long)S * p->nz) % p->rb32 != 0) ++S;
+  return p->ny >= 3 * S ? S : 0;
+}
+
+hipError_t setup_chunking(ibp_plan_s* p) {
+  p->chunk = chunk_planes(p);
+  if (p->chunk == 0) return hipSuccess;
+  const int nch = (p->ny + p->chunk - 1) / p->chunk;
+  hipError_t e = hipStreamCreateWithFlags(&p->s2, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+  for (int c = 0; c < nch && e == hipSuccess; ++c) {
+    hipEvent_t a = nullptr, b = nullptr;
+    e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
+    if (e == hipSuccess) p->ev_a.push_back(a);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b, hipEventDisableTiming);
+    if (e == hipSuccess) p->ev_b.push_back(b);
+  }
+  return e;
+}
+
+void release(ibp_plan_s* p) {
+  for (hipEvent_t e : p->ev_pool) hipEventDestroy(e);
+  for (hipEvent_t e : p->ev_a) hipEventDestroy(e);
+  for (hipEvent_t e : p->ev_b) hipEventDestroy(e);
+  if (p->ev_fork) hipEventDestroy(p->ev_fork);
+  if (p->s2) hipStreamDestroy(p->s2);
+  if (p->ws_owned && p->ws) hipFree(p->ws);
+  if (p->tables) hipFree(p->tables);
+  delete p;
+}
 
 enum Pass { P_XR2C, P_ZFWD, P_Y, P_ZINV, P_XC2R, P_XRES, P_CHECK, P_XRESONLY, P_XC2R_ADD, P_DIV, P_COUNT };
 const char* const kPassName[P_COUNT] = {"x_r2c", "z_fwd", "y_solve", "z_inv", "x_c2r", "x_resid_r2c",
@@ -381,6 +439,12 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     }
     p->ws_owned = true;
     carve_workspace(p);
+    e = setup_chunking(p);
+    if (e == hipSuccess) e = hipMemset(p->ticket, 0, sizeof(int));
+    if (e != hipSuccess) {
+      release(p);
+      return from_hip(e);
+    }
     *out = p;
     return IBP_SUCCESS;
   } catch (...) {
@@ -391,10 +455,7 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
 ibp_status_t ibp_plan_destroy(ibp_plan_t p) {
   if (p == nullptr) return IBP_SUCCESS;
   try {
-    for (hipEvent_t e : p->ev_pool) hipEventDestroy(e);
-    if (p->ws_owned && p->ws) hipFree(p->ws);
-    if (p->tables) hipFree(p->tables);
-    delete p;
+    release(p);
     return IBP_SUCCESS;
   } catch (...) {
     return IBP_ERROR_INTERNAL;
@@ -441,7 +502,7 @@ ibp_status_t ibp_plan_set_workspace(ibp_plan_t p, void* ptr, size_t bytes) {
       p->ws_owned = true;
     }
     carve_workspace(p);
-    return IBP_SUCCESS;
+    return from_hip(hipMemset(p->ticket, 0, sizeof(int)));
   } catch (...) {
     return IBP_ERROR_INTERNAL;
   }
@@ -591,8 +652,12 @@ XArgs<T> xargs(ibp_plan_s* p, const double* rhs, const double* phi_in, double* p
   a.nz = p->nz;
   a.h = p->h;
   a.hp = p->hp;
+  a.rs = spec_row_stride<T>(p->hp);
+  a.ps = spec_plane_stride<T>(p->hp, p->nz);
   a.rows_per_block = rb;
+  a.row_begin = 0;
   a.nrows = (long)p->ny * p->nz;
+  a.parts = 1;
   a.idx2 = 1.0 / (p->dx * p->dx);
   a.idz2 = 1.0 / (p->dz * p->dz);
   a.out_scale = 1.0 / ((double)p->h * (double)p->nz);
@@ -604,6 +669,8 @@ XArgs<T> xargs(ibp_plan_s* p, const double* rhs, const double* phi_in, double* p
 ZeroArgs zargs(ibp_plan_s* p, long nparts, int init, int mixed, int iter, int final_pass) {
   ZeroArgs z{};
   z.rowsum = p->rowsum;
+  z.ghat = p->ghat;
+  z.ticket = p->ticket;
   z.phi00 = p->phi00;
   z.dyf = p->dyf;
   z.dyc = p->dyc;
@@ -622,13 +689,19 @@ ZeroArgs zargs(ibp_plan_s* p, long nparts, int init, int mixed, int iter, int fi
   return z;
 }
 
-// Launch with optional profiling events around it.
-#define IBP_LAUNCH(pass, ...)                              \
-  do {                                                     \
-    hipError_t e_ = prof_mark(p, (pass), s, true);         \
-    if (e_ == hipSuccess) e_ = (__VA_ARGS__);              \
-    if (e_ == hipSuccess) e_ = prof_mark(p, (pass), s, false); \
-    if (e_ != hipSuccess) return from_hip(e_);             \
+// Launch `call` on `strm` with optional profiling events around it.
+#define IBP_LAUNCH_ON(pass, strm, ...)                         \
+  do {                                                         \
+    hipError_t e_ = prof_mark(p, (pass), (strm), true);        \
+    if (e_ == hipSuccess) e_ = (__VA_ARGS__);                  \
+    if (e_ == hipSuccess) e_ = prof_mark(p, (pass), (strm), false); \
+    if (e_ != hipSuccess) return from_hip(e_);                 \
+  } while (0)
+#define IBP_LAUNCH(pass, ...) IBP_LAUNCH_ON(pass, s, __VA_ARGS__)
+#define IBP_HIP(...)                                  \
+  do {                                                \
+    hipError_t e_ = (__VA_ARGS__);                    \
+    if (e_ != hipSuccess) return from_hip(e_);        \
   } while (0)
 
 template <typename T>
@@ -637,21 +710,92 @@ hipError_t run_xr2c(const ibp_plan_s* p, int mode, const XArgs<T>& a, hipStream_
   if (mode == XM_RESID_ONLY) {
     XArgs<T> b = a;
     b.rows_per_block = kTileX32 / p->h;
-    return launch_xr2c<T>(mode, b, p->nbro, s);
+    b.row_begin = 0;
+    b.nrows = (long)p->ny * p->nz;
+    b.parts = 1;
+    return launch_xr2c<T>(mode, b, s);
   }
-  return launch_xr2c<T>(mode, a, sizeof(T) == 8 ? p->nb64 : p->nb32, s);
+  return launch_xr2c<T>(mode, a, s);
 }
 
 template <typename T>
 hipError_t run_xc2r(const ibp_plan_s* p, int mode, const XArgs<T>& a, hipStream_t s) {
   if (p->xfast) return launch_xc2r_fast<T>(mode, a, s);
-  return launch_xc2r<T>(mode, a, sizeof(T) == 8 ? p->nb64 : p->nb32, s);
+  return launch_xc2r<T>(mode, a, s);
 }
 
 template <typename T>
-hipError_t run_zfft(const ibp_plan_s* p, bool inverse, const ZfArgs<T>& a, hipStream_t s) {
-  if (p->zfast) return launch_zfft_fast<T>(inverse, a, p->ny, s);
-  return launch_zfft<T>(inverse, a, p->ny, s);
+hipError_t run_zfft(const ibp_plan_s* p, bool inverse, const ZfArgs<T>& a, int nplanes, hipStream_t s) {
+  if (p->zfast) return launch_zfft_fast<T>(inverse, a, nplanes, s);
+  return launch_zfft<T>(inverse, a, nplanes, s);
+}
+
+// Forward transforms of the whole grid: x R2C then z FFT.  With chunking,
+// the two passes run plane chunk by plane chunk, the z pass of chunk c on
+// the plan's second stream right after the x pass of chunk c, so a chunk's
+// half spectrum is still resident in the Infinity Cache when the z pass
+// reads it; at most two chunks are in flight.
+template <typename T>
+ibp_status_t forward_xz(ibp_plan_s* p, XArgs<T> xa, int xmode, int xpass, ZfArgs<T> za, hipStream_t s) {
+  const int ny = p->ny, nz = p->nz, S = p->chunk;
+  if (S <= 0 || nz == 1) {
+    xa.row_begin = 0;
+    xa.nrows = (long)ny * nz;
+    IBP_LAUNCH(xpass, run_xr2c<T>(p, xmode, xa, s));
+    za.plane0 = 0;
+    if (nz > 1) IBP_LAUNCH(P_ZFWD, run_zfft<T>(p, false, za, ny, s));
+    return IBP_SUCCESS;
+  }
+  hipStream_t s2 = p->s2;
+  const int nch = (ny + S - 1) / S;
+  IBP_HIP(hipEventRecord(p->ev_fork, s));
+  IBP_HIP(hipStreamWaitEvent(s2, p->ev_fork, 0));
+  for (int c = 0; c < nch; ++c) {
+    const int j0 = c * S, j1 = j0 + S < ny ? j0 + S : ny;
+    if (c >= 2) IBP_HIP(hipStreamWaitEvent(s, p->ev_b[c - 2], 0));
+    xa.row_begin = (long)j0 * nz;
+    xa.nrows = (long)j1 * nz;
+    IBP_LAUNCH_ON(xpass, s, run_xr2c<T>(p, xmode, xa, s));
+    IBP_HIP(hipEventRecord(p->ev_a[c], s));
+    IBP_HIP(hipStreamWaitEvent(s2, p->ev_a[c], 0));
+    za.plane0 = j0;
+    IBP_LAUNCH_ON(P_ZFWD, s2, run_zfft<T>(p, false, za, j1 - j0, s2));
+    IBP_HIP(hipEventRecord(p->ev_b[c], s2));
+  }
+  IBP_HIP(hipStreamWaitEvent(s, p->ev_b[nch - 1], 0));
+  return IBP_SUCCESS;
+}
+
+// Inverse transforms: z inverse FFT then x C2R, chunked the same way (z on
+// the second stream, x on the caller's stream).
+template <typename T>
+ibp_status_t inverse_zx(ibp_plan_s* p, XArgs<T> xa, int cmode, int xpass, ZfArgs<T> za, hipStream_t s) {
+  const int ny = p->ny, nz = p->nz, S = p->chunk;
+  if (S <= 0 || nz == 1) {
+    za.plane0 = 0;
+    if (nz > 1) IBP_LAUNCH(P_ZINV, run_zfft<T>(p, true, za, ny, s));
+    xa.row_begin = 0;
+    xa.nrows = (long)ny * nz;
+    IBP_LAUNCH(xpass, run_xc2r<T>(p, cmode, xa, s));
+    return IBP_SUCCESS;
+  }
+  hipStream_t s2 = p->s2;
+  const int nch = (ny + S - 1) / S;
+  IBP_HIP(hipEventRecord(p->ev_fork, s));
+  IBP_HIP(hipStreamWaitEvent(s2, p->ev_fork, 0));
+  for (int c = 0; c < nch; ++c) {
+    const int j0 = c * S, j1 = j0 + S < ny ? j0 + S : ny;
+    if (c >= 2) IBP_HIP(hipStreamWaitEvent(s2, p->ev_a[c - 2], 0));
+    za.plane0 = j0;
+    IBP_LAUNCH_ON(P_ZINV, s2, run_zfft<T>(p, true, za, j1 - j0, s2));
+    IBP_HIP(hipEventRecord(p->ev_b[c], s2));
+    IBP_HIP(hipStreamWaitEvent(s, p->ev_b[c], 0));
+    xa.row_begin = (long)j0 * nz;
+    xa.nrows = (long)j1 * nz;
+    IBP_LAUNCH_ON(xpass, s, run_xc2r<T>(p, cmode, xa, s));
+    IBP_HIP(hipEventRecord(p->ev_a[c], s));
+  }
+  return IBP_SUCCESS;
 }
 
 template <typename U>
@@ -664,15 +808,16 @@ ibp_status_t enqueue_solve(ibp_plan_s* p, const double* rhs, double* phi, hipStr
   if (p->prec == IBP_MIXED_F64SWEEP) return enqueue_mixed<double>(p, rhs, phi, s);
   // FP64 direct solve: x R2C, z FFT, y line solves + FP64 (0,0), z inverse, x C2R
   XArgs<double> xa = xargs<double>(p, rhs, nullptr, phi, p->spec64, p->twx, p->rb64, 0);
-  IBP_LAUNCH(P_XR2C, run_xr2c<double>(p, XM_PLAIN, xa, s));
-  ZfArgs<double> za{p->spec64, p->twz, p->ctl, p->fpz, p->nz, p->hp, p->zc64, 0};
-  if (p->nz > 1) IBP_LAUNCH(P_ZFWD, run_zfft<double>(p, false, za, s));
+  xa.parts = 0;   // no norms needed: non-finite input shows up in the FP64 plane sums
+  ZfArgs<double> za{p->spec64, p->twz, p->ctl, p->fpz, p->nz, p->hp, p->zc64,
+                    spec_row_stride<double>(p->hp), spec_plane_stride<double>(p->hp, p->nz), 0, 0};
+  ibp_status_t st = forward_xz<double>(p, xa, XM_PLAIN, P_XR2C, za, s);
+  if (st != IBP_SUCCESS) return st;
   YArgs<double, double> ya{p->spec64, p->lamx, p->lamz, p->ya, p->yc, p->ctl,
-                           (long)p->nz * p->hp, p->ny, p->hp, 0};
-  IBP_LAUNCH(P_Y, launch_ytri<double, double>(p->yP, p->yK, ya, zargs(p, p->nb64, 1, 0, 0, 0), s));
-  if (p->nz > 1) IBP_LAUNCH(P_ZINV, run_zfft<double>(p, true, za, s));
-  IBP_LAUNCH(P_XC2R, run_xc2r<double>(p, CM_SET, xa, s));
-  return IBP_SUCCESS;
+                           (long)p->nz * spec_row_stride<double>(p->hp), spec_row_stride<double>(p->hp),
+                           spec_plane_stride<double>(p->hp, p->nz), p->ny, p->hp, 0};
+  IBP_LAUNCH(P_Y, launch_ytri<double, double>(p->yP, p->yK, ya, zargs(p, 0, 1, 0, 0, 0), s));
+  return inverse_zx<double>(p, xa, CM_SET, P_XC2R, za, s);
 }
 
 // Mixed forms: FP32 spectral passes wrapped in FP64 iterative refinement.
@@ -692,27 +837,33 @@ ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStr
   } else {
     lx = p->lamx32; lz = p->lamz32; ca = p->ya32; cc = p->yc32;
   }
-  const long Q = (long)p->nz * p->hp;
-  ZfArgs<float> za{p->spec32, p->twz32, p->ctl, p->fpz, p->nz, p->hp, p->zc32, 0};
-  YArgs<float, U> ya{p->spec32, lx, lz, ca, cc, p->ctl, Q, p->ny, p->hp, 0};
+  const long rs = spec_row_stride<float>(p->hp), ps = spec_plane_stride<float>(p->hp, p->nz);
+  const long Q = (long)p->nz * rs;
+  ZfArgs<float> za{p->spec32, p->twz32, p->ctl, p->fpz, p->nz, p->hp, p->zc32, rs, ps, 0, 0};
+  YArgs<float, U> ya{p->spec32, lx, lz, ca, cc, p->ctl, Q, rs, ps, p->ny, p->hp, 0};
 
   XArgs<float> xa = xargs<float>(p, rhs, phi, phi, p->spec32, p->twx32, p->rb32, 0);
-  IBP_LAUNCH(P_XR2C, run_xr2c<float>(p, XM_PLAIN, xa, s));
-  if (p->nz > 1) IBP_LAUNCH(P_ZFWD, run_zfft<float>(p, false, za, s));
+  ibp_status_t st = forward_xz<float>(p, xa, XM_PLAIN, P_XR2C, za, s);
+  if (st != IBP_SUCCESS) return st;
   IBP_LAUNCH(P_Y, launch_ytri<float, U>(p->yP, p->yK, ya, zargs(p, p->nb32, 1, 1, 0, 0), s));
-  if (p->nz > 1) IBP_LAUNCH(P_ZINV, run_zfft<float>(p, true, za, s));
-  IBP_LAUNCH(P_XC2R, run_xc2r<float>(p, CM_SET, xa, s));
+  st = inverse_zx<float>(p, xa, CM_SET, P_XC2R, za, s);
+  if (st != IBP_SUCCESS) return st;
 
   za.check_done = 1;
   ya.check_done = 1;
   for (int k = 1; k <= p->max_iters; ++k) {
     xa.iter = k;
+    // the residual pass is not chunked: the convergence test needs all of it
+    xa.row_begin = 0;
+    xa.nrows = (long)p->ny * p->nz;
     IBP_LAUNCH(P_XRES, run_xr2c<float>(p, XM_RESID, xa, s));
     IBP_LAUNCH(P_CHECK, launch_check(zargs(p, p->nb32, 0, 1, k, 0), s));
-    if (p->nz > 1) IBP_LAUNCH(P_ZFWD, run_zfft<float>(p, false, za, s));
+    ZfArgs<float> zf = za;
+    zf.plane0 = 0;
+    if (p->nz > 1) IBP_LAUNCH(P_ZFWD, run_zfft<float>(p, false, zf, p->ny, s));
     IBP_LAUNCH(P_Y, launch_ytri<float, U>(p->yP, p->yK, ya, zargs(p, p->nb32, 0, 1, k, 0), s));
-    if (p->nz > 1) IBP_LAUNCH(P_ZINV, run_zfft<float>(p, true, za, s));
-    IBP_LAUNCH(P_XC2R_ADD, run_xc2r<float>(p, CM_ADD, xa, s));
+    st = inverse_zx<float>(p, xa, CM_ADD, P_XC2R_ADD, za, s);
+    if (st != IBP_SUCCESS) return st;
   }
   xa.iter = p->max_iters + 1;
   IBP_LAUNCH(P_XRESONLY, run_xr2c<float>(p, XM_RESID_ONLY, xa, s));

@@ -29,7 +29,8 @@ __global__ __launch_bounds__(kThreads) void k_xr2c_reg(XArgs<T> A) {
   __shared__ double sh[4 * 5];
   if (MODE != XM_PLAIN && A.ctl->done) return;
   const int lr = threadIdx.x / TT, t = threadIdx.x % TT;
-  const long row = (long)blockIdx.x * RB + lr;
+  const long blk = A.row_begin / RB + blockIdx.x;
+  const long row = blk * RB + lr;
   const bool live = row < A.nrows;
   const int nx = A.nx, nz = A.nz, ny = A.ny;
   const int j = live ? (int)(row / nz) : 0;
@@ -83,13 +84,13 @@ __global__ __launch_bounds__(kThreads) void k_xr2c_reg(XArgs<T> A) {
 #pragma unroll
   for (int off = TT / 2; off > 0; off >>= 1) rs += __shfl_xor(rs, off, kWave);
   if (live && t == 0) A.rowsum[row] = rs;
-  {
+  if (A.parts) {
     double vals[5] = {acc_in2, acc_f2, acc_max, acc_bad, acc_wphi};
     const bool ismax[5] = {false, false, true, false, false};
     block_reduce<5>(vals, ismax, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
-      for (int q = 0; q < kPartStride; ++q) A.part[(long)blockIdx.x * kPartStride + q] = vals[q];
+      for (int q = 0; q < kPartStride; ++q) A.part[blk * kPartStride + q] = vals[q];
     }
   }
   Cx<T>* my = lds + lr * SS;
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(kThreads) void k_xr2c_reg(XArgs<T> A) {
   for (int q = 0; q < kE; ++q) my[pad8(t + TT * final_index<RL>(q))] = v[q];
   __syncthreads();
   if (!live) return;
-  Cx<T>* srow = A.spec + row * A.hp;
+  Cx<T>* srow = A.spec + row * A.rs + (row / nz) * (A.ps - (long)nz * A.rs);
 #pragma unroll
   for (int i = 0; i < kE; ++i) {
     const int kk = t + TT * i;
@@ -123,10 +124,12 @@ __global__ __launch_bounds__(kThreads) void k_xc2r_reg(XArgs<T> A) {
   __shared__ Cx<T> lds[RB * SS];
   if (MODE == CM_ADD && A.ctl->done) return;
   const int lr = threadIdx.x / TT, t = threadIdx.x % TT;
-  const long row = (long)blockIdx.x * RB + lr;
+  const long blk = A.row_begin / RB + blockIdx.x;
+  const long row = blk * RB + lr;
   const bool live = row < A.nrows;
   Cx<T> v[kE];
-  const Cx<T>* srow = A.spec + (live ? row : 0) * A.hp;
+  const long srow0 = live ? row * A.rs + (row / A.nz) * (A.ps - (long)A.nz * A.rs) : 0;
+  const Cx<T>* srow = A.spec + srow0;
 #pragma unroll
   for (int i = 0; i < kE; ++i) {
     const int kk = t + TT * i;
@@ -178,20 +181,20 @@ __global__ __launch_bounds__(C*(NZ / kE)) void k_zfft_reg(ZfArgs<T> A) {
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int col = blockIdx.x * C + c;
   const bool live = col < A.hp;
-  const int hp = A.hp;
-  Cx<T>* plane = A.spec + (size_t)blockIdx.y * NZ * hp;
+  const long rs = A.rs;
+  Cx<T>* plane = A.spec + (size_t)(A.plane0 + blockIdx.y) * A.ps;
   Cx<T> v[kE];
 #pragma unroll
   for (int i = 0; i < kE; ++i) {
     const int z = t + TT * i;
-    v[i] = live ? plane[(size_t)z * hp + col] : Cx<T>{T(0), T(0)};
+    v[i] = live ? plane[(size_t)z * rs + col] : Cx<T>{T(0), T(0)};
   }
   P::run(v, t, lds + c * SS, A.twz, 1);
   if (!live) return;
 #pragma unroll
   for (int q = 0; q < kE; ++q) {
     const int z = t + TT * final_index<RL>(q);
-    plane[(size_t)z * hp + col] = v[q];
+    plane[(size_t)z * rs + col] = v[q];
   }
 }
 
@@ -200,7 +203,7 @@ template <typename T, int MODE>
 static hipError_t xr2c_h(int h, const XArgs<T>& a, hipStream_t s) {
   auto go = [&](auto kern, int H) {
     const int RB = kThreads / (H / kE);
-    const long nb = (a.nrows + RB - 1) / RB;
+    const long nb = (a.nrows - a.row_begin + RB - 1) / RB;
     hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kThreads), 0, s, a);
     return hipGetLastError();
   };
@@ -218,7 +221,7 @@ template <typename T, int MODE>
 static hipError_t xc2r_h(int h, const XArgs<T>& a, hipStream_t s) {
   auto go = [&](auto kern, int H) {
     const int RB = kThreads / (H / kE);
-    const long nb = (a.nrows + RB - 1) / RB;
+    const long nb = (a.nrows - a.row_begin + RB - 1) / RB;
     hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kThreads), 0, s, a);
     return hipGetLastError();
   };
@@ -257,9 +260,9 @@ int fast_z_cols(int nz) {
 }
 
 template <typename T, bool INV>
-static hipError_t zfft_n(const ZfArgs<T>& a, int ny, hipStream_t s) {
+static hipError_t zfft_n(const ZfArgs<T>& a, int nplanes, hipStream_t s) {
   const int C = fast_z_cols<T>(a.nz);
-  const dim3 grid((unsigned)((a.hp + C - 1) / C), (unsigned)ny);
+  const dim3 grid((unsigned)((a.hp + C - 1) / C), (unsigned)nplanes);
   auto go = [&](auto kern, int threads) {
     hipLaunchKernelGGL(kern, grid, dim3(threads), 0, s, a);
     return hipGetLastError();
@@ -277,8 +280,8 @@ static hipError_t zfft_n(const ZfArgs<T>& a, int ny, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_zfft_fast(bool inverse, const ZfArgs<T>& a, int ny, hipStream_t s) {
-  return inverse ? zfft_n<T, true>(a, ny, s) : zfft_n<T, false>(a, ny, s);
+hipError_t launch_zfft_fast(bool inverse, const ZfArgs<T>& a, int nplanes, hipStream_t s) {
+  return inverse ? zfft_n<T, true>(a, nplanes, s) : zfft_n<T, false>(a, nplanes, s);
 }
 
 template hipError_t launch_xr2c_fast<double>(int, const XArgs<double>&, hipStream_t);

@@ -9,6 +9,20 @@
 
 namespace ibp {
 
+// Spectrum layout: each kz row of a y plane starts on a 128-byte boundary
+// (row stride rs = hp rounded up to 128 bytes) and each plane is padded by a
+// further 128 bytes (plane stride ps = nz*rs + 128 bytes), which keeps the
+// strided z-pass and line-solve accesses off a few HBM channels.
+template <typename T>
+inline long spec_row_stride(int hp) {
+  const long e = 128 / (2 * (long)sizeof(T));
+  return (hp + e - 1) / e * e;
+}
+template <typename T>
+inline long spec_plane_stride(int hp, int nz) {
+  return (long)nz * spec_row_stride<T>(hp) + 128 / (2 * (long)sizeof(T));
+}
+
 // Solve state kept in device memory.  The iteration-0 (0,0)-mode block
 // re-initialises it at the start of every solve, before any kernel reads it,
 // so no memset is ever enqueued (solves stay graph-capturable).
@@ -37,7 +51,7 @@ struct XArgs {
   const double* f;       // right-hand side [ny][nz][nx]
   const double* phi;     // current iterate (residual modes)
   double* out;           // solution [ny][nz][nx] (C2R)
-  Cx<T>* spec;           // half spectrum [ny][nz][hp]
+  Cx<T>* spec;           // half spectrum: (j, kz, kx) at j*ps + kz*rs + kx, kx < hp
   double* rowsum;        // [ny*nz] FP64 sums of each transformed row
   double* part;          // [nblocks][kPartStride]
   const double* phi00;   // [ny] (0,0)-mode solution (C2R)
@@ -48,8 +62,11 @@ struct XArgs {
   const double* dyf;     // cell widths (volume weights of the mean of phi)
   FftPlan fp;            // length h = nx/2
   int nx, ny, nz, h, hp;
+  long rs, ps;           // spectrum row and plane strides (elements)
   int rows_per_block;
-  long nrows;            // ny * nz
+  long row_begin;        // rows [row_begin, nrows) of the [ny][nz] row space; a multiple of rows_per_block
+  long nrows;            // end row (ny * nz for a whole-grid pass)
+  int parts;             // write the per-block norm partials
   double idx2, idz2;     // 1/dx^2, 1/dz^2
   double out_scale;      // 1/(h nz): normalisation of the two inverse transforms
   double inv_nxnz;
@@ -63,7 +80,9 @@ struct ZfArgs {
   Ctl* ctl;
   FftPlan fp;            // length nz
   int nz, hp, cols;      // cols: kx columns per block
+  long rs, ps;           // spectrum row and plane strides (elements)
   int check_done;
+  int plane0;            // first y plane of this launch
 };
 
 template <typename T, typename U>   // T: spectral storage, U: line-solve arithmetic
@@ -74,12 +93,15 @@ struct YArgs {
   const U* ya;           // [ny] face coefficients: sub- and super-diagonal of the y operator
   const U* yc;
   Ctl* ctl;
-  long Q;                // nz * hp spectral columns
+  long Q;                // nz * rs column slots (kx >= hp are padding)
+  long rs, ps;           // spectrum row and plane strides (elements)
   int ny, hp, check_done;
 };
 
 struct ZeroArgs {        // FP64 (0,0) mode and solve control
   const double* rowsum;
+  double* ghat;          // [ny] plane sums
+  int* ticket;           // completion counter of the plane blocks (0 between launches)
   double* phi00;
   const double* dyf;     // [ny]
   const double* dyc;     // [ny+1], entries 1..ny-1 used
@@ -118,12 +140,14 @@ template <> inline int tile_x<float>() { return kTileX32; }
 template <> inline int tile_z<double>() { return kTileZ64; }
 template <> inline int tile_z<float>() { return kTileZ32; }
 
+// x passes cover rows [a.row_begin, a.nrows); z passes cover planes
+// [a.plane0, a.plane0 + nplanes).
 template <typename T>
-hipError_t launch_xr2c(int mode, const XArgs<T>& a, long nblocks, hipStream_t s);
+hipError_t launch_xr2c(int mode, const XArgs<T>& a, hipStream_t s);
 template <typename T>
-hipError_t launch_xc2r(int mode, const XArgs<T>& a, long nblocks, hipStream_t s);
+hipError_t launch_xc2r(int mode, const XArgs<T>& a, hipStream_t s);
 template <typename T>
-hipError_t launch_zfft(bool inverse, const ZfArgs<T>& a, int ny, hipStream_t s);
+hipError_t launch_zfft(bool inverse, const ZfArgs<T>& a, int nplanes, hipStream_t s);
 template <typename T, typename U>
 hipError_t launch_ytri(int P, int K, const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s);
 hipError_t launch_check(const ZeroArgs& z, hipStream_t s);
@@ -134,7 +158,7 @@ hipError_t launch_xr2c_fast(int mode, const XArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_xc2r_fast(int mode, const XArgs<T>& a, hipStream_t s);
 template <typename T>
-hipError_t launch_zfft_fast(bool inverse, const ZfArgs<T>& a, int ny, hipStream_t s);
+hipError_t launch_zfft_fast(bool inverse, const ZfArgs<T>& a, int nplanes, hipStream_t s);
 long fast_x_rows_per_block(int h);
 template <typename T>
 int fast_z_cols(int nz);

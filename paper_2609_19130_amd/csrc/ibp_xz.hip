@@ -24,7 +24,8 @@ __global__ __launch_bounds__(kThreads) void k_xr2c(XArgs<T> A) {
   __shared__ double sh[4 * 5];
   if (MODE != XM_PLAIN && A.ctl->done) return;
   const int h = A.h, RB = A.rows_per_block, nx = A.nx, nz = A.nz, ny = A.ny;
-  const long row0 = (long)blockIdx.x * RB;
+  const long blk = A.row_begin / RB + blockIdx.x;
+  const long row0 = blk * RB;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   double acc_in2 = 0.0, acc_f2 = 0.0, acc_max = 0.0, acc_bad = 0.0, acc_wphi = 0.0;
   double mean = 0.0, s = 1.0;
@@ -82,13 +83,13 @@ __global__ __launch_bounds__(kThreads) void k_xr2c(XArgs<T> A) {
     rs = wave_sum(rs);
     if (MODE != XM_RESID_ONLY && lane == 0) A.rowsum[row] = rs;
   }
-  {
+  if (A.parts) {
     double vals[5] = {acc_in2, acc_f2, acc_max, acc_bad, acc_wphi};
     const bool ismax[5] = {false, false, true, false, false};
     block_reduce<5>(vals, ismax, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
-      for (int i = 0; i < kPartStride; ++i) A.part[(long)blockIdx.x * kPartStride + i] = vals[i];
+      for (int i = 0; i < kPartStride; ++i) A.part[blk * kPartStride + i] = vals[i];
     }
   }
   if (MODE == XM_RESID_ONLY) return;
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(kThreads) void k_xr2c(XArgs<T> A) {
     const Cx<T> D = csub(Zk, Zc);
     const Cx<T> O = Cx<T>{T(0.5) * D.y, T(-0.5) * D.x};     // D / 2i
     const Cx<T> WO = cmul(A.twx[k], O);
-    Cx<T>* srow = A.spec + row * A.hp;
+    Cx<T>* srow = A.spec + row * A.rs + (row / nz) * (A.ps - (long)nz * A.rs);
     srow[k] = cadd(E, WO);
     if (h - k != k) srow[h - k] = cconj(csub(E, WO));
   }
@@ -117,14 +118,15 @@ __global__ __launch_bounds__(kThreads) void k_xc2r(XArgs<T> A) {
   __shared__ Cx<T> buf[TILE];
   if (MODE == CM_ADD && A.ctl->done) return;
   const int h = A.h, RB = A.rows_per_block, nx = A.nx, nz = A.nz;
-  const long row0 = (long)blockIdx.x * RB;
+  const long blk = A.row_begin / RB + blockIdx.x;
+  const long row0 = blk * RB;
   const int hh = h / 2 + 1;
   for (int e = threadIdx.x; e < RB * hh; e += kThreads) {
     const int lr = e / hh, k = e - lr * hh;
     const long row = row0 + lr;
     Cx<T> Xk{T(0), T(0)}, Xm{T(0), T(0)};
     if (row < A.nrows) {
-      const Cx<T>* srow = A.spec + row * A.hp;
+      const Cx<T>* srow = A.spec + row * A.rs + (row / nz) * (A.ps - (long)nz * A.rs);
       Xk = srow[k];
       Xm = srow[h - k];
     }
@@ -172,24 +174,26 @@ __global__ __launch_bounds__(kThreads) void k_zfft(ZfArgs<T> A) {
   __shared__ Cx<T> buf[TILE + 64];
   if (A.check_done && A.ctl->done) return;
   const int nz = A.nz, C = A.cols, hp = A.hp, ss = nz + 1;
+  const long rs = A.rs;
   const int c0 = blockIdx.x * C;
-  Cx<T>* plane = A.spec + (size_t)blockIdx.y * nz * hp;
+  Cx<T>* plane = A.spec + (size_t)(A.plane0 + blockIdx.y) * A.ps;
   for (int e = threadIdx.x; e < C * nz; e += kThreads) {
     const int z = e / C, c = e - z * C;
-    buf[c * ss + z] = (c0 + c < hp) ? plane[(size_t)z * hp + c0 + c] : Cx<T>{T(0), T(0)};
+    buf[c * ss + z] = (c0 + c < hp) ? plane[(size_t)z * rs + c0 + c] : Cx<T>{T(0), T(0)};
   }
   __syncthreads();
   lds_fft<TILE, INV, T>(buf, C, ss, A.fp, A.twz, 1);
   for (int e = threadIdx.x; e < C * nz; e += kThreads) {
     const int z = e / C, c = e - z * C;
-    if (c0 + c < hp) plane[(size_t)z * hp + c0 + c] = buf[c * ss + z];
+    if (c0 + c < hp) plane[(size_t)z * rs + c0 + c] = buf[c * ss + z];
   }
 }
 
 // ---------------------------------------------------------------- launchers
 template <typename T>
-hipError_t launch_xr2c(int mode, const XArgs<T>& a, long nblocks, hipStream_t s) {
+hipError_t launch_xr2c(int mode, const XArgs<T>& a, hipStream_t s) {
   constexpr int TL = (sizeof(T) == 8) ? kTileX64 : kTileX32;
+  const long nblocks = (a.nrows - a.row_begin + a.rows_per_block - 1) / a.rows_per_block;
   dim3 grid((unsigned)nblocks), block(kThreads);
   switch (mode) {
     case XM_PLAIN: hipLaunchKernelGGL((k_xr2c<T, XM_PLAIN, TL>), grid, block, 0, s, a); break;
@@ -201,8 +205,9 @@ hipError_t launch_xr2c(int mode, const XArgs<T>& a, long nblocks, hipStream_t s)
 }
 
 template <typename T>
-hipError_t launch_xc2r(int mode, const XArgs<T>& a, long nblocks, hipStream_t s) {
+hipError_t launch_xc2r(int mode, const XArgs<T>& a, hipStream_t s) {
   constexpr int TL = (sizeof(T) == 8) ? kTileX64 : kTileX32;
+  const long nblocks = (a.nrows - a.row_begin + a.rows_per_block - 1) / a.rows_per_block;
   dim3 grid((unsigned)nblocks), block(kThreads);
   switch (mode) {
     case CM_SET: hipLaunchKernelGGL((k_xc2r<T, CM_SET, TL>), grid, block, 0, s, a); break;
@@ -213,9 +218,9 @@ hipError_t launch_xc2r(int mode, const XArgs<T>& a, long nblocks, hipStream_t s)
 }
 
 template <typename T>
-hipError_t launch_zfft(bool inverse, const ZfArgs<T>& a, int ny, hipStream_t s) {
+hipError_t launch_zfft(bool inverse, const ZfArgs<T>& a, int nplanes, hipStream_t s) {
   constexpr int TL = (sizeof(T) == 8) ? kTileZ64 : kTileZ32;
-  dim3 grid((unsigned)((a.hp + a.cols - 1) / a.cols), (unsigned)ny), block(kThreads);
+  dim3 grid((unsigned)((a.hp + a.cols - 1) / a.cols), (unsigned)nplanes), block(kThreads);
   if (inverse)
     hipLaunchKernelGGL((k_zfft<T, true, TL>), grid, block, 0, s, a);
   else
@@ -223,10 +228,10 @@ hipError_t launch_zfft(bool inverse, const ZfArgs<T>& a, int ny, hipStream_t s) 
   return hipGetLastError();
 }
 
-template hipError_t launch_xr2c<double>(int, const XArgs<double>&, long, hipStream_t);
-template hipError_t launch_xr2c<float>(int, const XArgs<float>&, long, hipStream_t);
-template hipError_t launch_xc2r<double>(int, const XArgs<double>&, long, hipStream_t);
-template hipError_t launch_xc2r<float>(int, const XArgs<float>&, long, hipStream_t);
+template hipError_t launch_xr2c<double>(int, const XArgs<double>&, hipStream_t);
+template hipError_t launch_xr2c<float>(int, const XArgs<float>&, hipStream_t);
+template hipError_t launch_xc2r<double>(int, const XArgs<double>&, hipStream_t);
+template hipError_t launch_xc2r<float>(int, const XArgs<float>&, hipStream_t);
 template hipError_t launch_zfft<double>(bool, const ZfArgs<double>&, int, hipStream_t);
 template hipError_t launch_zfft<float>(bool, const ZfArgs<float>&, int, hipStream_t);
 

@@ -68,14 +68,16 @@ __device__ double next_scale(double rmax) {
   return ldexp(1.0, 20 - ilogb(rmax));
 }
 
+// Scans of the (0,0) mode over the plane sums ghat[0..ny) (run by one block).
 template <int NT>
-__device__ void zero_mode_block(const ZeroArgs& Z) {
+__device__ void zero_mode_scans(const ZeroArgs& Z) {
   __shared__ double sc[NT];
   __shared__ double sh[(NT / kWave) * kPartStride];
-  const int t = threadIdx.x, ny = Z.ny, nz = Z.nz;
+  const int t = threadIdx.x, ny = Z.ny;
   constexpr int CHM = (kMaxNy + NT - 1) / NT;   // rows per thread at the largest ny
   const int CH = (ny + NT - 1) / NT;
   const int j0 = t * CH;
+  const volatile double* gh = Z.ghat;            // written by other blocks of this launch
   double g[CHM];
   double wsum = 0.0, dsum = 0.0, bad = 0.0;
 #pragma unroll
@@ -83,13 +85,11 @@ __device__ void zero_mode_block(const ZeroArgs& Z) {
     g[c] = 0.0;
     const int j = j0 + c;
     if (c < CH && j < ny) {
-      double s = 0.0;
-      const double* rs = Z.rowsum + (long)j * nz;
-      for (int k = 0; k < nz; ++k) s += rs[k];
-      g[c] = s;
-      wsum += Z.dyf[j] * s;
+      const double v = gh[j];
+      g[c] = v;
+      wsum += Z.dyf[j] * v;
       dsum += Z.dyf[j];
-      if (!isfinite(s)) bad += 1.0;
+      if (!isfinite(v)) bad += 1.0;
     }
   }
   wsum = block_sum_det<NT>(wsum, sh);
@@ -158,6 +158,30 @@ __device__ void zero_mode_block(const ZeroArgs& Z) {
   }
 }
 
+// Block j < ny: plane sum ghat[j] of the FP64 row sums (fixed-order tree);
+// the block that finishes last (atomic ticket) then runs the scans and
+// re-arms the ticket for the next launch.
+template <int NT>
+__device__ void zero_mode_plane(const ZeroArgs& Z, int j) {
+  __shared__ double sh[NT / kWave];
+  __shared__ int last;
+  double s = 0.0;
+  const double* rs = Z.rowsum + (long)j * Z.nz;
+  for (int k = threadIdx.x; k < Z.nz; k += NT) s += rs[k];
+  s = block_sum_det<NT>(s, sh);
+  if (threadIdx.x == 0) {
+    Z.ghat[j] = s;
+    __threadfence();
+    const int ticket = atomicAdd(Z.ticket, 1);
+    last = (ticket == Z.ny - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  zero_mode_scans<NT>(Z);
+  if (threadIdx.x == 0) atomicExch(Z.ticket, 0);
+}
+
 // ---------------------------------------------------------------- line solves
 // With L = -(lambda_x + lambda_z) >= 0 and the diagonal equal to
 // -(a_j + c_j + L) (the y operator is a difference of face fluxes), Thomas
@@ -193,14 +217,14 @@ __global__ __launch_bounds__(M * P) void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
   constexpr int KS = K + 1;     // LDS slots per partition: odd, so lanes spread over banks
   constexpr int LS = ytile_col<K, P>();   // LDS slots per column
   __shared__ Cx<T> tile[M * LS];
-  if (blockIdx.x == gridDim.x - 1) {
-    if (!(A.check_done && A.ctl->done)) zero_mode_block<NT>(Z);
+  if (A.check_done && A.ctl->done) return;
+  if (blockIdx.x < (unsigned)A.ny) {   // the first ny blocks: FP64 (0,0) mode
+    zero_mode_plane<NT>(Z, blockIdx.x);
     return;
   }
-  if (A.check_done && A.ctl->done) return;
   const int ny = A.ny;
   const long Q = A.Q;
-  const long q0 = (long)blockIdx.x * M;
+  const long q0 = (long)(blockIdx.x - ny) * M;
   // ---- coalesced load of the [ny][M] tile into per-column partition slots:
   // thread (row0 = tid / M, m = tid % M) moves rows row0 + P*i, i < K; all K
   // loads are issued before the first LDS write (rows and columns past the
@@ -212,7 +236,7 @@ __global__ __launch_bounds__(M * P) void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       const int row = row0 + P * i;
-      ld[i] = A.spec[(long)(row < ny ? row : ny - 1) * Q + qc];
+      ld[i] = A.spec[(long)(row < ny ? row : ny - 1) * A.ps + qc];
     }
 #pragma unroll
     for (int i = 0; i < K; ++i) {
@@ -224,11 +248,11 @@ __global__ __launch_bounds__(M * P) void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
   __syncthreads();
   const int p = threadIdx.x % P, m = threadIdx.x / P;
   const long q = q0 + m;
-  const bool valid = q < Q;
-  const int kz = valid ? (int)(q / A.hp) : 0;
-  const int kx = valid ? (int)(q - (long)kz * A.hp) : 0;
+  const int kz = q < Q ? (int)(q / A.rs) : 0;
+  const int kx = q < Q ? (int)(q - (long)kz * A.rs) : 0;
+  const bool valid = q < Q && kx < A.hp;   // row padding slots are not solved
   U L = valid ? -(A.lamx[kx] + A.lamz[kz]) : U(1);
-  if (q == 0) L = U(1);   // (0,0) is singular: solved in FP64 by the last block, zeroed here
+  if (q == 0) L = U(1);   // (0,0) is singular: solved in FP64 by the plane blocks, zeroed here
   const int s = p * K;
   Cx<T>* my = tile + m * LS + p * KS;
 
@@ -358,7 +382,8 @@ __global__ __launch_bounds__(M * P) void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
   __syncthreads();
   {
     const int mm = threadIdx.x % M, row0 = threadIdx.x / M;
-    if (q0 + mm < Q) {
+    const long qs = q0 + mm;
+    if (qs < Q && qs % A.rs < A.hp) {
       Cx<T> st[K];
 #pragma unroll
       for (int i = 0; i < K; ++i) {
@@ -369,7 +394,7 @@ __global__ __launch_bounds__(M * P) void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
 #pragma unroll
       for (int i = 0; i < K; ++i) {
         const int row = row0 + P * i;
-        if (row < ny) A.spec[(long)row * Q + q0 + mm] = st[i];
+        if (row < ny) A.spec[(long)row * A.ps + qs] = st[i];
       }
     }
   }
@@ -454,7 +479,7 @@ template <typename T, typename U, int M, int P, int K>
 static hipError_t launch_ytri_mpk(const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s) {
   // only shapes ytri_cols can select are instantiated (staged tile <= 72 KB)
   if constexpr ((long)M * ytile_col<K, P>() * (long)sizeof(Cx<T>) <= kYTileBytes && M * P <= 1024) {
-    const long nb = (a.Q + M - 1) / M + 1;   // + the (0,0)-mode block
+    const long nb = (a.Q + M - 1) / M + a.ny;   // + the (0,0)-mode plane blocks
     hipLaunchKernelGGL((k_ytri<T, U, M, P, K>), dim3((unsigned)nb), dim3(M * P), 0, s, a, z);
     return hipGetLastError();
   } else {
