@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -80,6 +81,10 @@ struct ibp_plan_s {
   long nb64 = 1, nb32 = 1;  // x-pass blocks (transform passes)
   long nbro = 1;            // blocks of the residual-only pass
   bool xfast = false, zfast = false;   // register-FFT kernels for power-of-two lengths
+  // fused persistent x/z passes (nz = nx and both lengths register-FFT sizes)
+  bool fused = false;
+  int fblocks64 = 0, fblocks32 = 0;   // persistent blocks (FP64 / FP32 spectrum)
+  long nbf = 0;                       // x-row blocks of a fused pass (= its partials)
   // device tables
   void* tables = nullptr;
   const double *ya = nullptr, *yc = nullptr, *dyf = nullptr, *dyc = nullptr;
@@ -97,6 +102,9 @@ struct ibp_plan_s {
   double* phi00 = nullptr;
   double* ghat = nullptr;
   int* ticket = nullptr;
+  int* fctl = nullptr;   // fused-pass counters: queues[16], exit count, error flag, pad[2], done[ny]
+  int nq = 0;                               // XCD work queues of the fused passes
+  signed char xcc_queue[kMaxXcc] = {0};     // hardware XCC id -> queue
   double* part = nullptr;
   Ctl* ctl = nullptr;
   hipStream_t last_stream = nullptr;
@@ -115,9 +123,21 @@ struct ibp_plan_s {
 
 namespace {
 
+// fused-pass counter block: queues, exit count, error flag, padding, done[ny]
+constexpr int kFctlQueue = 0, kFctlExit = kMaxXcc, kFctlError = kMaxXcc + 1, kFctlHead = kMaxXcc + 4;
+
 long max_parts(const ibp_plan_s* p) {
   long nb = p->nb64 > p->nb32 ? p->nb64 : p->nb32;
+  nb = nb > p->nbf ? nb : p->nbf;
   return nb > p->nbro ? nb : p->nbro;
+}
+
+// Counters that kernels expect at zero between launches (each kernel that
+// uses one re-arms it before it exits).
+hipError_t reset_counters(ibp_plan_s* p) {
+  hipError_t e = hipMemset(p->ticket, 0, sizeof(int));
+  if (e == hipSuccess) e = hipMemset(p->fctl, 0, (size_t)(kFctlHead + p->ny) * sizeof(int));
+  return e;
 }
 
 size_t spec_bytes(const ibp_plan_s* p) {
@@ -132,6 +152,7 @@ size_t workspace_bytes(const ibp_plan_s* p) {
   b += align256((size_t)p->ny * sizeof(double));   // phi00
   b += align256((size_t)p->ny * sizeof(double));   // ghat
   b += align256(sizeof(int));                      // ticket
+  b += align256((size_t)(kFctlHead + p->ny) * sizeof(int)); // fused-pass counters
   b += align256((size_t)max_parts(p) * kPartStride * sizeof(double));
   b += align256(sizeof(Ctl));
   return b;
@@ -150,6 +171,8 @@ void carve_workspace(ibp_plan_s* p) {
   c += align256((size_t)p->ny * sizeof(double));
   p->ticket = reinterpret_cast<int*>(c);
   c += align256(sizeof(int));
+  p->fctl = reinterpret_cast<int*>(c);
+  c += align256((size_t)(kFctlHead + p->ny) * sizeof(int));
   p->part = reinterpret_cast<double*>(c);
   c += align256((size_t)max_parts(p) * kPartStride * sizeof(double));
   p->ctl = reinterpret_cast<Ctl*>(c);
@@ -167,6 +190,40 @@ ibp_status_t check_dims(int nx, int ny, int nz, FftPlan* fpx, FftPlan* fpz) {
   if (fpx) *fpx = a;
   if (fpz) *fpz = b;
   return IBP_SUCCESS;
+}
+
+// XCD map of a device: the hardware XCC ids that blocks of a wide launch
+// report, numbered densely in increasing order.  Probed once per device.
+struct XccMap {
+  bool probed = false;
+  int nq = 0;
+  signed char queue[kMaxXcc];
+};
+
+hipError_t xcc_map(int device, XccMap* out) {
+  static std::mutex mu;
+  static std::vector<XccMap> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)cache.size() <= device) cache.resize(device + 1);
+  XccMap& m = cache[device];
+  if (!m.probed) {
+    constexpr int kProbeBlocks = 4096;
+    int* d = nullptr;
+    std::vector<int> ids(kProbeBlocks, -1);
+    hipError_t e = hipMalloc(&d, kProbeBlocks * sizeof(int));
+    if (e == hipSuccess) e = launch_xcc_probe(d, kProbeBlocks, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(ids.data(), d, kProbeBlocks * sizeof(int), hipMemcpyDeviceToHost);
+    if (d) hipFree(d);
+    if (e != hipSuccess) return e;
+    bool seen[kMaxXcc] = {false};
+    for (int v : ids)
+      if (v >= 0 && v < kMaxXcc) seen[v] = true;
+    m.nq = 0;
+    for (int i = 0; i < kMaxXcc; ++i) m.queue[i] = seen[i] ? (signed char)m.nq++ : (signed char)-1;
+    m.probed = true;
+  }
+  *out = m;
+  return hipSuccess;
 }
 
 bool valid_plan(const ibp_plan_s* p) { return p != nullptr && p->tables != nullptr && p->ws != nullptr; }
@@ -213,9 +270,14 @@ void release(ibp_plan_s* p) {
   delete p;
 }
 
-enum Pass { P_XR2C, P_ZFWD, P_Y, P_ZINV, P_XC2R, P_XRES, P_CHECK, P_XRESONLY, P_XC2R_ADD, P_DIV, P_COUNT };
-const char* const kPassName[P_COUNT] = {"x_r2c", "z_fwd", "y_solve", "z_inv", "x_c2r", "x_resid_r2c",
-                                        "check", "x_resid_only", "x_c2r_add", "divergence"};
+enum Pass {
+  P_XR2C, P_ZFWD, P_Y, P_ZINV, P_XC2R, P_XRES, P_CHECK, P_XRESONLY, P_XC2R_ADD, P_DIV,
+  P_XZF, P_ZXI, P_ZXI_ADD, P_COUNT
+};
+const char* const kPassName[P_COUNT] = {"x_r2c",  "z_fwd",      "y_solve",    "z_inv",
+                                        "x_c2r",  "x_resid_r2c", "check",      "x_resid_only",
+                                        "x_c2r_add", "divergence", "xz_fwd",   "zx_inv",
+                                        "zx_inv_add"};
 
 // Algorithmic bytes of one launch of each pass (each input element read
 // once, each output element written once).  N = nx ny nz cells, Nh =
@@ -234,6 +296,9 @@ double pass_bytes(const ibp_plan_s* p, int pass) {
     case P_XRESONLY: return 16.0 * N;
     case P_XC2R_ADD: return cb * Nh + 16.0 * N;    // spectrum and phi in, phi out
     case P_DIV: return 32.0 * N;                   // u, v, w in, f out
+    case P_XZF: return 8.0 * N + cb * Nh;          // fused: the spectrum makes one trip
+    case P_ZXI: return cb * Nh + 8.0 * N;
+    case P_ZXI_ADD: return cb * Nh + 16.0 * N;
     default: return 0.0;
   }
 }
@@ -324,6 +389,12 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     }
     p->nb64 = (nrows + p->rb64 - 1) / p->rb64;
     p->nb32 = (nrows + p->rb32 - 1) / p->rb32;
+    // Fused persistent x/z passes: opt-in (IBP_FUSED=1).  Measured on MI355X
+    // at 512x384x512 they move the same HBM bytes as the separate passes
+    // (a plane's intermediate does not stay in its XCD's L2) and run slower.
+    p->fused = false;
+    if (const char* e = getenv("IBP_FUSED")) p->fused = atoi(e) != 0 && p->xfast && p->zfast && fused_supported(p->h, nz);
+    if (p->fused) p->nbf = nrows / fused_x_rows(p->h);
     p->zc64 = kTileZ64 / nz;
     p->zc32 = kTileZ32 / nz;
     if (p->zc64 > 64) p->zc64 = 64;
@@ -407,6 +478,28 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     const size_t o_twz32 = put(cz32.data(), cz32.size() * sizeof(float));
 
     hipError_t e = hipGetDevice(&p->device);
+    if (e == hipSuccess && p->fused) {
+      int cus = 0, b64 = 0, b32 = 0;
+      e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+      if (e == hipSuccess) e = fused_blocks_per_cu<double>(p->h, &b64);
+      if (e == hipSuccess) e = fused_blocks_per_cu<float>(p->h, &b32);
+      if (const char* v = getenv("IBP_FUSED_BPCU")) {   // tuning override
+        const int o = atoi(v);
+        if (o > 0) {
+          b64 = o < b64 ? o : b64;
+          b32 = o < b32 ? o : b32;
+        }
+      }
+      p->fblocks64 = cus * b64;
+      p->fblocks32 = cus * b32;
+      XccMap xm;
+      if (e == hipSuccess) e = xcc_map(p->device, &xm);
+      if (e == hipSuccess) {
+        p->nq = xm.nq;
+        for (int i = 0; i < kMaxXcc; ++i) p->xcc_queue[i] = xm.queue[i];
+        if (p->nq < 1 || p->fblocks64 < p->nq || p->fblocks32 < p->nq) p->fused = false;
+      }
+    }
     if (e == hipSuccess) e = hipMalloc(&p->tables, host.size());
     if (e == hipSuccess) e = hipMemcpy(p->tables, host.data(), host.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -440,7 +533,7 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     p->ws_owned = true;
     carve_workspace(p);
     e = setup_chunking(p);
-    if (e == hipSuccess) e = hipMemset(p->ticket, 0, sizeof(int));
+    if (e == hipSuccess) e = reset_counters(p);
     if (e != hipSuccess) {
       release(p);
       return from_hip(e);
@@ -502,7 +595,7 @@ ibp_status_t ibp_plan_set_workspace(ibp_plan_t p, void* ptr, size_t bytes) {
       p->ws_owned = true;
     }
     carve_workspace(p);
-    return from_hip(hipMemset(p->ticket, 0, sizeof(int)));
+    return from_hip(reset_counters(p));
   } catch (...) {
     return IBP_ERROR_INTERNAL;
   }
@@ -557,7 +650,13 @@ ibp_status_t ibp_get_info(ibp_plan_t p, ibp_info_t* out) {
     hipError_t e = hipStreamSynchronize(p->last_stream);
     Ctl c{};
     if (e == hipSuccess) e = hipMemcpy(&c, p->ctl, sizeof(Ctl), hipMemcpyDeviceToHost);
+    int dep_error = 0;
+    if (e == hipSuccess) e = hipMemcpy(&dep_error, p->fctl + kFctlError, sizeof(int), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return from_hip(e);
+    if (dep_error) {   // a fused pass gave up waiting on a dependency: results invalid
+      hipMemset(p->fctl + kFctlError, 0, sizeof(int));
+      return IBP_ERROR_INTERNAL;
+    }
     out->iterations = c.iters;
     out->converged = c.converged;
     out->nonfinite_input = c.nonfinite;
@@ -736,8 +835,41 @@ hipError_t run_zfft(const ibp_plan_s* p, bool inverse, const ZfArgs<T>& a, int n
 // half spectrum is still resident in the Infinity Cache when the z pass
 // reads it; at most two chunks are in flight.
 template <typename T>
+FusedArgs<T> fused_args(const ibp_plan_s* p, const XArgs<T>& xa, const ZfArgs<T>& za, bool fwd) {
+  FusedArgs<T> F{};
+  F.x = xa;
+  F.x.row_begin = 0;
+  F.x.nrows = (long)p->ny * p->nz;
+  F.z = za;
+  F.z.plane0 = 0;
+  F.queue = p->fctl + kFctlQueue;
+  F.exit_count = p->fctl + kFctlExit;
+  F.error = p->fctl + kFctlError;
+  F.done = p->fctl + kFctlHead;
+  F.nq = p->nq;
+  for (int i = 0; i < kMaxXcc; ++i) F.xcc_queue[i] = p->xcc_queue[i];
+  const int nx_items = p->nz / fused_x_rows(p->h);
+  const int nz_items = (p->hp + fused_z_cols(p->nz) - 1) / fused_z_cols(p->nz);
+  F.nfirst = fwd ? nx_items : nz_items;
+  F.nsecond = fwd ? nz_items : nx_items;
+  F.ny = p->ny;
+  const int G = (sizeof(T) == 8 ? p->fblocks64 : p->fblocks32) / p->nq;   // blocks per XCD
+  // lag: rounds between a plane's first-stage and second-stage items, so
+  // that the blocks in flight on one XCD rarely wait on a dependency
+  int lag = (G + F.nfirst + F.nsecond - 1) / (F.nfirst + F.nsecond) + 1;
+  if (const char* e = getenv("IBP_FUSED_LAG")) lag = atoi(e) > 0 ? atoi(e) : lag;
+  F.lag = lag < 1 ? 1 : lag;
+  return F;
+}
+
+template <typename T>
 ibp_status_t forward_xz(ibp_plan_s* p, XArgs<T> xa, int xmode, int xpass, ZfArgs<T> za, hipStream_t s) {
   const int ny = p->ny, nz = p->nz, S = p->chunk;
+  if (p->fused && xmode == XM_PLAIN && S <= 0) {
+    const int G = sizeof(T) == 8 ? p->fblocks64 : p->fblocks32;
+    IBP_LAUNCH(P_XZF, launch_fused_fwd<T>(fused_args<T>(p, xa, za, true), G, s));
+    return IBP_SUCCESS;
+  }
   if (S <= 0 || nz == 1) {
     xa.row_begin = 0;
     xa.nrows = (long)ny * nz;
@@ -771,6 +903,11 @@ ibp_status_t forward_xz(ibp_plan_s* p, XArgs<T> xa, int xmode, int xpass, ZfArgs
 template <typename T>
 ibp_status_t inverse_zx(ibp_plan_s* p, XArgs<T> xa, int cmode, int xpass, ZfArgs<T> za, hipStream_t s) {
   const int ny = p->ny, nz = p->nz, S = p->chunk;
+  if (p->fused && S <= 0 && (cmode == CM_SET || sizeof(T) == 4)) {
+    const int G = sizeof(T) == 8 ? p->fblocks64 : p->fblocks32;
+    IBP_LAUNCH(cmode == CM_SET ? P_ZXI : P_ZXI_ADD, launch_fused_inv<T>(cmode, fused_args<T>(p, xa, za, false), G, s));
+    return IBP_SUCCESS;
+  }
   if (S <= 0 || nz == 1) {
     za.plane0 = 0;
     if (nz > 1) IBP_LAUNCH(P_ZINV, run_zfft<T>(p, true, za, ny, s));
@@ -845,7 +982,9 @@ ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStr
   XArgs<float> xa = xargs<float>(p, rhs, phi, phi, p->spec32, p->twx32, p->rb32, 0);
   ibp_status_t st = forward_xz<float>(p, xa, XM_PLAIN, P_XR2C, za, s);
   if (st != IBP_SUCCESS) return st;
-  IBP_LAUNCH(P_Y, launch_ytri<float, U>(p->yP, p->yK, ya, zargs(p, p->nb32, 1, 1, 0, 0), s));
+  // partials of the initial pass: one per x-row block of whichever x kernel ran
+  const long np0 = (p->fused && p->chunk <= 0) ? p->nbf : p->nb32;
+  IBP_LAUNCH(P_Y, launch_ytri<float, U>(p->yP, p->yK, ya, zargs(p, np0, 1, 1, 0, 0), s));
   st = inverse_zx<float>(p, xa, CM_SET, P_XC2R, za, s);
   if (st != IBP_SUCCESS) return st;
 

@@ -18,18 +18,16 @@ using rfft::final_index;
 using rfft::kE;
 using rfft::pad8;
 
-template <typename T, int MODE, int H>
-__global__ __launch_bounds__(kThreads) void k_xr2c_reg(XArgs<T> A) {
+// x R2C of rows [blk*RB, blk*RB + RB) with NT threads (RB = NT / (H/8)).
+// Every thread of the block must call it; it returns with LDS free.
+template <typename T, int MODE, int H, int NT>
+__device__ __forceinline__ void xr2c_body(const XArgs<T>& A, long blk, Cx<T>* lds, double* sh, int tid) {
   constexpr int TT = H / kE;
-  constexpr int RB = kThreads / TT;
   constexpr int SS = rfft::Seq<H>::stride;
   using P = rfft::Plan<H, false, T>;
   constexpr int RL = P::last_radix();
-  __shared__ Cx<T> lds[RB * SS];
-  __shared__ double sh[4 * 5];
-  if (MODE != XM_PLAIN && A.ctl->done) return;
-  const int lr = threadIdx.x / TT, t = threadIdx.x % TT;
-  const long blk = A.row_begin / RB + blockIdx.x;
+  constexpr int RB = NT / TT;
+  const int lr = tid / TT, t = tid % TT;
   const long row = blk * RB + lr;
   const bool live = row < A.nrows;
   const int nx = A.nx, nz = A.nz, ny = A.ny;
@@ -87,7 +85,7 @@ __global__ __launch_bounds__(kThreads) void k_xr2c_reg(XArgs<T> A) {
   if (A.parts) {
     double vals[5] = {acc_in2, acc_f2, acc_max, acc_bad, acc_wphi};
     const bool ismax[5] = {false, false, true, false, false};
-    block_reduce<5>(vals, ismax, sh);
+    block_reduce<5, NT>(vals, ismax, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
       for (int q = 0; q < kPartStride; ++q) A.part[blk * kPartStride + q] = vals[q];
@@ -98,10 +96,9 @@ __global__ __launch_bounds__(kThreads) void k_xr2c_reg(XArgs<T> A) {
 #pragma unroll
   for (int q = 0; q < kE; ++q) my[pad8(t + TT * final_index<RL>(q))] = v[q];
   __syncthreads();
-  if (!live) return;
   Cx<T>* srow = A.spec + row * A.rs + (row / nz) * (A.ps - (long)nz * A.rs);
 #pragma unroll
-  for (int i = 0; i < kE; ++i) {
+  for (int i = 0; i < kE && live; ++i) {
     const int kk = t + TT * i;
     const Cx<T> Zk = my[pad8(kk)];
     const Cx<T> Zc = cconj(my[pad8((H - kk) & (H - 1))]);
@@ -112,19 +109,27 @@ __global__ __launch_bounds__(kThreads) void k_xr2c_reg(XArgs<T> A) {
     srow[kk] = cadd(E, WO);
     if (kk == 0) srow[H] = cconj(csub(E, WO));
   }
+  __syncthreads();
 }
 
 template <typename T, int MODE, int H>
-__global__ __launch_bounds__(kThreads) void k_xc2r_reg(XArgs<T> A) {
+__global__ __launch_bounds__(kThreads) void k_xr2c_reg(XArgs<T> A) {
+  constexpr int RB = kThreads / (H / kE);
+  __shared__ Cx<T> lds[RB * rfft::Seq<H>::stride];
+  __shared__ double sh[(kThreads / kWave) * 5];
+  if (MODE != XM_PLAIN && A.ctl->done) return;
+  xr2c_body<T, MODE, H, kThreads>(A, A.row_begin / RB + blockIdx.x, lds, sh, threadIdx.x);
+}
+
+// x C2R of rows [blk*RB, blk*RB + RB) with NT threads; called by every thread.
+template <typename T, int MODE, int H, int NT>
+__device__ __forceinline__ void xc2r_body(const XArgs<T>& A, long blk, Cx<T>* lds, int tid) {
   constexpr int TT = H / kE;
-  constexpr int RB = kThreads / TT;
   constexpr int SS = rfft::Seq<H>::stride;
   using P = rfft::Plan<H, true, T>;
   constexpr int RL = P::last_radix();
-  __shared__ Cx<T> lds[RB * SS];
-  if (MODE == CM_ADD && A.ctl->done) return;
-  const int lr = threadIdx.x / TT, t = threadIdx.x % TT;
-  const long blk = A.row_begin / RB + blockIdx.x;
+  constexpr int RB = NT / TT;
+  const int lr = tid / TT, t = tid % TT;
   const long row = blk * RB + lr;
   const bool live = row < A.nrows;
   Cx<T> v[kE];
@@ -149,7 +154,7 @@ __global__ __launch_bounds__(kThreads) void k_xc2r_reg(XArgs<T> A) {
     v[i] = Cx<T>{E.x - O.y, E.y + O.x};   // E + i O
   }
   P::run(v, t, lds + lr * SS, A.twx, 2);
-  if (!live) return;
+  if (!live) return;   // no barrier follows
   double cs = A.out_scale;
   if (MODE == CM_ADD) cs = cs / A.ctl->scale[A.iter & 1];
   const int j = (int)(row / A.nz);
@@ -170,19 +175,28 @@ __global__ __launch_bounds__(kThreads) void k_xc2r_reg(XArgs<T> A) {
   }
 }
 
+template <typename T, int MODE, int H>
+__global__ __launch_bounds__(kThreads) void k_xc2r_reg(XArgs<T> A) {
+  constexpr int RB = kThreads / (H / kE);
+  __shared__ Cx<T> lds[RB * rfft::Seq<H>::stride];
+  if (MODE == CM_ADD && A.ctl->done) return;
+  xc2r_body<T, MODE, H, kThreads>(A, A.row_begin / RB + blockIdx.x, lds, threadIdx.x);
+}
+
+// z FFT of kx columns [colblk*C, colblk*C + C) of one y plane with C*NZ/8
+// threads; called by every thread; returns with LDS free.
 template <typename T, bool INV, int NZ, int C>
-__global__ __launch_bounds__(C*(NZ / kE)) void k_zfft_reg(ZfArgs<T> A) {
+__device__ __forceinline__ void zfft_body(const ZfArgs<T>& A, int colblk, long plane_index, Cx<T>* lds,
+                                          int tid) {
   constexpr int TT = NZ / kE;
   constexpr int SS = rfft::Seq<NZ>::stride;
   using P = rfft::Plan<NZ, INV, T>;
   constexpr int RL = P::last_radix();
-  __shared__ Cx<T> lds[C * SS];
-  if (A.check_done && A.ctl->done) return;
-  const int c = threadIdx.x % C, t = threadIdx.x / C;
-  const int col = blockIdx.x * C + c;
+  const int c = tid % C, t = tid / C;
+  const int col = colblk * C + c;
   const bool live = col < A.hp;
   const long rs = A.rs;
-  Cx<T>* plane = A.spec + (size_t)(A.plane0 + blockIdx.y) * A.ps;
+  Cx<T>* plane = A.spec + (size_t)plane_index * A.ps;
   Cx<T> v[kE];
 #pragma unroll
   for (int i = 0; i < kE; ++i) {
@@ -190,13 +204,262 @@ __global__ __launch_bounds__(C*(NZ / kE)) void k_zfft_reg(ZfArgs<T> A) {
     v[i] = live ? plane[(size_t)z * rs + col] : Cx<T>{T(0), T(0)};
   }
   P::run(v, t, lds + c * SS, A.twz, 1);
-  if (!live) return;
+  if (!live) return;   // no barrier follows
 #pragma unroll
   for (int q = 0; q < kE; ++q) {
     const int z = t + TT * final_index<RL>(q);
     plane[(size_t)z * rs + col] = v[q];
   }
 }
+
+template <typename T, bool INV, int NZ, int C>
+__global__ __launch_bounds__(C*(NZ / kE)) void k_zfft_reg(ZfArgs<T> A) {
+  __shared__ Cx<T> lds[C * rfft::Seq<NZ>::stride];
+  if (A.check_done && A.ctl->done) return;
+  zfft_body<T, INV, NZ, C>(A, blockIdx.x, A.plane0 + blockIdx.y, lds, threadIdx.x);
+}
+
+
+
+// ---------------------------------------------------------------- fused x/z
+// Item g of the round sequence -> (stage, plane, index within the plane).
+__device__ __forceinline__ void decode_item(long g, int ny, int D, int n1, int n2, int* stage, int* plane,
+                                            int* idx) {
+  const long a = (long)D * n1;
+  if (g < a) {
+    *stage = 0;
+    *plane = (int)(g / n1);
+    *idx = (int)(g - (long)(*plane) * n1);
+    return;
+  }
+  g -= a;
+  const long n12 = (long)n1 + n2;
+  const long b = (long)(ny - D) * n12;
+  if (g < b) {
+    const long r = g / n12;
+    const int o = (int)(g - r * n12);
+    if (o < n1) {
+      *stage = 0;
+      *plane = D + (int)r;
+      *idx = o;
+    } else {
+      *stage = 1;
+      *plane = (int)r;
+      *idx = o - n1;
+    }
+    return;
+  }
+  g -= b;
+  *stage = 1;
+  *plane = (ny - D) + (int)(g / n2);
+  *idx = (int)(g % n2);
+}
+
+// Control flow of the fused kernel is kept wave-uniform: the queue claim,
+// the dependency wait and the completion count are done by all 64 lanes of
+// wave 0 (only lane 0 adds 1) and their results are broadcast with
+// readfirstlane.  With per-thread branches (threadIdx.x == 0) around these
+// steps the compiler may thread the branches across the loop's barriers so
+// that the other lanes loop back before lane 0 has claimed the next item.
+
+// Hardware id of the XCD (accelerator complex die) this wave runs on: bits
+// [3:0] of the XCC_ID hardware register (register 20 on CDNA3/CDNA4).
+__device__ __forceinline__ int xcc_id() {
+  constexpr int kXccIdReg = 20, kSize = 4, kOffset = 0;
+  return __builtin_amdgcn_readfirstlane(
+      __builtin_amdgcn_s_getreg(((kSize - 1) << 11) | (kOffset << 6) | kXccIdReg) & 15);
+}
+
+__global__ void k_xcc_probe(int* out) {
+  const int x = xcc_id();
+  if (threadIdx.x == 0) out[blockIdx.x] = x;
+}
+
+hipError_t launch_xcc_probe(int* out, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_xcc_probe, dim3((unsigned)nblocks), dim3(64), 0, s, out);
+  return hipGetLastError();
+}
+
+// Wave 0 waits until `counter` reaches `need`; bounded so that a broken
+// dependency raises the error flag instead of hanging the device.
+__device__ __forceinline__ void wave_wait_count(int* counter, int need, int* error) {
+  for (int spins = 0;; ++spins) {
+    const int v = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (v >= need) break;
+    if (spins >= (1 << 20)) {
+      __hip_atomic_store(error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+// s_waitcnt immediate for vmcnt(0) with expcnt and lgkmcnt left free
+// (gfx9 encoding: vmcnt [3:0] and [15:14], expcnt [6:4], lgkmcnt [11:8]).
+constexpr int kWaitVmcnt0 = 0x0F70;
+
+// Planes of queue q: q, q + nq, q + 2 nq, ... below ny.
+__device__ __forceinline__ int queue_planes(int q, int nq, int ny) { return q < ny ? (ny - q + nq - 1) / nq : 0; }
+
+// Coherence within one XCD: the vector L1 is write-through and the L2 is
+// shared by all compute units of the XCD, so a producer's stores are in the
+// L2 once its store counter drains (workgroup release), and a consumer reads
+// them through the L2.  A consumer's L1 never holds an older copy of a line
+// it reads: within one launch a block reads a line of the intermediate only
+// after the line is final (forward) or only lines it wrote itself before
+// (inverse z stage), and the L1 starts the launch empty.
+template <typename T, int H, int NZ, bool FWD, int MODE>
+__global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fused_xz(FusedArgs<T> F) {
+  constexpr int NT = kFusedThreads;
+  constexpr int RBX = NT / (H / kE), CZ = NT / (NZ / kE);
+  constexpr int LX = RBX * rfft::Seq<H>::stride, LZ = CZ * rfft::Seq<NZ>::stride;
+  __shared__ Cx<T> lds[LX > LZ ? LX : LZ];
+  __shared__ double sh[(NT / kWave) * 5];
+  __shared__ int item;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x) / kWave;   // uniform
+  const int lane = (int)threadIdx.x % kWave;
+  if (FWD ? MODE != XM_PLAIN : MODE == CM_ADD) {
+    if (__builtin_amdgcn_readfirstlane(F.x.ctl->done)) return;   // every block: no counter touched
+  }
+  const int q = __builtin_amdgcn_readfirstlane((int)F.xcc_queue[xcc_id()]);
+  const int n12 = F.nfirst + F.nsecond;
+  const int nplanes = q >= 0 ? queue_planes(q, F.nq, F.ny) : 0;
+  const int lag = F.lag < nplanes ? F.lag : nplanes;
+  const long total = (long)nplanes * n12;
+  int* queue = F.queue + (q >= 0 ? q : 0);
+  for (;;) {
+    if (total == 0) break;
+    if (wave == 0) {
+      const int got = atomicAdd(queue, lane == 0 ? 1 : 0);
+      item = __builtin_amdgcn_readfirstlane(got);
+    }
+    __syncthreads();
+    const long g = __builtin_amdgcn_readfirstlane(item);
+    __syncthreads();
+    if (g >= total) break;
+    int stage, k, idx;
+    decode_item(g, nplanes, lag, F.nfirst, F.nsecond, &stage, &k, &idx);
+    stage = __builtin_amdgcn_readfirstlane(stage);
+    const int plane = __builtin_amdgcn_readfirstlane(q + k * F.nq);
+    idx = __builtin_amdgcn_readfirstlane(idx);
+    // Opaque copy of the thread index: keeps the bodies' per-thread index
+    // arithmetic inside the loop instead of hoisted (and held in registers)
+    // across both bodies.
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    if (stage == 0) {
+      if (FWD)
+        xr2c_body<T, MODE, H, NT>(F.x, (long)plane * F.nfirst + idx, lds, sh, tid);
+      else
+        zfft_body<T, true, NZ, CZ>(F.z, idx, plane, lds, tid);
+      // wait until this wave's stores are acknowledged by the L2 (a workgroup
+      // release fence emits no such wait: the waves of a block share the L1)
+      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+      __syncthreads();
+      if (wave == 0) atomicAdd(&F.done[plane], lane == 0 ? 1 : 0);
+    } else {
+      if (wave == 0) wave_wait_count(&F.done[plane], F.nfirst, F.error);
+      __syncthreads();
+      if (FWD)
+        zfft_body<T, false, NZ, CZ>(F.z, idx, plane, lds, tid);
+      else
+        xc2r_body<T, MODE, H, NT>(F.x, (long)plane * F.nsecond + idx, lds, tid);
+      __syncthreads();
+    }
+  }
+  if (wave == 0) {
+    const int t = __builtin_amdgcn_readfirstlane(atomicAdd(F.exit_count, lane == 0 ? 1 : 0));
+    if (t == (int)gridDim.x - 1) {   // every block has left its loop
+      // a queue whose XCD received no block leaves its planes untransformed
+      int unserved = 0;
+      for (int qq = 0; qq < F.nq; ++qq) {
+        const int claimed = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(F.queue + qq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (claimed < queue_planes(qq, F.nq, F.ny) * n12) unserved = 1;
+      }
+      if (unserved && lane == 0) __hip_atomic_store(F.error, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int j = lane; j < F.ny; j += kWave) F.done[j] = 0;
+      if (lane < kMaxXcc) F.queue[lane] = 0;
+      if (lane == 0) *F.exit_count = 0;
+    }
+  }
+}
+
+bool fused_supported(int h, int nz) {
+  if (!rfft::supported(h) || !rfft::supported(nz) || nz != 2 * h) return false;
+  return nz % fused_x_rows(h) == 0;
+}
+int fused_x_rows(int h) { return kFusedThreads / (h / kE); }
+int fused_z_cols(int nz) { return kFusedThreads / (nz / kE); }
+
+template <typename T>
+hipError_t launch_fused_fwd(const FusedArgs<T>& a, int blocks, hipStream_t s) {
+  const dim3 grid((unsigned)blocks), block(kFusedThreads);
+  switch (a.x.h) {
+    case 32: hipLaunchKernelGGL((k_fused_xz<T, 32, 64, true, XM_PLAIN>), grid, block, 0, s, a); break;
+    case 64: hipLaunchKernelGGL((k_fused_xz<T, 64, 128, true, XM_PLAIN>), grid, block, 0, s, a); break;
+    case 128: hipLaunchKernelGGL((k_fused_xz<T, 128, 256, true, XM_PLAIN>), grid, block, 0, s, a); break;
+    case 256: hipLaunchKernelGGL((k_fused_xz<T, 256, 512, true, XM_PLAIN>), grid, block, 0, s, a); break;
+    case 512: hipLaunchKernelGGL((k_fused_xz<T, 512, 1024, true, XM_PLAIN>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int MODE>
+static hipError_t fused_inv_m(const FusedArgs<T>& a, int blocks, hipStream_t s) {
+  const dim3 grid((unsigned)blocks), block(kFusedThreads);
+  switch (a.x.h) {
+    case 32: hipLaunchKernelGGL((k_fused_xz<T, 32, 64, false, MODE>), grid, block, 0, s, a); break;
+    case 64: hipLaunchKernelGGL((k_fused_xz<T, 64, 128, false, MODE>), grid, block, 0, s, a); break;
+    case 128: hipLaunchKernelGGL((k_fused_xz<T, 128, 256, false, MODE>), grid, block, 0, s, a); break;
+    case 256: hipLaunchKernelGGL((k_fused_xz<T, 256, 512, false, MODE>), grid, block, 0, s, a); break;
+    case 512: hipLaunchKernelGGL((k_fused_xz<T, 512, 1024, false, MODE>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fused_inv(int cmode, const FusedArgs<T>& a, int blocks, hipStream_t s) {
+  if (cmode == CM_SET) return fused_inv_m<T, CM_SET>(a, blocks, s);
+  if constexpr (sizeof(T) == 4) {
+    if (cmode == CM_ADD) return fused_inv_m<T, CM_ADD>(a, blocks, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int H>
+static hipError_t fused_occ(int* blocks) {
+  int a = 0, b = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &a, reinterpret_cast<const void*>(&k_fused_xz<T, H, 2 * H, true, XM_PLAIN>), kFusedThreads, 0);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &b, reinterpret_cast<const void*>(&k_fused_xz<T, H, 2 * H, false, CM_SET>), kFusedThreads, 0);
+  *blocks = a < b ? a : b;
+  return e;
+}
+
+template <typename T>
+hipError_t fused_blocks_per_cu(int h, int* blocks) {
+  switch (h) {
+    case 32: return fused_occ<T, 32>(blocks);
+    case 64: return fused_occ<T, 64>(blocks);
+    case 128: return fused_occ<T, 128>(blocks);
+    case 256: return fused_occ<T, 256>(blocks);
+    case 512: return fused_occ<T, 512>(blocks);
+    default: *blocks = 0; return hipErrorInvalidValue;
+  }
+}
+template hipError_t fused_blocks_per_cu<double>(int, int*);
+template hipError_t fused_blocks_per_cu<float>(int, int*);
+
+template hipError_t launch_fused_fwd<double>(const FusedArgs<double>&, int, hipStream_t);
+template hipError_t launch_fused_fwd<float>(const FusedArgs<float>&, int, hipStream_t);
+template hipError_t launch_fused_inv<double>(int, const FusedArgs<double>&, int, hipStream_t);
+template hipError_t launch_fused_inv<float>(int, const FusedArgs<float>&, int, hipStream_t);
 
 // ---------------------------------------------------------------- launchers
 template <typename T, int MODE>

@@ -117,6 +117,32 @@ struct ZeroArgs {        // FP64 (0,0) mode and solve control
   double dyf_sum;        // sum_j dyf_j
 };
 
+// Fused x/z pass (persistent).  The y planes are dealt out to one work
+// queue per XCD (plane p to queue p % nq) and a block only serves the queue
+// of the XCD it runs on, so a plane's producer and consumer blocks share
+// one L2 and the intermediate half spectrum never needs a device-wide cache
+// write-back or invalidation.  Round r of a queue holds the first-stage
+// items of its r-th plane followed by the second-stage items of its
+// (r - lag)-th plane; second-stage items of a plane wait until all its
+// first-stage items are complete (per-plane counters in `done`).  Forward:
+// x R2C then z FFT; inverse: z inverse FFT then x C2R.  The last block to
+// finish checks that every queue was served and zeroes the counters.
+constexpr int kMaxXcc = 16;
+template <typename T>
+struct FusedArgs {
+  XArgs<T> x;
+  ZfArgs<T> z;
+  int* queue;            // [kMaxXcc]
+  int* done;             // [ny]
+  int* exit_count;
+  int* error;            // 1: a dependency wait ran out, 2: a queue had no block (results invalid)
+  int nfirst, nsecond;   // items per plane of the first and second stage
+  int lag;
+  int ny;
+  int nq;                           // queues (XCDs)
+  signed char xcc_queue[kMaxXcc];   // hardware XCC id -> queue (-1: none)
+};
+
 struct DivArgs {
   const double* u;
   const double* v;
@@ -160,6 +186,23 @@ hipError_t launch_xc2r_fast(int mode, const XArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_zfft_fast(bool inverse, const ZfArgs<T>& a, int nplanes, hipStream_t s);
 long fast_x_rows_per_block(int h);
+
+// Fused persistent forward (x R2C + z FFT) or inverse (z inverse + x C2R)
+// pass; available when fused_supported(h, nz).  `blocks` persistent blocks.
+constexpr int kFusedThreads = 512;
+bool fused_supported(int h, int nz);
+int fused_x_rows(int h);
+int fused_z_cols(int nz);
+template <typename T>
+hipError_t launch_fused_fwd(const FusedArgs<T>& a, int blocks, hipStream_t s);
+template <typename T>
+hipError_t launch_fused_inv(int cmode, const FusedArgs<T>& a, int blocks, hipStream_t s);
+// Resident blocks per compute unit of the fused kernels (minimum over the
+// forward and inverse forms) for half length h.
+template <typename T>
+hipError_t fused_blocks_per_cu(int h, int* blocks);
+// Hardware XCC id of `nblocks` blocks (one int each), for the XCD map.
+hipError_t launch_xcc_probe(int* out, int nblocks, hipStream_t s);
 template <typename T>
 int fast_z_cols(int nz);
 hipError_t launch_divergence(const DivArgs& a, hipStream_t s);

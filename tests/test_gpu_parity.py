@@ -46,6 +46,8 @@ SHAPES = [  # (nx, ny, nz, beta): several tiles, ragged tails, every radix
     # power-of-two lengths take the register-FFT kernels (x, z or both)
     (64, 20, 32, 2.0), (128, 33, 64, 2.5), (256, 17, 128, 2.0), (512, 9, 512, 3.0),
     (1024, 6, 1024, 2.0), (32, 50, 20, 2.0), (48, 30, 256, 2.0), (64, 3, 1024, 1.0),
+    # nz = nx with register-FFT lengths: fused persistent x/z passes
+    (32, 5, 32, 2.0), (64, 19, 64, 2.5), (128, 40, 128, 2.0), (256, 11, 256, 3.0),
 ]
 
 
@@ -125,6 +127,51 @@ def test_plane_chunking_is_bitwise_neutral(monkeypatch, precision, nx, ny, nz, c
     if precision == "fp64":
         ref, _ = oracle.solve(f, Lx, Lz, yf)
         assert rel(b, ref) <= TOL64
+
+
+FUSED_CASES = [(128, 19, 128), (256, 11, 256), (512, 9, 512), (1024, 3, 1024)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("nx,ny,nz", FUSED_CASES)
+def test_fused_xz_matches_separate_passes(monkeypatch, precision, nx, ny, nz):
+    """The fused persistent x/z passes against the separate x and z kernels:
+    bitwise for FP64; the mixed form differs only in the order of its norm
+    partial sums, so it is held to the refinement's own accuracy."""
+    Lx, Lz = 2 * np.pi, 1.1
+    yf = synth.tanh_faces(ny, 2.0)
+    f = np.random.default_rng(nx + 7 * ny).standard_normal((ny, nz, nx))
+    monkeypatch.setenv("IBP_FUSED", "0")
+    a, _ = gpu_solve(f, Lx, Lz, yf, precision=precision, max_iters=3)
+    monkeypatch.setenv("IBP_FUSED", "1")
+    b, info = gpu_solve(f, Lx, Lz, yf, precision=precision, max_iters=3)
+    ref, _ = oracle.solve(f, Lx, Lz, yf)
+    if precision == "fp64":
+        assert np.array_equal(a, b)
+        assert rel(b, ref) <= TOL64
+    else:
+        assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
+        assert rel(b, ref) <= 1e-8
+
+
+@pytest.mark.parametrize("lag,bpcu", [("1", "1"), ("1", ""), ("2", "1"), ("1000", "")])
+def test_fused_schedule_is_bitwise_neutral(monkeypatch, lag, bpcu):
+    """Any lag between a plane's first- and second-stage items and any
+    persistent grid size give the same bits (lag 1 makes most second-stage
+    items wait on their plane's counter; lag >= ny runs the stages apart)."""
+    nx = nz = 256
+    ny = 13
+    Lx, Lz = 2 * np.pi, 2.0
+    yf = synth.tanh_faces(ny, 2.0)
+    f = np.random.default_rng(11).standard_normal((ny, nz, nx))
+    monkeypatch.setenv("IBP_FUSED", "0")
+    a, _ = gpu_solve(f, Lx, Lz, yf)
+    monkeypatch.setenv("IBP_FUSED", "1")
+    monkeypatch.setenv("IBP_FUSED_LAG", lag)
+    monkeypatch.setenv("IBP_FUSED_BPCU", bpcu)
+    for _ in range(3):   # the counters re-arm between launches
+        b, _ = gpu_solve(f, Lx, Lz, yf)
+        assert np.array_equal(a, b)
 
 
 def test_caller_workspace():
