@@ -282,13 +282,18 @@ def test_batched_matches_single_and_oracle():
 # ---------------------------------------------------------------- full size
 def sampled_modes(f, phi, Lx, Lz, yf, modes):
     """For each (kx, kz): the oracle's 1-D y solve of the mode's DFT of f,
-    against the same DFT of the GPU phi (O(N) per mode, so any size works)."""
+    against the same DFT of the GPU phi (O(N) per mode, so any size works).
+    The error of a mode is measured against the larger of its own norm and
+    the RMS norm of all modes (= ||phi||_F by Parseval), so that modes the
+    input leaves empty (pure rounding) are held to the solve's absolute
+    accuracy rather than to a relative one they cannot have."""
     ny, nz, nx = f.shape
     g = geometry(nx, ny, nz, Lx, Lz, yf)
     m = weighted_mean(f, g)
     from oracle.grid import lambda_x, lambda_z
     from oracle.poisson import thomas_modes, zero_mode_flux_integration
     lx, lz = lambda_x(g), lambda_z(g)
+    scale = float(np.linalg.norm(phi))
     worst = 0.0
     for kx, kz in modes:
         ex = np.exp(-2j * np.pi * kx * np.arange(nx) / nx)
@@ -298,8 +303,8 @@ def sampled_modes(f, phi, Lx, Lz, yf, modes):
         if kx == 0 and kz == 0:
             X, _ = zero_mode_flux_integration(g, F.real)
         else:
-            X = thomas_modes(g.a, g.b, g.c, np.array(lx[kx] + lz[kz]), F)
-        worst = max(worst, float(np.linalg.norm(P - X) / np.linalg.norm(X)))
+            X = thomas_modes(g.a, g.c, -np.array(lx[kx] + lz[kz]), F)
+        worst = max(worst, float(np.linalg.norm(P - X) / max(np.linalg.norm(X), scale)))
     return worst
 
 
@@ -315,7 +320,10 @@ def c3_case():
     return f, Lx, Lz, yf
 
 
-MODES = [(0, 0), (1, 0), (0, 1), (1, 1), (3, 7), (17, 250), (100, 3), (255, 511), (256, 0), (256, 256)]
+# low modes, modes with content near the cut-off |k| = 64 (kz = 500 is -12),
+# and modes the k^-5/3 input leaves empty, including both Nyquist lines
+MODES = [(0, 0), (1, 0), (0, 1), (1, 1), (3, 7), (40, 5), (7, 500), (64, 0), (17, 250), (255, 511),
+         (256, 0), (256, 256)]
 
 
 def test_c3_fullsize_fp64_and_mixed(c3_case):
@@ -332,4 +340,4 @@ def test_c3_fullsize_fp64_and_mixed(c3_case):
     pm = phim.cpu().numpy()
     r = residual(f, pm, Lx, Lz, yf)
     assert info["converged"] == 1 and r <= RTOL_MIXED, (r, info)
-    assert rel(pm, p64) <= 1e-10
+    assert rel(pm, p64) <= 1e-8   # error <= condition x residual: a sanity bound, as for the small mixed cases
