@@ -110,6 +110,119 @@ def cpu_baseline(args):
                       + ("" if scale == 1.0 else f"; rate scaled by the cell ratio {scale:.3f}")}
 
 
+def run_c5(args):
+    """One GPU's share at paper scale: 1024 x 768 x 1024 cells, beta = 3.  A
+    bank of 4 right-hand sides (divergences of seeded k^-5/3 velocity fields,
+    drawn on the GPU) feeds an AR(1) sequence f_{t+1} = 0.95 f_t +
+    sqrt(1 - 0.95^2) s_t roll(bank[t mod 4]).  `--seq` steps of (solve,
+    advance) are captured as one graph per form and replayed; the advance
+    steps alone are captured and timed too, and their time is subtracted."""
+    import numpy as np
+    import torch
+
+    from paper_2609_19130_amd import ibpoisson as ibp
+    from paper_2609_19130_amd import synth
+
+    nx, ny, nz, beta, seed, nbank = 1024, 768, 1024, 3.0, 5, 4
+    steps = args.seq
+    workload = f"poisson_{nx}x{ny}x{nz}_beta{beta:g}_ar1_kolmogorov_graph{steps}"
+    Lx = Lz = 2 * np.pi
+    yf = synth.tanh_faces(ny, beta)
+    log(f"[bench c5] drawing a bank of {nbank} k^-5/3 velocity fields on the GPU")
+    plan = ibp.Plan(nx, ny, nz, Lx, Lz, yf)
+    bank = []
+    for b in range(nbank):
+        u, v, w = synth.kolmogorov_velocity_device(nx, ny, nz, seed=1000 * seed + b)
+        bank.append(plan.divergence(u, v, w))
+        del u, v, w
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    sched = synth.ar1_schedule(seed, steps + 1, nx, nz, nbank)
+    f0 = bank[0] * sched[0][3]
+    f = torch.empty_like(f0)
+    gbuf = torch.empty_like(f0)
+    phi = torch.empty_like(f0)
+
+    def capture(with_solve):
+        g = torch.cuda.CUDAGraph()
+        f.copy_(f0)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            for t in range(steps):
+                if with_solve:
+                    plan.solve(f, phi)
+                synth.ar1_advance(f, gbuf, bank, sched[t + 1])
+        return g
+
+    def replay_ms(g, reps):
+        times = []
+        for _ in range(reps):
+            f.copy_(f0)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            g.replay()
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        return float(np.median(times))
+
+    log("[bench c5] timing the AR(1) advance alone")
+    g_adv = capture(False)
+    g_adv.replay()
+    adv_ms = replay_ms(g_adv, 3)
+    del g_adv
+    forms = [s for s in args.forms.split(",") if s in ("fp64", "mixed", "mixed_f64sweep")]
+    res = {}
+    finals = {}
+    for form in forms:
+        plan.set_precision(form, 1e-10, args.mixed_iters)
+        plan.solve(f0, phi)
+        torch.cuda.synchronize()
+        log(f"[bench c5] {form}: capturing {steps} x (solve, advance)")
+        g = capture(True)
+        g.replay()                       # warm-up replay
+        torch.cuda.synchronize()
+        ms = replay_ms(g, 3)
+        info = plan.info()
+        finals[form] = phi.clone()
+        res[form] = dict(seq_ms=ms, solve_ms=(ms - adv_ms) / steps, info=info)
+        log(f"[bench c5] {form}: {ms:.1f} ms per sequence, {(ms - adv_ms) / steps:.3f} ms per solve, {info}")
+        del g
+    N = nx * ny * nz
+    Nh = (nx // 2 + 1) * ny * nz
+    stage_bytes = 16.0 * N + 8 * 16.0 * Nh
+    r64 = res.get("fp64")
+    out = {"metric": METRIC, "unit": "solves/s", "n_gpus": 1, "steps": steps, "warmup": 1,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic: AR(1) blend (rho 0.95) of rolled, sign-flipped divergences of 4 seeded "
+                   "k^-5/3 velocity fields drawn on the GPU",
+           "config": {"workload": workload, "nx": nx, "ny": ny, "nz": nz, "beta": beta,
+                      "form": "captured graph of (solve, AR(1) advance) steps; advance time subtracted"},
+           "ar1_advance_ms_per_step": adv_ms / steps}
+    if r64 is not None:
+        out["value"] = 1000.0 / r64["solve_ms"]
+        out["ms_per_step"] = r64["solve_ms"]
+        out["hbm_gbs_stage_model"] = stage_bytes / (r64["solve_ms"] * 1e-3) / 1e9
+        out["roofline_frac_stage_model"] = out["hbm_gbs_stage_model"] / HBM_PEAK_GBS
+    mixed = {}
+    for form in forms:
+        if form == "fp64":
+            continue
+        r = res[form]
+        d = None
+        if "fp64" in finals:
+            d = float(torch.linalg.vector_norm(finals[form] - finals["fp64"]) / torch.linalg.vector_norm(finals["fp64"]))
+        mixed[form] = {"solves_per_s": 1000.0 / r["solve_ms"], "ms_per_step": r["solve_ms"],
+                       "iterations_last": r["info"]["iterations"], "converged_last": r["info"]["converged"],
+                       "rel_residual_last": r["info"]["rel_residual"], "rel_diff_vs_fp64_last": d,
+                       "vs_fp64": (r64["solve_ms"] / r["solve_ms"]) if r64 else None}
+    out["mixed"] = mixed
+    out["source_hash"] = source_hash()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,11 +238,18 @@ def main():
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-launch events (no per-pass breakdown or roofline)")
     ap.add_argument("--cpu-sample", choices=["full", "quarter"], default="full")
+    ap.add_argument("--config", choices=["c3", "c5"], default="c3",
+                    help="c3: the 512x384x512 solve (default, the headline line); "
+                         "c5: a captured graph of --seq solves at 1024x768x1024, beta 3, AR(1) right-hand sides")
+    ap.add_argument("--seq", type=int, default=100, help="solves per captured sequence (c5)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
+    if args.config == "c5":
+        run_c5(args)
+        return
 
     import numpy as np
     import torch

@@ -2,9 +2,10 @@
 
 This module draws random numbers and lays out grids; it holds none of the
 solver's arithmetic (no discrete operator, transform or tridiagonal step).
-Every generator uses ``numpy.random.default_rng`` (PCG64) seeded explicitly
-and draws in the order documented on each function, so any caller
-reproduces the same inputs.
+Every host generator uses ``numpy.random.default_rng`` (PCG64) seeded
+explicitly and draws in the order documented on each function, so any caller
+reproduces the same inputs.  The ``*_device`` generators (for grids too
+large to draw on the host) use a seeded ``torch.Generator`` on the GPU.
 
 The workloads mirror the paper's setting (periodic uniform x and z, a
 wall-bounded stretched wall-normal direction, a right-hand side that is the
@@ -118,3 +119,87 @@ def batch_grids(seed=4, count=64):
         out.append(dict(nx=nx, ny=ny, nz=nz, beta=beta, Lx=2 * np.pi, Lz=2 * np.pi,
                         seed=int(ss.generate_state(1)[0])))
     return out
+
+
+# ---------------------------------------------------------------- device-side inputs
+# Grids of ~1e9 cells are too large to draw on the host in reasonable time;
+# these generators follow the same spectral recipe with torch on the GPU
+# (torch.Generator on the device, seeded explicitly).  They are input
+# synthesis only: the solver's own arithmetic never runs here.
+
+def _spectral_scalar_device(shape, gen, kmax, device, chunk=64):
+    import torch
+    noise = torch.randn(shape, generator=gen, device=device, dtype=torch.float64)
+    spec = torch.fft.rfftn(noise)
+    del noise
+    n0, n1, n2 = shape
+    k1 = torch.fft.fftfreq(n1, 1.0 / n1, device=device, dtype=torch.float64).view(1, -1, 1)
+    k2 = torch.arange(n2 // 2 + 1, device=device, dtype=torch.float64).view(1, 1, -1)
+    k0all = torch.fft.fftfreq(n0, 1.0 / n0, device=device, dtype=torch.float64)
+    for s0 in range(0, n0, chunk):   # chunks of planes keep the temporaries small
+        k0 = k0all[s0:s0 + chunk].view(-1, 1, 1)
+        kk = torch.sqrt(k0 * k0 + k1 * k1 + k2 * k2)
+        filt = torch.where((kk >= 1.0) & (kk <= kmax), torch.clamp(kk, min=1.0).pow(-11.0 / 6.0),
+                           torch.zeros((), device=device, dtype=torch.float64))
+        spec[s0:s0 + chunk] *= filt
+    field = torch.fft.irfftn(spec, s=shape)
+    del spec
+    field /= torch.sqrt(torch.mean(field * field))
+    return field
+
+
+def kolmogorov_velocity_device(nx, ny, nz, seed, kmax=64, device="cuda"):
+    """kolmogorov_velocity's recipe drawn on the GPU: torch.Generator seeded
+    with `seed`, draw order u, v, w; v gets ny+1 rows with zero wall rows.
+    Returns contiguous float64 device tensors."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    u = _spectral_scalar_device((ny, nz, nx), gen, kmax, device)
+    vf = _spectral_scalar_device((ny, nz, nx), gen, kmax, device)
+    v = torch.zeros((ny + 1, nz, nx), device=device, dtype=torch.float64)
+    v[1:ny] = vf[1:ny]
+    del vf
+    w = _spectral_scalar_device((ny, nz, nx), gen, kmax, device)
+    return u, v, w
+
+
+def ar1_schedule(seed, steps, nx, nz, bank=4):
+    """Per-step innovation draws for an AR(1) sequence of right-hand sides:
+    step t uses bank member t mod `bank`, rolled by (dz, dx) planes/columns
+    in z and x (uniform integers) and multiplied by a sign (+1 or -1).  Draw
+    order per step: dx, dz, sign."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for t in range(steps):
+        dx = int(rng.integers(nx))
+        dz = int(rng.integers(nz))
+        sign = 1.0 if rng.integers(2) == 0 else -1.0
+        out.append((t % bank, dx, dz, sign))
+    return out
+
+
+def roll_into(dst, src, dz, dx):
+    """dst = src rolled by dz along axis 1 (z) and dx along axis 2 (x),
+    periodic, written in place with slice copies (no allocation, so it can be
+    captured in a graph)."""
+    nz, nx = src.shape[1], src.shape[2]
+    dz %= nz
+    dx %= nx
+    parts_z = [(slice(dz, nz), slice(0, nz - dz)), (slice(0, dz), slice(nz - dz, nz))]
+    parts_x = [(slice(dx, nx), slice(0, nx - dx)), (slice(0, dx), slice(nx - dx, nx))]
+    for dzs, szs in parts_z:
+        if dzs.start == dzs.stop:
+            continue
+        for dxs, sxs in parts_x:
+            if dxs.start == dxs.stop:
+                continue
+            dst[:, dzs, dxs].copy_(src[:, szs, sxs])
+
+
+def ar1_advance(f, g, bank, step, rho=0.95):
+    """f <- rho f + sqrt(1 - rho^2) * sign * roll(bank[k]), for one entry
+    (k, dx, dz, sign) of ar1_schedule; g is a scratch field of f's shape."""
+    k, dx, dz, sign = step
+    roll_into(g, bank[k], dz, dx)
+    f.mul_(rho).add_(g, alpha=sign * float(np.sqrt(1.0 - rho * rho)))
