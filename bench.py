@@ -110,6 +110,80 @@ def cpu_baseline(args):
                       + ("" if scale == 1.0 else f"; rate scaled by the cell ratio {scale:.3f}")}
 
 
+def run_c4(args):
+    """64 uneven grids (each dimension in {32, 48, ..., 192}, beta in [1.5, 3],
+    divergence of a uniform random velocity as right-hand side): one batched
+    solve of all grids (one launch per stage) against the loop of per-grid
+    solves, FP64 and mixed.  A step solves all 64 grids."""
+    import numpy as np
+    import torch
+
+    from paper_2609_19130_amd import ibpoisson as ibp
+    from paper_2609_19130_amd import synth
+
+    grids = synth.batch_grids(seed=4, count=64)
+    rhs, yfs = [], []
+    for gd in grids:
+        nx, ny, nz = gd["nx"], gd["ny"], gd["nz"]
+        yf = synth.tanh_faces(ny, gd["beta"])
+        u, v, w = synth.uniform_velocity(nx, ny, nz, seed=gd["seed"])
+        yfs.append(yf)
+        rhs.append((u, v, w))
+    cells = sum(gd["nx"] * gd["ny"] * gd["nz"] for gd in grids)
+    out = {"metric": METRIC, "unit": "grid solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic: divergence of i.i.d. U[-1,1] staggered velocity per grid",
+           "config": {"workload": "poisson_batch64_dims32to192_seed4", "grids": len(grids), "cells": cells}}
+    for form in [s for s in args.forms.split(",") if s in ("fp64", "mixed")]:
+        plans = [ibp.Plan(gd["nx"], gd["ny"], gd["nz"], gd["Lx"], gd["Lz"], yf, precision=form,
+                          max_iters=args.mixed_iters) for gd, yf in zip(grids, yfs)]
+        fs = [p.divergence(*(torch.from_numpy(a).cuda() for a in uvw)) for p, uvw in zip(plans, rhs)]
+        phis = [torch.empty_like(f) for f in fs]
+
+        def loop():
+            for p, f, q in zip(plans, fs, phis):
+                p.solve(f, q)
+
+        def batched():
+            ibp.solve_batched(plans, fs, phis)
+
+        batch = ibp.Batch(plans)
+        tune = batch.autotune(fs, phis)
+        log(f"[bench c4] {form} autotuned batch: {tune}")
+
+        def tuned():
+            batch.solve(fs, phis)
+
+        res = {"autotune": tune}
+        for name, fn in (("per_grid_loop", loop), ("batched", batched), ("batched_autotuned", tuned)):
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(args.steps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / args.steps
+            res[name] = {"ms_per_step": ms, "grid_solves_per_s": 64 * 1000.0 / ms, "cells_per_s": cells * 1000.0 / ms}
+            log(f"[bench c4] {form} {name}: {ms:.3f} ms for 64 grids")
+        if form == "mixed":
+            res["converged"] = int(sum(p.info()["converged"] for p in plans))
+        res["batched_vs_loop"] = res["per_grid_loop"]["ms_per_step"] / res["batched"]["ms_per_step"]
+        res["autotuned_vs_loop"] = res["per_grid_loop"]["ms_per_step"] / res["batched_autotuned"]["ms_per_step"]
+        out[form] = res
+        batch.close()
+        for p in plans:
+            p.close()
+    if "fp64" in out:
+        out["value"] = out["fp64"]["batched_autotuned"]["grid_solves_per_s"]
+        out["ms_per_step"] = out["fp64"]["batched_autotuned"]["ms_per_step"]
+    out["source_hash"] = source_hash()
+    print(json.dumps(out), flush=True)
+
+
 def run_c5(args):
     """One GPU's share at paper scale: 1024 x 768 x 1024 cells, beta = 3.  A
     bank of 4 right-hand sides (divergences of seeded k^-5/3 velocity fields,
@@ -238,7 +312,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-launch events (no per-pass breakdown or roofline)")
     ap.add_argument("--cpu-sample", choices=["full", "quarter"], default="full")
-    ap.add_argument("--config", choices=["c3", "c5"], default="c3",
+    ap.add_argument("--config", choices=["c3", "c4", "c5"], default="c3",
                     help="c3: the 512x384x512 solve (default, the headline line); "
                          "c5: a captured graph of --seq solves at 1024x768x1024, beta 3, AR(1) right-hand sides")
     ap.add_argument("--seq", type=int, default=100, help="solves per captured sequence (c5)")
@@ -249,6 +323,9 @@ def main():
         sys.exit(2)
     if args.config == "c5":
         run_c5(args)
+        return
+    if args.config == "c4":
+        run_c4(args)
         return
 
     import numpy as np

@@ -122,9 +122,75 @@ ibp_status_t ibp_solve(ibp_plan_t plan, const double* rhs, double* phi, void* st
 /* Solve `count` independent problems, problem i with plans[i], rhs[i],
  * phi[i] (each as in ibp_solve; HOST arrays of plans and device pointers).
  * The plans must be distinct (each owns its workspace).  All work is
- * enqueued on `stream`. */
+ * enqueued on `stream`.
+ *
+ * When every plan is on the current device with the same precision
+ * (IBP_FP64 or IBP_MIXED) and, for IBP_MIXED, the same max_iters, the grids
+ * are solved together: each stage of the solve is one launch covering all
+ * grids (in groups of IBP_BATCH_MAX), through a batch the library builds for
+ * that sequence of plans and keeps until one of them is destroyed.  Building
+ * it (the first call with a given sequence, or after a plan's precision or
+ * workspace changed) allocates and synchronises; later calls do neither.
+ * Callers that capture graphs from the first call build the batch
+ * explicitly with ibp_batch_create.  Otherwise the plans are solved one after
+ * another on `stream`.  The batched stages use the general mixed-radix
+ * transforms for every grid, so results can differ from ibp_solve's in the
+ * last bits for grids that ibp_solve transforms with its power-of-two
+ * kernels. */
 ibp_status_t ibp_solve_batched(const ibp_plan_t* plans, int count, const double* const* rhs,
                                double* const* phi, void* stream);
+
+/* ---------------------------------------------------------------- batches
+ * Many uneven grids solved together (one launch per stage covering every
+ * grid).  A batch records per-grid arguments (tables, workspaces, shapes) in
+ * a device table; the right-hand sides and solutions are given per call. */
+#define IBP_BATCH_MAX 64
+typedef struct ibp_batch_s* ibp_batch_t;
+
+/* Build a batch over plans[0..count) (1 <= count <= IBP_BATCH_MAX; distinct
+ * plans on the current device, all IBP_FP64 or all IBP_MIXED with one
+ * max_iters; else IBP_ERROR_INVALID_VALUE or IBP_ERROR_UNSUPPORTED_SIZE for a
+ * precision form that batches do not support).  Allocates and synchronises.
+ * The plans must outlive the batch; changing a plan's precision or workspace
+ * afterwards makes ibp_batch_solve return IBP_ERROR_INVALID_VALUE. */
+ibp_status_t ibp_batch_create(const ibp_plan_t* plans, int count, ibp_batch_t* out);
+
+/* Solve problem i of the batch with rhs[i], phi[i] (HOST arrays of device
+ * pointers, as in ibp_solve).  Asynchronous on `stream`; never allocates,
+ * synchronises or copies to the host, so it can be captured in a graph.
+ * Per-grid state is read with ibp_get_info on the grid's plan. */
+ibp_status_t ibp_batch_solve(ibp_batch_t batch, const double* const* rhs, double* const* phi, void* stream);
+
+/* Line-solve columns per block of the batch's stage launches (2, 4, 8 or 16;
+ * capped by the LDS budget).  Used by the batch autotuner. */
+ibp_status_t ibp_batch_set_ycols(ibp_batch_t batch, int cols);
+
+/* Free the batch's device table (the plans are untouched).  NULL accepted. */
+ibp_status_t ibp_batch_destroy(ibp_batch_t batch);
+
+/* ---------------------------------------------------------------- autotuning
+ * Work splits chosen by timing: how many rows, columns or lines each block
+ * of a stage takes.  They change which block computes what, never the
+ * arithmetic, so solutions are bitwise the same under every choice. */
+typedef struct {
+  int xdiv;          /* x-stage rows per block = the largest tile's / xdiv (batches, FP64) */
+  int zdiv;          /* z-stage columns per block = the largest tile's / zdiv (general z transform) */
+  int ycols;         /* line-solve columns per block */
+  int tried;         /* configurations timed */
+  double ms;         /* time of one solve with the chosen configuration (HIP events) */
+  double ms_before;  /* time of one solve with the configuration in place before tuning */
+} ibp_tune_t;
+
+/* Time solves of rhs into phi (device pointers as in ibp_solve; phi is
+ * overwritten with the solution) over the plan's tunable splits and keep
+ * the fastest.  Synchronises `stream`; not for use under graph capture. */
+ibp_status_t ibp_plan_autotune(ibp_plan_t plan, const double* rhs, double* phi, void* stream, ibp_tune_t* out);
+
+/* The same for a batch (x rows, z columns and line-solve columns per block
+ * of its stage launches; the x split is tuned for IBP_FP64 batches only,
+ * because the mixed forms' norm partials follow it). */
+ibp_status_t ibp_batch_autotune(ibp_batch_t batch, const double* const* rhs, double* const* phi, void* stream,
+                                ibp_tune_t* out);
 
 /* Wait for the plan's last solve and report its state (iterations,
  * convergence, non-finite flag, residuals, removed mean). */

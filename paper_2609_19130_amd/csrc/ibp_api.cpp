@@ -3,6 +3,7 @@
 // entry point is extern "C", returns a status and catches C++ exceptions.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstdint>
@@ -76,6 +77,8 @@ struct ibp_plan_s {
   int max_iters = 4;
   FftPlan fpx{}, fpz{};
   int yP = 32, yK = 2;   // line solve: lanes per column, rows per lane
+  int ycols = 0;         // line-solve columns per block (0: 128-byte rows; set by the autotuner)
+  int zc64max = 1, zc32max = 1;   // z-pass columns per block of the general kernel before tuning
   int zc64 = 1, zc32 = 1;   // z-pass kx columns per block
   int rb64 = 1, rb32 = 1;   // x-pass rows per block
   long nb64 = 1, nb32 = 1;  // x-pass blocks (transform passes)
@@ -109,6 +112,7 @@ struct ibp_plan_s {
   Ctl* ctl = nullptr;
   hipStream_t last_stream = nullptr;
   bool solved = false;
+  unsigned gen = 0;   // bumped when the precision or the workspace changes (batches check it)
   // chunked x/z passes: second stream and dependency events
   int chunk = 0;                   // y planes per chunk (0: whole grid per launch)
   hipStream_t s2 = nullptr;
@@ -229,6 +233,9 @@ hipError_t xcc_map(int device, XccMap* out) {
 bool valid_plan(const ibp_plan_s* p) { return p != nullptr && p->tables != nullptr && p->ws != nullptr; }
 
 ibp_status_t enqueue_solve(ibp_plan_s* p, const double* rhs, double* phi, hipStream_t s);
+void purge_batch_cache(const ibp_plan_s* p);
+ibp_status_t batched_or_loop(const ibp_plan_t* plans, int count, const double* const* rhs, double* const* phi,
+                             hipStream_t s);
 
 // y planes per chunk when the x/z passes run chunk by chunk on two streams
 // (IBP_CHUNK planes, rounded up to whole x-pass blocks; off by default and
@@ -401,6 +408,8 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     if (p->zc32 > 64) p->zc32 = 64;
     if (p->zc64 > p->hp) p->zc64 = p->hp;
     if (p->zc32 > p->hp) p->zc32 = p->hp;
+    p->zc64max = p->zc64;
+    p->zc32max = p->zc32;
 
     // ---- FP64 geometry of the y operator (staggered, Neumann walls)
     // face coefficients a_j, c_j; the diagonal -(a_j + c_j) is never formed:
@@ -548,6 +557,7 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
 ibp_status_t ibp_plan_destroy(ibp_plan_t p) {
   if (p == nullptr) return IBP_SUCCESS;
   try {
+    purge_batch_cache(p);
     release(p);
     return IBP_SUCCESS;
   } catch (...) {
@@ -565,6 +575,7 @@ ibp_status_t ibp_plan_set_precision(ibp_plan_t p, ibp_precision_t prec, double r
     p->max_iters = max_iters;
   }
   p->prec = prec;
+  ++p->gen;
   return IBP_SUCCESS;
 }
 
@@ -595,6 +606,7 @@ ibp_status_t ibp_plan_set_workspace(ibp_plan_t p, void* ptr, size_t bytes) {
       p->ws_owned = true;
     }
     carve_workspace(p);
+    ++p->gen;
     return from_hip(reset_counters(p));
   } catch (...) {
     return IBP_ERROR_INTERNAL;
@@ -632,11 +644,11 @@ ibp_status_t ibp_solve_batched(const ibp_plan_t* plans, int count, const double*
     for (int k = 0; k < i; ++k)
       if (plans[k] == plans[i]) return IBP_ERROR_INVALID_VALUE;
   }
-  for (int i = 0; i < count; ++i) {
-    ibp_status_t st = ibp_solve(plans[i], rhs[i], phi[i], stream);
-    if (st != IBP_SUCCESS) return st;
+  try {
+    return batched_or_loop(plans, count, rhs, phi, static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
   }
-  return IBP_SUCCESS;
 }
 
 ibp_status_t ibp_get_info(ibp_plan_t p, ibp_info_t* out) {
@@ -953,7 +965,7 @@ ibp_status_t enqueue_solve(ibp_plan_s* p, const double* rhs, double* phi, hipStr
   YArgs<double, double> ya{p->spec64, p->lamx, p->lamz, p->ya, p->yc, p->ctl,
                            (long)p->nz * spec_row_stride<double>(p->hp), spec_row_stride<double>(p->hp),
                            spec_plane_stride<double>(p->hp, p->nz), p->ny, p->hp, 0};
-  IBP_LAUNCH(P_Y, launch_ytri<double, double>(p->yP, p->yK, ya, zargs(p, 0, 1, 0, 0, 0), s));
+  IBP_LAUNCH(P_Y, launch_ytri<double, double>(p->yP, p->yK, p->ycols, ya, zargs(p, 0, 1, 0, 0, 0), s));
   return inverse_zx<double>(p, xa, CM_SET, P_XC2R, za, s);
 }
 
@@ -984,7 +996,7 @@ ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStr
   if (st != IBP_SUCCESS) return st;
   // partials of the initial pass: one per x-row block of whichever x kernel ran
   const long np0 = (p->fused && p->chunk <= 0) ? p->nbf : p->nb32;
-  IBP_LAUNCH(P_Y, launch_ytri<float, U>(p->yP, p->yK, ya, zargs(p, np0, 1, 1, 0, 0), s));
+  IBP_LAUNCH(P_Y, launch_ytri<float, U>(p->yP, p->yK, p->ycols, ya, zargs(p, np0, 1, 1, 0, 0), s));
   st = inverse_zx<float>(p, xa, CM_SET, P_XC2R, za, s);
   if (st != IBP_SUCCESS) return st;
 
@@ -1000,7 +1012,7 @@ ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStr
     ZfArgs<float> zf = za;
     zf.plane0 = 0;
     if (p->nz > 1) IBP_LAUNCH(P_ZFWD, run_zfft<float>(p, false, zf, p->ny, s));
-    IBP_LAUNCH(P_Y, launch_ytri<float, U>(p->yP, p->yK, ya, zargs(p, p->nb32, 0, 1, k, 0), s));
+    IBP_LAUNCH(P_Y, launch_ytri<float, U>(p->yP, p->yK, p->ycols, ya, zargs(p, p->nb32, 0, 1, k, 0), s));
     st = inverse_zx<float>(p, xa, CM_ADD, P_XC2R_ADD, za, s);
     if (st != IBP_SUCCESS) return st;
   }
@@ -1011,3 +1023,485 @@ ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStr
 }
 
 }  // namespace
+
+// ======================================================================
+// Batches: many uneven grids solved together, one launch per stage that
+// covers every grid.  Per-grid arguments sit in a device table built once;
+// the line-solve coefficient tables are re-padded to the batch's common
+// lanes x rows shape (the largest ny decides it).
+struct ibp_batch_s {
+  int device = 0;
+  int count = 0;
+  ibp_precision_t prec = IBP_FP64;
+  int max_iters = 0;
+  std::vector<ibp_plan_t> plans;
+  std::vector<unsigned> gens;
+  void* dmem = nullptr;
+  void* desc = nullptr;      // BatchGrid<T>[count]
+  long* start = nullptr;     // [3][count + 1]: x, z, y stage prefix offsets
+  long nblk[3] = {0, 0, 0};  // blocks of the x, z and y stage launches
+  int yP = 32, yK = 2, yM = 8;
+  int xdiv = 1, zdiv = 1;    // x rows and z columns per block: the largest tile's, divided by these
+  std::vector<long> hstart;
+  std::vector<int> rbmax, zcmax;   // per grid: rows per block and z columns of the largest tile
+  std::vector<BatchGrid<double>> h64;
+  std::vector<BatchGrid<float>> h32;
+};
+
+namespace {
+
+constexpr int kBatchDivMax = 4;   // finest x split the partial buffers are sized for
+
+// Apply the batch's work split (x rows per block, z columns per block, line-
+// solve columns per block) to the per-grid arguments and prefix offsets and
+// upload them (synchronous).  The split changes which block does what, not
+// the arithmetic: results are bitwise the same for every split.
+template <typename T>
+hipError_t batch_apply(ibp_batch_s* b, std::vector<BatchGrid<T>>& hd) {
+  const int n = b->count;
+  b->hstart.assign(3 * (n + 1), 0);
+  long* hx = b->hstart.data();
+  long* hz = hx + (n + 1);
+  long* hy = hz + (n + 1);
+  for (int g = 0; g < n; ++g) {
+    BatchGrid<T>& d = hd[g];
+    const int rb = b->rbmax[g] / b->xdiv > 0 ? b->rbmax[g] / b->xdiv : 1;
+    const int zc = b->zcmax[g] / b->zdiv > 0 ? b->zcmax[g] / b->zdiv : 1;
+    const long nxb = (d.x.nrows + rb - 1) / rb;
+    d.x.rows_per_block = rb;
+    if (d.x.parts) d.zero.nparts = nxb;
+    d.z.cols = zc;
+    d.zcolblocks = (d.z.hp + zc - 1) / zc;
+    hx[g + 1] = hx[g] + nxb;
+    hz[g + 1] = hz[g] + (d.z.nz > 1 ? (long)d.zcolblocks * d.y.ny : 0);
+    hy[g + 1] = hy[g] + (d.y.Q + b->yM - 1) / b->yM + d.y.ny;
+  }
+  b->nblk[0] = hx[n];
+  b->nblk[1] = hz[n];
+  b->nblk[2] = hy[n];
+  hipError_t e = hipMemcpy(b->desc, hd.data(), n * sizeof(BatchGrid<T>), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->start, b->hstart.data(), b->hstart.size() * sizeof(long), hipMemcpyHostToDevice);
+  return e;
+}
+
+hipError_t batch_reapply(ibp_batch_s* b) {
+  return b->prec == IBP_FP64 ? batch_apply<double>(b, b->h64) : batch_apply<float>(b, b->h32);
+}
+
+template <typename T>
+ibp_status_t batch_build(ibp_batch_s* b) {
+  constexpr bool kF64 = sizeof(T) == 8;
+  constexpr int TLX = kF64 ? kTileX64 : kTileX32;
+  constexpr int TLZ = kF64 ? kTileZ64 : kTileZ32;
+  const int n = b->count;
+  int maxny = 0;
+  for (ibp_plan_t p : b->plans) maxny = p->ny > maxny ? p->ny : maxny;
+  if (!ytri_shape(maxny, &b->yP, &b->yK)) return IBP_ERROR_UNSUPPORTED_SIZE;
+  int want = 0;
+  if (const char* e = getenv("IBP_YCOLS")) want = atoi(e);
+  b->yM = batch_ytri_cols<T>(b->yP, b->yK, want);
+  const int PK = b->yP * b->yK;
+  // device memory: descriptors | prefix offsets | padded a, c tables | partials
+  std::vector<size_t> o_part(n);
+  const size_t o_start = align256(n * sizeof(BatchGrid<T>));
+  const size_t o_tab = o_start + align256(3 * (n + 1) * sizeof(long));
+  size_t bytes = o_tab + align256((size_t)n * 2 * PK * sizeof(T));
+  for (int g = 0; g < n; ++g) {
+    const ibp_plan_s* p = b->plans[g];
+    o_part[g] = bytes;
+    if (!kF64) {   // partials of the finest x split
+      const long nrows = (long)p->ny * p->nz;
+      const int rbmin = TLX / p->h / kBatchDivMax > 0 ? TLX / p->h / kBatchDivMax : 1;
+      bytes += align256((size_t)((nrows + rbmin - 1) / rbmin) * kPartStride * sizeof(double));
+    }
+  }
+  hipError_t e = hipMalloc(&b->dmem, bytes);
+  if (e != hipSuccess) return from_hip(e);
+  char* base = static_cast<char*>(b->dmem);
+  b->desc = base;
+  b->start = reinterpret_cast<long*>(base + o_start);
+  T* dtab = reinterpret_cast<T*>(base + o_tab);
+  std::vector<T> tab((size_t)n * 2 * PK, T(0));
+  std::vector<BatchGrid<T>> hd(n);
+  b->rbmax.assign(n, 1);
+  b->zcmax.assign(n, 1);
+  for (int g = 0; g < n; ++g) {
+    ibp_plan_s* p = b->plans[g];
+    std::vector<double> a(p->ny), c(p->ny);
+    e = hipMemcpy(a.data(), p->ya, p->ny * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(c.data(), p->yc, p->ny * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return from_hip(e);
+    T* ta = tab.data() + (size_t)g * 2 * PK;
+    T* tc = ta + PK;
+    for (int j = 0; j < p->ny; ++j) {
+      ta[j] = (T)a[j];
+      tc[j] = (T)c[j];
+    }
+    BatchGrid<T>& d = hd[g];
+    Cx<T>* spec;
+    const Cx<T>* twx;
+    const Cx<T>* twz;
+    const T *lx, *lz;
+    if constexpr (kF64) {
+      spec = p->spec64; twx = p->twx; twz = p->twz; lx = p->lamx; lz = p->lamz;
+    } else {
+      spec = p->spec32; twx = p->twx32; twz = p->twz32; lx = p->lamx32; lz = p->lamz32;
+    }
+    b->rbmax[g] = TLX / p->h;
+    int cols = TLZ / p->nz;
+    if (cols > 64) cols = 64;
+    if (cols > p->hp) cols = p->hp;
+    b->zcmax[g] = cols;
+    double* part = kF64 ? p->part : reinterpret_cast<double*>(base + o_part[g]);
+    d.x = xargs<T>(p, nullptr, nullptr, nullptr, spec, twx, b->rbmax[g], 0);
+    d.x.parts = kF64 ? 0 : 1;
+    d.x.part = part;
+    const long rs = spec_row_stride<T>(p->hp), ps = spec_plane_stride<T>(p->hp, p->nz);
+    d.z = ZfArgs<T>{spec, twz, p->ctl, p->fpz, p->nz, p->hp, cols, rs, ps, 0, 0};
+    d.y = YArgs<T, T>{spec, lx, lz, dtab + (size_t)g * 2 * PK, dtab + (size_t)g * 2 * PK + PK, p->ctl,
+                      (long)p->nz * rs, rs, ps, p->ny, p->hp, 0};
+    d.zero = zargs(p, 0, 0, 0, 0, 0);
+    d.zero.part = part;
+  }
+  e = hipMemcpy(dtab, tab.data(), tab.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = batch_apply<T>(b, hd);
+  if (e != hipSuccess) return from_hip(e);
+  if constexpr (kF64) b->h64 = std::move(hd); else b->h32 = std::move(hd);
+  return IBP_SUCCESS;
+}
+
+template <typename T>
+ibp_status_t batch_enqueue(ibp_batch_s* b, const double* const* rhs, double* const* phi, hipStream_t s) {
+  const int n = b->count;
+  BatchPtrs P{};
+  for (int g = 0; g < n; ++g) {
+    P.f[g] = rhs[g];
+    P.phi[g] = phi[g];
+  }
+  const BatchGrid<T>* d = static_cast<const BatchGrid<T>*>(b->desc);
+  const long* sx = b->start;
+  const long* sz = sx + (n + 1);
+  const long* sy = sz + (n + 1);
+  const bool mixed = b->prec == IBP_MIXED;
+  for (ibp_plan_t p : b->plans) {
+    p->last_stream = s;
+    p->solved = true;
+  }
+  BatchLaunch L{n, 0, 1, mixed ? 1 : 0, 0, 0};
+  IBP_HIP(launch_batch_xr2c<T>(XM_PLAIN, d, sx, b->nblk[0], P, L, s));
+  IBP_HIP(launch_batch_zfft<T>(false, d, sz, b->nblk[1], L, s));
+  IBP_HIP(launch_batch_ytri<T>(b->yP, b->yK, b->yM, d, sy, b->nblk[2], L, s));
+  IBP_HIP(launch_batch_zfft<T>(true, d, sz, b->nblk[1], L, s));
+  IBP_HIP(launch_batch_xc2r<T>(CM_SET, d, sx, b->nblk[0], P, L, s));
+  if (!mixed) return IBP_SUCCESS;
+  for (int k = 1; k <= b->max_iters; ++k) {
+    L = BatchLaunch{n, k, 0, 1, 0, 1};
+    IBP_HIP(launch_batch_xr2c<T>(XM_RESID, d, sx, b->nblk[0], P, L, s));
+    IBP_HIP(launch_batch_check<T>(d, L, s));
+    IBP_HIP(launch_batch_zfft<T>(false, d, sz, b->nblk[1], L, s));
+    IBP_HIP(launch_batch_ytri<T>(b->yP, b->yK, b->yM, d, sy, b->nblk[2], L, s));
+    IBP_HIP(launch_batch_zfft<T>(true, d, sz, b->nblk[1], L, s));
+    IBP_HIP(launch_batch_xc2r<T>(CM_ADD, d, sx, b->nblk[0], P, L, s));
+  }
+  L = BatchLaunch{n, b->max_iters + 1, 0, 1, 1, 1};
+  IBP_HIP(launch_batch_xr2c<T>(XM_RESID_ONLY, d, sx, b->nblk[0], P, L, s));
+  IBP_HIP(launch_batch_check<T>(d, L, s));
+  return IBP_SUCCESS;
+}
+
+void batch_free(ibp_batch_s* b) {
+  if (b == nullptr) return;
+  if (b->dmem) hipFree(b->dmem);
+  delete b;
+}
+
+// Checks shared by ibp_batch_create and the cached path of ibp_solve_batched.
+ibp_status_t batch_eligible(const ibp_plan_t* plans, int count, int device) {
+  if (count < 1 || count > kBatchMax) return IBP_ERROR_INVALID_VALUE;
+  for (int i = 0; i < count; ++i) {
+    if (!valid_plan(plans[i]) || plans[i]->device != device) return IBP_ERROR_INVALID_VALUE;
+    for (int k = 0; k < i; ++k)
+      if (plans[k] == plans[i]) return IBP_ERROR_INVALID_VALUE;
+    if (plans[i]->prec != plans[0]->prec) return IBP_ERROR_INVALID_VALUE;
+    if (plans[i]->prec == IBP_MIXED && plans[i]->max_iters != plans[0]->max_iters) return IBP_ERROR_INVALID_VALUE;
+  }
+  if (plans[0]->prec != IBP_FP64 && plans[0]->prec != IBP_MIXED) return IBP_ERROR_UNSUPPORTED_SIZE;
+  return IBP_SUCCESS;
+}
+
+ibp_status_t batch_create(const ibp_plan_t* plans, int count, ibp_batch_s** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return from_hip(e);
+  ibp_status_t st = batch_eligible(plans, count, dev);
+  if (st != IBP_SUCCESS) return st;
+  ibp_batch_s* b = new (std::nothrow) ibp_batch_s;
+  if (!b) return IBP_ERROR_OUT_OF_MEMORY;
+  b->device = dev;
+  b->count = count;
+  b->prec = plans[0]->prec;
+  b->max_iters = plans[0]->max_iters;
+  b->plans.assign(plans, plans + count);
+  for (int i = 0; i < count; ++i) b->gens.push_back(plans[i]->gen);
+  st = b->prec == IBP_FP64 ? batch_build<double>(b) : batch_build<float>(b);
+  if (st != IBP_SUCCESS) {
+    batch_free(b);
+    return st;
+  }
+  *out = b;
+  return IBP_SUCCESS;
+}
+
+bool batch_current(const ibp_batch_s* b) {
+  for (int i = 0; i < b->count; ++i)
+    if (b->plans[i]->gen != b->gens[i]) return false;
+  return true;
+}
+
+ibp_status_t batch_solve(ibp_batch_s* b, const double* const* rhs, double* const* phi, hipStream_t s) {
+  if (rhs == nullptr || phi == nullptr) return IBP_ERROR_INVALID_VALUE;
+  if (!batch_current(b)) return IBP_ERROR_INVALID_VALUE;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return from_hip(e);
+  if (dev != b->device) return IBP_ERROR_INVALID_VALUE;
+  for (int g = 0; g < b->count; ++g) {
+    if (rhs[g] == nullptr || phi[g] == nullptr) return IBP_ERROR_INVALID_VALUE;
+    if ((reinterpret_cast<uintptr_t>(rhs[g]) & 15) != 0 || (reinterpret_cast<uintptr_t>(phi[g]) & 15) != 0)
+      return IBP_ERROR_INVALID_VALUE;
+    if (b->prec != IBP_FP64) {
+      const ibp_plan_s* p = b->plans[g];
+      const size_t n = (size_t)p->nx * p->ny * p->nz * sizeof(double);
+      const uintptr_t r0 = reinterpret_cast<uintptr_t>(rhs[g]), q0 = reinterpret_cast<uintptr_t>(phi[g]);
+      if (r0 < q0 + n && q0 < r0 + n) return IBP_ERROR_INVALID_VALUE;
+    }
+  }
+  return b->prec == IBP_FP64 ? batch_enqueue<double>(b, rhs, phi, s) : batch_enqueue<float>(b, rhs, phi, s);
+}
+
+// Batches built by ibp_solve_batched, keyed by the exact plan sequence.
+struct BatchCacheEntry {
+  std::vector<ibp_plan_t> key;
+  ibp_batch_s* batch;
+};
+std::mutex g_batch_mu;
+std::vector<BatchCacheEntry> g_batch_cache;
+constexpr size_t kBatchCacheMax = 16;
+
+void purge_batch_cache(const ibp_plan_s* p) {
+  std::lock_guard<std::mutex> lock(g_batch_mu);
+  for (size_t i = 0; i < g_batch_cache.size();) {
+    const auto& k = g_batch_cache[i].key;
+    if (std::find(k.begin(), k.end(), p) != k.end()) {
+      batch_free(g_batch_cache[i].batch);
+      g_batch_cache.erase(g_batch_cache.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+}
+
+ibp_status_t batched_or_loop(const ibp_plan_t* plans, int count, const double* const* rhs, double* const* phi,
+                             hipStream_t s) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return from_hip(e);
+  bool together = count >= 2;
+  for (int c0 = 0; together && c0 < count; c0 += kBatchMax) {
+    const int m = count - c0 < kBatchMax ? count - c0 : kBatchMax;
+    if (m >= 2 && batch_eligible(plans + c0, m, dev) != IBP_SUCCESS) together = false;
+  }
+  if (!together) {
+    for (int i = 0; i < count; ++i) {
+      ibp_status_t st = ibp_solve(plans[i], rhs[i], phi[i], s);
+      if (st != IBP_SUCCESS) return st;
+    }
+    return IBP_SUCCESS;
+  }
+  for (int c0 = 0; c0 < count; c0 += kBatchMax) {
+    const int m = count - c0 < kBatchMax ? count - c0 : kBatchMax;
+    if (m == 1) {
+      ibp_status_t st = ibp_solve(plans[c0], rhs[c0], phi[c0], s);
+      if (st != IBP_SUCCESS) return st;
+      continue;
+    }
+    ibp_batch_s* b = nullptr;
+    {
+      std::lock_guard<std::mutex> lock(g_batch_mu);
+      std::vector<ibp_plan_t> key(plans + c0, plans + c0 + m);
+      for (size_t i = 0; i < g_batch_cache.size(); ++i) {
+        if (g_batch_cache[i].key == key) {
+          if (batch_current(g_batch_cache[i].batch)) {
+            b = g_batch_cache[i].batch;
+          } else {
+            batch_free(g_batch_cache[i].batch);
+            g_batch_cache.erase(g_batch_cache.begin() + i);
+          }
+          break;
+        }
+      }
+      if (b == nullptr) {
+        ibp_status_t st = batch_create(plans + c0, m, &b);
+        if (st != IBP_SUCCESS) return st;
+        if (g_batch_cache.size() >= kBatchCacheMax) {
+          batch_free(g_batch_cache.front().batch);
+          g_batch_cache.erase(g_batch_cache.begin());
+        }
+        g_batch_cache.push_back(BatchCacheEntry{key, b});
+      }
+    }
+    ibp_status_t st = batch_solve(b, rhs + c0, phi + c0, s);
+    if (st != IBP_SUCCESS) return st;
+  }
+  return IBP_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+ibp_status_t ibp_batch_create(const ibp_plan_t* plans, int count, ibp_batch_t* out) {
+  if (plans == nullptr || out == nullptr) return IBP_ERROR_INVALID_VALUE;
+  try {
+    return batch_create(plans, count, out);
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+ibp_status_t ibp_batch_solve(ibp_batch_t batch, const double* const* rhs, double* const* phi, void* stream) {
+  if (batch == nullptr) return IBP_ERROR_INVALID_VALUE;
+  try {
+    return batch_solve(batch, rhs, phi, static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+ibp_status_t ibp_batch_set_ycols(ibp_batch_t b, int cols) {
+  if (b == nullptr || (cols != 2 && cols != 4 && cols != 8 && cols != 16)) return IBP_ERROR_INVALID_VALUE;
+  try {
+    b->yM = b->prec == IBP_FP64 ? batch_ytri_cols<double>(b->yP, b->yK, cols)
+                                : batch_ytri_cols<float>(b->yP, b->yK, cols);
+    return from_hip(batch_reapply(b));
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+ibp_status_t ibp_batch_destroy(ibp_batch_t b) {
+  try {
+    batch_free(b);
+    return IBP_SUCCESS;
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+}  // extern "C"
+
+// ======================================================================
+// Autotuning: time each candidate work split with HIP events on the
+// caller's stream (one warm-up solve, then the mean of a few) and keep the
+// fastest.
+namespace {
+
+struct TuneCfg {
+  int xdiv, zdiv, ycols;
+};
+
+template <class Apply, class Run>
+ibp_status_t autotune(const std::vector<TuneCfg>& cands, Apply apply, Run run, hipStream_t s, ibp_tune_t* out) {
+  constexpr int kReps = 3;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  ibp_status_t st = from_hip(e);
+  double best = 1e300, before = 0.0;
+  TuneCfg bestc = cands.front();
+  for (size_t i = 0; i < cands.size() && st == IBP_SUCCESS; ++i) {
+    st = apply(cands[i]);
+    if (st == IBP_SUCCESS) st = run();
+    if (st == IBP_SUCCESS) st = from_hip(hipEventRecord(e0, s));
+    for (int r = 0; r < kReps && st == IBP_SUCCESS; ++r) st = run();
+    if (st == IBP_SUCCESS) st = from_hip(hipEventRecord(e1, s));
+    if (st == IBP_SUCCESS) st = from_hip(hipEventSynchronize(e1));
+    float ms = 0.f;
+    if (st == IBP_SUCCESS) st = from_hip(hipEventElapsedTime(&ms, e0, e1));
+    if (st != IBP_SUCCESS) break;
+    const double t = ms / kReps;
+    if (i == 0) before = t;
+    if (t < best) {
+      best = t;
+      bestc = cands[i];
+    }
+  }
+  if (st == IBP_SUCCESS) st = apply(bestc);
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  if (st == IBP_SUCCESS && out) {
+    out->xdiv = bestc.xdiv;
+    out->zdiv = bestc.zdiv;
+    out->ycols = bestc.ycols;
+    out->tried = (int)cands.size();
+    out->ms = best;
+    out->ms_before = before;
+  }
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+ibp_status_t ibp_plan_autotune(ibp_plan_t p, const double* rhs, double* phi, void* stream, ibp_tune_t* out) {
+  if (!valid_plan(p) || rhs == nullptr || phi == nullptr) return IBP_ERROR_INVALID_VALUE;
+  try {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int zd0 = p->zc64max / (p->zc64 > 0 ? p->zc64 : 1);
+    std::vector<TuneCfg> cands{{1, zd0 > 0 ? zd0 : 1, p->ycols}};   // the configuration in place first
+    const bool zgen = !p->zfast && p->nz > 1;
+    for (int zd : {1, 2, 4}) {
+      if (!zgen && zd > 1) continue;
+      for (int yc : {2, 4, 8, 16}) cands.push_back(TuneCfg{1, zd, yc});
+    }
+    auto apply = [&](const TuneCfg& c) {
+      p->ycols = c.ycols;
+      p->zc64 = p->zc64max / c.zdiv > 0 ? p->zc64max / c.zdiv : 1;
+      p->zc32 = p->zc32max / c.zdiv > 0 ? p->zc32max / c.zdiv : 1;
+      return IBP_SUCCESS;
+    };
+    auto run = [&]() { return ibp_solve(p, rhs, phi, stream); };
+    return autotune(cands, apply, run, s, out);
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+ibp_status_t ibp_batch_autotune(ibp_batch_t b, const double* const* rhs, double* const* phi, void* stream,
+                                ibp_tune_t* out) {
+  if (b == nullptr || rhs == nullptr || phi == nullptr) return IBP_ERROR_INVALID_VALUE;
+  try {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<TuneCfg> cands{{b->xdiv, b->zdiv, b->yM}};
+    for (int xd : {1, 2, 4}) {
+      if (b->prec != IBP_FP64 && xd > 1) continue;   // the mixed forms' partials follow the x split
+      for (int zd : {1, 2, 4})
+        for (int yc : {2, 4, 8, 16}) cands.push_back(TuneCfg{xd, zd, yc});
+    }
+    auto apply = [&](const TuneCfg& c) {
+      b->xdiv = c.xdiv;
+      b->zdiv = c.zdiv;
+      b->yM = b->prec == IBP_FP64 ? batch_ytri_cols<double>(b->yP, b->yK, c.ycols)
+                                  : batch_ytri_cols<float>(b->yP, b->yK, c.ycols);
+      return from_hip(batch_reapply(b));
+    };
+    auto run = [&]() { return batch_solve(b, rhs, phi, s); };
+    return autotune(cands, apply, run, s, out);
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+}  // extern "C"

@@ -238,7 +238,7 @@ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 // nb sequences of length fp.n; sequence b starts at buf + b*ss.
 // TILE is the compile-time bound on nb * n.
 template <int TILE, bool INV, typename T>
-__device__ void lds_fft(Cx<T>* buf, int nb, int ss, const FftPlan& fp,
+__device__ __forceinline__ void lds_fft(Cx<T>* buf, int nb, int ss, const FftPlan& fp,
                         const Cx<T>* __restrict__ tw, int twstride) {
   const int n = fp.n;
   int Ns = 1;

@@ -143,6 +143,106 @@ struct FusedArgs {
   signed char xcc_queue[kMaxXcc];   // hardware XCC id -> queue (-1: none)
 };
 
+// ---------------------------------------------------------------- batches
+// Many grids solved together: every stage is one launch whose blocks cover
+// all grids.  Block b of a stage belongs to grid g with
+// start[g] <= b < start[g + 1] (prefix offsets of the per-grid block counts)
+// and runs that grid's block b - start[g].  Per-grid arguments live in a
+// device table written once per batch; the right-hand side and solution
+// pointers, which change from call to call, travel in the launch arguments.
+constexpr int kBatchMax = 64;
+
+template <typename T>
+struct BatchGrid {
+  XArgs<T> x;      // f, phi, out and iter are replaced at launch
+  ZfArgs<T> z;     // check_done replaced at launch
+  YArgs<T, T> y;   // check_done replaced at launch
+  ZeroArgs zero;   // init, mixed, iter, final_pass replaced at launch
+  int zcolblocks;  // z-pass column blocks per plane
+};
+
+// Pointers read from a device table are generic (flat) to the compiler;
+// re-deriving them from a global-address-space cast lets it use global
+// loads and stores (as it does for kernel-argument pointers).
+template <typename P>
+__device__ __forceinline__ P* as_global(P* p) {
+  return (P*)((__attribute__((address_space(1))) P*)p);
+}
+
+template <typename T>
+__device__ __forceinline__ void globalize(XArgs<T>& a) {
+  a.f = as_global(a.f);
+  a.phi = as_global(a.phi);
+  a.out = as_global(a.out);
+  a.spec = as_global(a.spec);
+  a.rowsum = as_global(a.rowsum);
+  a.part = as_global(a.part);
+  a.phi00 = as_global(a.phi00);
+  a.ctl = as_global(a.ctl);
+  a.twx = as_global(a.twx);
+  a.ya = as_global(a.ya);
+  a.yc = as_global(a.yc);
+  a.dyf = as_global(a.dyf);
+}
+template <typename T>
+__device__ __forceinline__ void globalize(ZfArgs<T>& a) {
+  a.spec = as_global(a.spec);
+  a.twz = as_global(a.twz);
+  a.ctl = as_global(a.ctl);
+}
+template <typename T, typename U>
+__device__ __forceinline__ void globalize(YArgs<T, U>& a) {
+  a.spec = as_global(a.spec);
+  a.lamx = as_global(a.lamx);
+  a.lamz = as_global(a.lamz);
+  a.ya = as_global(a.ya);
+  a.yc = as_global(a.yc);
+  a.ctl = as_global(a.ctl);
+}
+__device__ __forceinline__ void globalize(ZeroArgs& z) {
+  z.rowsum = as_global(z.rowsum);
+  z.ghat = as_global(z.ghat);
+  z.ticket = as_global(z.ticket);
+  z.phi00 = as_global(z.phi00);
+  z.dyf = as_global(z.dyf);
+  z.dyc = as_global(z.dyc);
+  z.part = as_global(z.part);
+  z.ctl = as_global(z.ctl);
+}
+
+struct BatchPtrs {
+  const double* f[kBatchMax];
+  double* phi[kBatchMax];
+};
+
+struct BatchLaunch {
+  int count;
+  int iter;
+  int init;
+  int mixed;
+  int final_pass;
+  int check_done;
+};
+
+// Stages of a batched solve; each launcher covers every grid in one launch.
+template <typename T>
+hipError_t launch_batch_xr2c(int mode, const BatchGrid<T>* d, const long* start, long nblocks, const BatchPtrs& p,
+                             const BatchLaunch& l, hipStream_t s);
+template <typename T>
+hipError_t launch_batch_xc2r(int mode, const BatchGrid<T>* d, const long* start, long nblocks, const BatchPtrs& p,
+                             const BatchLaunch& l, hipStream_t s);
+template <typename T>
+hipError_t launch_batch_zfft(bool inverse, const BatchGrid<T>* d, const long* start, long nblocks,
+                             const BatchLaunch& l, hipStream_t s);
+template <typename T>
+hipError_t launch_batch_ytri(int P, int K, int M, const BatchGrid<T>* d, const long* start, long nblocks,
+                             const BatchLaunch& l, hipStream_t s);
+template <typename T>
+hipError_t launch_batch_check(const BatchGrid<T>* d, const BatchLaunch& l, hipStream_t s);
+// Columns per block of the batched line solve for lanes P, rows per lane K.
+template <typename T>
+int batch_ytri_cols(int P, int K, int want);
+
 struct DivArgs {
   const double* u;
   const double* v;
@@ -174,8 +274,10 @@ template <typename T>
 hipError_t launch_xc2r(int mode, const XArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_zfft(bool inverse, const ZfArgs<T>& a, int nplanes, hipStream_t s);
+// M columns per block: `want` (2, 4, 8 or 16) if given, else 128-byte rows;
+// capped by the LDS budget.
 template <typename T, typename U>
-hipError_t launch_ytri(int P, int K, const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s);
+hipError_t launch_ytri(int P, int K, int want, const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s);
 hipError_t launch_check(const ZeroArgs& z, hipStream_t s);
 
 // Register-FFT kernels for power-of-two lengths 32..1024 (ibp_fastxz.hip).

@@ -18,13 +18,13 @@
 
 namespace ibp {
 
+// Rows [blk * RB, blk * RB + RB) of one grid; every thread of the block calls
+// it, and it returns with LDS free (uniform early exits only).
 template <typename T, int MODE, int TILE>
-__global__ __launch_bounds__(kThreads) void k_xr2c(XArgs<T> A) {
-  __shared__ Cx<T> buf[TILE];
-  __shared__ double sh[4 * 5];
-  if (MODE != XM_PLAIN && A.ctl->done) return;
+__device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& fp, long blk, Cx<T>* buf,
+                                              double* sh) {
+  if (MODE != XM_PLAIN && __builtin_amdgcn_readfirstlane(A.ctl->done)) return;
   const int h = A.h, RB = A.rows_per_block, nx = A.nx, nz = A.nz, ny = A.ny;
-  const long blk = A.row_begin / RB + blockIdx.x;
   const long row0 = blk * RB;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   double acc_in2 = 0.0, acc_f2 = 0.0, acc_max = 0.0, acc_bad = 0.0, acc_wphi = 0.0;
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kThreads) void k_xr2c(XArgs<T> A) {
   }
   if (MODE == XM_RESID_ONLY) return;
   __syncthreads();
-  lds_fft<TILE, false, T>(buf, RB, h, A.fp, A.twx, 2);
+  lds_fft<TILE, false, T>(buf, RB, h, fp, A.twx, 2);
 
   const int hh = h / 2 + 1;
   for (int e = threadIdx.x; e < RB * hh; e += kThreads) {
@@ -111,14 +111,20 @@ __global__ __launch_bounds__(kThreads) void k_xr2c(XArgs<T> A) {
     srow[k] = cadd(E, WO);
     if (h - k != k) srow[h - k] = cconj(csub(E, WO));
   }
+  __syncthreads();
 }
 
 template <typename T, int MODE, int TILE>
-__global__ __launch_bounds__(kThreads) void k_xc2r(XArgs<T> A) {
+__global__ __launch_bounds__(kThreads) void k_xr2c(XArgs<T> A) {
   __shared__ Cx<T> buf[TILE];
-  if (MODE == CM_ADD && A.ctl->done) return;
+  __shared__ double sh[4 * 5];
+  xr2c_gen_body<T, MODE, TILE>(A, A.fp, A.row_begin / A.rows_per_block + blockIdx.x, buf, sh);
+}
+
+template <typename T, int MODE, int TILE>
+__device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& fp, long blk, Cx<T>* buf) {
+  if (MODE == CM_ADD && __builtin_amdgcn_readfirstlane(A.ctl->done)) return;
   const int h = A.h, RB = A.rows_per_block, nx = A.nx, nz = A.nz;
-  const long blk = A.row_begin / RB + blockIdx.x;
   const long row0 = blk * RB;
   const int hh = h / 2 + 1;
   for (int e = threadIdx.x; e < RB * hh; e += kThreads) {
@@ -143,7 +149,7 @@ __global__ __launch_bounds__(kThreads) void k_xc2r(XArgs<T> A) {
     if (km != k) buf[lr * h + km] = Cx<T>{E.x + O.y, O.x - E.y};   // conj(E) + i conj(O)
   }
   __syncthreads();
-  lds_fft<TILE, true, T>(buf, RB, h, A.fp, A.twx, 2);
+  lds_fft<TILE, true, T>(buf, RB, h, fp, A.twx, 2);
 
   double cs = A.out_scale;
   if (MODE == CM_ADD) cs = cs / A.ctl->scale[A.iter & 1];
@@ -167,27 +173,151 @@ __global__ __launch_bounds__(kThreads) void k_xc2r(XArgs<T> A) {
       *o = make_double2(v0, v1);
     }
   }
+  __syncthreads();
+}
+
+template <typename T, int MODE, int TILE>
+__global__ __launch_bounds__(kThreads) void k_xc2r(XArgs<T> A) {
+  __shared__ Cx<T> buf[TILE];
+  xc2r_gen_body<T, MODE, TILE>(A, A.fp, A.row_begin / A.rows_per_block + blockIdx.x, buf);
 }
 
 template <typename T, bool INV, int TILE>
-__global__ __launch_bounds__(kThreads) void k_zfft(ZfArgs<T> A) {
-  __shared__ Cx<T> buf[TILE + 64];
-  if (A.check_done && A.ctl->done) return;
+__device__ __forceinline__ void zfft_gen_body(const ZfArgs<T>& A, const FftPlan& fp, int colblk, long plane_index,
+                                              Cx<T>* buf) {
+  if (A.check_done && __builtin_amdgcn_readfirstlane(A.ctl->done)) return;
   const int nz = A.nz, C = A.cols, hp = A.hp, ss = nz + 1;
   const long rs = A.rs;
-  const int c0 = blockIdx.x * C;
-  Cx<T>* plane = A.spec + (size_t)(A.plane0 + blockIdx.y) * A.ps;
+  const int c0 = colblk * C;
+  Cx<T>* plane = A.spec + (size_t)plane_index * A.ps;
   for (int e = threadIdx.x; e < C * nz; e += kThreads) {
     const int z = e / C, c = e - z * C;
     buf[c * ss + z] = (c0 + c < hp) ? plane[(size_t)z * rs + c0 + c] : Cx<T>{T(0), T(0)};
   }
   __syncthreads();
-  lds_fft<TILE, INV, T>(buf, C, ss, A.fp, A.twz, 1);
+  lds_fft<TILE, INV, T>(buf, C, ss, fp, A.twz, 1);
   for (int e = threadIdx.x; e < C * nz; e += kThreads) {
     const int z = e / C, c = e - z * C;
     if (c0 + c < hp) plane[(size_t)z * rs + c0 + c] = buf[c * ss + z];
   }
+  __syncthreads();
 }
+
+template <typename T, bool INV, int TILE>
+__global__ __launch_bounds__(kThreads) void k_zfft(ZfArgs<T> A) {
+  __shared__ Cx<T> buf[TILE + 64];
+  zfft_gen_body<T, INV, TILE>(A, A.fp, blockIdx.x, A.plane0 + blockIdx.y, buf);
+}
+
+// ---------------------------------------------------------------- batched stages
+// Per-grid arguments are copied from the device table into registers, except
+// the FFT plans: the stage loops index them at run time, so they are read
+// from the table in place (a private copy would live in scratch memory).
+__device__ __forceinline__ int batch_grid_of(const long* start, int count, long b) {
+  int lo = 0, hi = count - 1;   // largest g with start[g] <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (__builtin_amdgcn_readfirstlane((int)(start[mid] <= b))) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T, int MODE, int TILE>
+__global__ __launch_bounds__(kThreads) void kb_xr2c(const BatchGrid<T>* __restrict__ D, const long* __restrict__ start,
+                                                     BatchPtrs P, BatchLaunch L) {
+  __shared__ Cx<T> buf[TILE];
+  __shared__ double sh[4 * 5];
+  const int g = batch_grid_of(start, L.count, blockIdx.x);
+  XArgs<T> a = D[g].x;
+  a.f = P.f[g];
+  a.phi = P.phi[g];
+  a.out = P.phi[g];
+  a.iter = L.iter;
+  globalize(a);
+  xr2c_gen_body<T, MODE, TILE>(a, D[g].x.fp, (long)blockIdx.x - start[g], buf, sh);
+}
+
+template <typename T, int MODE, int TILE>
+__global__ __launch_bounds__(kThreads) void kb_xc2r(const BatchGrid<T>* __restrict__ D, const long* __restrict__ start,
+                                                     BatchPtrs P, BatchLaunch L) {
+  __shared__ Cx<T> buf[TILE];
+  const int g = batch_grid_of(start, L.count, blockIdx.x);
+  XArgs<T> a = D[g].x;
+  a.f = P.f[g];
+  a.phi = P.phi[g];
+  a.out = P.phi[g];
+  a.iter = L.iter;
+  globalize(a);
+  xc2r_gen_body<T, MODE, TILE>(a, D[g].x.fp, (long)blockIdx.x - start[g], buf);
+}
+
+template <typename T, bool INV, int TILE>
+__global__ __launch_bounds__(kThreads) void kb_zfft(const BatchGrid<T>* __restrict__ D, const long* __restrict__ start,
+                                                     BatchLaunch L) {
+  __shared__ Cx<T> buf[TILE + 64];
+  const int g = batch_grid_of(start, L.count, blockIdx.x);
+  ZfArgs<T> a = D[g].z;
+  a.check_done = L.check_done;
+  globalize(a);
+  const long local = (long)blockIdx.x - start[g];
+  const int ncb = D[g].zcolblocks;
+  zfft_gen_body<T, INV, TILE>(a, D[g].z.fp, (int)(local % ncb), local / ncb, buf);
+}
+
+template <typename T>
+hipError_t launch_batch_xr2c(int mode, const BatchGrid<T>* d, const long* start, long nblocks, const BatchPtrs& p,
+                             const BatchLaunch& l, hipStream_t s) {
+  constexpr int TL = (sizeof(T) == 8) ? kTileX64 : kTileX32;
+  if (nblocks <= 0) return hipSuccess;
+  const dim3 grid((unsigned)nblocks), block(kThreads);
+  switch (mode) {
+    case XM_PLAIN: hipLaunchKernelGGL((kb_xr2c<T, XM_PLAIN, TL>), grid, block, 0, s, d, start, p, l); break;
+    case XM_RESID: hipLaunchKernelGGL((kb_xr2c<T, XM_RESID, TL>), grid, block, 0, s, d, start, p, l); break;
+    case XM_RESID_ONLY: hipLaunchKernelGGL((kb_xr2c<T, XM_RESID_ONLY, TL>), grid, block, 0, s, d, start, p, l); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch_xc2r(int mode, const BatchGrid<T>* d, const long* start, long nblocks, const BatchPtrs& p,
+                             const BatchLaunch& l, hipStream_t s) {
+  constexpr int TL = (sizeof(T) == 8) ? kTileX64 : kTileX32;
+  if (nblocks <= 0) return hipSuccess;
+  const dim3 grid((unsigned)nblocks), block(kThreads);
+  switch (mode) {
+    case CM_SET: hipLaunchKernelGGL((kb_xc2r<T, CM_SET, TL>), grid, block, 0, s, d, start, p, l); break;
+    case CM_ADD: hipLaunchKernelGGL((kb_xc2r<T, CM_ADD, TL>), grid, block, 0, s, d, start, p, l); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch_zfft(bool inverse, const BatchGrid<T>* d, const long* start, long nblocks,
+                             const BatchLaunch& l, hipStream_t s) {
+  constexpr int TL = (sizeof(T) == 8) ? kTileZ64 : kTileZ32;
+  if (nblocks <= 0) return hipSuccess;
+  const dim3 grid((unsigned)nblocks), block(kThreads);
+  if (inverse)
+    hipLaunchKernelGGL((kb_zfft<T, true, TL>), grid, block, 0, s, d, start, l);
+  else
+    hipLaunchKernelGGL((kb_zfft<T, false, TL>), grid, block, 0, s, d, start, l);
+  return hipGetLastError();
+}
+
+template hipError_t launch_batch_xr2c<double>(int, const BatchGrid<double>*, const long*, long, const BatchPtrs&,
+                                              const BatchLaunch&, hipStream_t);
+template hipError_t launch_batch_xr2c<float>(int, const BatchGrid<float>*, const long*, long, const BatchPtrs&,
+                                             const BatchLaunch&, hipStream_t);
+template hipError_t launch_batch_xc2r<double>(int, const BatchGrid<double>*, const long*, long, const BatchPtrs&,
+                                              const BatchLaunch&, hipStream_t);
+template hipError_t launch_batch_xc2r<float>(int, const BatchGrid<float>*, const long*, long, const BatchPtrs&,
+                                             const BatchLaunch&, hipStream_t);
+template hipError_t launch_batch_zfft<double>(bool, const BatchGrid<double>*, const long*, long, const BatchLaunch&,
+                                              hipStream_t);
+template hipError_t launch_batch_zfft<float>(bool, const BatchGrid<float>*, const long*, long, const BatchLaunch&,
+                                             hipStream_t);
 
 // ---------------------------------------------------------------- launchers
 template <typename T>

@@ -21,34 +21,14 @@ namespace ibp {
 // mean m = sum dyf g / (sum dyf nx nz) removed, then the face flux and the
 // potential integrated upwards from the lower wall:
 //   flux_0 = 0, flux_{j+1} = flux_j + dyf_j g_j,  X_0 = 0, X_j = X_{j-1} + dyc_j flux_j,
-// and X shifted to zero weighted mean.  Deterministic: fixed-order sums and
-// a Hillis-Steele scan over the 256 thread chunks.
-template <int NT>
-__device__ double block_excl_scan(double v, double* sc) {
-  const int t = threadIdx.x;
-  sc[t] = v;
-  __syncthreads();
-  for (int off = 1; off < NT; off <<= 1) {
-    const double add = t >= off ? sc[t - off] : 0.0;
-    __syncthreads();
-    sc[t] += add;
-    __syncthreads();
-  }
-  const double r = t > 0 ? sc[t - 1] : 0.0;
-  __syncthreads();
-  return r;
-}
+// and X shifted to zero weighted mean.  Deterministic: one wave does it with
+// fixed-order sums and a Hillis-Steele scan over its 64 lane chunks, so the
+// bits do not depend on the shape of the block that runs it.
 
+// Reduction of the per-block norm partials of an x pass (fixed order for a
+// given NT).
 template <int NT>
-__device__ double block_sum_det(double v, double* sh) {
-  bool ism[1] = {false};
-  double a[1] = {v};
-  block_reduce<1, NT>(a, ism, sh);
-  return a[0];
-}
-
-template <int NT>
-__device__ void reduce_parts(const ZeroArgs& Z, double* sh, double out[kPartStride]) {
+__device__ __forceinline__ void reduce_parts(const ZeroArgs& Z, double* sh, double out[kPartStride]) {
   double v[kPartStride] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (long b = threadIdx.x; b < Z.nparts; b += NT) {
     const double* p = Z.part + b * kPartStride;
@@ -68,15 +48,30 @@ __device__ double next_scale(double rmax) {
   return ldexp(1.0, 20 - ilogb(rmax));
 }
 
-// Scans of the (0,0) mode over the plane sums ghat[0..ny) (run by one block).
-template <int NT>
-__device__ void zero_mode_scans(const ZeroArgs& Z) {
-  __shared__ double sc[NT];
-  __shared__ double sh[(NT / kWave) * kPartStride];
-  const int t = threadIdx.x, ny = Z.ny;
-  constexpr int CHM = (kMaxNy + NT - 1) / NT;   // rows per thread at the largest ny
-  const int CH = (ny + NT - 1) / NT;
-  const int j0 = t * CH;
+// Sum over the wave, lane 0's association order, broadcast to every lane.
+__device__ __forceinline__ double wave_total(double v) { return __shfl(wave_sum(v), 0, kWave); }
+
+// Exclusive prefix sum over the 64 lanes (Hillis-Steele; each lane's result
+// has a fixed association order).
+__device__ __forceinline__ double wave_excl_scan(double v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const double u = __shfl_up(v, off, kWave);
+    if (lane >= off) v += u;
+  }
+  const double e = __shfl_up(v, 1, kWave);
+  return lane > 0 ? e : 0.0;
+}
+
+// Scans of the (0,0) mode over the plane sums ghat[0..ny), run by one wave
+// (so the result does not depend on the size of the block that runs it).
+// `p`: reduced norm partials of the right-hand side pass (used when Z.init).
+__device__ __forceinline__ void zero_mode_scans(const ZeroArgs& Z, const double (&p)[kPartStride]) {
+  const int lane = threadIdx.x & (kWave - 1), ny = Z.ny;
+  constexpr int CHM = (kMaxNy + kWave - 1) / kWave;   // rows per lane at the largest ny
+  const int CH = (ny + kWave - 1) / kWave;
+  const int j0 = lane * CH;
   const volatile double* gh = Z.ghat;            // written by other blocks of this launch
   double g[CHM];
   double wsum = 0.0, dsum = 0.0, bad = 0.0;
@@ -92,9 +87,9 @@ __device__ void zero_mode_scans(const ZeroArgs& Z) {
       if (!isfinite(v)) bad += 1.0;
     }
   }
-  wsum = block_sum_det<NT>(wsum, sh);
-  dsum = block_sum_det<NT>(dsum, sh);
-  bad = block_sum_det<NT>(bad, sh);
+  wsum = wave_total(wsum);
+  dsum = wave_total(dsum);
+  bad = wave_total(bad);
   const double nxnz = double(Z.nx) * double(Z.nz);
   const double m = wsum / (dsum * nxnz);
   // flux at the lower face of every cell of the chunk
@@ -107,7 +102,7 @@ __device__ void zero_mode_scans(const ZeroArgs& Z) {
       loc += Z.dyf[j] * g[c];
     }
   }
-  double flux = block_excl_scan<NT>(loc, sc);
+  double flux = wave_excl_scan(loc);
   double tl = 0.0;
 #pragma unroll
   for (int c = 0; c < CHM; ++c) {      // g[c] <- dyc_j flux_j
@@ -119,7 +114,7 @@ __device__ void zero_mode_scans(const ZeroArgs& Z) {
       tl += g[c];
     }
   }
-  double X = block_excl_scan<NT>(tl, sc);
+  double X = wave_excl_scan(tl);
   double xw = 0.0;
 #pragma unroll
   for (int c = 0; c < CHM; ++c) {      // g[c] <- X_j
@@ -130,55 +125,57 @@ __device__ void zero_mode_scans(const ZeroArgs& Z) {
       xw += Z.dyf[j] * X;
     }
   }
-  xw = block_sum_det<NT>(xw, sh);
+  xw = wave_total(xw);
   const double xbar = xw / dsum;
 #pragma unroll
   for (int c = 0; c < CHM; ++c) {
     const int j = j0 + c;
     if (c < CH && j < ny) Z.phi00[j] = g[c] - xbar;
   }
-  if (Z.init) {
-    double p[kPartStride];
-    reduce_parts<NT>(Z, sh, p);
-    if (t == 0) {
-      Ctl* c = Z.ctl;
-      c->done = 0;
-      c->iters = 0;
-      c->converged = Z.mixed ? 0 : 1;
-      c->nonfinite = (bad > 0.0 || p[3] > 0.0) ? 1 : 0;
-      c->scale[0] = 1.0;
-      c->scale[1] = next_scale(p[2]);
-      c->fnorm2 = p[1];
-      c->rnorm2 = __builtin_nan("");
-      c->rmax = __builtin_nan("");
-      c->removed_mean = m;
-      c->rel_residual = __builtin_nan("");
-      c->phimean = 0.0;
-    }
+  if (Z.init && lane == 0) {
+    Ctl* c = Z.ctl;
+    c->done = 0;
+    c->iters = 0;
+    c->converged = Z.mixed ? 0 : 1;
+    c->nonfinite = (bad > 0.0 || p[3] > 0.0) ? 1 : 0;
+    c->scale[0] = 1.0;
+    c->scale[1] = next_scale(p[2]);
+    c->fnorm2 = p[1];
+    c->rnorm2 = __builtin_nan("");
+    c->rmax = __builtin_nan("");
+    c->removed_mean = m;
+    c->rel_residual = __builtin_nan("");
+    c->phimean = 0.0;
   }
 }
 
-// Block j < ny: plane sum ghat[j] of the FP64 row sums (fixed-order tree);
-// the block that finishes last (atomic ticket) then runs the scans and
-// re-arms the ticket for the next launch.
+// Block j < ny: plane sum ghat[j] of the FP64 row sums (wave 0, fixed
+// order); the block that finishes last (atomic ticket) then runs the scans
+// and re-arms the ticket for the next launch.
 template <int NT>
-__device__ void zero_mode_plane(const ZeroArgs& Z, int j) {
-  __shared__ double sh[NT / kWave];
+__device__ __forceinline__ void zero_mode_plane(const ZeroArgs& Z, int j) {
+  __shared__ double sh[(NT / kWave) * kPartStride];
   __shared__ int last;
-  double s = 0.0;
-  const double* rs = Z.rowsum + (long)j * Z.nz;
-  for (int k = threadIdx.x; k < Z.nz; k += NT) s += rs[k];
-  s = block_sum_det<NT>(s, sh);
-  if (threadIdx.x == 0) {
-    Z.ghat[j] = s;
-    __threadfence();
-    const int ticket = atomicAdd(Z.ticket, 1);
-    last = (ticket == Z.ny - 1);
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (wave == 0) {
+    double s = 0.0;
+    const double* rs = Z.rowsum + (long)j * Z.nz;
+    for (int k = lane; k < Z.nz; k += kWave) s += rs[k];
+    s = wave_total(s);
+    if (lane == 0) {
+      Z.ghat[j] = s;
+      __threadfence();
+      const int ticket = atomicAdd(Z.ticket, 1);
+      last = (ticket == Z.ny - 1);
+    }
   }
   __syncthreads();
-  if (!last) return;
+  if (!__builtin_amdgcn_readfirstlane(last)) return;
   __threadfence();
-  zero_mode_scans<NT>(Z);
+  double p[kPartStride] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (Z.init) reduce_parts<NT>(Z, sh, p);
+  if (wave == 0) zero_mode_scans(Z, p);
   if (threadIdx.x == 0) atomicExch(Z.ticket, 0);
 }
 
@@ -206,25 +203,29 @@ __host__ __device__ constexpr int ytile_col() {
   return P * (K + 1) + ((2 - (P * (K + 1)) % 32) + 32) % 32;
 }
 
+inline int ytile_col_host(int P, int K) { return P * (K + 1) + ((2 - (P * (K + 1)) % 32) + 32) % 32; }
+
 template <typename U>
 __device__ __forceinline__ U shfl_up_w(U v, int d, int w) { return __shfl_up(v, d, w); }
 template <typename U>
 __device__ __forceinline__ U shfl_down_w(U v, int d, int w) { return __shfl_down(v, d, w); }
 
+// Block `blk` of one grid's line-solve pass: blocks [0, ny) reduce the FP64
+// plane sums of the (0,0) mode, the rest own M consecutive columns each.
+// Every thread of the block calls it.
 template <typename T, typename U, int M, int P, int K>
-__global__ __launch_bounds__(M * P) void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
+__device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& Z, long blk, Cx<T>* tile) {
   constexpr int NT = M * P;
   constexpr int KS = K + 1;     // LDS slots per partition: odd, so lanes spread over banks
   constexpr int LS = ytile_col<K, P>();   // LDS slots per column
-  __shared__ Cx<T> tile[M * LS];
-  if (A.check_done && A.ctl->done) return;
-  if (blockIdx.x < (unsigned)A.ny) {   // the first ny blocks: FP64 (0,0) mode
-    zero_mode_plane<NT>(Z, blockIdx.x);
+  if (A.check_done && __builtin_amdgcn_readfirstlane(A.ctl->done)) return;
+  if (blk < A.ny) {   // the first ny blocks: FP64 (0,0) mode
+    zero_mode_plane<NT>(Z, (int)blk);
     return;
   }
   const int ny = A.ny;
   const long Q = A.Q;
-  const long q0 = (long)(blockIdx.x - ny) * M;
+  const long q0 = (blk - ny) * M;
   // ---- coalesced load of the [ny][M] tile into per-column partition slots:
   // thread (row0 = tid / M, m = tid % M) moves rows row0 + P*i, i < K; all K
   // loads are issued before the first LDS write (rows and columns past the
@@ -400,13 +401,18 @@ __global__ __launch_bounds__(M * P) void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
   }
 }
 
+template <typename T, typename U, int M, int P, int K>
+__global__ __launch_bounds__(M * P) void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
+  __shared__ Cx<T> tile[M * ytile_col<K, P>()];
+  ytri_body<T, U, M, P, K>(A, Z, blockIdx.x, tile);
+}
+
 // ---------------------------------------------------------------- control
 // Convergence test of a refinement pass (one block): reduce the partials of
 // the residual pass, record ||r||/||f - m||, and either stop the refinement or
 // set the FP32 input scale of the next pass.
-__global__ __launch_bounds__(kThreads) void k_check(ZeroArgs Z) {
-  __shared__ double sh[4 * kPartStride];
-  if (Z.ctl->done) return;
+__device__ __forceinline__ void check_body(const ZeroArgs& Z, double* sh) {
+  if (__builtin_amdgcn_readfirstlane(Z.ctl->done)) return;
   double p[kPartStride];
   reduce_parts<kThreads>(Z, sh, p);
   if (threadIdx.x != 0) return;
@@ -429,6 +435,11 @@ __global__ __launch_bounds__(kThreads) void k_check(ZeroArgs Z) {
     c->iters = Z.iter;
     c->scale[(Z.iter + 1) & 1] = next_scale(p[2]);
   }
+}
+
+__global__ __launch_bounds__(kThreads) void k_check(ZeroArgs Z) {
+  __shared__ double sh[4 * kPartStride];
+  check_body(Z, sh);
 }
 
 hipError_t launch_check(const ZeroArgs& z, hipStream_t s) {
@@ -462,13 +473,13 @@ static int ycol_override() {
 }
 
 template <typename T>
-static int ytri_cols(int P, int K) {
+static int ytri_cols(int P, int K, int want) {
   auto tile = [&](int M) {
     const int col = P * (K + 1) + ((2 - (P * (K + 1)) % 32) + 32) % 32;
     return (long)M * col * (long)sizeof(Cx<T>);
   };
   int M = 128 / (int)sizeof(Cx<T>);
-  const int o = ycol_override();
+  const int o = want ? want : ycol_override();
   if (o == 2 || o == 4 || o == 8 || o == 16) M = o;
   while (M > 2 && tile(M) > kYTileBytes) M /= 2;
   while (M * P > 1024) M /= 2;
@@ -501,8 +512,8 @@ static hipError_t launch_ytri_mp(int K, const YArgs<T, U>& a, const ZeroArgs& z,
 }
 
 template <typename T, typename U>
-hipError_t launch_ytri(int P, int K, const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s) {
-  const int M = ytri_cols<T>(P, K);
+hipError_t launch_ytri(int P, int K, int want, const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s) {
+  const int M = ytri_cols<T>(P, K, want);
   if (P == 32) {
     switch (M) {
       case 16: return launch_ytri_mp<T, U, 16, 32>(K, a, z, s);
@@ -524,8 +535,123 @@ hipError_t launch_ytri(int P, int K, const YArgs<T, U>& a, const ZeroArgs& z, hi
   return hipErrorInvalidValue;
 }
 
-template hipError_t launch_ytri<double, double>(int, int, const YArgs<double, double>&, const ZeroArgs&, hipStream_t);
-template hipError_t launch_ytri<float, float>(int, int, const YArgs<float, float>&, const ZeroArgs&, hipStream_t);
-template hipError_t launch_ytri<float, double>(int, int, const YArgs<float, double>&, const ZeroArgs&, hipStream_t);
+// ---------------------------------------------------------------- batched
+__device__ __forceinline__ int ybatch_grid_of(const long* start, int count, long b) {
+  int lo = 0, hi = count - 1;   // largest g with start[g] <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (__builtin_amdgcn_readfirstlane((int)(start[mid] <= b))) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T, int M, int P, int K>
+__global__ __launch_bounds__(M * P) void kb_ytri(const BatchGrid<T>* __restrict__ D, const long* __restrict__ start,
+                                                 BatchLaunch L) {
+  __shared__ Cx<T> tile[M * ytile_col<K, P>()];
+  const int g = ybatch_grid_of(start, L.count, blockIdx.x);
+  YArgs<T, T> a = D[g].y;
+  a.check_done = L.check_done;
+  ZeroArgs z = D[g].zero;
+  z.init = L.init;
+  z.mixed = L.mixed;
+  z.iter = L.iter;
+  z.final_pass = L.final_pass;
+  globalize(a);
+  globalize(z);
+  ytri_body<T, T, M, P, K>(a, z, (long)blockIdx.x - start[g], tile);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void kb_check(const BatchGrid<T>* __restrict__ D, BatchLaunch L) {
+  __shared__ double sh[4 * kPartStride];
+  ZeroArgs z = D[blockIdx.x].zero;
+  z.init = L.init;
+  z.mixed = L.mixed;
+  z.iter = L.iter;
+  z.final_pass = L.final_pass;
+  globalize(z);
+  check_body(z, sh);
+}
+
+template <typename T>
+int batch_ytri_cols(int P, int K, int want) {
+  auto tile = [&](int M) { return (long)M * ytile_col_host(P, K) * (long)sizeof(Cx<T>); };
+  int M = (want == 2 || want == 4 || want == 8 || want == 16) ? want : 128 / (int)sizeof(Cx<T>);
+  while (M > 2 && tile(M) > kYTileBytes) M /= 2;
+  while (M * P > 1024) M /= 2;
+  return M;
+}
+
+template <typename T, int M, int P, int K>
+static hipError_t launch_kb_ytri(const BatchGrid<T>* d, const long* start, long nb, const BatchLaunch& l,
+                                 hipStream_t s) {
+  if constexpr ((long)M * ytile_col<K, P>() * (long)sizeof(Cx<T>) <= kYTileBytes && M * P <= 1024) {
+    hipLaunchKernelGGL((kb_ytri<T, M, P, K>), dim3((unsigned)nb), dim3(M * P), 0, s, d, start, l);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int M, int P>
+static hipError_t launch_kb_ytri_k(int K, const BatchGrid<T>* d, const long* start, long nb, const BatchLaunch& l,
+                                   hipStream_t s) {
+  switch (K) {
+    case 2: return launch_kb_ytri<T, M, P, 2>(d, start, nb, l, s);
+    case 4: return launch_kb_ytri<T, M, P, 4>(d, start, nb, l, s);
+    case 8: return launch_kb_ytri<T, M, P, 8>(d, start, nb, l, s);
+    case 12: return launch_kb_ytri<T, M, P, 12>(d, start, nb, l, s);
+    case 16: return launch_kb_ytri<T, M, P, 16>(d, start, nb, l, s);
+    case 24: return launch_kb_ytri<T, M, P, 24>(d, start, nb, l, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_batch_ytri(int P, int K, int M, const BatchGrid<T>* d, const long* start, long nblocks,
+                             const BatchLaunch& l, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  if (P == 32) {
+    switch (M) {
+      case 16: return launch_kb_ytri_k<T, 16, 32>(K, d, start, nblocks, l, s);
+      case 8: return launch_kb_ytri_k<T, 8, 32>(K, d, start, nblocks, l, s);
+      case 4: return launch_kb_ytri_k<T, 4, 32>(K, d, start, nblocks, l, s);
+      case 2: return launch_kb_ytri_k<T, 2, 32>(K, d, start, nblocks, l, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (P == 64) {
+    switch (M) {
+      case 16: return launch_kb_ytri_k<T, 16, 64>(K, d, start, nblocks, l, s);
+      case 8: return launch_kb_ytri_k<T, 8, 64>(K, d, start, nblocks, l, s);
+      case 4: return launch_kb_ytri_k<T, 4, 64>(K, d, start, nblocks, l, s);
+      case 2: return launch_kb_ytri_k<T, 2, 64>(K, d, start, nblocks, l, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_batch_check(const BatchGrid<T>* d, const BatchLaunch& l, hipStream_t s) {
+  hipLaunchKernelGGL(kb_check<T>, dim3((unsigned)l.count), dim3(kThreads), 0, s, d, l);
+  return hipGetLastError();
+}
+
+template int batch_ytri_cols<double>(int, int, int);
+template int batch_ytri_cols<float>(int, int, int);
+template hipError_t launch_batch_ytri<double>(int, int, int, const BatchGrid<double>*, const long*, long,
+                                              const BatchLaunch&, hipStream_t);
+template hipError_t launch_batch_ytri<float>(int, int, int, const BatchGrid<float>*, const long*, long,
+                                             const BatchLaunch&, hipStream_t);
+template hipError_t launch_batch_check<double>(const BatchGrid<double>*, const BatchLaunch&, hipStream_t);
+template hipError_t launch_batch_check<float>(const BatchGrid<float>*, const BatchLaunch&, hipStream_t);
+
+template hipError_t launch_ytri<double, double>(int, int, int, const YArgs<double, double>&, const ZeroArgs&,
+                                                hipStream_t);
+template hipError_t launch_ytri<float, float>(int, int, int, const YArgs<float, float>&, const ZeroArgs&, hipStream_t);
+template hipError_t launch_ytri<float, double>(int, int, int, const YArgs<float, double>&, const ZeroArgs&,
+                                               hipStream_t);
 
 }  // namespace ibp

@@ -41,6 +41,14 @@ class PassStat(ctypes.Structure):
                 ("total_ms", ctypes.c_double), ("bytes_per_launch", ctypes.c_double)]
 
 
+class Tune(ctypes.Structure):
+    _fields_ = [("xdiv", ctypes.c_int), ("zdiv", ctypes.c_int), ("ycols", ctypes.c_int), ("tried", ctypes.c_int),
+                ("ms", ctypes.c_double), ("ms_before", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 def lib():
     """Load libibpoisson.so (once) and declare its signatures."""
     global _lib
@@ -63,6 +71,12 @@ def lib():
         "ibp_divergence": (ci, [vp, vp, vp, vp, vp, vp]),
         "ibp_plan_set_profiling": (ci, [vp, ci]),
         "ibp_plan_get_profile": (ci, [vp, ci, ctypes.POINTER(ci), ctypes.POINTER(PassStat)]),
+        "ibp_batch_create": (ci, [ctypes.POINTER(vp), ci, ctypes.POINTER(vp)]),
+        "ibp_batch_solve": (ci, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]),
+        "ibp_batch_set_ycols": (ci, [vp, ci]),
+        "ibp_batch_destroy": (ci, [vp]),
+        "ibp_plan_autotune": (ci, [vp, vp, vp, vp, ctypes.POINTER(Tune)]),
+        "ibp_batch_autotune": (ci, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.POINTER(Tune)]),
         "ibp_status_string": (ctypes.c_char_p, [ci]),
         "ibp_version": (ci, []),
     }
@@ -163,6 +177,18 @@ class Plan:
         _check(lib().ibp_solve(self.handle, r, p, _stream_ptr(stream)), "ibp_solve")
         return phi
 
+    def autotune(self, rhs, phi=None, stream=None):
+        """Time the plan's work splits on this input and keep the fastest
+        (synchronises; phi receives the solution).  Returns the choice."""
+        import torch
+        r = _field(rhs, self.shape, "rhs")
+        if phi is None:
+            phi = torch.empty(self.shape, dtype=torch.float64, device=rhs.device)
+        t = Tune()
+        _check(lib().ibp_plan_autotune(self.handle, r, _field(phi, self.shape, "phi"), _stream_ptr(stream),
+                                       ctypes.byref(t)), "ibp_plan_autotune")
+        return t.as_dict()
+
     def info(self):
         inf = Info()
         _check(lib().ibp_get_info(self.handle, ctypes.byref(inf)), "ibp_get_info")
@@ -214,3 +240,70 @@ def solve_batched(plans, rhs, phi, stream=None):
     P = (ctypes.c_void_p * n)(*[_field(q, p.shape, "phi").value for q, p in zip(phi, plans)])
     _check(lib().ibp_solve_batched(H, n, R, P, _stream_ptr(stream)), "ibp_solve_batched")
     return phi
+
+
+BATCH_MAX = 64
+
+
+class Batch:
+    """Grids solved together, one launch per solve stage (ibp_batch_*).  The
+    plans must outlive the batch."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        n = len(self.plans)
+        H = (ctypes.c_void_p * n)(*[p.handle for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib().ibp_batch_create(H, n, ctypes.byref(h)), "ibp_batch_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("batch is closed")
+        return self._h
+
+    def set_ycols(self, cols):
+        _check(lib().ibp_batch_set_ycols(self.handle, int(cols)), "ibp_batch_set_ycols")
+
+    def _ptrs(self, rhs, phi):
+        n = len(self.plans)
+        if len(rhs) != n or len(phi) != n:
+            raise ValueError("one right-hand side and one solution per plan")
+        R = (ctypes.c_void_p * n)(*[_field(r, p.shape, "rhs").value for r, p in zip(rhs, self.plans)])
+        P = (ctypes.c_void_p * n)(*[_field(q, p.shape, "phi").value for q, p in zip(phi, self.plans)])
+        return R, P
+
+    def autotune(self, rhs, phi=None, stream=None):
+        """Time the batch's work splits on these inputs and keep the fastest
+        (synchronises; phi receives the solutions).  Returns the choice."""
+        import torch
+        if phi is None:
+            phi = [torch.empty(p.shape, dtype=torch.float64, device=r.device) for p, r in zip(self.plans, rhs)]
+        R, P = self._ptrs(rhs, phi)
+        t = Tune()
+        _check(lib().ibp_batch_autotune(self.handle, R, P, _stream_ptr(stream), ctypes.byref(t)),
+               "ibp_batch_autotune")
+        return t.as_dict()
+
+    def solve(self, rhs, phi=None, stream=None):
+        import torch
+        n = len(self.plans)
+        if len(rhs) != n:
+            raise ValueError("one right-hand side per plan")
+        if phi is None:
+            phi = [torch.empty(p.shape, dtype=torch.float64, device=r.device) for p, r in zip(self.plans, rhs)]
+        R, P = self._ptrs(rhs, phi)
+        _check(lib().ibp_batch_solve(self.handle, R, P, _stream_ptr(stream)), "ibp_batch_solve")
+        return phi
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().ibp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -82,3 +82,11 @@ def test_null_plan_calls_fail_cleanly():
     assert L.ibp_solve_batched(None, 0, None, None, None) == ibp.SUCCESS
     assert L.ibp_solve_batched(None, -1, None, None, None) == ibp.INVALID_VALUE
     assert L.ibp_solve_batched(None, 2, None, None, None) == ibp.INVALID_VALUE
+    out = ctypes.c_void_p()
+    assert L.ibp_batch_create(None, 1, ctypes.byref(out)) == ibp.INVALID_VALUE
+    assert L.ibp_batch_solve(None, None, None, None) == ibp.INVALID_VALUE
+    assert L.ibp_batch_set_ycols(None, 8) == ibp.INVALID_VALUE
+    assert L.ibp_batch_destroy(None) == ibp.SUCCESS
+    t = ibp.Tune()
+    assert L.ibp_plan_autotune(None, None, None, None, ctypes.byref(t)) == ibp.INVALID_VALUE
+    assert L.ibp_batch_autotune(None, None, None, None, ctypes.byref(t)) == ibp.INVALID_VALUE

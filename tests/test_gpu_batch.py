@@ -1,0 +1,176 @@
+"""Batched solves of many uneven grids: one launch per solve stage covering
+every grid (ibp_batch_* and ibp_solve_batched).  GPU only."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.grid import geometry
+from oracle.operators import divergence
+from paper_2609_19130_amd import ibpoisson as ibp
+from paper_2609_19130_amd import synth
+
+from gpu_helpers import rel, require_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+REG_LENGTHS = {32, 64, 128, 256, 512, 1024}   # lengths the single-grid path transforms in registers
+
+
+def line_solve_rows(ny):
+    """Rows per lane of the line solve for ny (32 lanes up to ny = 768, then
+    64; rows from 2, 4, 8, 12, 16, 24): a batch uses the value of its largest
+    ny, so grids with another value compose their scans differently."""
+    lanes = 64 if ny > 768 else 32
+    need = -(-ny // lanes)
+    return next(k for k in (2, 4, 8, 12, 16, 24) if k >= need)
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def batch_case(count=64, seed=4, precision="fp64", max_iters=4):
+    grids = synth.batch_grids(seed=seed, count=count)
+    plans, rhs, fs = [], [], []
+    for gd in grids:
+        yf = synth.tanh_faces(gd["ny"], gd["beta"])
+        g = geometry(gd["nx"], gd["ny"], gd["nz"], gd["Lx"], gd["Lz"], yf)
+        u, v, w = synth.uniform_velocity(gd["nx"], gd["ny"], gd["nz"], seed=gd["seed"])
+        f = divergence(u, v, w, g)
+        fs.append((f, yf))
+        plans.append(ibp.Plan(gd["nx"], gd["ny"], gd["nz"], gd["Lx"], gd["Lz"], yf,
+                              precision=precision, max_iters=max_iters))
+        rhs.append(to_dev(f))
+    return grids, plans, rhs, fs
+
+
+@pytest.fixture(scope="module")
+def c4():
+    return batch_case()
+
+
+def test_batched_fp64_matches_single_and_oracle(c4):
+    """64 uneven grids in one launch per stage: every grid within 1e-12 of
+    its single solve, bitwise where the single solve uses the same
+    arithmetic (mixed-radix transforms and the batch's rows per lane), and
+    within 1e-12 of the oracle on 8 grids."""
+    grids, plans, rhs, fs = c4
+    phis = [torch.empty_like(r) for r in rhs]
+    ibp.solve_batched(plans, rhs, phis)
+    torch.cuda.synchronize()
+    kb = line_solve_rows(max(gd["ny"] for gd in grids))
+    same = 0
+    for i, (p, r) in enumerate(zip(plans, rhs)):
+        single = p.solve(r)
+        gd = grids[i]
+        assert float(torch.linalg.vector_norm(single - phis[i]) / torch.linalg.vector_norm(single)) <= TOL64, i
+        if gd["nx"] // 2 not in REG_LENGTHS and gd["nz"] not in REG_LENGTHS and line_solve_rows(gd["ny"]) == kb:
+            same += 1
+            assert torch.equal(single, phis[i]), f"grid {i}: batched differs from single"
+    assert same >= 3
+    for i in range(0, 64, 8):
+        f, yf = fs[i]
+        gd = grids[i]
+        ref, _ = oracle.solve(f, gd["Lx"], gd["Lz"], yf)
+        assert rel(phis[i].cpu().numpy(), ref) <= TOL64, (i, gd)
+
+
+def test_batch_object_graph_and_ycols(c4):
+    """The explicit batch gives the cached path's bits, under graph capture
+    (every replay) and for every line-solve column count."""
+    grids, plans, rhs, _ = c4
+    ref = [torch.empty_like(r) for r in rhs]
+    ibp.solve_batched(plans, rhs, ref)
+    b = ibp.Batch(plans)
+    out = b.solve(rhs)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, c) for a, c in zip(ref, out))
+    for cols in (2, 4, 16, 8):
+        b.set_ycols(cols)
+        out = b.solve(rhs)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, c) for a, c in zip(ref, out)), cols
+    inp = [r.clone() for r in rhs]
+    outg = [torch.empty_like(r) for r in rhs]
+    b.solve(inp, outg)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.solve(inp, outg)
+    for k in range(3):
+        scale = float(2 ** (k + 1))   # powers of two scale every intermediate exactly
+        for a, r in zip(inp, rhs):
+            a.copy_(r * scale)
+        for o in outg:
+            o.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(rhs)):
+            assert torch.equal(outg[i], ref[i] * scale), (k, i)
+    b.close()
+
+
+def test_batched_mixed_converges_per_grid():
+    grids, plans, rhs, fs = batch_case(count=24, seed=9, precision="mixed", max_iters=6)
+    phis = [torch.empty_like(r) for r in rhs]
+    ibp.solve_batched(plans, rhs, phis)
+    torch.cuda.synchronize()
+    for i, p in enumerate(plans):
+        info = p.info()
+        assert info["converged"] == 1 and info["rel_residual"] <= 1e-10, (i, info)
+    for i in range(0, 24, 6):
+        f, yf = fs[i]
+        gd = grids[i]
+        ref, _ = oracle.solve(f, gd["Lx"], gd["Lz"], yf)
+        assert rel(phis[i].cpu().numpy(), ref) <= 1e-8, (i, gd)
+
+
+def test_batched_more_than_max_and_stale_batch():
+    """70 grids run as a batch of 64 and a batch of 6; a batch whose plan
+    changed precision refuses to run; a mixed-precision sequence falls back
+    to one solve after another."""
+    grids, plans, rhs, _ = batch_case(count=70, seed=11)
+    phis = ibp.solve_batched(plans, rhs, [torch.empty_like(r) for r in rhs])
+    torch.cuda.synchronize()
+    for i in (0, 63, 64, 69):
+        single = plans[i].solve(rhs[i])
+        assert float(torch.linalg.vector_norm(single - phis[i]) / torch.linalg.vector_norm(single)) <= TOL64
+    b = ibp.Batch(plans[:4])
+    plans[1].set_precision("mixed", 1e-10, 4)
+    with pytest.raises(ibp.IbpError) as e:
+        b.solve(rhs[:4])
+    assert e.value.status == ibp.INVALID_VALUE
+    b.close()
+    out = ibp.solve_batched(plans[:4], rhs[:4], [torch.empty_like(r) for r in rhs[:4]])   # loop fallback
+    torch.cuda.synchronize()
+    for i in range(4):
+        assert plans[i].info()["converged"] == 1
+        assert torch.isfinite(out[i]).all()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autotune_is_bitwise_neutral(precision):
+    """Autotuning picks work splits by timing; the solution bits do not
+    depend on the choice (single plans and batches)."""
+    grids, plans, rhs, _ = batch_case(count=12, seed=13, precision=precision)
+    ref = [p.solve(r) for p, r in zip(plans, rhs)]
+    torch.cuda.synchronize()
+    for p, r, a in zip(plans[:4], rhs[:4], ref[:4]):
+        t = p.autotune(r)
+        assert t["tried"] >= 5 and t["ms"] > 0 and t["ycols"] in (0, 2, 4, 8, 16)   # 0: default shape kept
+        assert torch.equal(p.solve(r), a)
+    b = ibp.Batch(plans)
+    before = b.solve(rhs)
+    t = b.autotune(rhs)
+    assert t["tried"] >= 13 and t["ms"] <= t["ms_before"] * 1.5
+    if precision == "mixed":
+        assert t["xdiv"] == 1
+    after = b.solve(rhs)
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(before, after))
+    b.close()

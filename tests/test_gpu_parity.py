@@ -253,32 +253,6 @@ def test_mixed_nonconvergence_reported():
     assert info["rel_residual"] > 0
 
 
-# ---------------------------------------------------------------- batched
-def test_batched_matches_single_and_oracle():
-    grids = synth.batch_grids(seed=4, count=64)
-    plans, rhs, ref_idx = [], [], list(range(0, 64, 8))
-    fs = []
-    for gd in grids:
-        yf = synth.tanh_faces(gd["ny"], gd["beta"])
-        g = geometry(gd["nx"], gd["ny"], gd["nz"], gd["Lx"], gd["Lz"], yf)
-        u, v, w = synth.uniform_velocity(gd["nx"], gd["ny"], gd["nz"], seed=gd["seed"])
-        f = divergence(u, v, w, g)
-        fs.append((f, yf))
-        plans.append(ibp.Plan(gd["nx"], gd["ny"], gd["nz"], gd["Lx"], gd["Lz"], yf))
-        rhs.append(to_dev(f))
-    phis = [torch.empty_like(r) for r in rhs]
-    ibp.solve_batched(plans, rhs, phis)
-    torch.cuda.synchronize()
-    for i, (p, r) in enumerate(zip(plans, rhs)):
-        single = p.solve(r)
-        assert torch.equal(single, phis[i]), f"grid {i}: batched differs from single"
-    for i in ref_idx:
-        f, yf = fs[i]
-        gd = grids[i]
-        ref, _ = oracle.solve(f, gd["Lx"], gd["Lz"], yf)
-        assert rel(phis[i].cpu().numpy(), ref) <= TOL64, (i, gd)
-
-
 # ---------------------------------------------------------------- full size
 def cdft(a, ex, ez):
     """sum_{k,i} a[:, k, i] ex[i] ez[k] with real matrix-vector products only
