@@ -13,12 +13,13 @@ What it computes (paper: "Fluid Mechanics" subsection, eqs. ``velsolen``,
 * the second-order staggered discrete operators D (divergence), G (gradient)
   and L_h = D G on a grid uniform and periodic in x and z and non-uniform in
   y, with homogeneous Neumann conditions for the pressure correction at the
-  two y walls (``operators``);
+  two y walls (``operators``), or a homogeneous Dirichlet condition at either
+  wall (the ``neumann_velocity`` outlet option uses it at the upper wall);
 * the unique discrete solution of L_h phi = f - m with volume-weighted mean
   zero, where m is the volume-weighted mean of f, computed by real FFT in x,
   complex FFT in z, one tridiagonal system per horizontal Fourier mode along y,
   flux integration for the singular (0,0) mode, and the inverse FFTs
-  (``poisson``);
+  (``poisson``); with a Dirichlet wall, the solution of L_h phi = f;
 * independent pins: a dense bordered solve (``dense``), an exact rational
   bordered solve (``exact``) and manufactured solutions built from the
   discrete y eigenvectors (``manufactured``).

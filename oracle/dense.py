@@ -47,6 +47,11 @@ def laplacian_matrix(g):
                     t = 1 / (g.dyf[j] * (g.yc[j] - g.yc[j - 1]))
                     A[r, _index(j - 1, k, i, nz, nx)] += t
                     A[r, r] -= t
+                # Dirichlet wall: phi = 0 on the wall face, half a cell away
+                if j == 0 and g.bc[0] == "dirichlet":
+                    A[r, r] -= 1 / (g.dyf[0] * (g.yc[0] - g.yf[0]))
+                if j == ny - 1 and g.bc[1] == "dirichlet":
+                    A[r, r] -= 1 / (g.dyf[ny - 1] * (g.yf[ny] - g.yc[ny - 1]))
     return A
 
 
@@ -61,11 +66,14 @@ def bordered_matrix(g):
     return B
 
 
-def dense_solve(f, Lx, Lz, yf):
-    """Returns (phi, mu) from the bordered dense system (LAPACK gesv)."""
+def dense_solve(f, Lx, Lz, yf, bc=("neumann", "neumann")):
+    """Returns (phi, mu) from the bordered dense system (LAPACK gesv); with a
+    Dirichlet wall L_h is non-singular and is solved directly (mu = 0)."""
     f = np.asarray(f, dtype=np.float64)
     ny, nz, nx = f.shape
-    g = geometry(nx, ny, nz, Lx, Lz, yf)
+    g = geometry(nx, ny, nz, Lx, Lz, yf, bc=bc)
+    if not g.singular:
+        return np.linalg.solve(laplacian_matrix(g), f.ravel()).reshape(ny, nz, nx), 0.0
     B = bordered_matrix(g)
     rhs = np.concatenate([f.ravel(), [0.0]])
     sol = np.linalg.solve(B, rhs)

@@ -30,19 +30,33 @@ class Geometry:
     dyf: np.ndarray   # (ny,)   cell widths yf[j+1] - yf[j]
     yc: np.ndarray    # (ny,)   cell centres
     dyc: np.ndarray   # (ny+1,) centre distances; dyc[j] = yc[j] - yc[j-1] for 1 <= j <= ny-1, walls unused (nan)
-    a: np.ndarray     # (ny,) sub-diagonal of the y operator (a[0] = 0: Neumann wall)
+    a: np.ndarray     # (ny,) wall-side face coefficient of row j (a[0]: lower wall, 0 if Neumann)
     b: np.ndarray     # (ny,) diagonal, -(a + c)
-    c: np.ndarray     # (ny,) super-diagonal (c[ny-1] = 0: Neumann wall)
+    c: np.ndarray     # (ny,) upper face coefficient (c[ny-1]: upper wall, 0 if Neumann)
+    bc: tuple = ("neumann", "neumann")   # (lower wall, upper wall) condition on phi
+
+    @property
+    def singular(self):
+        """Neumann at both walls: L_h has the constants as null space."""
+        return self.bc == ("neumann", "neumann")
 
 
-def geometry(nx, ny, nz, Lx, Lz, yf, dtype=np.float64):
+BCS = ("neumann", "dirichlet")
+
+
+def geometry(nx, ny, nz, Lx, Lz, yf, dtype=np.float64, bc=("neumann", "neumann")):
     """Grid spacings and the coefficients of the 1-D y operator.
 
     The y part of L_h at cell j is the difference of the two face fluxes
     (phi[j+1]-phi[j])/dyc[j+1] and (phi[j]-phi[j-1])/dyc[j], divided by the
-    cell width dyf[j]; a wall face carries zero flux (homogeneous Neumann
-    condition for the pressure correction, paper's boundary-condition
-    paragraph after eq. ``pressure``).
+    cell width dyf[j].  Wall faces (paper's boundary-condition paragraph after
+    eq. ``pressure``):
+    * "neumann" (the default configuration): zero flux, so a[0] = 0 or
+      c[ny-1] = 0;
+    * "dirichlet" (the ``neumann_velocity`` outlet option, applied to the
+      upper wall there): phi = 0 on the wall face, half a cell from the
+      centre, so the wall flux is (0 - phi[0]) / (dyf[0] / 2) and
+      a[0] = 2 / dyf[0]^2 (likewise c[ny-1] = 2 / dyf[ny-1]^2).
     """
     nx, ny, nz = int(nx), int(ny), int(nz)
     if nx < 1 or nz < 1 or ny < 2:
@@ -56,6 +70,9 @@ def geometry(nx, ny, nz, Lx, Lz, yf, dtype=np.float64):
     Lz = dtype(Lz)
     if not (np.isfinite(Lx) and np.isfinite(Lz) and Lx > 0 and Lz > 0):
         raise ValueError("Lx and Lz must be finite and positive")
+    bc = tuple(bc)
+    if len(bc) != 2 or any(w not in BCS for w in bc):
+        raise ValueError(f"bc must be two of {BCS}")
     dx = Lx / nx
     dz = Lz / nz
     dyf = yf[1:] - yf[:-1]
@@ -69,8 +86,12 @@ def geometry(nx, ny, nz, Lx, Lz, yf, dtype=np.float64):
             a[j] = 1 / (dyf[j] * dyc[j])
         if j < ny - 1:
             c[j] = 1 / (dyf[j] * dyc[j + 1])
+    if bc[0] == "dirichlet":
+        a[0] = 1 / (dyf[0] * (dyf[0] / 2))
+    if bc[1] == "dirichlet":
+        c[ny - 1] = 1 / (dyf[ny - 1] * (dyf[ny - 1] / 2))
     b = -(a + c)
-    return Geometry(nx, ny, nz, Lx, Lz, dx, dz, yf, dyf, yc, dyc, a, b, c)
+    return Geometry(nx, ny, nz, Lx, Lz, dx, dz, yf, dyf, yc, dyc, a, b, c, bc)
 
 
 def lambda_x(g, dtype=np.float64):

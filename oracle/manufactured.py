@@ -24,9 +24,10 @@ from .operators import laplacian
 
 
 def y_eigenpairs(g):
-    """Eigenpairs (mu_p, v_p) of the Neumann y operator, p = 0..ny-1, with
-    mu_0 = 0 (constant mode) and mu decreasing; v_p scaled to max-norm 1 with
-    v_p[0] > 0."""
+    """Eigenpairs (mu_p, v_p) of the y operator, p = 0..ny-1, mu decreasing
+    (mu_0 = 0, the constant mode, with Neumann walls); v_p scaled to max-norm
+    1 with v_p[0] > 0 (v_p[argmax] > 0 when a Dirichlet lower wall makes
+    v_p[0] small)."""
     ny = g.ny
     s = np.sqrt(g.dyf)
     # K[j, j+1] = 1 / dyc[j+1]; diagonal of K = -(sum of the two face terms)
@@ -34,6 +35,11 @@ def y_eigenpairs(g):
     kdiag = np.zeros(ny)
     kdiag[:-1] -= off
     kdiag[1:] -= off
+    # a Dirichlet wall adds the wall-face term 1 / (half cell) to its row
+    if g.bc[0] == "dirichlet":
+        kdiag[0] -= 1.0 / (g.yc[0] - g.yf[0])
+    if g.bc[1] == "dirichlet":
+        kdiag[-1] -= 1.0 / (g.yf[ny] - g.yc[ny - 1])
     d = kdiag / g.dyf
     e = off / (s[:-1] * s[1:])
     mu, U = eigh_tridiagonal(d, e)
@@ -41,17 +47,21 @@ def y_eigenpairs(g):
     mu = mu[order]
     V = U[:, order] / s.reshape(-1, 1)
     V = V / np.abs(V).max(axis=0, keepdims=True)
-    V = V * np.where(V[0] < 0, -1.0, 1.0)
-    mu[0] = 0.0
+    if g.singular:
+        V = V * np.where(V[0] < 0, -1.0, 1.0)
+        mu[0] = 0.0
+    else:
+        pick = V[np.argmax(np.abs(V), axis=0), np.arange(ny)]
+        V = V * np.where(pick < 0, -1.0, 1.0)
     return mu, V
 
 
-def manufactured_field(nx, ny, nz, Lx, Lz, yf, modes):
+def manufactured_field(nx, ny, nz, Lx, Lz, yf, modes, bc=("neumann", "neumann")):
     """phi*[ny,nz,nx] and f = L_h phi* (longdouble, rounded to FP64).
 
     ``modes`` is an iterable of (kx, kz, p, amplitude, phase) with integer
     index wavenumbers kx, kz and y-mode index p."""
-    g = geometry(nx, ny, nz, Lx, Lz, yf)
+    g = geometry(nx, ny, nz, Lx, Lz, yf, bc=bc)
     _, V = y_eigenpairs(g)
     x = (np.arange(nx) + 0.5) * g.dx
     z = (np.arange(nz) + 0.5) * g.dz
@@ -60,6 +70,6 @@ def manufactured_field(nx, ny, nz, Lx, Lz, yf, modes):
         arg = (2 * np.pi * kx / Lx) * x.reshape(1, -1) + (2 * np.pi * kz / Lz) * z.reshape(-1, 1) + th
         phi += amp * np.cos(arg)[None, :, :] * V[:, int(p)].reshape(-1, 1, 1)
     gl = geometry(nx, ny, nz, np.longdouble(Lx), np.longdouble(Lz),
-                  np.asarray(yf, dtype=np.longdouble), dtype=np.longdouble)
+                  np.asarray(yf, dtype=np.longdouble), dtype=np.longdouble, bc=bc)
     f = laplacian(phi.astype(np.longdouble), gl).astype(np.float64)
     return phi, f

@@ -45,9 +45,10 @@ def laplacian(phi, g):
     """7-point staggered Laplacian L_h phi, written out stencil by stencil.
 
     x and z: periodic second differences; y: the difference of the two face
-    fluxes, a[j] (phi[j-1] - phi[j]) + c[j] (phi[j+1] - phi[j]), with
-    a[0] = c[ny-1] = 0 (the diagonal b = -(a + c) is not formed, so no
-    rounding of it enters the operator).  Works in any float dtype
+    fluxes, a[j] (phi[j-1] - phi[j]) + c[j] (phi[j+1] - phi[j]), where the
+    value beyond a wall is the wall value 0 (Dirichlet wall; a Neumann wall
+    has a[0] = 0 or c[ny-1] = 0, so it carries no flux).  The diagonal
+    b = -(a + c) is not formed, so no rounding of it enters the operator.  Works in any float dtype
     (``numpy.longdouble`` for manufactured right-hand sides) provided the
     geometry was built in that dtype.
     """
@@ -58,6 +59,10 @@ def laplacian(phi, g):
     ylap = np.zeros_like(phi)
     ylap[1:] += a[1:] * (phi[:-1] - phi[1:])
     ylap[:-1] += c[:-1] * (phi[1:] - phi[:-1])
+    if g.bc[0] == "dirichlet":
+        ylap[0] += a[0] * (0 - phi[0])
+    if g.bc[1] == "dirichlet":
+        ylap[-1] += c[-1] * (0 - phi[-1])
     return out + ylap
 
 
