@@ -95,6 +95,21 @@ ibp_status_t ibp_plan_create(ibp_plan_t* plan, int nx, int ny, int nz, double Lx
  * with this plan is still running. */
 ibp_status_t ibp_plan_destroy(ibp_plan_t plan);
 
+/* Wall condition of the pressure correction at a y wall.  The paper's
+ * default configuration has homogeneous Neumann conditions at both walls
+ * (boundary-condition paragraph after eq. ``pressure``): then L_h is
+ * singular, the volume-weighted mean of rhs is removed (ibp_info_t.removed_mean)
+ * and phi has zero volume-weighted mean.  Its ``neumann_velocity`` outlet
+ * option gives the upper wall a homogeneous Dirichlet condition (phi = 0 on
+ * the wall face, half a cell from the nearest centre); with a Dirichlet wall
+ * the problem is non-singular, nothing is removed and phi is unique. */
+typedef enum { IBP_BC_NEUMANN = 0, IBP_BC_DIRICHLET = 1 } ibp_bc_t;
+
+/* Set the conditions at the lower (y = y_nodes[0]) and upper wall; a new
+ * plan has Neumann at both.  Rewrites the plan's coefficient tables
+ * (synchronous); batches built on the plan must be rebuilt. */
+ibp_status_t ibp_plan_set_bc(ibp_plan_t plan, ibp_bc_t lower, ibp_bc_t upper);
+
 /* Select the precision form.  rtol: relative residual target of the mixed
  * forms (> 0, e.g. 1e-10); max_iters: maximum refinement corrections after
  * the initial FP32 solve, 0..64.  Both are ignored for IBP_FP64. */

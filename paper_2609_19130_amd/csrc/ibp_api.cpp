@@ -112,7 +112,10 @@ struct ibp_plan_s {
   Ctl* ctl = nullptr;
   hipStream_t last_stream = nullptr;
   bool solved = false;
-  unsigned gen = 0;   // bumped when the precision or the workspace changes (batches check it)
+  unsigned gen = 0;   // bumped when the precision, workspace or wall conditions change (batches check it)
+  ibp_bc_t bc_lo = IBP_BC_NEUMANN, bc_hi = IBP_BC_NEUMANN;
+  std::vector<double> ya_host, yc_host, dyf_host;   // Neumann face coefficients and cell widths
+  bool singular() const { return bc_lo == IBP_BC_NEUMANN && bc_hi == IBP_BC_NEUMANN; }
   // chunked x/z passes: second stream and dependency events
   int chunk = 0;                   // y planes per chunk (0: whole grid per launch)
   hipStream_t s2 = nullptr;
@@ -425,6 +428,9 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
       if (j > 0) a[j] = 1.0 / (dyf[j] * dyc[j]);
       if (j < ny - 1) c[j] = 1.0 / (dyf[j] * dyc[j + 1]);
     }
+    p->ya_host = a;
+    p->yc_host = c;
+    p->dyf_host = dyf;
     // ---- closed-form eigenvalues of the periodic second differences
     const long double pi = 3.141592653589793238462643383279502884L;
     std::vector<double> lx(p->hp), lz(nz);
@@ -577,6 +583,33 @@ ibp_status_t ibp_plan_set_precision(ibp_plan_t p, ibp_precision_t prec, double r
   p->prec = prec;
   ++p->gen;
   return IBP_SUCCESS;
+}
+
+ibp_status_t ibp_plan_set_bc(ibp_plan_t p, ibp_bc_t lower, ibp_bc_t upper) {
+  if (!valid_plan(p)) return IBP_ERROR_INVALID_VALUE;
+  if ((lower != IBP_BC_NEUMANN && lower != IBP_BC_DIRICHLET) || (upper != IBP_BC_NEUMANN && upper != IBP_BC_DIRICHLET))
+    return IBP_ERROR_INVALID_VALUE;
+  try {
+    const int ny = p->ny;
+    std::vector<double> a = p->ya_host, c = p->yc_host;
+    // a Dirichlet wall: phi = 0 on the wall face, half a cell from the centre
+    if (lower == IBP_BC_DIRICHLET) a[0] = 1.0 / (p->dyf_host[0] * (0.5 * p->dyf_host[0]));
+    if (upper == IBP_BC_DIRICHLET) c[ny - 1] = 1.0 / (p->dyf_host[ny - 1] * (0.5 * p->dyf_host[ny - 1]));
+    const float a32[2] = {(float)a[0], (float)a[ny - 1]};
+    const float c32[2] = {(float)c[0], (float)c[ny - 1]};
+    // only the two wall rows of each table change
+    hipError_t e = hipMemcpy((void*)p->ya, a.data(), sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy((void*)(p->yc + ny - 1), &c[ny - 1], sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy((void*)p->ya32, &a32[0], sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy((void*)(p->yc32 + ny - 1), &c32[1], sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return from_hip(e);
+    p->bc_lo = lower;
+    p->bc_hi = upper;
+    ++p->gen;
+    return IBP_SUCCESS;
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
 }
 
 ibp_status_t ibp_plan_workspace_size(ibp_plan_t p, size_t* bytes) {
@@ -797,6 +830,7 @@ ZeroArgs zargs(ibp_plan_s* p, long nparts, int init, int mixed, int iter, int fi
   z.final_pass = final_pass;
   z.rtol = p->rtol;
   z.dyf_sum = p->dyf_sum;
+  z.singular = p->singular();
   return z;
 }
 
@@ -964,7 +998,7 @@ ibp_status_t enqueue_solve(ibp_plan_s* p, const double* rhs, double* phi, hipStr
   if (st != IBP_SUCCESS) return st;
   YArgs<double, double> ya{p->spec64, p->lamx, p->lamz, p->ya, p->yc, p->ctl,
                            (long)p->nz * spec_row_stride<double>(p->hp), spec_row_stride<double>(p->hp),
-                           spec_plane_stride<double>(p->hp, p->nz), p->ny, p->hp, 0};
+                           spec_plane_stride<double>(p->hp, p->nz), p->ny, p->hp, 0, p->singular()};
   IBP_LAUNCH(P_Y, launch_ytri<double, double>(p->yP, p->yK, p->ycols, ya, zargs(p, 0, 1, 0, 0, 0), s));
   return inverse_zx<double>(p, xa, CM_SET, P_XC2R, za, s);
 }
@@ -989,7 +1023,7 @@ ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStr
   const long rs = spec_row_stride<float>(p->hp), ps = spec_plane_stride<float>(p->hp, p->nz);
   const long Q = (long)p->nz * rs;
   ZfArgs<float> za{p->spec32, p->twz32, p->ctl, p->fpz, p->nz, p->hp, p->zc32, rs, ps, 0, 0};
-  YArgs<float, U> ya{p->spec32, lx, lz, ca, cc, p->ctl, Q, rs, ps, p->ny, p->hp, 0};
+  YArgs<float, U> ya{p->spec32, lx, lz, ca, cc, p->ctl, Q, rs, ps, p->ny, p->hp, 0, p->singular()};
 
   XArgs<float> xa = xargs<float>(p, rhs, phi, phi, p->spec32, p->twx32, p->rb32, 0);
   ibp_status_t st = forward_xz<float>(p, xa, XM_PLAIN, P_XR2C, za, s);
@@ -1160,7 +1194,7 @@ ibp_status_t batch_build(ibp_batch_s* b) {
     const long rs = spec_row_stride<T>(p->hp), ps = spec_plane_stride<T>(p->hp, p->nz);
     d.z = ZfArgs<T>{spec, twz, p->ctl, p->fpz, p->nz, p->hp, cols, rs, ps, 0, 0};
     d.y = YArgs<T, T>{spec, lx, lz, dtab + (size_t)g * 2 * PK, dtab + (size_t)g * 2 * PK + PK, p->ctl,
-                      (long)p->nz * rs, rs, ps, p->ny, p->hp, 0};
+                      (long)p->nz * rs, rs, ps, p->ny, p->hp, 0, p->singular()};
     d.zero = zargs(p, 0, 0, 0, 0, 0);
     d.zero.part = part;
   }

@@ -96,6 +96,7 @@ struct YArgs {
   long Q;                // nz * rs column slots (kx >= hp are padding)
   long rs, ps;           // spectrum row and plane strides (elements)
   int ny, hp, check_done;
+  int singular;          // Neumann at both walls: column (0,0) is left to the FP64 (0,0) path
 };
 
 struct ZeroArgs {        // FP64 (0,0) mode and solve control
@@ -115,6 +116,7 @@ struct ZeroArgs {        // FP64 (0,0) mode and solve control
   int final_pass;
   double rtol;
   double dyf_sum;        // sum_j dyf_j
+  int singular;          // Neumann at both walls: remove the mean, solve (0,0) by flux integration
 };
 
 // Fused x/z pass (persistent).  The y planes are dealt out to one work

@@ -91,7 +91,7 @@ __device__ __forceinline__ void zero_mode_scans(const ZeroArgs& Z, const double 
   dsum = wave_total(dsum);
   bad = wave_total(bad);
   const double nxnz = double(Z.nx) * double(Z.nz);
-  const double m = wsum / (dsum * nxnz);
+  const double m = Z.singular ? wsum / (dsum * nxnz) : 0.0;
   // flux at the lower face of every cell of the chunk
   double loc = 0.0;
 #pragma unroll
@@ -128,9 +128,9 @@ __device__ __forceinline__ void zero_mode_scans(const ZeroArgs& Z, const double 
   xw = wave_total(xw);
   const double xbar = xw / dsum;
 #pragma unroll
-  for (int c = 0; c < CHM; ++c) {
+  for (int c = 0; c < CHM; ++c) {   // with a Dirichlet wall (0,0) goes through the line solve
     const int j = j0 + c;
-    if (c < CH && j < ny) Z.phi00[j] = g[c] - xbar;
+    if (c < CH && j < ny) Z.phi00[j] = Z.singular ? g[c] - xbar : 0.0;
   }
   if (Z.init && lane == 0) {
     Ctl* c = Z.ctl;
@@ -189,7 +189,7 @@ __device__ __forceinline__ void zero_mode_plane(const ZeroArgs& Z, int j) {
 // FP32).  A column's rows are split into P partitions of K rows, one per
 // lane of a P-lane group inside one wave; the three recurrences are composed
 // per partition (eps by 2x2 Moebius matrices with non-negative entries, d'
-// and X by affine maps with coefficients in [0, 1]), chained across the
+// and X by affine maps), chained across the
 // partitions with wave shuffles (Hillis-Steele), and each lane re-sweeps its
 // K rows.  The block's M columns are staged through LDS so that global loads
 // and stores are M * element-size contiguous bytes per row.
@@ -253,7 +253,8 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
   const int kx = q < Q ? (int)(q - (long)kz * A.rs) : 0;
   const bool valid = q < Q && kx < A.hp;   // row padding slots are not solved
   U L = valid ? -(A.lamx[kx] + A.lamz[kz]) : U(1);
-  if (q == 0) L = U(1);   // (0,0) is singular: solved in FP64 by the plane blocks, zeroed here
+  const bool zero = A.singular && q == 0;
+  if (zero) L = U(1);   // singular (0,0): solved in FP64 by the plane blocks, zeroed here
   const int s = p * K;
   Cx<T>* my = tile + m * LS + p * KS;
 
@@ -274,34 +275,44 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
   const U c_ = cc[i];           \
   const U l_ = cl[i];
 
-  // ---- scan 1: eps_out = (mA eps_in + mB) / (mC eps_in + 1) over the partition
-  U mA = U(1), mB = U(0), mC = U(0);
+  // ---- scan 1: eps_out = (mA eps_in + mB) / (mC eps_in + mD) over the
+  // partition, all entries >= 0, normalised to mC + mD = 1 (the denominator
+  // at eps_in = 1, positive for every row; the constant term mD alone can
+  // vanish, e.g. rows with shift 0 under a Neumann upper wall)
+  U mA = U(1), mB = U(0), mC = U(0), mD = U(1);
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     IBP_COEF(i, a, c, l)
-    const U n00 = a * mA + l * mC, n01 = a * mB + l;
-    const U n10 = a * mA + (c + l) * mC, n11 = a * mB + (c + l);
-    const U inv = U(1) / n11;
+    const U n00 = a * mA + l * mC, n01 = a * mB + l * mD;
+    const U n10 = a * mA + (c + l) * mC, n11 = a * mB + (c + l) * mD;
+    const U inv = U(1) / (n10 + n11);
     mA = n00 * inv;
     mB = n01 * inv;
     mC = n10 * inv;
+    mD = n11 * inv;
   }
 #pragma unroll
   for (int off = 1; off < P; off <<= 1) {   // inclusive prefix: mine after the earlier ones
-    const U pA = shfl_up_w(mA, off, P), pB = shfl_up_w(mB, off, P), pC = shfl_up_w(mC, off, P);
+    const U pA = shfl_up_w(mA, off, P), pB = shfl_up_w(mB, off, P);
+    const U pC = shfl_up_w(mC, off, P), pD = shfl_up_w(mD, off, P);
     if (p >= off) {
-      const U n00 = mA * pA + mB * pC, n01 = mA * pB + mB;
-      const U n10 = mC * pA + pC, n11 = mC * pB + U(1);
-      const U inv = U(1) / n11;
+      const U n00 = mA * pA + mB * pC, n01 = mA * pB + mB * pD;
+      const U n10 = mC * pA + mD * pC, n11 = mC * pB + mD * pD;
+      const U inv = U(1) / (n10 + n11);
       mA = n00 * inv;
       mB = n01 * inv;
       mC = n10 * inv;
+      mD = n11 * inv;
     }
   }
   U rD[K];
   {
-    U e = shfl_up_w(mB, 1, P);     // eps entering the partition: earlier composite applied to 0
-    if (p == 0) e = U(0);
+    // eps entering the partition: the earlier composite applied to
+    // eps_{-1} = 1 (the value beyond the lower wall does not depend on X_0)
+    const U eA = shfl_up_w(mA, 1, P), eB = shfl_up_w(mB, 1, P);
+    const U eC = shfl_up_w(mC, 1, P), eD = shfl_up_w(mD, 1, P);
+    U e = (eA + eB) / (eC + eD);
+    if (p == 0) e = U(1);
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       IBP_COEF(i, a, c, l)
@@ -377,7 +388,6 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
     }
   }
 #undef IBP_COEF
-  const bool zero = (q == 0);
 #pragma unroll
   for (int i = 0; i < K; ++i) my[i] = zero ? Cx<T>{T(0), T(0)} : Cx<T>{T(d[i].x), T(d[i].y)};
   __syncthreads();
@@ -426,7 +436,9 @@ __device__ __forceinline__ void check_body(const ZeroArgs& Z, double* sh) {
   c->fnorm2 = p[1];
   c->rmax = p[2];
   c->rel_residual = rel;
-  c->phimean = p[4] / (Z.dyf_sum * double(Z.nx) * double(Z.nz));
+  // the mean of a Neumann-Neumann iterate is fixed to zero; with a
+  // Dirichlet wall the solution's mean is part of it
+  c->phimean = Z.singular ? p[4] / (Z.dyf_sum * double(Z.nx) * double(Z.nz)) : 0.0;
   if (p[3] > 0.0) c->nonfinite = 1;
   if (Z.final_pass || !(rel > Z.rtol)) {
     c->done = 1;

@@ -63,6 +63,7 @@ def lib():
         "ibp_plan_create": (ci, [ctypes.POINTER(vp), ci, ci, ci, cd, cd, ctypes.POINTER(cd)]),
         "ibp_plan_destroy": (ci, [vp]),
         "ibp_plan_set_precision": (ci, [vp, ci, cd, ci]),
+        "ibp_plan_set_bc": (ci, [vp, ci, ci]),
         "ibp_plan_workspace_size": (ci, [vp, ctypes.POINTER(cs)]),
         "ibp_plan_set_workspace": (ci, [vp, vp, cs]),
         "ibp_solve": (ci, [vp, vp, vp, vp]),
@@ -124,7 +125,8 @@ class Plan:
     """One grid: nx, ny, nz pressure cells, periodic lengths Lx, Lz and the
     ny+1 wall-normal face coordinates ``y_nodes`` (host array)."""
 
-    def __init__(self, nx, ny, nz, Lx, Lz, y_nodes, precision="fp64", rtol=1e-10, max_iters=4):
+    def __init__(self, nx, ny, nz, Lx, Lz, y_nodes, precision="fp64", rtol=1e-10, max_iters=4,
+                 bc=("neumann", "neumann")):
         L = lib()
         y = [float(v) for v in y_nodes]
         if len(y) != ny + 1:
@@ -136,6 +138,9 @@ class Plan:
         self._h = h
         self.shape = (int(ny), int(nz), int(nx))
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.bc = ("neumann", "neumann")
+        if tuple(bc) != self.bc:
+            self.set_bc(*bc)
         self.set_precision(precision, rtol, max_iters)
 
     @property
@@ -143,6 +148,12 @@ class Plan:
         if self._h is None:
             raise RuntimeError("plan destroyed")
         return self._h
+
+    def set_bc(self, lower="neumann", upper="neumann"):
+        """Wall conditions of the pressure correction ("neumann" or "dirichlet")."""
+        code = {"neumann": 0, "dirichlet": 1}
+        _check(lib().ibp_plan_set_bc(self.handle, code[lower], code[upper]), "ibp_plan_set_bc")
+        self.bc = (lower, upper)
 
     def set_precision(self, precision, rtol=1e-10, max_iters=4):
         code = PRECISIONS[precision] if isinstance(precision, str) else int(precision)

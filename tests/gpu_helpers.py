@@ -15,11 +15,11 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
-def gpu_solve(f, Lx, Lz, yf, precision="fp64", rtol=1e-10, max_iters=4, plan=None):
+def gpu_solve(f, Lx, Lz, yf, precision="fp64", rtol=1e-10, max_iters=4, plan=None, bc=("neumann", "neumann")):
     ny, nz, nx = f.shape
     own = plan is None
     if own:
-        plan = ibp.Plan(nx, ny, nz, Lx, Lz, yf, precision=precision, rtol=rtol, max_iters=max_iters)
+        plan = ibp.Plan(nx, ny, nz, Lx, Lz, yf, precision=precision, rtol=rtol, max_iters=max_iters, bc=bc)
     fd = to_dev(f)
     phi = plan.solve(fd)
     info = plan.info()
