@@ -31,13 +31,13 @@ and exact-rational solves (see ``tests/test_oracle_pins.py``).
 """
 
 from .grid import Geometry, geometry
-from .operators import divergence, gradient, laplacian
+from .operators import divergence, gradient, laplacian, projection_step, rhs_from_velocity
 from .poisson import solve, solve_modes, thomas_modes, zero_mode_flux_integration
 from .dense import bordered_matrix, dense_solve
 from .manufactured import y_eigenpairs, manufactured_field
 
 __all__ = [
-    "Geometry", "geometry", "divergence", "gradient", "laplacian", "solve",
+    "Geometry", "geometry", "divergence", "gradient", "laplacian", "projection_step", "rhs_from_velocity", "solve",
     "solve_modes", "thomas_modes", "zero_mode_flux_integration",
     "bordered_matrix", "dense_solve", "y_eigenpairs", "manufactured_field",
 ]

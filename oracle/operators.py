@@ -29,16 +29,46 @@ def divergence(u, v, w, g):
 def gradient(phi, g):
     """(G phi) on the faces: returns (gx, gy, gz) laid out like (u, v, w).
 
-    The wall-normal component on the two wall faces is zero: the homogeneous
-    Neumann condition, so that the projection leaves the wall-normal velocity
-    unchanged (paper's boundary-condition paragraph after eq. ``pressure``).
+    On a Neumann wall face the wall-normal component is zero, so that the
+    projection leaves the wall-normal velocity unchanged (paper's
+    boundary-condition paragraph after eq. ``pressure``).  On a Dirichlet
+    wall face (phi = 0 there) it is the one-sided difference over the half
+    cell between the wall and the nearest centre.
     """
     gx = (phi - np.roll(phi, 1, axis=2)) / g.dx
     gz = (phi - np.roll(phi, 1, axis=1)) / g.dz
     gy = np.zeros((g.ny + 1,) + phi.shape[1:], dtype=phi.dtype)
     dyc = g.dyc[1:g.ny].reshape(-1, 1, 1)
     gy[1:g.ny] = (phi[1:] - phi[:-1]) / dyc
+    if g.bc[0] == "dirichlet":
+        gy[0] = (phi[0] - 0) / (g.yc[0] - g.yf[0])
+    if g.bc[1] == "dirichlet":
+        gy[g.ny] = (0 - phi[g.ny - 1]) / (g.yf[g.ny] - g.yc[g.ny - 1])
     return gx, gy, gz
+
+
+def rhs_from_velocity(u, v, w, q, g, alpha_dt):
+    """Right-hand side of the elliptic equation (eq. ``elliptic``):
+    (D u* - q) / (alpha dt); q (mass sources, cell centred) may be None."""
+    d = divergence(u, v, w, g)
+    if q is not None:
+        d = d - q
+    return d / alpha_dt
+
+
+def projection_step(u, v, w, p, phi, g, alpha_dt, visc):
+    """Projection (eq. ``velsolen``) and pressure update (eq. ``pressure``):
+    u_{n+1} = u* - alpha dt G phi, and p_{n+1} = p_n + phi - visc L_h phi with
+    visc = alpha dt / (2 Re) for implicit viscous terms, 0 for explicit ones.
+    Returns new arrays (u, v, w, p); p may be None."""
+    gx, gy, gz = gradient(phi, g)
+    un = u - alpha_dt * gx
+    vn = v - alpha_dt * gy
+    wn = w - alpha_dt * gz
+    pn = None
+    if p is not None:
+        pn = p + phi - visc * laplacian(phi, g)
+    return un, vn, wn, pn
 
 
 def laplacian(phi, g):

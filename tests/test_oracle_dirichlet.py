@@ -138,3 +138,30 @@ def test_dirichlet_pins_catch_planted_mistakes(monkeypatch):
         phi, _ = op.solve(f - f.mean(), Lx, Lz, yf, bc=bc)
         return phi
     assert rel(solve_mean_removed(f + 1.0, 1.0, 1.0, yf, bc), oracle.dense_solve(f + 1.0, 1.0, 1.0, yf, bc=bc)[0]) > 1e-6
+
+
+@pytest.mark.parametrize("bc", [("neumann", "neumann")] + BCS)
+def test_fractional_step_invariants(bc):
+    """One projection substep with mass sources q (eqs. ``velsolen``,
+    ``elliptic``, ``pressure``): after phi solves lap(phi) = (D u* - q)/(alpha dt),
+    the projected velocity satisfies D u_{n+1} = q (plus alpha dt m when a
+    Neumann-Neumann solve removes an incompatible mean m), and the pressure
+    update is p + phi - visc L_h phi.  Holds because L_h = D G also at
+    Dirichlet wall faces."""
+    nx, ny, nz = 12, 10, 8
+    yf = synth.tanh_faces(ny, 2.0)
+    g = geometry(nx, ny, nz, 2 * np.pi, 1.5, yf, bc=bc)
+    u, v, w = synth.uniform_velocity(nx, ny, nz, seed=21)
+    q = np.random.default_rng(22).standard_normal((ny, nz, nx)) * 0.1
+    alpha_dt, visc = 0.037, 0.002
+    f = oracle.rhs_from_velocity(u, v, w, q, g, alpha_dt)
+    phi, m = oracle.solve(f, 2 * np.pi, 1.5, yf, bc=bc)
+    p = np.random.default_rng(23).standard_normal((ny, nz, nx))
+    un, vn, wn, pn = oracle.projection_step(u, v, w, p, phi, g, alpha_dt, visc)
+    div = oracle.divergence(un, vn, wn, g)
+    assert np.abs(div - q - alpha_dt * m).max() <= 1e-12 * np.abs(oracle.divergence(u, v, w, g)).max()
+    if bc[0] == "neumann":
+        assert np.array_equal(vn[0], v[0])
+    if bc[1] == "neumann":
+        assert np.array_equal(vn[ny], v[ny])
+    assert np.allclose(pn, p + phi - visc * laplacian(phi, g), rtol=0, atol=1e-14)
