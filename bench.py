@@ -309,6 +309,7 @@ def main():
     ap.add_argument("--mixed-iters", type=int, default=6)
     ap.add_argument("--forms", default="fp64,mixed,mixed_f64sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-substep", action="store_true", help="skip the fractional-step substep timing")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-launch events (no per-pass breakdown or roofline)")
     ap.add_argument("--cpu-sample", choices=["full", "quarter"], default="full")
@@ -347,7 +348,6 @@ def main():
     ud, vd, wd = (torch.from_numpy(a).cuda() for a in (u, v, w))
     del u, v, w
     f = plan.divergence(ud, vd, wd)
-    del ud, vd, wd
     phi = torch.empty_like(f)
     torch.cuda.synchronize()
 
@@ -366,6 +366,41 @@ def main():
             ms_prof, _, prof = timed_solves(plan, f, phi, args.steps, 0, True)
         results[form] = dict(ms=ms, wall=wall, prof=prof, info=info, ms_prof=ms_prof)
         log(f"[bench] {form}: {ms:.3f} ms/solve, info {info}")
+
+    substep = None
+    if "fp64" in forms and not args.no_substep:
+        # one fractional-step substep around the FP64 solve: right-hand side
+        # from the velocity, solve, projection + pressure update
+        plan.set_precision("fp64")
+        adt = 0.01
+        pr = torch.zeros_like(f)
+        fbuf = torch.empty_like(f)
+
+        def fused():
+            plan.solve_divergence(ud, vd, wd, adt, phi=phi)
+            plan.project(phi, adt, ud, vd, wd, p=pr)
+
+        def unfused():
+            plan.divergence(ud, vd, wd, fbuf)
+            fbuf.mul_(1.0 / adt)
+            plan.solve(fbuf, phi)
+            plan.project(phi, adt, ud, vd, wd, p=pr)
+
+        substep = {}
+        for name, fn in (("fused_rhs", fused), ("separate_divergence", unfused)):
+            for _ in range(2):
+                fn()
+            torch.cuda.synchronize()
+            a0 = torch.cuda.Event(enable_timing=True)
+            b0 = torch.cuda.Event(enable_timing=True)
+            a0.record()
+            for _ in range(args.steps):
+                fn()
+            b0.record()
+            torch.cuda.synchronize()
+            substep[name + "_ms"] = a0.elapsed_time(b0) / args.steps
+        log(f"[bench] substep (rhs + solve + projection): {substep}")
+    del ud, vd, wd
 
     N = nx * ny * nz
     Nh = (nx // 2 + 1) * ny * nz
@@ -408,6 +443,8 @@ def main():
                        "rel_residual": r["info"]["rel_residual"],
                        "vs_fp64": (r64["ms"] / r["ms"]) if r64 else None}
     out["mixed"] = mixed
+    if substep is not None:
+        out["substep_fp64"] = substep
     out["source_hash"] = source_hash()
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline: oracle on the host")

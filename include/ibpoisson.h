@@ -220,6 +220,31 @@ ibp_status_t ibp_get_info(ibp_plan_t plan, ibp_info_t* out);
 ibp_status_t ibp_divergence(ibp_plan_t plan, const double* u, const double* v, const double* w,
                             double* f, void* stream);
 
+/* One substep of the fractional-step method around the solve (paper, eqs.
+ * ``elliptic``, ``velsolen`` and ``pressure``).
+ *
+ * ibp_solve_divergence: solve lap(phi) = (div u* - q) / alpha_dt with the
+ * right-hand side built from the provisional velocity (u, v, w laid out as
+ * for ibp_divergence) and the mass sources q ([ny][nz][nx], NULL for none);
+ * alpha_dt > 0.  With IBP_FP64 and rhs_out == NULL the right-hand side is
+ * assembled inside the first transform pass and never stored (one field
+ * write and read fewer than ibp_divergence + ibp_solve).  Otherwise it is
+ * written to rhs_out ([ny][nz][nx], required for the mixed forms, whose
+ * refinement passes read it again) and solved as by ibp_solve.  Device
+ * pointers, 16-byte aligned; asynchronous on `stream`. */
+ibp_status_t ibp_solve_divergence(ibp_plan_t plan, const double* u, const double* v, const double* w,
+                                  const double* q, double alpha_dt, double* rhs_out, double* phi, void* stream);
+
+/* Projection and pressure update in one pass over the cells:
+ *   u -= alpha_dt * G phi (x, y and z faces; at a Neumann wall the normal
+ *   velocity is unchanged, at a Dirichlet wall G is the one-sided difference
+ *   over the half cell to the wall value 0),
+ *   p += phi - visc * L_h phi   (visc = alpha_dt / (2 Re) with implicit
+ *   viscous terms, 0 with explicit ones; p may be NULL to skip it).
+ * u, v, w, p are updated in place; phi is read.  Asynchronous on `stream`. */
+ibp_status_t ibp_project(ibp_plan_t plan, const double* phi, double alpha_dt, double visc, double* u, double* v,
+                         double* w, double* p, void* stream);
+
 /* Per-pass timing.  While enabled, every kernel launch of ibp_solve is
  * bracketed by two HIP events recorded on the solve's stream (a few
  * microseconds of overhead per launch; not for graph capture). */

@@ -235,7 +235,14 @@ hipError_t xcc_map(int device, XccMap* out) {
 
 bool valid_plan(const ibp_plan_s* p) { return p != nullptr && p->tables != nullptr && p->ws != nullptr; }
 
-ibp_status_t enqueue_solve(ibp_plan_s* p, const double* rhs, double* phi, hipStream_t s);
+// Right-hand side assembled inside the first x pass (FP64 direct solve):
+// f = (D u - q) * rscale is never written to memory.
+struct RhsFromVelocity {
+  const double *u, *v, *w, *q;
+  double rscale;
+};
+ibp_status_t enqueue_solve(ibp_plan_s* p, const double* rhs, double* phi, hipStream_t s,
+                           const RhsFromVelocity* from_u);
 void purge_batch_cache(const ibp_plan_s* p);
 ibp_status_t batched_or_loop(const ibp_plan_t* plans, int count, const double* const* rhs, double* const* phi,
                              hipStream_t s);
@@ -282,12 +289,12 @@ void release(ibp_plan_s* p) {
 
 enum Pass {
   P_XR2C, P_ZFWD, P_Y, P_ZINV, P_XC2R, P_XRES, P_CHECK, P_XRESONLY, P_XC2R_ADD, P_DIV,
-  P_XZF, P_ZXI, P_ZXI_ADD, P_COUNT
+  P_XZF, P_ZXI, P_ZXI_ADD, P_PROJ, P_COUNT
 };
 const char* const kPassName[P_COUNT] = {"x_r2c",  "z_fwd",      "y_solve",    "z_inv",
                                         "x_c2r",  "x_resid_r2c", "check",      "x_resid_only",
                                         "x_c2r_add", "divergence", "xz_fwd",   "zx_inv",
-                                        "zx_inv_add"};
+                                        "zx_inv_add", "projection"};
 
 // Algorithmic bytes of one launch of each pass (each input element read
 // once, each output element written once).  N = nx ny nz cells, Nh =
@@ -309,6 +316,7 @@ double pass_bytes(const ibp_plan_s* p, int pass) {
     case P_XZF: return 8.0 * N + cb * Nh;          // fused: the spectrum makes one trip
     case P_ZXI: return cb * Nh + 8.0 * N;
     case P_ZXI_ADD: return cb * Nh + 16.0 * N;
+    case P_PROJ: return 72.0 * N;                  // phi, u, v, w, p in; u, v, w, p out
     default: return 0.0;
   }
 }
@@ -661,7 +669,7 @@ ibp_status_t ibp_solve(ibp_plan_t p, const double* rhs, double* phi, void* strea
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return from_hip(e);
     if (dev != p->device) return IBP_ERROR_INVALID_VALUE;
-    return enqueue_solve(p, rhs, phi, static_cast<hipStream_t>(stream));
+    return enqueue_solve(p, rhs, phi, static_cast<hipStream_t>(stream), nullptr);
   } catch (...) {
     return IBP_ERROR_INTERNAL;
   }
@@ -759,11 +767,62 @@ ibp_status_t ibp_divergence(ibp_plan_t p, const double* u, const double* v, cons
                             void* stream) {
   if (!valid_plan(p) || !u || !v || !w || !f) return IBP_ERROR_INVALID_VALUE;
   try {
-    DivArgs a{u, v, w, f, p->dyf, p->nx, p->ny, p->nz, 1.0 / p->dx, 1.0 / p->dz};
+    DivArgs a{u, v, w, nullptr, f, p->dyf, p->nx, p->ny, p->nz, 1.0 / p->dx, 1.0 / p->dz, 1.0};
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = prof_mark(p, P_DIV, s, true);
     if (e == hipSuccess) e = launch_divergence(a, s);
     if (e == hipSuccess) e = prof_mark(p, P_DIV, s, false);
+    return from_hip(e);
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+namespace {
+bool aligned16(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15) == 0; }
+}  // namespace
+
+ibp_status_t ibp_solve_divergence(ibp_plan_t p, const double* u, const double* v, const double* w, const double* q,
+                                  double alpha_dt, double* rhs_out, double* phi, void* stream) {
+  if (!valid_plan(p) || !u || !v || !w || !phi) return IBP_ERROR_INVALID_VALUE;
+  if (!(alpha_dt > 0.0) || !std::isfinite(alpha_dt)) return IBP_ERROR_INVALID_VALUE;
+  if (!aligned16(u) || !aligned16(v) || !aligned16(w) || !aligned16(phi) || (q && !aligned16(q)) ||
+      (rhs_out && !aligned16(rhs_out)))
+    return IBP_ERROR_INVALID_VALUE;
+  if (p->prec != IBP_FP64 && rhs_out == nullptr) return IBP_ERROR_INVALID_VALUE;   // refinement re-reads f
+  try {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return from_hip(e);
+    if (dev != p->device) return IBP_ERROR_INVALID_VALUE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (rhs_out == nullptr) {   // FP64: assembled inside the first x pass
+      RhsFromVelocity r{u, v, w, q, 1.0 / alpha_dt};
+      return enqueue_solve(p, nullptr, phi, s, &r);
+    }
+    DivArgs a{u, v, w, q, rhs_out, p->dyf, p->nx, p->ny, p->nz, 1.0 / p->dx, 1.0 / p->dz, 1.0 / alpha_dt};
+    e = prof_mark(p, P_DIV, s, true);
+    if (e == hipSuccess) e = launch_divergence(a, s);
+    if (e == hipSuccess) e = prof_mark(p, P_DIV, s, false);
+    if (e != hipSuccess) return from_hip(e);
+    return ibp_solve(p, rhs_out, phi, stream);
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+ibp_status_t ibp_project(ibp_plan_t p, const double* phi, double alpha_dt, double visc, double* u, double* v,
+                         double* w, double* pr, void* stream) {
+  if (!valid_plan(p) || !phi || !u || !v || !w) return IBP_ERROR_INVALID_VALUE;
+  if (!std::isfinite(alpha_dt) || !std::isfinite(visc)) return IBP_ERROR_INVALID_VALUE;
+  try {
+    ProjArgs a{phi, u, v, w, pr, p->dyf, p->dyc, p->ya, p->yc, p->nx, p->ny, p->nz,
+               p->bc_lo == IBP_BC_DIRICHLET ? 1 : 0, p->bc_hi == IBP_BC_DIRICHLET ? 1 : 0,
+               1.0 / p->dx, 1.0 / p->dz, alpha_dt, visc};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = prof_mark(p, P_PROJ, s, true);
+    if (e == hipSuccess) e = launch_project(a, s);
+    if (e == hipSuccess) e = prof_mark(p, P_PROJ, s, false);
     return from_hip(e);
   } catch (...) {
     return IBP_ERROR_INTERNAL;
@@ -984,7 +1043,8 @@ ibp_status_t inverse_zx(ibp_plan_s* p, XArgs<T> xa, int cmode, int xpass, ZfArgs
 template <typename U>
 ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStream_t s);
 
-ibp_status_t enqueue_solve(ibp_plan_s* p, const double* rhs, double* phi, hipStream_t s) {
+ibp_status_t enqueue_solve(ibp_plan_s* p, const double* rhs, double* phi, hipStream_t s,
+                           const RhsFromVelocity* from_u) {
   p->last_stream = s;
   p->solved = true;
   if (p->prec == IBP_MIXED) return enqueue_mixed<float>(p, rhs, phi, s);
@@ -992,9 +1052,20 @@ ibp_status_t enqueue_solve(ibp_plan_s* p, const double* rhs, double* phi, hipStr
   // FP64 direct solve: x R2C, z FFT, y line solves + FP64 (0,0), z inverse, x C2R
   XArgs<double> xa = xargs<double>(p, rhs, nullptr, phi, p->spec64, p->twx, p->rb64, 0);
   xa.parts = 0;   // no norms needed: non-finite input shows up in the FP64 plane sums
+  int xmode = XM_PLAIN;
+  if (from_u) {
+    xmode = XM_DIV;
+    xa.u = from_u->u;
+    xa.v = from_u->v;
+    xa.w = from_u->w;
+    xa.q = from_u->q;
+    xa.idx = 1.0 / p->dx;
+    xa.idz = 1.0 / p->dz;
+    xa.rscale = from_u->rscale;
+  }
   ZfArgs<double> za{p->spec64, p->twz, p->ctl, p->fpz, p->nz, p->hp, p->zc64,
                     spec_row_stride<double>(p->hp), spec_plane_stride<double>(p->hp, p->nz), 0, 0};
-  ibp_status_t st = forward_xz<double>(p, xa, XM_PLAIN, P_XR2C, za, s);
+  ibp_status_t st = forward_xz<double>(p, xa, xmode, P_XR2C, za, s);
   if (st != IBP_SUCCESS) return st;
   YArgs<double, double> ya{p->spec64, p->lamx, p->lamz, p->ya, p->yc, p->ctl,
                            (long)p->nz * spec_row_stride<double>(p->hp), spec_row_stride<double>(p->hp),

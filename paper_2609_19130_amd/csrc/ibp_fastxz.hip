@@ -33,8 +33,9 @@ __device__ __forceinline__ void xr2c_body(const XArgs<T>& A, long blk, Cx<T>* ld
   const int nx = A.nx, nz = A.nz, ny = A.ny;
   const int j = live ? (int)(row / nz) : 0;
   const int k = live ? (int)(row - (long)j * nz) : 0;
+  constexpr bool kRes = MODE == XM_RESID || MODE == XM_RESID_ONLY;
   double mean = 0.0, s = 1.0;
-  if (MODE != XM_PLAIN) mean = A.ctl->removed_mean;
+  if (kRes) mean = A.ctl->removed_mean;
   if (MODE == XM_RESID) s = A.ctl->scale[A.iter & 1];
 
   Cx<T> v[kE];
@@ -44,8 +45,9 @@ __device__ __forceinline__ void xr2c_body(const XArgs<T>& A, long blk, Cx<T>* ld
     const int m = t + TT * i;
     double v0 = 0.0, v1 = 0.0;
     if (live) {
-      const double2 fv = *reinterpret_cast<const double2*>(A.f + row * nx + 2 * m);
-      if (MODE == XM_PLAIN) {
+      const double2 fv = MODE == XM_DIV ? assemble_pair(A, row, j, k, m)
+                                        : *reinterpret_cast<const double2*>(A.f + row * nx + 2 * m);
+      if (!kRes) {
         v0 = fv.x;
         v1 = fv.y;
         acc_f2 += v0 * v0 + v1 * v1;
@@ -117,7 +119,7 @@ __global__ __launch_bounds__(kThreads) void k_xr2c_reg(XArgs<T> A) {
   constexpr int RB = kThreads / (H / kE);
   __shared__ Cx<T> lds[RB * rfft::Seq<H>::stride];
   __shared__ double sh[(kThreads / kWave) * 5];
-  if (MODE != XM_PLAIN && A.ctl->done) return;
+  if ((MODE == XM_RESID || MODE == XM_RESID_ONLY) && A.ctl->done) return;
   xr2c_body<T, MODE, H, kThreads>(A, A.row_begin / RB + blockIdx.x, lds, sh, threadIdx.x);
 }
 
@@ -504,6 +506,9 @@ template <typename T>
 hipError_t launch_xr2c_fast(int mode, const XArgs<T>& a, hipStream_t s) {
   if (mode == XM_PLAIN) return xr2c_h<T, XM_PLAIN>(a.h, a, s);
   if (mode == XM_RESID) return xr2c_h<T, XM_RESID>(a.h, a, s);
+  if constexpr (sizeof(T) == 8) {   // right-hand side assembled in the pass: FP64 direct solves
+    if (mode == XM_DIV) return xr2c_h<T, XM_DIV>(a.h, a, s);
+  }
   return hipErrorInvalidValue;
 }
 

@@ -40,7 +40,10 @@ struct alignas(64) Ctl {
   double phimean;     // volume-weighted mean of the iterate read by the latest residual pass
 };
 
-enum XMode { XM_PLAIN = 0, XM_RESID = 1, XM_RESID_ONLY = 2 };
+// x R2C input: f itself (PLAIN), the FP64 residual of the current iterate
+// (RESID; RESID_ONLY reduces it without transforming), or f assembled on the
+// fly from the provisional velocity and mass sources (DIV).
+enum XMode { XM_PLAIN = 0, XM_RESID = 1, XM_RESID_ONLY = 2, XM_DIV = 3 };
 enum CMode { CM_SET = 0, CM_ADD = 1 };
 
 // per-block partials: sum in^2, sum (f-m)^2, max |in|, #non-finite, sum_j dyf_j * (row sums of phi)
@@ -71,7 +74,38 @@ struct XArgs {
   double out_scale;      // 1/(h nz): normalisation of the two inverse transforms
   double inv_nxnz;
   int iter;              // refinement pass (selects ctl->scale slot)
+  // XM_DIV: f = (D u - q) * rscale from u, w [ny][nz][nx] (x and z faces),
+  // v [ny+1][nz][nx] (y faces) and q [ny][nz][nx] (may be null)
+  const double* u;
+  const double* v;
+  const double* w;
+  const double* q;
+  double idx, idz, rscale;
 };
+
+// f = (D u - q) * rscale for the two cells (2m, 2m+1) of row (j, k): the
+// staggered divergence of the provisional velocity, minus the mass sources.
+template <typename T>
+__device__ __forceinline__ double2 assemble_pair(const XArgs<T>& A, long row, int j, int k, int m) {
+  const int nx = A.nx, nz = A.nz;
+  const long e = row * nx + 2 * m;
+  const double2 uc = *reinterpret_cast<const double2*>(A.u + e);
+  const double ur = A.u[row * nx + (2 * m + 2 == nx ? 0 : 2 * m + 2)];
+  const double2 vb = *reinterpret_cast<const double2*>(A.v + e);
+  const double2 vt = *reinterpret_cast<const double2*>(A.v + e + (long)nz * nx);
+  const int kp = k + 1 == nz ? 0 : k + 1;
+  const double2 wc = *reinterpret_cast<const double2*>(A.w + e);
+  const double2 wn = *reinterpret_cast<const double2*>(A.w + ((long)j * nz + kp) * nx + 2 * m);
+  const double dyf = A.dyf[j];   // same operation order as the divergence kernel
+  double f0 = (uc.y - uc.x) * A.idx + (vt.x - vb.x) / dyf + (wn.x - wc.x) * A.idz;
+  double f1 = (ur - uc.y) * A.idx + (vt.y - vb.y) / dyf + (wn.y - wc.y) * A.idz;
+  if (A.q) {
+    const double2 qq = *reinterpret_cast<const double2*>(A.q + e);
+    f0 -= qq.x;
+    f1 -= qq.y;
+  }
+  return make_double2(f0 * A.rscale, f1 * A.rscale);
+}
 
 template <typename T>
 struct ZfArgs {
@@ -245,15 +279,30 @@ hipError_t launch_batch_check(const BatchGrid<T>* d, const BatchLaunch& l, hipSt
 template <typename T>
 int batch_ytri_cols(int P, int K, int want);
 
-struct DivArgs {
+struct DivArgs {          // f = (D u - q) * scale; q may be null
   const double* u;
   const double* v;
   const double* w;
+  const double* q;
   double* f;
   const double* dyf;
   int nx, ny, nz;
-  double idx, idz;
+  double idx, idz, scale;
 };
+
+// Projection (u -= adt G phi) and pressure update (p += phi - visc L_h phi).
+struct ProjArgs {
+  const double* phi;
+  double *u, *v, *w, *p;     // p may be null
+  const double* dyf;         // [ny]
+  const double* dyc;         // [ny+1], entries 1..ny-1
+  const double* ya;          // face coefficients of L_h (wall rows carry the Dirichlet terms)
+  const double* yc;
+  int nx, ny, nz;
+  int dir_lo, dir_hi;        // Dirichlet walls
+  double idx, idz, adt, visc;
+};
+hipError_t launch_project(const ProjArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- launchers
 constexpr int kTileX64 = 2048, kTileX32 = 4096;   // complex elements per x-pass block

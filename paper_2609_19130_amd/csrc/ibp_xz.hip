@@ -23,13 +23,14 @@ namespace ibp {
 template <typename T, int MODE, int TILE>
 __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& fp, long blk, Cx<T>* buf,
                                               double* sh) {
-  if (MODE != XM_PLAIN && __builtin_amdgcn_readfirstlane(A.ctl->done)) return;
+  constexpr bool kRes = MODE == XM_RESID || MODE == XM_RESID_ONLY;
+  if (kRes && __builtin_amdgcn_readfirstlane(A.ctl->done)) return;
   const int h = A.h, RB = A.rows_per_block, nx = A.nx, nz = A.nz, ny = A.ny;
   const long row0 = blk * RB;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   double acc_in2 = 0.0, acc_f2 = 0.0, acc_max = 0.0, acc_bad = 0.0, acc_wphi = 0.0;
   double mean = 0.0, s = 1.0;
-  if (MODE != XM_PLAIN) mean = A.ctl->removed_mean;
+  if (kRes) mean = A.ctl->removed_mean;
   if (MODE == XM_RESID) s = A.ctl->scale[A.iter & 1];
 
   for (int lr = wave; lr < RB; lr += kThreads / kWave) {
@@ -44,9 +45,10 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
     const int j = (int)(row / nz);
     const int k = (int)(row - (long)j * nz);
     for (int m = lane; m < h; m += kWave) {
-      const double2 fv = *reinterpret_cast<const double2*>(frow + 2 * m);
+      const double2 fv = MODE == XM_DIV ? assemble_pair(A, row, j, k, m)
+                                        : *reinterpret_cast<const double2*>(frow + 2 * m);
       double v0, v1;
-      if (MODE == XM_PLAIN) {
+      if (!kRes) {
         v0 = fv.x;
         v1 = fv.y;
         acc_f2 += v0 * v0 + v1 * v1;
@@ -329,6 +331,12 @@ hipError_t launch_xr2c(int mode, const XArgs<T>& a, hipStream_t s) {
     case XM_PLAIN: hipLaunchKernelGGL((k_xr2c<T, XM_PLAIN, TL>), grid, block, 0, s, a); break;
     case XM_RESID: hipLaunchKernelGGL((k_xr2c<T, XM_RESID, TL>), grid, block, 0, s, a); break;
     case XM_RESID_ONLY: hipLaunchKernelGGL((k_xr2c<T, XM_RESID_ONLY, TL>), grid, block, 0, s, a); break;
+    case XM_DIV:
+      if constexpr (sizeof(T) == 8) {
+        hipLaunchKernelGGL((k_xr2c<T, XM_DIV, TL>), grid, block, 0, s, a);
+        break;
+      }
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -70,6 +70,8 @@ def lib():
         "ibp_solve_batched": (ci, [ctypes.POINTER(vp), ci, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]),
         "ibp_get_info": (ci, [vp, ctypes.POINTER(Info)]),
         "ibp_divergence": (ci, [vp, vp, vp, vp, vp, vp]),
+        "ibp_solve_divergence": (ci, [vp, vp, vp, vp, vp, cd, vp, vp, vp]),
+        "ibp_project": (ci, [vp, vp, cd, cd, vp, vp, vp, vp, vp]),
         "ibp_plan_set_profiling": (ci, [vp, ci]),
         "ibp_plan_get_profile": (ci, [vp, ci, ctypes.POINTER(ci), ctypes.POINTER(PassStat)]),
         "ibp_batch_create": (ci, [ctypes.POINTER(vp), ci, ctypes.POINTER(vp)]),
@@ -228,6 +230,31 @@ class Plan:
         pf = _field(f, self.shape, "f")
         _check(lib().ibp_divergence(self.handle, pu, pv, pw, pf, _stream_ptr(stream)), "ibp_divergence")
         return f
+
+    def solve_divergence(self, u, v, w, alpha_dt, q=None, rhs_out=None, phi=None, stream=None):
+        """Solve lap(phi) = (div u* - q) / alpha_dt (ibp_solve_divergence)."""
+        import torch
+        ny, nz, nx = self.shape
+        pu = _field(u, self.shape, "u")
+        pv = _field(v, (ny + 1, nz, nx), "v")
+        pw = _field(w, self.shape, "w")
+        pq = _field(q, self.shape, "q") if q is not None else None
+        pr = _field(rhs_out, self.shape, "rhs_out") if rhs_out is not None else None
+        if phi is None:
+            phi = torch.empty(self.shape, dtype=torch.float64, device=u.device)
+        _check(lib().ibp_solve_divergence(self.handle, pu, pv, pw, pq, float(alpha_dt), pr,
+                                          _field(phi, self.shape, "phi"), _stream_ptr(stream)),
+               "ibp_solve_divergence")
+        return phi
+
+    def project(self, phi, alpha_dt, u, v, w, p=None, visc=0.0, stream=None):
+        """u -= alpha_dt G phi and p += phi - visc L_h phi, in place (ibp_project)."""
+        ny, nz, nx = self.shape
+        _check(lib().ibp_project(self.handle, _field(phi, self.shape, "phi"), float(alpha_dt), float(visc),
+                                 _field(u, self.shape, "u"), _field(v, (ny + 1, nz, nx), "v"),
+                                 _field(w, self.shape, "w"),
+                                 _field(p, self.shape, "p") if p is not None else None, _stream_ptr(stream)),
+               "ibp_project")
 
     def close(self):
         if getattr(self, "_h", None) is not None:

@@ -1,0 +1,92 @@
+"""The steps either side of the solve on the GPU: right-hand side assembled
+from the provisional velocity and mass sources inside the first transform
+pass (ibp_solve_divergence), and projection with pressure update in one
+pass (ibp_project), against the oracle (eqs. ``elliptic``, ``velsolen``,
+``pressure``).  GPU only."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.grid import geometry
+from paper_2609_19130_amd import ibpoisson as ibp
+from paper_2609_19130_amd import synth
+
+from gpu_helpers import rel, require_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(64, 40, 32, ("neumann", "neumann")), (48, 33, 20, ("neumann", "neumann")),
+         (256, 17, 128, ("neumann", "dirichlet")), (30, 25, 18, ("dirichlet", "dirichlet"))]
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def fields(nx, ny, nz, seed):
+    u, v, w = synth.uniform_velocity(nx, ny, nz, seed=seed)
+    q = np.random.default_rng(seed + 1).standard_normal((ny, nz, nx)) * 0.05
+    return u, v, w, q
+
+
+@pytest.mark.parametrize("nx,ny,nz,bc", CASES)
+@pytest.mark.parametrize("with_q", [False, True])
+def test_solve_divergence_fp64_assembled_in_pass(nx, ny, nz, bc, with_q):
+    yf = synth.tanh_faces(ny, 2.0)
+    Lx, Lz, adt = 2 * np.pi, 1.3, 0.021
+    g = geometry(nx, ny, nz, Lx, Lz, yf, bc=bc)
+    u, v, w, q = fields(nx, ny, nz, 31)
+    qq = q if with_q else None
+    f = oracle.rhs_from_velocity(u, v, w, qq, g, adt)
+    ref, _ = oracle.solve(f, Lx, Lz, yf, bc=bc)
+    plan = ibp.Plan(nx, ny, nz, Lx, Lz, yf, bc=bc)
+    phi = plan.solve_divergence(to_dev(u), to_dev(v), to_dev(w), adt, q=to_dev(qq) if with_q else None)
+    assert rel(phi.cpu().numpy(), ref) <= 1e-12
+    # the same through the stored right-hand side
+    fout = torch.empty_like(phi)
+    phi2 = plan.solve_divergence(to_dev(u), to_dev(v), to_dev(w), adt, q=to_dev(qq) if with_q else None,
+                                 rhs_out=fout)
+    assert rel(fout.cpu().numpy(), f) <= 1e-14
+    assert float(torch.linalg.vector_norm(phi2 - phi) / torch.linalg.vector_norm(phi)) <= 1e-14
+
+
+def test_solve_divergence_mixed_needs_rhs_out():
+    nx, ny, nz = 64, 30, 32
+    yf = synth.tanh_faces(ny, 2.0)
+    u, v, w, q = fields(nx, ny, nz, 41)
+    plan = ibp.Plan(nx, ny, nz, 2 * np.pi, 1.0, yf, precision="mixed", max_iters=6)
+    du, dv, dw = to_dev(u), to_dev(v), to_dev(w)
+    with pytest.raises(ibp.IbpError):
+        plan.solve_divergence(du, dv, dw, 0.1)
+    fout = torch.empty_like(du)
+    phi = plan.solve_divergence(du, dv, dw, 0.1, q=to_dev(q), rhs_out=fout)
+    info = plan.info()
+    g = geometry(nx, ny, nz, 2 * np.pi, 1.0, yf)
+    ref, _ = oracle.solve(oracle.rhs_from_velocity(u, v, w, q, g, 0.1), 2 * np.pi, 1.0, yf)
+    assert info["converged"] == 1 and rel(phi.cpu().numpy(), ref) <= 1e-8
+
+
+@pytest.mark.parametrize("nx,ny,nz,bc", CASES + [(40, 21, 24, ("dirichlet", "neumann"))])
+def test_projection_and_pressure_update(nx, ny, nz, bc):
+    """ibp_project against the oracle's projection step, and the substep
+    invariant D u_{n+1} = q (+ alpha dt m) on the GPU result."""
+    yf = synth.tanh_faces(ny, 2.5)
+    Lx, Lz, adt, visc = 2 * np.pi, 1.7, 0.013, 3e-4
+    g = geometry(nx, ny, nz, Lx, Lz, yf, bc=bc)
+    u, v, w, q = fields(nx, ny, nz, 51)
+    p0 = np.random.default_rng(52).standard_normal((ny, nz, nx))
+    plan = ibp.Plan(nx, ny, nz, Lx, Lz, yf, bc=bc)
+    du, dv, dw, dp = to_dev(u), to_dev(v), to_dev(w), to_dev(p0)
+    phi = plan.solve_divergence(du, dv, dw, adt, q=to_dev(q))
+    m = plan.info()["removed_mean"]
+    plan.project(phi, adt, du, dv, dw, p=dp, visc=visc)
+    torch.cuda.synchronize()
+    ph = phi.cpu().numpy()
+    un, vn, wn, pn = oracle.projection_step(u, v, w, p0, ph, g, adt, visc)
+    for got, want in ((du, un), (dv, vn), (dw, wn), (dp, pn)):
+        assert rel(got.cpu().numpy(), want) <= 1e-13
+    div = oracle.divergence(du.cpu().numpy(), dv.cpu().numpy(), dw.cpu().numpy(), g)
+    assert np.abs(div - q - adt * m).max() <= 1e-11 * np.abs(oracle.divergence(u, v, w, g)).max()
