@@ -9,6 +9,8 @@
 // half-spectrum coefficients k = t + TT*i (+ k = H from thread 0).
 // z pass: C consecutive threads own C consecutive kx columns of one y plane
 // (C*element-size contiguous bytes per z), TT = NZ/8 thread groups cover z.
+#include <cstdlib>
+
 #include "ibp_internal.hpp"
 #include "ibp_regfft.hpp"
 
@@ -19,9 +21,11 @@ using rfft::kE;
 using rfft::pad8;
 
 // x R2C of rows [blk*RB, blk*RB + RB) with NT threads (RB = NT / (H/8)).
-// Every thread of the block must call it; it returns with LDS free.
-template <typename T, int MODE, int H, int NT>
-__device__ __forceinline__ void xr2c_body(const XArgs<T>& A, long blk, Cx<T>* lds, double* sh, int tid) {
+// Every thread of the block must call it; it returns with LDS free.  PRE:
+// the thread's eight input pairs were loaded beforehand into pre[0..8).
+template <typename T, int MODE, int H, int NT, bool PRE = false>
+__device__ __forceinline__ void xr2c_body(const XArgs<T>& A, long blk, Cx<T>* lds, double* sh, int tid,
+                                          const double2* pre = nullptr) {
   constexpr int TT = H / kE;
   constexpr int SS = rfft::Seq<H>::stride;
   using P = rfft::Plan<H, false, T>;
@@ -45,8 +49,9 @@ __device__ __forceinline__ void xr2c_body(const XArgs<T>& A, long blk, Cx<T>* ld
     const int m = t + TT * i;
     double v0 = 0.0, v1 = 0.0;
     if (live) {
-      const double2 fv = MODE == XM_DIV ? assemble_pair(A, row, j, k, m)
-                                        : *reinterpret_cast<const double2*>(A.f + row * nx + 2 * m);
+      const double2 fv = PRE ? pre[i]
+                         : MODE == XM_DIV ? assemble_pair(A, row, j, k, m)
+                                          : *reinterpret_cast<const double2*>(A.f + row * nx + 2 * m);
       if (!kRes) {
         v0 = fv.x;
         v1 = fv.y;
@@ -123,9 +128,38 @@ __global__ __launch_bounds__(kThreads) void k_xr2c_reg(XArgs<T> A) {
   xr2c_body<T, MODE, H, kThreads>(A, A.row_begin / RB + blockIdx.x, lds, sh, threadIdx.x);
 }
 
+// Two row groups per block (plain right-hand side): the loads of both are
+// issued before the first transform, so one group's memory traffic overlaps
+// the other's transform (the single-group kernel leaves the FFT latency
+// exposed: 0.42 ms against 0.35 ms for the 512x384x512 FP64 pass).
+constexpr int kXGroups = 2;
+
+template <typename T, int MODE, int H>
+__global__ __launch_bounds__(kThreads) void k_xr2c_pipe(XArgs<T> A) {
+  constexpr int TT = H / kE;
+  constexpr int RB = kThreads / TT;
+  __shared__ Cx<T> lds[RB * rfft::Seq<H>::stride];
+  __shared__ double sh[(kThreads / kWave) * 5];
+  const long blk0 = A.row_begin / RB + (long)blockIdx.x * kXGroups;
+  const int tid = threadIdx.x, lr = tid / TT, t = tid % TT;
+  double2 buf[kXGroups][kE];
+#pragma unroll
+  for (int g = 0; g < kXGroups; ++g) {
+    const long row = (blk0 + g) * RB + lr;
+#pragma unroll
+    for (int i = 0; i < kE; ++i)
+      buf[g][i] = row < A.nrows ? *reinterpret_cast<const double2*>(A.f + row * A.nx + 2 * (t + TT * i))
+                                : make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (int g = 0; g < kXGroups; ++g) xr2c_body<T, MODE, H, kThreads, true>(A, blk0 + g, lds, sh, tid, buf[g]);
+}
+
 // x C2R of rows [blk*RB, blk*RB + RB) with NT threads; called by every thread.
-template <typename T, int MODE, int H, int NT>
-__device__ __forceinline__ void xc2r_body(const XArgs<T>& A, long blk, Cx<T>* lds, int tid) {
+// PRE: the thread's spectrum pairs (X[k], X[H-k]) were loaded beforehand.
+template <typename T, int MODE, int H, int NT, bool PRE = false>
+__device__ __forceinline__ void xc2r_body(const XArgs<T>& A, long blk, Cx<T>* lds, int tid,
+                                          const Cx<T>* pre = nullptr) {
   constexpr int TT = H / kE;
   constexpr int SS = rfft::Seq<H>::stride;
   using P = rfft::Plan<H, true, T>;
@@ -141,7 +175,10 @@ __device__ __forceinline__ void xc2r_body(const XArgs<T>& A, long blk, Cx<T>* ld
   for (int i = 0; i < kE; ++i) {
     const int kk = t + TT * i;
     Cx<T> Xk{T(0), T(0)}, Xm{T(0), T(0)};
-    if (live) {
+    if (PRE) {
+      Xk = pre[2 * i];
+      Xm = pre[2 * i + 1];
+    } else if (live) {
       Xk = srow[kk];
       Xm = srow[H - kk];
     }
@@ -174,6 +211,34 @@ __device__ __forceinline__ void xc2r_body(const XArgs<T>& A, long blk, Cx<T>* ld
       v1 += old.y;
     }
     *o = make_double2(v0, v1);
+  }
+}
+
+template <typename T, int MODE, int H>
+__global__ __launch_bounds__(kThreads) void k_xc2r_pipe(XArgs<T> A) {
+  constexpr int TT = H / kE;
+  constexpr int RB = kThreads / TT;
+  __shared__ Cx<T> lds[RB * rfft::Seq<H>::stride];
+  if (MODE == CM_ADD && A.ctl->done) return;
+  const long blk0 = A.row_begin / RB + (long)blockIdx.x * kXGroups;
+  const int tid = threadIdx.x, lr = tid / TT, t = tid % TT;
+  Cx<T> buf[kXGroups][2 * kE];
+#pragma unroll
+  for (int g = 0; g < kXGroups; ++g) {
+    const long row = (blk0 + g) * RB + lr;
+    const bool live = row < A.nrows;
+    const Cx<T>* srow = A.spec + (live ? row * A.rs + (row / A.nz) * (A.ps - (long)A.nz * A.rs) : 0);
+#pragma unroll
+    for (int i = 0; i < kE; ++i) {
+      const int kk = t + TT * i;
+      buf[g][2 * i] = live ? srow[kk] : Cx<T>{T(0), T(0)};
+      buf[g][2 * i + 1] = live ? srow[H - kk] : Cx<T>{T(0), T(0)};
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < kXGroups; ++g) {
+    xc2r_body<T, MODE, H, kThreads, true>(A, blk0 + g, lds, tid, buf[g]);
+    __syncthreads();   // the next group reuses the LDS rows
   }
 }
 
@@ -220,7 +285,6 @@ __global__ __launch_bounds__(C*(NZ / kE)) void k_zfft_reg(ZfArgs<T> A) {
   if (A.check_done && A.ctl->done) return;
   zfft_body<T, INV, NZ, C>(A, blockIdx.x, A.plane0 + blockIdx.y, lds, threadIdx.x);
 }
-
 
 
 // ---------------------------------------------------------------- fused x/z
@@ -466,36 +530,44 @@ template hipError_t launch_fused_inv<float>(int, const FusedArgs<float>&, int, h
 // ---------------------------------------------------------------- launchers
 template <typename T, int MODE>
 static hipError_t xr2c_h(int h, const XArgs<T>& a, hipStream_t s) {
-  auto go = [&](auto kern, int H) {
+  auto go = [&](auto kern, auto pipe, int H) {
     const int RB = kThreads / (H / kE);
     const long nb = (a.nrows - a.row_begin + RB - 1) / RB;
-    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kThreads), 0, s, a);
+    if (MODE == XM_PLAIN && nb % kXGroups == 0)
+      hipLaunchKernelGGL(pipe, dim3((unsigned)(nb / kXGroups)), dim3(kThreads), 0, s, a);
+    else
+      hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kThreads), 0, s, a);
     return hipGetLastError();
   };
   switch (h) {
-    case 32: return go(k_xr2c_reg<T, MODE, 32>, 32);
-    case 64: return go(k_xr2c_reg<T, MODE, 64>, 64);
-    case 128: return go(k_xr2c_reg<T, MODE, 128>, 128);
-    case 256: return go(k_xr2c_reg<T, MODE, 256>, 256);
-    case 512: return go(k_xr2c_reg<T, MODE, 512>, 512);
+    case 32: return go(k_xr2c_reg<T, MODE, 32>, k_xr2c_pipe<T, XM_PLAIN, 32>, 32);
+    case 64: return go(k_xr2c_reg<T, MODE, 64>, k_xr2c_pipe<T, XM_PLAIN, 64>, 64);
+    case 128: return go(k_xr2c_reg<T, MODE, 128>, k_xr2c_pipe<T, XM_PLAIN, 128>, 128);
+    case 256: return go(k_xr2c_reg<T, MODE, 256>, k_xr2c_pipe<T, XM_PLAIN, 256>, 256);
+    case 512: return go(k_xr2c_reg<T, MODE, 512>, k_xr2c_pipe<T, XM_PLAIN, 512>, 512);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T, int MODE>
 static hipError_t xc2r_h(int h, const XArgs<T>& a, hipStream_t s) {
-  auto go = [&](auto kern, int H) {
+  auto go = [&](auto kern, auto pipe, int H) {
     const int RB = kThreads / (H / kE);
     const long nb = (a.nrows - a.row_begin + RB - 1) / RB;
-    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kThreads), 0, s, a);
+    // FP32 only: two preloaded groups of FP64 spectrum pairs need ~200 VGPRs
+    // (2 waves per SIMD) and measured slower than one group
+    if (sizeof(T) == 4 && nb % kXGroups == 0)
+      hipLaunchKernelGGL(pipe, dim3((unsigned)(nb / kXGroups)), dim3(kThreads), 0, s, a);
+    else
+      hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kThreads), 0, s, a);
     return hipGetLastError();
   };
   switch (h) {
-    case 32: return go(k_xc2r_reg<T, MODE, 32>, 32);
-    case 64: return go(k_xc2r_reg<T, MODE, 64>, 64);
-    case 128: return go(k_xc2r_reg<T, MODE, 128>, 128);
-    case 256: return go(k_xc2r_reg<T, MODE, 256>, 256);
-    case 512: return go(k_xc2r_reg<T, MODE, 512>, 512);
+    case 32: return go(k_xc2r_reg<T, MODE, 32>, k_xc2r_pipe<T, MODE, 32>, 32);
+    case 64: return go(k_xc2r_reg<T, MODE, 64>, k_xc2r_pipe<T, MODE, 64>, 64);
+    case 128: return go(k_xc2r_reg<T, MODE, 128>, k_xc2r_pipe<T, MODE, 128>, 128);
+    case 256: return go(k_xc2r_reg<T, MODE, 256>, k_xc2r_pipe<T, MODE, 256>, 256);
+    case 512: return go(k_xc2r_reg<T, MODE, 512>, k_xc2r_pipe<T, MODE, 512>, 512);
     default: return hipErrorInvalidValue;
   }
 }
@@ -530,6 +602,8 @@ int fast_z_cols(int nz) {
 template <typename T, bool INV>
 static hipError_t zfft_n(const ZfArgs<T>& a, int nplanes, hipStream_t s) {
   const int C = fast_z_cols<T>(a.nz);
+  // (two planes per block with both loaded up front was measured slower: the
+  // preloaded columns double the VGPRs and halve the occupancy)
   const dim3 grid((unsigned)((a.hp + C - 1) / C), (unsigned)nplanes);
   auto go = [&](auto kern, int threads) {
     hipLaunchKernelGGL(kern, grid, dim3(threads), 0, s, a);
