@@ -194,16 +194,18 @@ __device__ __forceinline__ void zero_mode_plane(const ZeroArgs& Z, int j) {
 // K rows.  The block's M columns are staged through LDS so that global loads
 // and stores are M * element-size contiguous bytes per row.
 
-// Column stride of the staged tile, = 2 (mod 32) elements: the coalesced
-// load/store mapping (consecutive lanes on consecutive columns, then rows)
-// then falls on distinct banks within each 16-lane (FP64) or 32-lane (FP32)
-// LDS pass.
-template <int K, int P>
-__host__ __device__ constexpr int ytile_col() {
-  return P * (K + 1) + ((2 - (P * (K + 1)) % 32) + 32) % 32;
-}
+// Staged tile: partition-major, then row, then column, with one pad slot
+// after each partition: row r of partition pp of column m sits at slot
+// pp * (K M + 1) + r M + m.  The coalesced load/store mapping (consecutive
+// lanes on consecutive columns, then rows) touches consecutive slots, and
+// the solve's reads (lanes on consecutive partitions of one column) are an
+// odd number of slots apart, so both fall on distinct LDS banks.  P (K M + 1)
+// slots: 49.7 KB at K = 12, M = 8, P = 32 in FP64, so three blocks share
+// one CU's 160 KB.
+template <int M, int P, int K>
+__host__ __device__ constexpr long ytile_slots() { return (long)P * (K * M + 1); }
 
-inline int ytile_col_host(int P, int K) { return P * (K + 1) + ((2 - (P * (K + 1)) % 32) + 32) % 32; }
+inline long ytile_slots_host(int M, int P, int K) { return (long)P * (K * M + 1); }
 
 template <typename U>
 __device__ __forceinline__ U shfl_up_w(U v, int d, int w) { return __shfl_up(v, d, w); }
@@ -216,8 +218,7 @@ __device__ __forceinline__ U shfl_down_w(U v, int d, int w) { return __shfl_down
 template <typename T, typename U, int M, int P, int K>
 __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& Z, long blk, Cx<T>* tile) {
   constexpr int NT = M * P;
-  constexpr int KS = K + 1;     // LDS slots per partition: odd, so lanes spread over banks
-  constexpr int LS = ytile_col<K, P>();   // LDS slots per column
+  constexpr int PS = K * M + 1;   // LDS slots per partition
   if (A.check_done && __builtin_amdgcn_readfirstlane(A.ctl->done)) return;
   if (blk < A.ny) {   // the first ny blocks: FP64 (0,0) mode
     zero_mode_plane<NT>(Z, (int)blk);
@@ -243,7 +244,7 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
     for (int i = 0; i < K; ++i) {
       const int row = row0 + P * i;
       const int pp = row / K;
-      tile[m * LS + pp * KS + (row - pp * K)] = row < ny ? ld[i] : Cx<T>{T(0), T(0)};
+      tile[pp * PS + (row - pp * K) * M + m] = row < ny ? ld[i] : Cx<T>{T(0), T(0)};
     }
   }
   __syncthreads();
@@ -256,24 +257,23 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
   const bool zero = A.singular && q == 0;
   if (zero) L = U(1);   // singular (0,0): solved in FP64 by the plane blocks, zeroed here
   const int s = p * K;
-  Cx<T>* my = tile + m * LS + p * KS;
+  Cx<T>* my = tile + p * PS + m;   // row i of this lane's partition: my[i * M]
 
   // face coefficients of this lane's rows: the tables are zero-padded to
   // P*K rows, so rows past ny are decoupled (a = c = 0) and get shift 1
-  U ca[K], cc[K], cl[K];
+  U ca[K], cc[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     ca[i] = A.ya[s + i];
     cc[i] = A.yc[s + i];
-    cl[i] = (s + i < ny) ? L : U(1);
   }
   Cx<U> d[K];
 #pragma unroll
-  for (int i = 0; i < K; ++i) d[i] = Cx<U>{U(my[i].x), U(my[i].y)};
+  for (int i = 0; i < K; ++i) d[i] = Cx<U>{U(my[i * M].x), U(my[i * M].y)};
 #define IBP_COEF(i, a_, c_, l_) \
   const U a_ = ca[i];           \
   const U c_ = cc[i];           \
-  const U l_ = cl[i];
+  const U l_ = (s + (i) < ny) ? L : U(1);
 
   // ---- scan 1: eps_out = (mA eps_in + mB) / (mC eps_in + mD) over the
   // partition, all entries >= 0, normalised to mC + mD = 1 (the denominator
@@ -305,7 +305,6 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
       mD = n11 * inv;
     }
   }
-  U rD[K];
   {
     // eps entering the partition: the earlier composite applied to
     // eps_{-1} = 1 (the value beyond the lower wall does not depend on X_0)
@@ -313,12 +312,17 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
     const U eC = shfl_up_w(mC, 1, P), eD = shfl_up_w(mD, 1, P);
     U e = (eA + eB) / (eC + eD);
     if (p == 0) e = U(1);
+    // with the pivots known, keep a_j / D_j, c_j / D_j and F_j / D_j only
+    // (both later recurrences use nothing else)
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       IBP_COEF(i, a, c, l)
       const U n = l + a * e;
-      rD[i] = U(1) / (c + n);
-      e = n * rD[i];
+      const U r = U(1) / (c + n);
+      e = n * r;
+      ca[i] = a * r;
+      cc[i] = c * r;
+      d[i] = cscale(d[i], r);
     }
   }
   // ---- scan 2: d'_out = mu d'_in + nu over the partition
@@ -327,12 +331,9 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
     Cx<U> nu{U(0), U(0)};
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      IBP_COEF(i, a, c, l)
-      (void)c;
-      (void)l;
-      const U mi = a * rD[i];
+      const U mi = ca[i];
       mu = mi * mu;
-      nu = csub(cscale(nu, mi), cscale(d[i], rD[i]));
+      nu = csub(cscale(nu, mi), d[i]);
     }
 #pragma unroll
     for (int off = 1; off < P; off <<= 1) {
@@ -347,10 +348,7 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
     if (p == 0) prev = Cx<U>{U(0), U(0)};
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      IBP_COEF(i, a, c, l)
-      (void)c;
-      (void)l;
-      d[i] = cscale(csub(cscale(prev, a), d[i]), rD[i]);
+      d[i] = csub(cscale(prev, ca[i]), d[i]);
       prev = d[i];
     }
   }
@@ -360,10 +358,7 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
     Cx<U> S{U(0), U(0)};
 #pragma unroll
     for (int i = K - 1; i >= 0; --i) {
-      IBP_COEF(i, a, c, l)
-      (void)a;
-      (void)l;
-      const U tau = c * rD[i];
+      const U tau = cc[i];
       Tt = tau * Tt;
       S = cadd(d[i], cscale(S, tau));
     }
@@ -380,16 +375,13 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
     if (p == P - 1) nxt = Cx<U>{U(0), U(0)};
 #pragma unroll
     for (int i = K - 1; i >= 0; --i) {
-      IBP_COEF(i, a, c, l)
-      (void)a;
-      (void)l;
-      d[i] = cadd(d[i], cscale(nxt, c * rD[i]));
+      d[i] = cadd(d[i], cscale(nxt, cc[i]));
       nxt = d[i];
     }
   }
 #undef IBP_COEF
 #pragma unroll
-  for (int i = 0; i < K; ++i) my[i] = zero ? Cx<T>{T(0), T(0)} : Cx<T>{T(d[i].x), T(d[i].y)};
+  for (int i = 0; i < K; ++i) my[i * M] = zero ? Cx<T>{T(0), T(0)} : Cx<T>{T(d[i].x), T(d[i].y)};
   __syncthreads();
   {
     const int mm = threadIdx.x % M, row0 = threadIdx.x / M;
@@ -400,7 +392,7 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
       for (int i = 0; i < K; ++i) {
         const int row = row0 + P * i;
         const int pp = row / K;
-        st[i] = tile[mm * LS + pp * KS + (row - pp * K)];
+        st[i] = tile[pp * PS + (row - pp * K) * M + mm];
       }
 #pragma unroll
       for (int i = 0; i < K; ++i) {
@@ -411,9 +403,17 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
   }
 }
 
+// Occupancy floor per precision: the all-FP32 line solve fits 4 waves per
+// SIMD (<= 128 VGPRs, a 28-byte spill) and measured 1.6x faster there than at
+// the compiler's own 3; with FP64 coefficients or spectra the same cap spills
+// hundreds of bytes, and FP64 at 3 waves gained nothing.
+template <typename T, typename U = T>
+constexpr int ytri_waves() { return sizeof(T) == 4 && sizeof(U) == 4 ? 4 : 1; }
+
 template <typename T, typename U, int M, int P, int K>
-__global__ __launch_bounds__(M * P) void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
-  __shared__ Cx<T> tile[M * ytile_col<K, P>()];
+__global__ __launch_bounds__(M * P) __attribute__((amdgpu_waves_per_eu(ytri_waves<T, U>())))
+void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
+  __shared__ Cx<T> tile[ytile_slots<M, P, K>()];
   ytri_body<T, U, M, P, K>(A, Z, blockIdx.x, tile);
 }
 
@@ -486,10 +486,7 @@ static int ycol_override() {
 
 template <typename T>
 static int ytri_cols(int P, int K, int want) {
-  auto tile = [&](int M) {
-    const int col = P * (K + 1) + ((2 - (P * (K + 1)) % 32) + 32) % 32;
-    return (long)M * col * (long)sizeof(Cx<T>);
-  };
+  auto tile = [&](int M) { return ytile_slots_host(M, P, K) * (long)sizeof(Cx<T>); };
   int M = 128 / (int)sizeof(Cx<T>);
   const int o = want ? want : ycol_override();
   if (o == 2 || o == 4 || o == 8 || o == 16) M = o;
@@ -501,7 +498,7 @@ static int ytri_cols(int P, int K, int want) {
 template <typename T, typename U, int M, int P, int K>
 static hipError_t launch_ytri_mpk(const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s) {
   // only shapes ytri_cols can select are instantiated (staged tile <= 72 KB)
-  if constexpr ((long)M * ytile_col<K, P>() * (long)sizeof(Cx<T>) <= kYTileBytes && M * P <= 1024) {
+  if constexpr (ytile_slots<M, P, K>() * (long)sizeof(Cx<T>) <= kYTileBytes && M * P <= 1024) {
     const long nb = (a.Q + M - 1) / M + a.ny;   // + the (0,0)-mode plane blocks
     hipLaunchKernelGGL((k_ytri<T, U, M, P, K>), dim3((unsigned)nb), dim3(M * P), 0, s, a, z);
     return hipGetLastError();
@@ -558,9 +555,10 @@ __device__ __forceinline__ int ybatch_grid_of(const long* start, int count, long
 }
 
 template <typename T, int M, int P, int K>
-__global__ __launch_bounds__(M * P) void kb_ytri(const BatchGrid<T>* __restrict__ D, const long* __restrict__ start,
+__global__ __launch_bounds__(M * P) __attribute__((amdgpu_waves_per_eu(ytri_waves<T>())))
+void kb_ytri(const BatchGrid<T>* __restrict__ D, const long* __restrict__ start,
                                                  BatchLaunch L) {
-  __shared__ Cx<T> tile[M * ytile_col<K, P>()];
+  __shared__ Cx<T> tile[ytile_slots<M, P, K>()];
   const int g = ybatch_grid_of(start, L.count, blockIdx.x);
   YArgs<T, T> a = D[g].y;
   a.check_done = L.check_done;
@@ -588,7 +586,7 @@ __global__ __launch_bounds__(kThreads) void kb_check(const BatchGrid<T>* __restr
 
 template <typename T>
 int batch_ytri_cols(int P, int K, int want) {
-  auto tile = [&](int M) { return (long)M * ytile_col_host(P, K) * (long)sizeof(Cx<T>); };
+  auto tile = [&](int M) { return ytile_slots_host(M, P, K) * (long)sizeof(Cx<T>); };
   int M = (want == 2 || want == 4 || want == 8 || want == 16) ? want : 128 / (int)sizeof(Cx<T>);
   while (M > 2 && tile(M) > kYTileBytes) M /= 2;
   while (M * P > 1024) M /= 2;
@@ -598,7 +596,7 @@ int batch_ytri_cols(int P, int K, int want) {
 template <typename T, int M, int P, int K>
 static hipError_t launch_kb_ytri(const BatchGrid<T>* d, const long* start, long nb, const BatchLaunch& l,
                                  hipStream_t s) {
-  if constexpr ((long)M * ytile_col<K, P>() * (long)sizeof(Cx<T>) <= kYTileBytes && M * P <= 1024) {
+  if constexpr (ytile_slots<M, P, K>() * (long)sizeof(Cx<T>) <= kYTileBytes && M * P <= 1024) {
     hipLaunchKernelGGL((kb_ytri<T, M, P, K>), dim3((unsigned)nb), dim3(M * P), 0, s, d, start, l);
     return hipGetLastError();
   } else {
