@@ -20,6 +20,9 @@ What it computes (paper: "Fluid Mechanics" subsection, eqs. ``velsolen``,
   complex FFT in z, one tridiagonal system per horizontal Fourier mode along y,
   flux integration for the singular (0,0) mode, and the inverse FFTs
   (``poisson``); with a Dirichlet wall, the solution of L_h phi = f;
+* the factored implicit viscous solve of eq. ``nstime_discr`` with
+  Crank-Nicolson viscous terms: one tridiagonal (cyclic in x and z) system
+  per grid line and direction, solved densely (``helmholtz``);
 * independent pins: a dense bordered solve (``dense``), an exact rational
   bordered solve (``exact``) and manufactured solutions built from the
   discrete y eigenvectors (``manufactured``).
@@ -27,7 +30,9 @@ What it computes (paper: "Fluid Mechanics" subsection, eqs. ``velsolen``,
 Parity status: the paper prints no worked example, no error table and no
 Poisson-only numbers, so none of these functions is pinned to a printed
 value; every function is pinned instead to closed forms, invariants, dense
-and exact-rational solves (see ``tests/test_oracle_pins.py``).
+and exact-rational solves (see ``tests/test_oracle_pins.py``); the factored
+viscous solve to textbook Fourier and uniform-grid eigenvalues, the pinned
+stencils and a brute-force 3-D solve (``tests/test_oracle_helmholtz.py``).
 """
 
 from .grid import Geometry, geometry
@@ -35,9 +40,10 @@ from .operators import divergence, gradient, laplacian, projection_step, rhs_fro
 from .poisson import solve, solve_modes, thomas_modes, zero_mode_flux_integration
 from .dense import bordered_matrix, dense_solve
 from .manufactured import y_eigenpairs, manufactured_field
+from .helmholtz import helmholtz, velocity_bc
 
 __all__ = [
     "Geometry", "geometry", "divergence", "gradient", "laplacian", "projection_step", "rhs_from_velocity", "solve",
     "solve_modes", "thomas_modes", "zero_mode_flux_integration",
-    "bordered_matrix", "dense_solve", "y_eigenpairs", "manufactured_field",
+    "bordered_matrix", "dense_solve", "y_eigenpairs", "manufactured_field", "helmholtz", "velocity_bc",
 ]
