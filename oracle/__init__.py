@@ -22,7 +22,7 @@ What it computes (paper: "Fluid Mechanics" subsection, eqs. ``velsolen``,
   (``poisson``); with a Dirichlet wall, the solution of L_h phi = f;
 * the factored implicit viscous solve of eq. ``nstime_discr`` with
   Crank-Nicolson viscous terms: one tridiagonal (cyclic in x and z) system
-  per grid line and direction, solved densely (``helmholtz``);
+  per grid line and direction, solved densely (``helmholtz.factored_solve``);
 * independent pins: a dense bordered solve (``dense``), an exact rational
   bordered solve (``exact``) and manufactured solutions built from the
   discrete y eigenvectors (``manufactured``).
@@ -40,10 +40,10 @@ from .operators import divergence, gradient, laplacian, projection_step, rhs_fro
 from .poisson import solve, solve_modes, thomas_modes, zero_mode_flux_integration
 from .dense import bordered_matrix, dense_solve
 from .manufactured import y_eigenpairs, manufactured_field
-from .helmholtz import helmholtz, velocity_bc
+from .helmholtz import factored_solve, velocity_bc
 
 __all__ = [
     "Geometry", "geometry", "divergence", "gradient", "laplacian", "projection_step", "rhs_from_velocity", "solve",
     "solve_modes", "thomas_modes", "zero_mode_flux_integration",
-    "bordered_matrix", "dense_solve", "y_eigenpairs", "manufactured_field", "helmholtz", "velocity_bc",
+    "bordered_matrix", "dense_solve", "y_eigenpairs", "manufactured_field", "factored_solve", "velocity_bc",
 ]

@@ -97,7 +97,7 @@ def solve_lines(A, f, axis):
     return np.moveaxis(out, 0, axis)
 
 
-def helmholtz(f, g, beta, where="cells", order="xzy"):
+def factored_solve(f, g, beta, where="cells", order="xzy"):
     """du = (1 - beta L_y)^-1 (1 - beta L_z)^-1 (1 - beta L_x)^-1 f.
 
     `where` = "cells": f has shape (ny, nz, nx).
