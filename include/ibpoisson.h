@@ -245,6 +245,41 @@ ibp_status_t ibp_solve_divergence(ibp_plan_t plan, const double* u, const double
 ibp_status_t ibp_project(ibp_plan_t plan, const double* phi, double alpha_dt, double visc, double* u, double* v,
                          double* w, double* p, void* stream);
 
+/* Factored implicit viscous solve (paper: eq. ``nstime_discr`` with
+ * Crank-Nicolson viscous terms, split into direction-wise tridiagonal solves,
+ * Thomas with a Sherman-Morrison correction along the two periodic
+ * directions; "Fluid domain" parallelisation subsection):
+ *   field <- (1 - beta L_y)^-1 (1 - beta L_z)^-1 (1 - beta L_x)^-1 field,
+ * beta = alpha dt / (2 Re).  L_x, L_z: periodic uniform second differences.
+ * L_y: the wall-normal second difference with the velocity wall conditions,
+ * the complement of the plan's pressure-correction ones (ibp_plan_set_bc):
+ * prescribed velocity (zero increment) at a Neumann wall of the plan, zero
+ * normal gradient at a Dirichlet wall.
+ *
+ * IBP_AT_CELLS: a field [ny][nz][nx] at the y cell centres (u on the x faces,
+ *   w on the z faces, cell-centred scalars); a prescribed-velocity wall is a
+ *   zero value on the wall face, half a cell from the first centre.
+ * IBP_AT_YFACES: the wall-normal component, [ny+1][nz][nx] on the y faces;
+ *   rows 1..ny-1 are solved across the interior faces
+ *   ((v[j+1]-v[j])/dyf_j - (v[j]-v[j-1])/dyf_{j-1}) / dyc_j and rows 0 and
+ *   ny are set to zero (the increment vanishes on the walls).  Needs
+ *   prescribed velocity at both walls (the plan's walls both Neumann). */
+typedef enum { IBP_AT_CELLS = 0, IBP_AT_YFACES = 1 } ibp_location_t;
+
+/* Factors the line operators of all three directions for `beta` (finite,
+ * >= 0) on the host in FP64 and uploads them (synchronous; allocates the
+ * plan's factor tables on first use).  Must be called again after
+ * ibp_plan_set_bc.  IBP_ERROR_UNSUPPORTED_SIZE for lines longer than 1536. */
+ibp_status_t ibp_helmholtz_set(ibp_plan_t plan, double beta);
+
+/* Applies the factored solve in place to `field` (device pointer, 16-byte
+ * aligned, layout as above): three passes, each reading and writing the field
+ * once.  Asynchronous on `stream`, no allocation or host copy (graph
+ * capturable).  IBP_ERROR_INVALID_VALUE if ibp_helmholtz_set has not been
+ * called since the plan's last change of wall conditions, or for
+ * IBP_AT_YFACES without prescribed velocity at both walls. */
+ibp_status_t ibp_helmholtz(ibp_plan_t plan, double* field, ibp_location_t where, void* stream);
+
 /* Per-pass timing.  While enabled, every kernel launch of ibp_solve is
  * bracketed by two HIP events recorded on the solve's stream (a few
  * microseconds of overhead per launch; not for graph capture). */

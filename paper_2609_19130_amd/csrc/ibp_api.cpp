@@ -115,6 +115,18 @@ struct ibp_plan_s {
   unsigned gen = 0;   // bumped when the precision, workspace or wall conditions change (batches check it)
   ibp_bc_t bc_lo = IBP_BC_NEUMANN, bc_hi = IBP_BC_NEUMANN;
   std::vector<double> ya_host, yc_host, dyf_host;   // Neumann face coefficients and cell widths
+  std::vector<double> dyc_host;                      // centre distances, entries 1..ny-1
+  // factored viscous solve (ibp_helmholtz_set): device factor tables per direction
+  struct LineDir {
+    int P = 0, K = 0, n = 0, cyclic = 0;
+    long npad = 0, off = 0;   // table stride and offset in `helm` (doubles)
+    double g = 0.0;
+  };
+  double* helm = nullptr;
+  size_t helm_doubles = 0;
+  bool helm_ready = false, helm_faces = false;
+  ibp_bc_t helm_lo = IBP_BC_NEUMANN, helm_hi = IBP_BC_NEUMANN;
+  LineDir hx, hz, hyc, hyf;
   bool singular() const { return bc_lo == IBP_BC_NEUMANN && bc_hi == IBP_BC_NEUMANN; }
   // chunked x/z passes: second stream and dependency events
   int chunk = 0;                   // y planes per chunk (0: whole grid per launch)
@@ -284,17 +296,19 @@ void release(ibp_plan_s* p) {
   if (p->s2) hipStreamDestroy(p->s2);
   if (p->ws_owned && p->ws) hipFree(p->ws);
   if (p->tables) hipFree(p->tables);
+  if (p->helm) hipFree(p->helm);
   delete p;
 }
 
 enum Pass {
   P_XR2C, P_ZFWD, P_Y, P_ZINV, P_XC2R, P_XRES, P_CHECK, P_XRESONLY, P_XC2R_ADD, P_DIV,
-  P_XZF, P_ZXI, P_ZXI_ADD, P_PROJ, P_COUNT
+  P_XZF, P_ZXI, P_ZXI_ADD, P_PROJ, P_VX, P_VZ, P_VY, P_COUNT
 };
 const char* const kPassName[P_COUNT] = {"x_r2c",  "z_fwd",      "y_solve",    "z_inv",
                                         "x_c2r",  "x_resid_r2c", "check",      "x_resid_only",
                                         "x_c2r_add", "divergence", "xz_fwd",   "zx_inv",
-                                        "zx_inv_add", "projection"};
+                                        "zx_inv_add", "projection", "visc_x", "visc_z",
+                                        "visc_y"};
 
 // Algorithmic bytes of one launch of each pass (each input element read
 // once, each output element written once).  N = nx ny nz cells, Nh =
@@ -317,6 +331,9 @@ double pass_bytes(const ibp_plan_s* p, int pass) {
     case P_ZXI: return cb * Nh + 8.0 * N;
     case P_ZXI_ADD: return cb * Nh + 16.0 * N;
     case P_PROJ: return 72.0 * N;                  // phi, u, v, w, p in; u, v, w, p out
+    case P_VX:
+    case P_VZ:
+    case P_VY: return 16.0 * N;                    // the field in and out
     default: return 0.0;
   }
 }
@@ -338,6 +355,87 @@ hipError_t prof_mark(ibp_plan_s* p, int pass, hipStream_t s, bool begin) {
   hipError_t err = hipEventRecord(p->ev_pool[2 * p->ev_used + 1], s);
   p->ev_used++;
   return err;
+}
+
+}  // namespace
+
+namespace {
+
+// LU of one direction's line operator, shared by every line of that
+// direction.  Rows (lo_i, di_i, up_i): lo_i multiplies x_{i-1} and up_i
+// x_{i+1}; in a cyclic matrix lo_0 multiplies x_{n-1} and up_{n-1} x_0.
+// A cyclic matrix is split as B + u v^T (Sherman-Morrison) with gamma =
+// -di_0, u = (gamma, 0.., up_{n-1}), v = (1, 0.., lo_0 / gamma); B is
+// factored by Thomas and B^-1 u folds into w = B^-1 u / (1 + v.B^-1 u), so
+// that x = y - w (y_0 + g y_{n-1}) with y = B^-1 d and g = lo_0 / gamma.
+struct LineLu {
+  std::vector<double> m, s, t, w;
+  double g = 0.0;
+  int cyclic = 0;
+};
+
+LineLu line_lu(std::vector<double> lo, std::vector<double> di, std::vector<double> up, bool cyclic) {
+  const int n = (int)di.size();
+  LineLu L;
+  if (cyclic && n == 1) {   // both neighbours are the point itself
+    di[0] += lo[0] + up[0];
+    cyclic = false;
+  } else if (cyclic && n == 2) {   // both neighbours are the other point
+    up[0] += lo[0];
+    lo[1] += up[1];
+    cyclic = false;
+  }
+  std::vector<double> u;
+  if (cyclic) {
+    const double gamma = -di[0];
+    const double clo = lo[0], cup = up[n - 1];
+    di[0] -= gamma;
+    di[n - 1] -= clo * cup / gamma;
+    u.assign(n, 0.0);
+    u[0] = gamma;
+    u[n - 1] = cup;
+    L.g = clo / gamma;
+    L.cyclic = 1;
+  }
+  lo[0] = 0.0;
+  up[n - 1] = 0.0;
+  L.m.assign(n, 0.0);
+  L.s.assign(n, 0.0);
+  L.t.assign(n, 0.0);
+  L.w.assign(n, 0.0);
+  double den = 0.0;
+  for (int i = 0; i < n; ++i) {
+    den = i == 0 ? di[0] : di[i] - lo[i] * up[i - 1] / den;
+    L.s[i] = 1.0 / den;
+    L.m[i] = -lo[i] / den;
+    L.t[i] = -up[i] / den;
+  }
+  if (cyclic) {
+    std::vector<double> z(n);
+    double prev = 0.0;
+    for (int i = 0; i < n; ++i) prev = z[i] = L.m[i] * prev + L.s[i] * u[i];
+    double nxt = 0.0;
+    for (int i = n - 1; i >= 0; --i) nxt = z[i] = z[i] + L.t[i] * nxt;
+    const double vz = z[0] + L.g * z[n - 1];
+    for (int i = 0; i < n; ++i) L.w[i] = z[i] / (1.0 + vz);
+  }
+  return L;
+}
+
+// Appends the four padded tables of `L` to `buf` and fills `d`.
+void pack_line(ibp_plan_s::LineDir& d, const LineLu& L, int P, int K, std::vector<double>& buf) {
+  d.P = P;
+  d.K = K;
+  d.n = (int)L.m.size();
+  d.cyclic = L.cyclic;
+  d.g = L.g;
+  d.npad = (long)P * K;
+  d.off = (long)buf.size();
+  for (const std::vector<double>* v : {&L.m, &L.s, &L.t, &L.w}) {
+    std::vector<double> pad(d.npad, 0.0);
+    std::copy(v->begin(), v->end(), pad.begin());
+    buf.insert(buf.end(), pad.begin(), pad.end());
+  }
 }
 
 }  // namespace
@@ -439,6 +537,7 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     p->ya_host = a;
     p->yc_host = c;
     p->dyf_host = dyf;
+    p->dyc_host = dyc;
     // ---- closed-form eigenvalues of the periodic second differences
     const long double pi = 3.141592653589793238462643383279502884L;
     std::vector<double> lx(p->hp), lz(nz);
@@ -823,6 +922,117 @@ ibp_status_t ibp_project(ibp_plan_t p, const double* phi, double alpha_dt, doubl
     hipError_t e = prof_mark(p, P_PROJ, s, true);
     if (e == hipSuccess) e = launch_project(a, s);
     if (e == hipSuccess) e = prof_mark(p, P_PROJ, s, false);
+    return from_hip(e);
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+ibp_status_t ibp_helmholtz_set(ibp_plan_t p, double beta) {
+  if (!valid_plan(p)) return IBP_ERROR_INVALID_VALUE;
+  if (!(beta >= 0.0) || !std::isfinite(beta)) return IBP_ERROR_INVALID_VALUE;
+  try {
+    const int nx = p->nx, ny = p->ny, nz = p->nz;
+    int Px, Kx, Pz, Kz, Pc, Kc, Pf = 32, Kf = 2;
+    if (!line_shape(nx, &Px, &Kx) || !line_shape(nz, &Pz, &Kz) || !line_shape(ny, &Pc, &Kc))
+      return IBP_ERROR_UNSUPPORTED_SIZE;
+    const bool faces = p->bc_lo == IBP_BC_NEUMANN && p->bc_hi == IBP_BC_NEUMANN && ny >= 2;
+    if (faces && !line_shape(ny - 1, &Pf, &Kf)) return IBP_ERROR_UNSUPPORTED_SIZE;
+    std::vector<double> buf;
+    ibp_plan_s::LineDir hx, hz, hyc, hyf;
+    {   // periodic second differences along x and z
+      const double rx = beta / (p->dx * p->dx), rz = beta / (p->dz * p->dz);
+      pack_line(hx, line_lu(std::vector<double>(nx, -rx), std::vector<double>(nx, 1.0 + 2.0 * rx),
+                            std::vector<double>(nx, -rx), true), Px, Kx, buf);
+      pack_line(hz, line_lu(std::vector<double>(nz, -rz), std::vector<double>(nz, 1.0 + 2.0 * rz),
+                            std::vector<double>(nz, -rz), true), Pz, Kz, buf);
+    }
+    {   // cell centres: velocity prescribed where the plan's wall is Neumann
+      std::vector<double> a = p->ya_host, c = p->yc_host, lo(ny), di(ny), up(ny);
+      const std::vector<double>& dyf = p->dyf_host;
+      a[0] = p->bc_lo == IBP_BC_NEUMANN ? 1.0 / (dyf[0] * (0.5 * dyf[0])) : 0.0;
+      c[ny - 1] = p->bc_hi == IBP_BC_NEUMANN ? 1.0 / (dyf[ny - 1] * (0.5 * dyf[ny - 1])) : 0.0;
+      for (int j = 0; j < ny; ++j) {
+        lo[j] = -beta * a[j];
+        up[j] = -beta * c[j];
+        di[j] = 1.0 + beta * (a[j] + c[j]);
+      }
+      pack_line(hyc, line_lu(lo, di, up, false), Pc, Kc, buf);
+    }
+    if (faces) {   // interior y faces 1..ny-1, wall faces held at zero
+      const int n = ny - 1;
+      std::vector<double> lo(n), di(n), up(n);
+      for (int r = 0; r < n; ++r) {
+        const int j = r + 1;
+        const double l = 1.0 / (p->dyc_host[j] * p->dyf_host[j - 1]);
+        const double u = 1.0 / (p->dyc_host[j] * p->dyf_host[j]);
+        lo[r] = -beta * l;
+        up[r] = -beta * u;
+        di[r] = 1.0 + beta * (l + u);
+      }
+      pack_line(hyf, line_lu(lo, di, up, false), Pf, Kf, buf);
+    }
+    if (buf.size() > p->helm_doubles) {
+      if (p->helm) hipFree(p->helm);
+      p->helm = nullptr;
+      p->helm_doubles = 0;
+      p->helm_ready = false;
+      hipError_t e = hipMalloc((void**)&p->helm, buf.size() * sizeof(double));
+      if (e != hipSuccess) return from_hip(e);
+      p->helm_doubles = buf.size();
+    }
+    hipError_t e = hipMemcpy(p->helm, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      p->helm_ready = false;
+      return from_hip(e);
+    }
+    p->hx = hx;
+    p->hz = hz;
+    p->hyc = hyc;
+    p->hyf = hyf;
+    p->helm_faces = faces;
+    p->helm_lo = p->bc_lo;
+    p->helm_hi = p->bc_hi;
+    p->helm_ready = true;
+    return IBP_SUCCESS;
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+ibp_status_t ibp_helmholtz(ibp_plan_t p, double* field, ibp_location_t where, void* stream) {
+  if (!valid_plan(p) || field == nullptr || !aligned16(field)) return IBP_ERROR_INVALID_VALUE;
+  if (where != IBP_AT_CELLS && where != IBP_AT_YFACES) return IBP_ERROR_INVALID_VALUE;
+  if (!p->helm_ready || p->helm_lo != p->bc_lo || p->helm_hi != p->bc_hi) return IBP_ERROR_INVALID_VALUE;
+  if (where == IBP_AT_YFACES && !p->helm_faces) return IBP_ERROR_INVALID_VALUE;
+  try {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return from_hip(e);
+    if (dev != p->device) return IBP_ERROR_INVALID_VALUE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const long plane = (long)p->nx * p->nz;
+    const bool cells = where == IBP_AT_CELLS;
+    const int planes = cells ? p->ny : p->ny - 1;
+    double* base = cells ? field : field + plane;
+    const ibp_plan_s::LineDir& hy = cells ? p->hyc : p->hyf;
+    LineArgs ax{base, p->helm + p->hx.off, p->hx.npad, p->nx, p->hx.cyclic, p->hx.g, 0, 0, (long)planes * p->nz, 0};
+    LineArgs az{base, p->helm + p->hz.off, p->hz.npad, p->nz, p->hz.cyclic, p->hz.g, planes, plane, p->nx, p->nx};
+    LineArgs ay{base, p->helm + hy.off, hy.npad, planes, 0, 0.0, 1, 0, plane, plane};
+    if (!cells) {   // the increment vanishes on the wall faces
+      e = launch_fill_zero(field, plane, s);
+      if (e == hipSuccess) e = launch_fill_zero(field + (long)p->ny * plane, plane, s);
+      if (e != hipSuccess) return from_hip(e);
+    }
+    e = prof_mark(p, P_VX, s, true);
+    if (e == hipSuccess) e = launch_lines_contig(p->hx.P, p->hx.K, ax, s);
+    if (e == hipSuccess) e = prof_mark(p, P_VX, s, false);
+    if (e == hipSuccess) e = prof_mark(p, P_VZ, s, true);
+    if (e == hipSuccess) e = launch_lines_strided(p->hz.P, p->hz.K, az, s);
+    if (e == hipSuccess) e = prof_mark(p, P_VZ, s, false);
+    if (e == hipSuccess) e = prof_mark(p, P_VY, s, true);
+    if (e == hipSuccess) e = launch_lines_strided(hy.P, hy.K, ay, s);
+    if (e == hipSuccess) e = prof_mark(p, P_VY, s, false);
     return from_hip(e);
   } catch (...) {
     return IBP_ERROR_INTERNAL;

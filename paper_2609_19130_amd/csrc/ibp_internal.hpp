@@ -304,6 +304,27 @@ struct ProjArgs {
 };
 hipError_t launch_project(const ProjArgs& a, hipStream_t s);
 
+// Factored viscous solve: apply one direction's precomputed line LU in place.
+// `lu` holds four zero-padded tables of `npad` entries: forward multipliers
+// m, pivot reciprocals s, back-substitution multipliers t and the periodic
+// (Sherman-Morrison) correction w.
+struct LineArgs {
+  double* f;
+  const double* lu;
+  long npad;
+  int n;                 // line length
+  int cyclic;            // apply x -= w (x_0 + g x_{n-1})
+  double g;
+  long nouter;           // strided lines: outer count and stride
+  long ostride;
+  long ncol;             // strided: columns per outer index; contiguous: number of lines
+  long stride;           // strided: element stride along a line
+};
+int line_shape(int n, int* P, int* K);   // lanes and rows per lane for lines of n (0: too long)
+hipError_t launch_lines_contig(int P, int K, const LineArgs& a, hipStream_t s);
+hipError_t launch_lines_strided(int P, int K, const LineArgs& a, hipStream_t s);
+hipError_t launch_fill_zero(double* p, long n, hipStream_t s);
+
 // ---------------------------------------------------------------- launchers
 constexpr int kTileX64 = 2048, kTileX32 = 4096;   // complex elements per x-pass block
 constexpr int kTileZ64 = 4096, kTileZ32 = 8192;   // complex elements per z-pass block

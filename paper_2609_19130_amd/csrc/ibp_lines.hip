@@ -1,0 +1,268 @@
+// Factored implicit viscous solve: one tridiagonal system per grid line and
+// direction (paper: Crank-Nicolson viscous terms of eq. nstime_discr, split
+// into direction-wise Thomas solves with a Sherman-Morrison correction in the
+// two periodic directions; "Fluid domain" parallelisation subsection).
+//
+// Every line of one direction has the same matrix, so its LU is factored once
+// on the host (FP64) and the kernels only apply it:
+//   forward   y'_i = m_i y'_{i-1} + s_i d_i        (m_0 = 0)
+//   backward  y_i  = y'_i + t_i y_{i+1}            (t_{n-1} = 0)
+//   cyclic    x_i  = y_i - w_i (y_0 + g y_{n-1})   (Sherman-Morrison)
+// A line's rows are split over P lanes of one wave, K rows each; the two
+// affine recurrences are composed per lane, chained across the lanes with
+// wave shuffles and re-swept, as in the spectral line solve.  Tables are
+// zero-padded to P*K rows, so padding rows stay zero and decouple.
+#include "ibp_internal.hpp"
+
+namespace ibp {
+
+namespace {
+
+template <int P, int K, typename Slot>
+__device__ __forceinline__ void apply_line_lu(const LineArgs& A, double* tile, Slot slot, int m, int p) {
+  const double* tm = A.lu;
+  const double* ts = A.lu + A.npad;
+  const double* tt = A.lu + 2 * A.npad;
+  const double* tw = A.lu + 3 * A.npad;
+  const int s0 = p * K;
+  double d[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) d[i] = tile[slot(m, p, i)];
+  // ---- forward: y'_out = mu y'_in + nu over the lane's rows
+  {
+    double mu = 1.0, nu = 0.0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const double mi = tm[s0 + i];
+      nu = mi * nu + ts[s0 + i] * d[i];
+      mu = mi * mu;
+    }
+#pragma unroll
+    for (int off = 1; off < P; off <<= 1) {   // inclusive prefix: mine after the earlier ones
+      const double pm = __shfl_up(mu, off, P), pn = __shfl_up(nu, off, P);
+      if (p >= off) {
+        nu = mu * pn + nu;
+        mu = mu * pm;
+      }
+    }
+    double prev = __shfl_up(nu, 1, P);
+    if (p == 0) prev = 0.0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      d[i] = tm[s0 + i] * prev + ts[s0 + i] * d[i];
+      prev = d[i];
+    }
+  }
+  // ---- backward: y_first = T y_below + S over the lane's rows
+  {
+    double T = 1.0, S = 0.0;
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) {
+      const double ti = tt[s0 + i];
+      S = d[i] + ti * S;
+      T = ti * T;
+    }
+#pragma unroll
+    for (int off = 1; off < P; off <<= 1) {   // inclusive suffix: mine before the later ones
+      const double nT = __shfl_down(T, off, P), nS = __shfl_down(S, off, P);
+      if (p + off < P) {
+        S = T * nS + S;
+        T = T * nT;
+      }
+    }
+    double nxt = __shfl_down(S, 1, P);
+    if (p == P - 1) nxt = 0.0;
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) {
+      d[i] = d[i] + tt[s0 + i] * nxt;
+      nxt = d[i];
+    }
+  }
+  // ---- periodic lines: Sherman-Morrison correction from the two end values
+  if (A.cyclic) {
+    const int last = A.n - 1, lp = last / K, li = last - lp * K;
+    double mine = 0.0;
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+      if (i == li) mine = d[i];
+    const double y0 = __shfl(d[0], 0, P);
+    const double yl = __shfl(mine, lp, P);
+    const double sc = y0 + A.g * yl;
+#pragma unroll
+    for (int i = 0; i < K; ++i) d[i] -= tw[s0 + i] * sc;
+  }
+#pragma unroll
+  for (int i = 0; i < K; ++i) tile[slot(m, p, i)] = d[i];
+}
+
+// Lines contiguous in memory (x direction): block = M lines, line L at
+// f + L n.  LDS tile line-major, one pad slot per lane chunk (odd stride
+// K + 1, so the chunk reads fall on distinct banks).
+template <int M, int P, int K>
+__global__ __launch_bounds__(M * P) void k_lines_contig(LineArgs A) {
+  constexpr int NT = M * P;
+  constexpr int CS = K + 1;
+  constexpr int LS = P * CS;
+  __shared__ double tile[M * LS];
+  const long L0 = (long)blockIdx.x * M;
+  const int n = A.n;
+  const long nl = A.ncol;   // number of lines
+  const int nm = (int)((nl - L0) < M ? (nl - L0) : M);   // lines in this block
+  const long span = (long)nm * n;                         // contiguous doubles, n even
+  const double2* src = reinterpret_cast<const double2*>(A.f + L0 * n);
+  for (long e2 = threadIdx.x; 2 * e2 < span; e2 += NT) {
+    const double2 v = src[e2];
+    const long e = 2 * e2;
+    const int m = (int)(e / n), pos = (int)(e - (long)m * n);
+    const int pp = pos / K, r = pos - pp * K;   // K even: pos, pos + 1 share a chunk
+    tile[m * LS + pp * CS + r] = v.x;
+    tile[m * LS + pp * CS + r + 1] = v.y;
+  }
+  for (int e = threadIdx.x; e < M * (P * K - n); e += NT) {   // padding rows
+    const int m = e / (P * K - n), pos = n + (e - m * (P * K - n));
+    const int pp = pos / K;
+    tile[m * LS + pp * CS + (pos - pp * K)] = 0.0;
+  }
+  __syncthreads();
+  {
+    const int p = threadIdx.x % P, m = threadIdx.x / P;
+    auto slot = [](int mm, int pp, int i) { return mm * LS + pp * CS + i; };
+    if (m < nm) apply_line_lu<P, K>(A, tile, slot, m, p);
+  }
+  __syncthreads();
+  double2* dst = reinterpret_cast<double2*>(A.f + L0 * n);
+  for (long e2 = threadIdx.x; 2 * e2 < span; e2 += NT) {
+    const long e = 2 * e2;
+    const int m = (int)(e / n), pos = (int)(e - (long)m * n);
+    const int pp = pos / K, r = pos - pp * K;
+    dst[e2] = double2{tile[m * LS + pp * CS + r], tile[m * LS + pp * CS + r + 1]};
+  }
+}
+
+// Lines strided in memory (z and y directions): line (o, c) holds
+// f[o * ostride + c + t * stride], t < n; a block owns M consecutive columns
+// c of one outer index o (M * 8 contiguous bytes per row).  LDS tile
+// partition-major with one pad slot per partition, as in the spectral line
+// solve.
+template <int M, int P, int K>
+__global__ __launch_bounds__(M * P) void k_lines_strided(LineArgs A) {
+  constexpr int PS = K * M + 1;
+  __shared__ double tile[P * PS];
+  const long ncg = (A.ncol + M - 1) / M;
+  const long o = (long)blockIdx.x / ncg;
+  const long c0 = ((long)blockIdx.x - o * ncg) * M;
+  double* base = A.f + o * A.ostride + c0;
+  const int n = A.n;
+  {
+    const int mm = threadIdx.x % M, row0 = threadIdx.x / M;
+    const bool colok = c0 + mm < A.ncol;
+    double ld[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int row = row0 + P * i;
+      ld[i] = (colok && row < n) ? base[(long)row * A.stride + mm] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int row = row0 + P * i;
+      const int pp = row / K;
+      tile[pp * PS + (row - pp * K) * M + mm] = ld[i];
+    }
+  }
+  __syncthreads();
+  {
+    const int p = threadIdx.x % P, m = threadIdx.x / P;
+    auto slot = [](int mm, int pp, int i) { return pp * PS + i * M + mm; };
+    if (c0 + m < A.ncol) apply_line_lu<P, K>(A, tile, slot, m, p);
+  }
+  __syncthreads();
+  {
+    const int mm = threadIdx.x % M, row0 = threadIdx.x / M;
+    if (c0 + mm < A.ncol) {
+      double st[K];
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const int row = row0 + P * i;
+        const int pp = row / K;
+        st[i] = tile[pp * PS + (row - pp * K) * M + mm];
+      }
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const int row = row0 + P * i;
+        if (row < n) base[(long)row * A.stride + mm] = st[i];
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill_zero(double* p, long n) {
+  for (long e = (long)blockIdx.x * kThreads + threadIdx.x; e < n; e += (long)gridDim.x * kThreads) p[e] = 0.0;
+}
+
+template <int M, int P>
+hipError_t contig_k(int K, const LineArgs& a, hipStream_t s) {
+  const long nb = (a.ncol + M - 1) / M;
+  switch (K) {
+#define IBP_CASE(k) \
+  case k: hipLaunchKernelGGL((k_lines_contig<M, P, k>), dim3((unsigned)nb), dim3(M * P), 0, s, a); break;
+    IBP_CASE(2) IBP_CASE(4) IBP_CASE(8) IBP_CASE(12) IBP_CASE(16) IBP_CASE(24)
+#undef IBP_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int M, int P>
+hipError_t strided_k(int K, const LineArgs& a, hipStream_t s) {
+  const long nb = a.nouter * ((a.ncol + M - 1) / M);
+  switch (K) {
+#define IBP_CASE(k) \
+  case k: hipLaunchKernelGGL((k_lines_strided<M, P, k>), dim3((unsigned)nb), dim3(M * P), 0, s, a); break;
+    IBP_CASE(2) IBP_CASE(4) IBP_CASE(8) IBP_CASE(12) IBP_CASE(16) IBP_CASE(24)
+#undef IBP_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int line_shape(int n, int* P, int* K) {
+  static const int ks[] = {2, 4, 8, 12, 16, 24};
+  for (int pl : {32, 64}) {
+    if (pl == 32 && n > 32 * 16) continue;   // longer lines: 64 lanes
+    for (int k : ks)
+      if (pl * k >= n) {
+        *P = pl;
+        *K = k;
+        return 1;
+      }
+  }
+  return 0;
+}
+
+hipError_t launch_lines_contig(int P, int K, const LineArgs& a, hipStream_t s) {
+  if (a.ncol <= 0) return hipSuccess;
+  if (a.n % 2 != 0 || (long)P * K < a.n) return hipErrorInvalidValue;
+  if (P == 32) return contig_k<8, 32>(K, a, s);
+  if (P == 64) return contig_k<4, 64>(K, a, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_lines_strided(int P, int K, const LineArgs& a, hipStream_t s) {
+  if (a.ncol <= 0 || a.nouter <= 0) return hipSuccess;
+  if ((long)P * K < a.n) return hipErrorInvalidValue;
+  if (P == 32) return strided_k<16, 32>(K, a, s);
+  if (P == 64) return strided_k<8, 64>(K, a, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fill_zero(double* p, long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  long nb = (n + kThreads - 1) / kThreads;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)nb), dim3(kThreads), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace ibp

@@ -12,6 +12,7 @@ import os
 
 FP64, MIXED, MIXED_F64SWEEP = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "mixed": MIXED, "mixed_f64sweep": MIXED_F64SWEEP}
+LOCATIONS = {"cells": 0, "yfaces": 1}   # ibp_location_t
 
 SUCCESS, INVALID_VALUE, UNSUPPORTED_SIZE, OUT_OF_MEMORY, HIP_ERROR, INTERNAL = range(6)
 
@@ -72,6 +73,8 @@ def lib():
         "ibp_divergence": (ci, [vp, vp, vp, vp, vp, vp]),
         "ibp_solve_divergence": (ci, [vp, vp, vp, vp, vp, cd, vp, vp, vp]),
         "ibp_project": (ci, [vp, vp, cd, cd, vp, vp, vp, vp, vp]),
+        "ibp_helmholtz_set": (ci, [vp, cd]),
+        "ibp_helmholtz": (ci, [vp, vp, ci, vp]),
         "ibp_plan_set_profiling": (ci, [vp, ci]),
         "ibp_plan_get_profile": (ci, [vp, ci, ctypes.POINTER(ci), ctypes.POINTER(PassStat)]),
         "ibp_batch_create": (ci, [ctypes.POINTER(vp), ci, ctypes.POINTER(vp)]),
@@ -255,6 +258,21 @@ class Plan:
                                  _field(w, self.shape, "w"),
                                  _field(p, self.shape, "p") if p is not None else None, _stream_ptr(stream)),
                "ibp_project")
+
+    def helmholtz_set(self, beta):
+        """Factor the three directions' line operators for beta (ibp_helmholtz_set)."""
+        _check(lib().ibp_helmholtz_set(self.handle, float(beta)), "ibp_helmholtz_set")
+
+    def helmholtz(self, field, where="cells", stream=None):
+        """In place: field <- (1 - beta L_y)^-1 (1 - beta L_z)^-1 (1 - beta L_x)^-1 field
+        (ibp_helmholtz); where = "cells" ([ny][nz][nx]) or "yfaces" ([ny+1][nz][nx])."""
+        ny, nz, nx = self.shape
+        if where not in LOCATIONS:
+            raise ValueError("where must be 'cells' or 'yfaces'")
+        shape = self.shape if where == "cells" else (ny + 1, nz, nx)
+        _check(lib().ibp_helmholtz(self.handle, _field(field, shape, "field"), LOCATIONS[where],
+                                   _stream_ptr(stream)), "ibp_helmholtz")
+        return field
 
     def close(self):
         if getattr(self, "_h", None) is not None:

@@ -90,6 +90,8 @@ def test_null_plan_calls_fail_cleanly():
     assert L.ibp_plan_set_bc(None, 0, 1) == ibp.INVALID_VALUE
     assert L.ibp_solve_divergence(None, None, None, None, None, 1.0, None, None, None) == ibp.INVALID_VALUE
     assert L.ibp_project(None, None, 1.0, 0.0, None, None, None, None, None) == ibp.INVALID_VALUE
+    assert L.ibp_helmholtz_set(None, 0.1) == ibp.INVALID_VALUE
+    assert L.ibp_helmholtz(None, None, 0, None) == ibp.INVALID_VALUE
     t = ibp.Tune()
     assert L.ibp_plan_autotune(None, None, None, None, ctypes.byref(t)) == ibp.INVALID_VALUE
     assert L.ibp_batch_autotune(None, None, None, None, ctypes.byref(t)) == ibp.INVALID_VALUE
