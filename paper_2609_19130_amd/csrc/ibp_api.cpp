@@ -431,11 +431,36 @@ void pack_line(ibp_plan_s::LineDir& d, const LineLu& L, int P, int K, std::vecto
   d.g = L.g;
   d.npad = (long)P * K;
   d.off = (long)buf.size();
+  // zero-padded to P K rows, chunk-row major: entry i P + p is row p K + i
+  std::vector<std::vector<double>> padded;
   for (const std::vector<double>* v : {&L.m, &L.s, &L.t, &L.w}) {
     std::vector<double> pad(d.npad, 0.0);
-    std::copy(v->begin(), v->end(), pad.begin());
+    for (int r = 0; r < d.n; ++r) pad[(long)(r % K) * P + r / K] = (*v)[r];
     buf.insert(buf.end(), pad.begin(), pad.end());
+    padded.push_back(pad);
   }
+  // Multipliers of the lane scans, step by step: the product of m (forward)
+  // or t (backward) over the rows that lane p's running composite covers
+  // before each step, composed in the kernels' order.
+  const int S = P == 64 ? 6 : 5;
+  std::vector<double> mu(P, 1.0), T(P, 1.0), mf((size_t)S * P), mb((size_t)S * P);
+  for (int p = 0; p < P; ++p) {
+    for (int i = 0; i < K; ++i) mu[p] = padded[0][(size_t)i * P + p] * mu[p];
+    for (int i = K - 1; i >= 0; --i) T[p] = padded[2][(size_t)i * P + p] * T[p];
+  }
+  for (int st = 0, off = 1; off < P; ++st, off <<= 1) {
+    std::vector<double> mu2 = mu, T2 = T;
+    for (int p = 0; p < P; ++p) {
+      mf[(size_t)st * P + p] = mu[p];
+      mb[(size_t)st * P + p] = T[p];
+      if (p >= off) mu2[p] = mu[p] * mu[p - off];
+      if (p + off < P) T2[p] = T[p] * T[p + off];
+    }
+    mu = mu2;
+    T = T2;
+  }
+  buf.insert(buf.end(), mf.begin(), mf.end());
+  buf.insert(buf.end(), mb.begin(), mb.end());
 }
 
 }  // namespace

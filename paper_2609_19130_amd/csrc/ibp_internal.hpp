@@ -305,9 +305,10 @@ struct ProjArgs {
 hipError_t launch_project(const ProjArgs& a, hipStream_t s);
 
 // Factored viscous solve: apply one direction's precomputed line LU in place.
-// `lu` holds four zero-padded tables of `npad` entries: forward multipliers
-// m, pivot reciprocals s, back-substitution multipliers t and the periodic
-// (Sherman-Morrison) correction w.
+// `lu` holds four zero-padded tables of `npad` = P K entries (forward
+// multipliers m, pivot reciprocals s, back-substitution multipliers t, the
+// periodic Sherman-Morrison correction w), then the forward and backward
+// lane-scan multipliers (log2 P steps of P entries each).
 struct LineArgs {
   double* f;
   const double* lu;

@@ -11,70 +11,73 @@
 // A line's rows are split over P lanes of one wave, K rows each; the two
 // affine recurrences are composed per lane, chained across the lanes with
 // wave shuffles and re-swept, as in the spectral line solve.  Tables are
-// zero-padded to P*K rows, so padding rows stay zero and decouple.
+// zero-padded to P*K rows, so padding rows stay zero and decouple, and stored
+// chunk-row major (entry i * P + p holds row p * K + i), so that the lanes of
+// one line read a table row as one contiguous 8P-byte segment.  The products
+// of the multipliers that the lane scans compose do not depend on the data,
+// so the host tabulates them per scan step and only the data term crosses
+// lanes.
 #include "ibp_internal.hpp"
 
 namespace ibp {
 
 namespace {
 
+template <int P>
+constexpr int scan_steps() { return P == 64 ? 6 : 5; }
+
+// Doubles of one direction's tables for P lanes of K rows.
+template <int P, int K>
+constexpr int line_table_size() { return 4 * P * K + 2 * scan_steps<P>() * P; }
+
+// `tab`: the direction's tables (global or an LDS copy): m, s, t, w (P K
+// each), then the forward and backward scan multipliers (scan_steps * P each).
 template <int P, int K, typename Slot>
-__device__ __forceinline__ void apply_line_lu(const LineArgs& A, double* tile, Slot slot, int m, int p) {
-  const double* tm = A.lu;
-  const double* ts = A.lu + A.npad;
-  const double* tt = A.lu + 2 * A.npad;
-  const double* tw = A.lu + 3 * A.npad;
-  const int s0 = p * K;
+__device__ __forceinline__ void apply_line_lu(const LineArgs& A, const double* tab, double* tile, Slot slot, int m,
+                                              int p) {
+  constexpr int NP = P * K, S = scan_steps<P>();
+  const double* tm = tab;
+  const double* ts = tab + NP;
+  const double* tt = tab + 2 * NP;
+  const double* tw = tab + 3 * NP;
+  const double* mf = tab + 4 * NP;
+  const double* mb = mf + S * P;
   double d[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) d[i] = tile[slot(m, p, i)];
-  // ---- forward: y'_out = mu y'_in + nu over the lane's rows
+  // ---- forward: y'_out = mu y'_in + nu over the lane's rows (mu tabulated)
   {
-    double mu = 1.0, nu = 0.0;
+    double nu = 0.0;
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      const double mi = tm[s0 + i];
-      nu = mi * nu + ts[s0 + i] * d[i];
-      mu = mi * mu;
-    }
+    for (int i = 0; i < K; ++i) nu = tm[i * P + p] * nu + ts[i * P + p] * d[i];
 #pragma unroll
-    for (int off = 1; off < P; off <<= 1) {   // inclusive prefix: mine after the earlier ones
-      const double pm = __shfl_up(mu, off, P), pn = __shfl_up(nu, off, P);
-      if (p >= off) {
-        nu = mu * pn + nu;
-        mu = mu * pm;
-      }
+    for (int st = 0, off = 1; off < P; ++st, off <<= 1) {   // inclusive prefix: mine after the earlier ones
+      const double pn = __shfl_up(nu, off, P);
+      if (p >= off) nu = mf[st * P + p] * pn + nu;
     }
     double prev = __shfl_up(nu, 1, P);
     if (p == 0) prev = 0.0;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      d[i] = tm[s0 + i] * prev + ts[s0 + i] * d[i];
+      d[i] = tm[i * P + p] * prev + ts[i * P + p] * d[i];
       prev = d[i];
     }
   }
-  // ---- backward: y_first = T y_below + S over the lane's rows
+  // ---- backward: y_first = T y_below + V over the lane's rows (T tabulated)
   {
-    double T = 1.0, S = 0.0;
+    double V = 0.0;
 #pragma unroll
-    for (int i = K - 1; i >= 0; --i) {
-      const double ti = tt[s0 + i];
-      S = d[i] + ti * S;
-      T = ti * T;
-    }
+    for (int i = K - 1; i >= 0; --i) V = d[i] + tt[i * P + p] * V;
 #pragma unroll
-    for (int off = 1; off < P; off <<= 1) {   // inclusive suffix: mine before the later ones
-      const double nT = __shfl_down(T, off, P), nS = __shfl_down(S, off, P);
-      if (p + off < P) {
-        S = T * nS + S;
-        T = T * nT;
-      }
+    for (int st = 0, off = 1; off < P; ++st, off <<= 1) {   // inclusive suffix: mine before the later ones
+      const double nv = __shfl_down(V, off, P);
+      if (p + off < P) V = mb[st * P + p] * nv + V;
     }
-    double nxt = __shfl_down(S, 1, P);
+    double nxt = __shfl_down(V, 1, P);
     if (p == P - 1) nxt = 0.0;
 #pragma unroll
     for (int i = K - 1; i >= 0; --i) {
-      d[i] = d[i] + tt[s0 + i] * nxt;
+      d[i] = d[i] + tt[i * P + p] * nxt;
       nxt = d[i];
     }
   }
@@ -89,7 +92,7 @@ __device__ __forceinline__ void apply_line_lu(const LineArgs& A, double* tile, S
     const double yl = __shfl(mine, lp, P);
     const double sc = y0 + A.g * yl;
 #pragma unroll
-    for (int i = 0; i < K; ++i) d[i] -= tw[s0 + i] * sc;
+    for (int i = 0; i < K; ++i) d[i] -= tw[i * P + p] * sc;
   }
 #pragma unroll
   for (int i = 0; i < K; ++i) tile[slot(m, p, i)] = d[i];
@@ -104,38 +107,44 @@ __global__ __launch_bounds__(M * P) void k_lines_contig(LineArgs A) {
   constexpr int CS = K + 1;
   constexpr int LS = P * CS;
   __shared__ double tile[M * LS];
+  constexpr int NPAIR = P * K / 2;   // pairs per padded line
+  constexpr int IT = M * NPAIR / NT;  // = K / 2 pairs per thread
   const long L0 = (long)blockIdx.x * M;
-  const int n = A.n;
-  const long nl = A.ncol;   // number of lines
+  const int n = A.n;                  // even, <= P K
+  const long nl = A.ncol;             // number of lines
   const int nm = (int)((nl - L0) < M ? (nl - L0) : M);   // lines in this block
-  const long span = (long)nm * n;                         // contiguous doubles, n even
   const double2* src = reinterpret_cast<const double2*>(A.f + L0 * n);
-  for (long e2 = threadIdx.x; 2 * e2 < span; e2 += NT) {
-    const double2 v = src[e2];
-    const long e = 2 * e2;
-    const int m = (int)(e / n), pos = (int)(e - (long)m * n);
-    const int pp = pos / K, r = pos - pp * K;   // K even: pos, pos + 1 share a chunk
-    tile[m * LS + pp * CS + r] = v.x;
-    tile[m * LS + pp * CS + r + 1] = v.y;
-  }
-  for (int e = threadIdx.x; e < M * (P * K - n); e += NT) {   // padding rows
-    const int m = e / (P * K - n), pos = n + (e - m * (P * K - n));
-    const int pp = pos / K;
-    tile[m * LS + pp * CS + (pos - pp * K)] = 0.0;
+  {
+    double2 ld[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {   // all loads issued before the first LDS write
+      const int e2 = threadIdx.x + NT * it;
+      const int m = e2 / NPAIR, pos = 2 * (e2 - m * NPAIR);
+      ld[it] = (m < nm && pos < n) ? src[(long)m * (n / 2) + pos / 2] : double2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e2 = threadIdx.x + NT * it;
+      const int m = e2 / NPAIR, pos = 2 * (e2 - m * NPAIR);
+      const int pp = pos / K, r = pos - pp * K;   // K even: pos, pos + 1 share a chunk
+      tile[m * LS + pp * CS + r] = ld[it].x;
+      tile[m * LS + pp * CS + r + 1] = ld[it].y;
+    }
   }
   __syncthreads();
   {
     const int p = threadIdx.x % P, m = threadIdx.x / P;
     auto slot = [](int mm, int pp, int i) { return mm * LS + pp * CS + i; };
-    if (m < nm) apply_line_lu<P, K>(A, tile, slot, m, p);
+    if (m < nm) apply_line_lu<P, K>(A, A.lu, tile, slot, m, p);
   }
   __syncthreads();
   double2* dst = reinterpret_cast<double2*>(A.f + L0 * n);
-  for (long e2 = threadIdx.x; 2 * e2 < span; e2 += NT) {
-    const long e = 2 * e2;
-    const int m = (int)(e / n), pos = (int)(e - (long)m * n);
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e2 = threadIdx.x + NT * it;
+    const int m = e2 / NPAIR, pos = 2 * (e2 - m * NPAIR);
     const int pp = pos / K, r = pos - pp * K;
-    dst[e2] = double2{tile[m * LS + pp * CS + r], tile[m * LS + pp * CS + r + 1]};
+    if (m < nm && pos < n) dst[(long)m * (n / 2) + pos / 2] = double2{tile[m * LS + pp * CS + r], tile[m * LS + pp * CS + r + 1]};
   }
 }
 
@@ -147,21 +156,40 @@ __global__ __launch_bounds__(M * P) void k_lines_contig(LineArgs A) {
 template <int M, int P, int K>
 __global__ __launch_bounds__(M * P) void k_lines_strided(LineArgs A) {
   constexpr int PS = K * M + 1;
+  constexpr int NT = M * P, NTAB = line_table_size<P, K>();
+  constexpr int TIT = (NTAB + NT - 1) / NT;
   __shared__ double tile[P * PS];
+  __shared__ double tab[NTAB];   // the tables, staged once per block with the data loads
   const long ncg = (A.ncol + M - 1) / M;
   const long o = (long)blockIdx.x / ncg;
   const long c0 = ((long)blockIdx.x - o * ncg) * M;
   double* base = A.f + o * A.ostride + c0;
   const int n = A.n;
   {
+    // every load is issued before the first wait: data from clamped (always
+    // valid) addresses, values past the line or the last column discarded,
+    // then the tables
     const int mm = threadIdx.x % M, row0 = threadIdx.x / M;
     const bool colok = c0 + mm < A.ncol;
-    double ld[K];
+    const int mc = colok ? mm : 0;
+    double ld[K], tl[TIT];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       const int row = row0 + P * i;
-      ld[i] = (colok && row < n) ? base[(long)row * A.stride + mm] : 0.0;
+      ld[i] = base[(long)(row < n ? row : n - 1) * A.stride + mc];
     }
+#pragma unroll
+    for (int it = 0; it < TIT; ++it) {
+      const int e = threadIdx.x + NT * it;
+      tl[it] = A.lu[e < NTAB ? e : NTAB - 1];
+    }
+#pragma unroll
+    for (int it = 0; it < TIT; ++it) {   // threads past the end rewrite the last entry with its own value
+      const int e = threadIdx.x + NT * it;
+      tab[e < NTAB ? e : NTAB - 1] = tl[it];
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) ld[i] = (colok && row0 + P * i < n) ? ld[i] : 0.0;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       const int row = row0 + P * i;
@@ -173,7 +201,7 @@ __global__ __launch_bounds__(M * P) void k_lines_strided(LineArgs A) {
   {
     const int p = threadIdx.x % P, m = threadIdx.x / P;
     auto slot = [](int mm, int pp, int i) { return pp * PS + i * M + mm; };
-    if (c0 + m < A.ncol) apply_line_lu<P, K>(A, tile, slot, m, p);
+    if (c0 + m < A.ncol) apply_line_lu<P, K>(A, tab, tile, slot, m, p);
   }
   __syncthreads();
   {
