@@ -30,7 +30,7 @@ if ROOT not in sys.path:
 
 METRIC = "Poisson solves/s + HBM GB/s at 512x384x512, mixed vs FP64 at 1e-10 resid"
 HBM_PEAK_GBS = 8000.0
-SOURCES = ["ibp_api.cpp", "ibp_xz.hip", "ibp_fastxz.hip", "ibp_ytri.hip", "ibp_misc.hip", "ibp_device.hpp",
+SOURCES = ["ibp_api.cpp", "ibp_xz.hip", "ibp_fastxz.hip", "ibp_ytri.hip", "ibp_misc.hip", "ibp_lines.hip", "ibp_device.hpp",
            "ibp_internal.hpp", "ibp_regfft.hpp"]
 
 
@@ -400,6 +400,37 @@ def main():
             torch.cuda.synchronize()
             substep[name + "_ms"] = a0.elapsed_time(b0) / args.steps
         log(f"[bench] substep (rhs + solve + projection): {substep}")
+        # implicit viscous step: factored line solves of the three velocity
+        # components (eq. nstime_discr with Crank-Nicolson terms), beta =
+        # alpha dt / (2 Re) = 1e-4; the cost does not depend on beta
+        plan.helmholtz_set(1e-4)
+
+        def viscous():
+            plan.helmholtz(ud, "cells")
+            plan.helmholtz(vd, "yfaces")
+            plan.helmholtz(wd, "cells")
+
+        for _ in range(2):
+            viscous()
+        torch.cuda.synchronize()
+        a0 = torch.cuda.Event(enable_timing=True)
+        b0 = torch.cuda.Event(enable_timing=True)
+        a0.record()
+        for _ in range(args.steps):
+            viscous()
+        b0.record()
+        torch.cuda.synchronize()
+        substep["viscous_uvw_ms"] = a0.elapsed_time(b0) / args.steps
+        plan.set_profiling(True)
+        for _ in range(args.steps):
+            viscous()
+        vprof = plan.profile()
+        plan.set_profiling(False)
+        substep["viscous_passes"] = {
+            k: {"avg_ms": v["total_ms"] / v["launches"], "launches": v["launches"],
+                "gbs": v["bytes_per_launch"] / (v["total_ms"] / v["launches"] * 1e-3) / 1e9}
+            for k, v in vprof.items()}
+        log(f"[bench] viscous u, v, w: {substep['viscous_uvw_ms']:.3f} ms, passes {substep['viscous_passes']}")
     del ud, vd, wd
 
     N = nx * ny * nz

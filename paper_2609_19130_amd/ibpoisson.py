@@ -216,9 +216,9 @@ class Plan:
     def profile(self):
         """Per-pass launch counts, summed event times and algorithmic bytes
         since profiling was enabled or last queried (synchronises)."""
-        arr = (PassStat * 16)()
+        arr = (PassStat * 32)()
         n = ctypes.c_int()
-        _check(lib().ibp_plan_get_profile(self.handle, 16, ctypes.byref(n), arr), "ibp_plan_get_profile")
+        _check(lib().ibp_plan_get_profile(self.handle, 32, ctypes.byref(n), arr), "ibp_plan_get_profile")
         return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms,
                                            bytes_per_launch=arr[i].bytes_per_launch) for i in range(n.value)}
 
