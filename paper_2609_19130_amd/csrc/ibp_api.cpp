@@ -22,15 +22,18 @@ namespace {
 
 constexpr int kVersion = 100;  // 0.1.0
 
-// Radix factorisation for the LDS FFT: eights first, then fours, twos and the
-// odd primes.  Returns false if n has a prime factor above 11.
+// Radix factorisation for the LDS FFT: eights first, then fours, twos, the
+// odd primes with butterflies of their own (3, 5, 7, 11), then any larger
+// prime factors (direct-sum stages).  Returns false only past 16 stages.
 bool factorize(int n, FftPlan* fp) {
   fp->n = n;
   fp->nst = 0;
+  fp->any = 0;
   int m = n;
   auto push = [&](int r) {
     if (fp->nst >= 16) return false;
     fp->radix[fp->nst++] = r;
+    if (r > 11) fp->any = 1;
     m /= r;
     return true;
   };
@@ -43,6 +46,10 @@ bool factorize(int n, FftPlan* fp) {
   for (int p : {3, 5, 7, 11})
     while (m % p == 0)
       if (!push(p)) return false;
+  for (int p = 13; p * p <= m; p += 2)
+    while (m % p == 0)
+      if (!push(p)) return false;
+  if (m > 1 && !push(m)) return false;   // the remaining prime
   return m == 1;
 }
 
@@ -159,6 +166,14 @@ hipError_t reset_counters(ibp_plan_s* p) {
   return e;
 }
 
+// Rows (x) or columns (z) per block of the general LDS transforms: whole
+// tiles, or half tiles when the length has a prime factor above 11 (the
+// direct-sum stage writes into the other half).
+int x_tile_rows(const ibp_plan_s* p, int tile) { return (p->fpx.any ? tile / 2 : tile) / p->h; }
+int z_tile_cols(const ibp_plan_s* p, int tile) {
+  return p->fpz.any ? (tile / 2) / (p->nz + 1) : tile / p->nz;
+}
+
 size_t spec_bytes(const ibp_plan_s* p) {
   const size_t b64 = (size_t)p->ny * spec_plane_stride<double>(p->hp, p->nz) * sizeof(Cx<double>);
   const size_t b32 = (size_t)p->ny * spec_plane_stride<float>(p->hp, p->nz) * sizeof(Cx<float>);
@@ -204,6 +219,9 @@ ibp_status_t check_dims(int nx, int ny, int nz, FftPlan* fpx, FftPlan* fpz) {
   if (ny < 2 || ny > kMaxNy) return IBP_ERROR_UNSUPPORTED_SIZE;
   FftPlan a{}, b{};
   if (!factorize(nx / 2, &a) || !factorize(nz, &b)) return IBP_ERROR_UNSUPPORTED_SIZE;
+  // a prime factor above 11 needs the spare half of the general tiles
+  if (a.any && nx / 2 > kTileX64 / 2) return IBP_ERROR_UNSUPPORTED_SIZE;
+  if (b.any && nz + 1 > kTileZ64 / 2) return IBP_ERROR_UNSUPPORTED_SIZE;
   int M, K;
   if (!ytri_shape(ny, &M, &K)) return IBP_ERROR_UNSUPPORTED_SIZE;
   if (fpx) *fpx = a;
@@ -521,12 +539,12 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     p->xfast = rfft::supported(p->h);
     p->zfast = rfft::supported(nz);
     const long nrows = (long)ny * nz;
-    p->nbro = (nrows + kTileX32 / p->h - 1) / (kTileX32 / p->h);
+    p->nbro = (nrows + x_tile_rows(p, kTileX32) - 1) / x_tile_rows(p, kTileX32);
     if (p->xfast) {
       p->rb64 = p->rb32 = (int)fast_x_rows_per_block(p->h);
     } else {
-      p->rb64 = kTileX64 / p->h;
-      p->rb32 = kTileX32 / p->h;
+      p->rb64 = x_tile_rows(p, kTileX64);
+      p->rb32 = x_tile_rows(p, kTileX32);
     }
     p->nb64 = (nrows + p->rb64 - 1) / p->rb64;
     p->nb32 = (nrows + p->rb32 - 1) / p->rb32;
@@ -536,8 +554,8 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     p->fused = false;
     if (const char* e = getenv("IBP_FUSED")) p->fused = atoi(e) != 0 && p->xfast && p->zfast && fused_supported(p->h, nz);
     if (p->fused) p->nbf = nrows / fused_x_rows(p->h);
-    p->zc64 = kTileZ64 / nz;
-    p->zc32 = kTileZ32 / nz;
+    p->zc64 = z_tile_cols(p, kTileZ64);
+    p->zc32 = z_tile_cols(p, kTileZ32);
     if (p->zc64 > 64) p->zc64 = 64;
     if (p->zc32 > 64) p->zc32 = 64;
     if (p->zc64 > p->hp) p->zc64 = p->hp;
@@ -1148,7 +1166,7 @@ hipError_t run_xr2c(const ibp_plan_s* p, int mode, const XArgs<T>& a, hipStream_
   if (p->xfast && mode != XM_RESID_ONLY) return launch_xr2c_fast<T>(mode, a, s);
   if (mode == XM_RESID_ONLY) {
     XArgs<T> b = a;
-    b.rows_per_block = kTileX32 / p->h;
+    b.rows_per_block = x_tile_rows(p, kTileX32);
     b.row_begin = 0;
     b.nrows = (long)p->ny * p->nz;
     b.parts = 1;
@@ -1565,6 +1583,8 @@ ibp_status_t batch_eligible(const ibp_plan_t* plans, int count, int device) {
       if (plans[k] == plans[i]) return IBP_ERROR_INVALID_VALUE;
     if (plans[i]->prec != plans[0]->prec) return IBP_ERROR_INVALID_VALUE;
     if (plans[i]->prec == IBP_MIXED && plans[i]->max_iters != plans[0]->max_iters) return IBP_ERROR_INVALID_VALUE;
+    // batches size every grid's general tiles whole: no direct-sum stages
+    if (plans[i]->fpx.any || plans[i]->fpz.any) return IBP_ERROR_UNSUPPORTED_SIZE;
   }
   if (plans[0]->prec != IBP_FP64 && plans[0]->prec != IBP_MIXED) return IBP_ERROR_UNSUPPORTED_SIZE;
   return IBP_SUCCESS;

@@ -2,7 +2,8 @@
 //
 // * Cx<T>: interleaved complex value (T = double or float), aligned so a
 //   whole value moves in one 16-byte (double) or 8-byte (float) access.
-// * Radix-2/3/4/5/7/8/11 DFT butterflies.
+// * Radix-2/3/4/5/7/8/11 DFT butterflies, and a direct-sum stage for any
+//   other prime radix.
 // * lds_fft: mixed-radix Stockham autosort FFT of `nb` sequences of length
 //   `n` that sit in LDS, all threads of the block cooperating.  Stage with
 //   radix R and span Ns (product of the radices before it): butterfly j of a
@@ -47,6 +48,7 @@ struct FftPlan {
   int n;          // sequence length
   int nst;        // number of stages
   int radix[16];  // radices in stage order
+  int any;        // 1: a radix above 11 (direct-sum stage; half tiles)
 };
 
 // ---------------------------------------------------------------- butterflies
@@ -233,10 +235,65 @@ __device__ __forceinline__ void fft_stage(Cx<T>* buf, int n, int nb, int ss, int
   __syncthreads();
 }
 
+// Stage of any radix R (the prime factors above 11): output q of butterfly j
+// is the R-term DFT by definition,
+//   y_q = sum_r x[j + r m] w_q^r,   w_q = W_{Ns R}^{k + q Ns},   k = j mod Ns,
+// the stage twiddle W_{Ns R}^{r k} and the butterfly's own W_R^{q r} folded
+// into one root per output, summed by Horner's rule (y <- y w_q + x_r from
+// r = R-1 down), so each output takes one table read; a thread runs QA
+// outputs of one butterfly together, so each input read from LDS serves QA
+// accumulators.  O(n R) per stage.  Out of place: outputs go to
+// (j - k) R + k + q Ns of `spare` (the upper half of the block's tile, which
+// the host leaves free for plans with such a factor), then are copied back.
+template <bool INV, typename T>
+__device__ __forceinline__ void fft_stage_any(Cx<T>* buf, Cx<T>* spare, int n, int nb, int ss, int Ns, int R,
+                                              const Cx<T>* __restrict__ tw, int twstride) {
+  constexpr int QA = 4;
+  const int m = n / R;
+  const int twmul = (n / (Ns * R)) * twstride;
+  const int QB = (R + QA - 1) / QA;   // output groups per butterfly
+  const int items = nb * m * QB;
+  for (int t = threadIdx.x; t < items; t += kThreads) {
+    const int b = t / (m * QB);
+    const int w = t - b * (m * QB);
+    const int qb = w / m, j = w - qb * m;   // consecutive threads: consecutive butterflies
+    const int k = j % Ns;
+    const Cx<T>* base = buf + b * ss + j;
+    Cx<T> om[QA], y[QA];
+    const Cx<T> top = base[(R - 1) * m];
+#pragma unroll
+    for (int u = 0; u < QA; ++u) {
+      const int q = qb * QA + u < R ? qb * QA + u : R - 1;
+      om[u] = tw[(k + q * Ns) * twmul];
+      if (INV) om[u].y = -om[u].y;
+      y[u] = top;
+    }
+    for (int r = R - 2; r >= 0; --r) {
+      const Cx<T> x = base[r * m];
+#pragma unroll
+      for (int u = 0; u < QA; ++u) y[u] = cadd(cmul(y[u], om[u]), x);
+    }
+#pragma unroll
+    for (int u = 0; u < QA; ++u) {
+      const int q = qb * QA + u;
+      if (q < R) spare[b * ss + (j - k) * R + k + q * Ns] = y[u];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nb * n; t += kThreads) {
+    const int b = t / n;
+    const int i = b * ss + (t - b * n);
+    buf[i] = spare[i];
+  }
+  __syncthreads();
+}
+
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 // nb sequences of length fp.n; sequence b starts at buf + b*ss.
-// TILE is the compile-time bound on nb * n.
+// TILE is the compile-time bound on nb * ss; a plan with a prime factor
+// above 11 (fp.any) keeps nb * ss <= TILE / 2 (the direct-sum stage's spare
+// half).
 template <int TILE, bool INV, typename T>
 __device__ __forceinline__ void lds_fft(Cx<T>* buf, int nb, int ss, const FftPlan& fp,
                         const Cx<T>* __restrict__ tw, int twstride) {
@@ -252,7 +309,7 @@ __device__ __forceinline__ void lds_fft(Cx<T>* buf, int nb, int ss, const FftPla
       case 5: fft_stage<5, cdiv(TILE, 5 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride); break;
       case 7: fft_stage<7, cdiv(TILE, 7 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride); break;
       case 11: fft_stage<11, cdiv(TILE, 11 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride); break;
-      default: break;
+      default: fft_stage_any<INV, T>(buf, buf + TILE / 2, n, nb, ss, Ns, R, tw, twstride); break;
     }
     Ns *= R;
   }

@@ -39,8 +39,10 @@ def test_status_strings_and_version():
     ((64, 64, 64), ibp.SUCCESS), ((512, 384, 512), ibp.SUCCESS), ((1024, 768, 1024), ibp.SUCCESS),
     ((176, 32, 112), ibp.SUCCESS), ((2, 2, 1), ibp.SUCCESS), ((22, 5, 11), ibp.SUCCESS),
     ((63, 64, 64), ibp.UNSUPPORTED_SIZE),      # odd nx
-    ((26, 64, 64), ibp.UNSUPPORTED_SIZE),      # nx/2 = 13 prime
-    ((64, 64, 26), ibp.UNSUPPORTED_SIZE),      # nz = 2 * 13
+    ((26, 64, 64), ibp.SUCCESS),               # nx/2 = 13 prime: direct-sum stage
+    ((64, 64, 26), ibp.SUCCESS),               # nz = 2 * 13
+    ((632, 64, 632), ibp.SUCCESS),             # nx/2 = 4 * 79, nz = 8 * 79
+    ((64, 64, 501), ibp.SUCCESS),              # nz = 3 * 167
     ((64, 1, 64), ibp.UNSUPPORTED_SIZE),       # ny < 2
     ((64, 4096, 64), ibp.UNSUPPORTED_SIZE),    # ny too large
     ((8192, 8, 8), ibp.UNSUPPORTED_SIZE),      # nx too large
