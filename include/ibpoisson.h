@@ -73,12 +73,13 @@ typedef struct {
   double residual_norm; /* ||rhs - m - L_h phi||_2 (mixed) */
 } ibp_info_t;
 
-/* Host-only size check (touches no GPU).  nx must be even, nx <= 4096 and
- * nz <= 4096; 2 <= ny <= 1536.  Any prime factors are accepted (those above
- * 11 take a slower direct-sum transform stage, e.g. the paper's 632 = 8 x 79
- * and 501 = 3 x 167 points), but then nx/2 <= 1024 or nz <= 2047 for that
- * direction.  Returns IBP_SUCCESS or IBP_ERROR_UNSUPPORTED_SIZE
- * (IBP_ERROR_INVALID_VALUE for nx, nz < 1). */
+/* Host-only size check (touches no GPU).  Even nx <= 4096 (transformed as
+ * nx/2 complex pairs) or odd nx <= 2048 (as nx complex values); nz <= 4096;
+ * 2 <= ny <= 1536.  Any prime factors are accepted (those above 11 take a
+ * slower direct-sum transform stage, e.g. the paper's 632 = 8 x 79 and
+ * 501 = 3 x 167 points), but then the x transform length <= 1024 or
+ * nz <= 2047 for that direction.  Returns IBP_SUCCESS or
+ * IBP_ERROR_UNSUPPORTED_SIZE (IBP_ERROR_INVALID_VALUE for nx, nz < 1). */
 ibp_status_t ibp_check_dims(int nx, int ny, int nz);
 
 /* Create a plan for one grid.  y_nodes: HOST pointer to ny + 1 finite,

@@ -214,13 +214,15 @@ void carve_workspace(ibp_plan_s* p) {
 
 ibp_status_t check_dims(int nx, int ny, int nz, FftPlan* fpx, FftPlan* fpz) {
   if (nx < 1 || nz < 1 || ny < 1) return IBP_ERROR_INVALID_VALUE;
-  if (nx % 2 != 0 || nx > 2 * kTileX64) return IBP_ERROR_UNSUPPORTED_SIZE;
+  // x transform length: nx/2 complex pairs, or nx complex values for odd nx
+  const int hx = nx % 2 ? nx : nx / 2;
+  if (hx > kTileX64) return IBP_ERROR_UNSUPPORTED_SIZE;
   if (nz > kTileZ64) return IBP_ERROR_UNSUPPORTED_SIZE;
   if (ny < 2 || ny > kMaxNy) return IBP_ERROR_UNSUPPORTED_SIZE;
   FftPlan a{}, b{};
-  if (!factorize(nx / 2, &a) || !factorize(nz, &b)) return IBP_ERROR_UNSUPPORTED_SIZE;
+  if (!factorize(hx, &a) || !factorize(nz, &b)) return IBP_ERROR_UNSUPPORTED_SIZE;
   // a prime factor above 11 needs the spare half of the general tiles
-  if (a.any && nx / 2 > kTileX64 / 2) return IBP_ERROR_UNSUPPORTED_SIZE;
+  if (a.any && hx > kTileX64 / 2) return IBP_ERROR_UNSUPPORTED_SIZE;
   if (b.any && nz + 1 > kTileZ64 / 2) return IBP_ERROR_UNSUPPORTED_SIZE;
   int M, K;
   if (!ytri_shape(ny, &M, &K)) return IBP_ERROR_UNSUPPORTED_SIZE;
@@ -527,7 +529,7 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     p->nx = nx;
     p->ny = ny;
     p->nz = nz;
-    p->h = nx / 2;
+    p->h = nx % 2 ? nx : nx / 2;   // x transform length (odd nx: the whole row, no split)
     p->hp = nx / 2 + 1;
     p->Lx = Lx;
     p->Lz = Lz;
@@ -1583,8 +1585,9 @@ ibp_status_t batch_eligible(const ibp_plan_t* plans, int count, int device) {
       if (plans[k] == plans[i]) return IBP_ERROR_INVALID_VALUE;
     if (plans[i]->prec != plans[0]->prec) return IBP_ERROR_INVALID_VALUE;
     if (plans[i]->prec == IBP_MIXED && plans[i]->max_iters != plans[0]->max_iters) return IBP_ERROR_INVALID_VALUE;
-    // batches size every grid's general tiles whole: no direct-sum stages
-    if (plans[i]->fpx.any || plans[i]->fpz.any) return IBP_ERROR_UNSUPPORTED_SIZE;
+    // batches size every grid's general tiles whole (no direct-sum stages)
+    // and split every row into pairs (even nx)
+    if (plans[i]->fpx.any || plans[i]->fpz.any || plans[i]->nx % 2) return IBP_ERROR_UNSUPPORTED_SIZE;
   }
   if (plans[0]->prec != IBP_FP64 && plans[0]->prec != IBP_MIXED) return IBP_ERROR_UNSUPPORTED_SIZE;
   return IBP_SUCCESS;

@@ -107,6 +107,24 @@ __device__ __forceinline__ double2 assemble_pair(const XArgs<T>& A, long row, in
   return make_double2(f0 * A.rscale, f1 * A.rscale);
 }
 
+// The same for the single cell m of a row of odd length nx.
+template <typename T>
+__device__ __forceinline__ double assemble_one(const XArgs<T>& A, long row, int j, int k, int m) {
+  const int nx = A.nx, nz = A.nz;
+  const long e = row * nx + m;
+  const double uc = A.u[e];
+  const double ur = A.u[row * nx + (m + 1 == nx ? 0 : m + 1)];
+  const double vb = A.v[e];
+  const double vt = A.v[e + (long)nz * nx];
+  const int kp = k + 1 == nz ? 0 : k + 1;
+  const double wc = A.w[e];
+  const double wn = A.w[((long)j * nz + kp) * nx + m];
+  const double dyf = A.dyf[j];   // same operation order as the divergence kernel
+  double f0 = (ur - uc) * A.idx + (vt - vb) / dyf + (wn - wc) * A.idz;
+  if (A.q) f0 -= A.q[e];
+  return f0 * A.rscale;
+}
+
 template <typename T>
 struct ZfArgs {
   Cx<T>* spec;

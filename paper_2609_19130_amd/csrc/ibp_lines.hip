@@ -100,7 +100,8 @@ __device__ __forceinline__ void apply_line_lu(const LineArgs& A, const double* t
 
 // Lines contiguous in memory (x direction): block = M lines, line L at
 // f + L n.  LDS tile line-major, one pad slot per lane chunk (odd stride
-// K + 1, so the chunk reads fall on distinct banks).
+// K + 1, so the chunk reads fall on distinct banks).  Lines of even length
+// move 16-byte pairs; odd lengths go through k_lines_contig1.
 template <int M, int P, int K>
 __global__ __launch_bounds__(M * P) void k_lines_contig(LineArgs A) {
   constexpr int NT = M * P;
@@ -145,6 +146,52 @@ __global__ __launch_bounds__(M * P) void k_lines_contig(LineArgs A) {
     const int m = e2 / NPAIR, pos = 2 * (e2 - m * NPAIR);
     const int pp = pos / K, r = pos - pp * K;
     if (m < nm && pos < n) dst[(long)m * (n / 2) + pos / 2] = double2{tile[m * LS + pp * CS + r], tile[m * LS + pp * CS + r + 1]};
+  }
+}
+
+// Odd line length: the same with single 8-byte values (K per thread).
+template <int M, int P, int K>
+__global__ __launch_bounds__(M * P) void k_lines_contig1(LineArgs A) {
+  constexpr int NT = M * P;
+  constexpr int CS = K + 1;
+  constexpr int LS = P * CS;
+  constexpr int NE = P * K;   // values per padded line
+  __shared__ double tile[M * LS];
+  const long L0 = (long)blockIdx.x * M;
+  const int n = A.n;
+  const long nl = A.ncol;
+  const int nm = (int)((nl - L0) < M ? (nl - L0) : M);
+  const double* src = A.f + L0 * n;
+  {
+    double ld[K];
+#pragma unroll
+    for (int it = 0; it < K; ++it) {
+      const int e = threadIdx.x + NT * it;
+      const int m = e / NE, pos = e - m * NE;
+      ld[it] = (m < nm && pos < n) ? src[(long)m * n + pos] : 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < K; ++it) {
+      const int e = threadIdx.x + NT * it;
+      const int m = e / NE, pos = e - m * NE;
+      const int pp = pos / K;
+      tile[m * LS + pp * CS + (pos - pp * K)] = ld[it];
+    }
+  }
+  __syncthreads();
+  {
+    const int p = threadIdx.x % P, m = threadIdx.x / P;
+    auto slot = [](int mm, int pp, int i) { return mm * LS + pp * CS + i; };
+    if (m < nm) apply_line_lu<P, K>(A, A.lu, tile, slot, m, p);
+  }
+  __syncthreads();
+  double* dst = A.f + L0 * n;
+#pragma unroll
+  for (int it = 0; it < K; ++it) {
+    const int e = threadIdx.x + NT * it;
+    const int m = e / NE, pos = e - m * NE;
+    const int pp = pos / K;
+    if (m < nm && pos < n) dst[(long)m * n + pos] = tile[m * LS + pp * CS + (pos - pp * K)];
   }
 }
 
@@ -230,9 +277,15 @@ __global__ __launch_bounds__(kThreads) void k_fill_zero(double* p, long n) {
 template <int M, int P>
 hipError_t contig_k(int K, const LineArgs& a, hipStream_t s) {
   const long nb = (a.ncol + M - 1) / M;
+  const bool pairs = a.n % 2 == 0;
   switch (K) {
-#define IBP_CASE(k) \
-  case k: hipLaunchKernelGGL((k_lines_contig<M, P, k>), dim3((unsigned)nb), dim3(M * P), 0, s, a); break;
+#define IBP_CASE(k)                                                                                  \
+  case k:                                                                                            \
+    if (pairs)                                                                                       \
+      hipLaunchKernelGGL((k_lines_contig<M, P, k>), dim3((unsigned)nb), dim3(M * P), 0, s, a);      \
+    else                                                                                             \
+      hipLaunchKernelGGL((k_lines_contig1<M, P, k>), dim3((unsigned)nb), dim3(M * P), 0, s, a);     \
+    break;
     IBP_CASE(2) IBP_CASE(4) IBP_CASE(8) IBP_CASE(12) IBP_CASE(16) IBP_CASE(24)
 #undef IBP_CASE
     default: return hipErrorInvalidValue;
@@ -271,7 +324,7 @@ int line_shape(int n, int* P, int* K) {
 
 hipError_t launch_lines_contig(int P, int K, const LineArgs& a, hipStream_t s) {
   if (a.ncol <= 0) return hipSuccess;
-  if (a.n % 2 != 0 || (long)P * K < a.n) return hipErrorInvalidValue;
+  if ((long)P * K < a.n) return hipErrorInvalidValue;
   if (P == 32) return contig_k<8, 32>(K, a, s);
   if (P == 64) return contig_k<4, 64>(K, a, s);
   return hipErrorInvalidValue;

@@ -6,7 +6,9 @@
 // (x[2m], x[2m+1]), transformed by an h-point complex FFT in LDS, and split
 // into the nx/2+1 half-spectrum coefficients X[k] = E[k] + W_nx^k O[k] with
 // E = (Z[k] + conj Z[h-k]) / 2 and O = (Z[k] - conj Z[h-k]) / 2i.  The inverse
-// reverses both steps.  One block owns `rows_per_block` whole rows; each wave
+// reverses both steps.  A row of odd length (h = nx) is transformed as nx
+// complex values (x[m], 0) and its first (nx+1)/2 coefficients are kept; the
+// inverse rebuilds the other half as X[nx-k] = conj X[k].  One block owns `rows_per_block` whole rows; each wave
 // loads whole rows with 16-byte coalesced accesses and sums them in FP64 for
 // the (0,0) mode.
 //
@@ -26,6 +28,7 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
   constexpr bool kRes = MODE == XM_RESID || MODE == XM_RESID_ONLY;
   if (kRes && __builtin_amdgcn_readfirstlane(A.ctl->done)) return;
   const int h = A.h, RB = A.rows_per_block, nx = A.nx, nz = A.nz, ny = A.ny;
+  const bool odd = nx & 1;   // h = nx: single values, no split
   const long row0 = blk * RB;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   double acc_in2 = 0.0, acc_f2 = 0.0, acc_max = 0.0, acc_bad = 0.0, acc_wphi = 0.0;
@@ -44,6 +47,38 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
     double rs = 0.0;
     const int j = (int)(row / nz);
     const int k = (int)(row - (long)j * nz);
+    if (odd) {
+      for (int m = lane; m < nx; m += kWave) {
+        const double fv = MODE == XM_DIV ? assemble_one(A, row, j, k, m) : frow[m];
+        double v0;
+        if (!kRes) {
+          v0 = fv;
+          acc_f2 += v0 * v0;
+        } else {
+          // r = (f - m) - L_h phi, 7-point staggered stencil, FP64
+          const double* prow = A.phi + row * nx;
+          const double pc = prow[m];
+          const double pl = prow[m == 0 ? nx - 1 : m - 1];
+          const double pr = prow[m + 1 == nx ? 0 : m + 1];
+          const int kp = k + 1 == nz ? 0 : k + 1, km = k == 0 ? nz - 1 : k - 1;
+          const double zp = A.phi[((long)j * nz + kp) * nx + m];
+          const double zm = A.phi[((long)j * nz + km) * nx + m];
+          const double yp = j + 1 < ny ? A.phi[((long)(j + 1) * nz + k) * nx + m] : 0.0;
+          const double ym = j > 0 ? A.phi[((long)(j - 1) * nz + k) * nx + m] : 0.0;
+          const double L0 = (pr - 2.0 * pc + pl) * A.idx2 + (zp + zm - 2.0 * pc) * A.idz2 + A.ya[j] * (ym - pc) +
+                            A.yc[j] * (yp - pc);
+          const double f0 = fv - mean;
+          v0 = f0 - L0;
+          acc_f2 += f0 * f0;
+          acc_wphi += A.dyf[j] * pc;
+        }
+        rs += v0;
+        acc_in2 += v0 * v0;
+        acc_max = fmax(acc_max, fabs(v0));
+        if (!isfinite(v0)) acc_bad += 1.0;
+        if (MODE != XM_RESID_ONLY) buf[lr * h + m] = Cx<T>{T(v0 * s), T(0)};
+      }
+    } else
     for (int m = lane; m < h; m += kWave) {
       const double2 fv = MODE == XM_DIV ? assemble_pair(A, row, j, k, m)
                                         : *reinterpret_cast<const double2*>(frow + 2 * m);
@@ -96,8 +131,17 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
   }
   if (MODE == XM_RESID_ONLY) return;
   __syncthreads();
-  lds_fft<TILE, false, T>(buf, RB, h, fp, A.twx, 2);
+  lds_fft<TILE, false, T>(buf, RB, h, fp, A.twx, odd ? 1 : 2);
 
+  if (odd) {   // the first (nx+1)/2 coefficients, no split
+    for (int e = threadIdx.x; e < RB * A.hp; e += kThreads) {
+      const int lr = e / A.hp, kk = e - lr * A.hp;
+      const long row = row0 + lr;
+      if (row < A.nrows) A.spec[row * A.rs + (row / nz) * (A.ps - (long)nz * A.rs) + kk] = buf[lr * h + kk];
+    }
+    __syncthreads();
+    return;
+  }
   const int hh = h / 2 + 1;
   for (int e = threadIdx.x; e < RB * hh; e += kThreads) {
     const int lr = e / hh, k = e - lr * hh;
@@ -127,8 +171,20 @@ template <typename T, int MODE, int TILE>
 __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& fp, long blk, Cx<T>* buf) {
   if (MODE == CM_ADD && __builtin_amdgcn_readfirstlane(A.ctl->done)) return;
   const int h = A.h, RB = A.rows_per_block, nx = A.nx, nz = A.nz;
+  const bool odd = nx & 1;   // h = nx: rebuild the full spectrum
   const long row0 = blk * RB;
-  const int hh = h / 2 + 1;
+  const int hh = odd ? 0 : h / 2 + 1;
+  if (odd) {
+    for (int e = threadIdx.x; e < RB * A.hp; e += kThreads) {
+      const int lr = e / A.hp, k = e - lr * A.hp;
+      const long row = row0 + lr;
+      Cx<T> X{T(0), T(0)};
+      if (row < A.nrows) X = A.spec[row * A.rs + (row / nz) * (A.ps - (long)nz * A.rs) + k];
+      if (k == 0) X.y = T(0);   // X[0] of a real sequence is real
+      buf[lr * h + k] = X;
+      if (k > 0) buf[lr * h + nx - k] = cconj(X);
+    }
+  }
   for (int e = threadIdx.x; e < RB * hh; e += kThreads) {
     const int lr = e / hh, k = e - lr * hh;
     const long row = row0 + lr;
@@ -151,7 +207,7 @@ __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& 
     if (km != k) buf[lr * h + km] = Cx<T>{E.x + O.y, O.x - E.y};   // conj(E) + i conj(O)
   }
   __syncthreads();
-  lds_fft<TILE, true, T>(buf, RB, h, fp, A.twx, 2);
+  lds_fft<TILE, true, T>(buf, RB, h, fp, A.twx, odd ? 1 : 2);
 
   double cs = A.out_scale;
   if (MODE == CM_ADD) cs = cs / A.ctl->scale[A.iter & 1];
@@ -163,6 +219,14 @@ __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& 
     double c00 = A.phi00[j] * A.inv_nxnz;
     if (MODE == CM_ADD) c00 -= A.ctl->phimean;
     double* orow = A.out + row * nx;
+    if (odd) {
+      for (int m = lane; m < nx; m += kWave) {
+        double v0 = double(buf[lr * h + m].x) * cs + c00;
+        if (MODE == CM_ADD) v0 += orow[m];
+        orow[m] = v0;
+      }
+      continue;
+    }
     for (int m = lane; m < h; m += kWave) {
       const Cx<T> z = buf[lr * h + m];
       double v0 = double(z.x) * cs + c00, v1 = double(z.y) * cs + c00;

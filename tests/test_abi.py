@@ -38,7 +38,9 @@ def test_status_strings_and_version():
 @pytest.mark.parametrize("dims,expect", [
     ((64, 64, 64), ibp.SUCCESS), ((512, 384, 512), ibp.SUCCESS), ((1024, 768, 1024), ibp.SUCCESS),
     ((176, 32, 112), ibp.SUCCESS), ((2, 2, 1), ibp.SUCCESS), ((22, 5, 11), ibp.SUCCESS),
-    ((63, 64, 64), ibp.UNSUPPORTED_SIZE),      # odd nx
+    ((63, 64, 64), ibp.SUCCESS),               # odd nx: whole-row transform
+    ((501, 64, 501), ibp.SUCCESS),             # the paper's 501 = 3 * 167 points
+    ((2049, 8, 8), ibp.UNSUPPORTED_SIZE),      # odd nx above one tile
     ((26, 64, 64), ibp.SUCCESS),               # nx/2 = 13 prime: direct-sum stage
     ((64, 64, 26), ibp.SUCCESS),               # nz = 2 * 13
     ((632, 64, 632), ibp.SUCCESS),             # nx/2 = 4 * 79, nz = 8 * 79
@@ -66,7 +68,7 @@ def test_plan_create_rejects_bad_arguments_before_any_device_call():
     assert L.ibp_plan_create(ctypes.byref(h), 8, 4, 8, 1.0, float("inf"), y) == ibp.INVALID_VALUE
     assert L.ibp_plan_create(ctypes.byref(h), 8, 4, 8, 1.0, 1.0, ybad) == ibp.INVALID_VALUE
     assert L.ibp_plan_create(ctypes.byref(h), 8, 4, 8, 1.0, 1.0, ynan) == ibp.INVALID_VALUE
-    assert L.ibp_plan_create(ctypes.byref(h), 9, 4, 8, 1.0, 1.0, y) == ibp.UNSUPPORTED_SIZE
+    assert L.ibp_plan_create(ctypes.byref(h), 2049, 4, 8, 1.0, 1.0, y) == ibp.UNSUPPORTED_SIZE
     assert h.value is None
 
 

@@ -1,14 +1,15 @@
-"""Transform lengths with prime factors above 11 (the paper's scaling grids
-have 501 = 3 x 167 and 632 = 8 x 79 points per periodic direction, "Fluid
-domain" scaling paragraphs): the direct-sum Stockham stage on the GPU
-against the oracle (numpy transforms of any length).  GPU only."""
+"""Transform lengths with prime factors above 11 and odd nx (the paper's
+scaling grids have 501 = 3 x 167 and 632 = 8 x 79 points per periodic
+direction, "Fluid domain" scaling paragraphs): the direct-sum Stockham stage
+and the whole-row x transform on the GPU against the oracle (numpy
+transforms of any length).  GPU only."""
 
 import numpy as np
 import pytest
 
 import oracle
 from oracle.grid import geometry
-from oracle.operators import divergence
+from oracle.operators import divergence, rhs_from_velocity
 from paper_2609_19130_amd import ibpoisson as ibp
 from paper_2609_19130_amd import synth
 
@@ -93,3 +94,100 @@ def test_paper_size_632_sampled_modes():
     finally:
         plan.close()
     assert sampled_modes(f, phi, Lx, Lz, yf, MODES) <= 1e-11
+
+
+# ---------------------------------------------------------------- odd nx
+ODD = [(1, 4, 3), (3, 5, 4), (9, 6, 7), (63, 8, 16), (167, 5, 9), (501, 6, 24), (15, 40, 1)]
+
+
+@pytest.mark.parametrize("nx,ny,nz", ODD)
+def test_odd_nx_fp64_match_oracle(nx, ny, nz):
+    yf = synth.tanh_faces(ny, 2.0)
+    f = np.random.default_rng(nx * 5 + ny + nz).uniform(-1, 1, (ny, nz, nx))
+    phi, info = gpu_solve(f, 1.9, 1.3, yf)
+    ref, m = oracle.solve(f, 1.9, 1.3, yf)
+    assert abs(info["removed_mean"] - m) <= 1e-12 * max(1.0, abs(m))
+    assert rel(phi, ref) <= 1e-12, rel(phi, ref)
+
+
+@pytest.mark.parametrize("bc", [("neumann", "dirichlet"), ("dirichlet", "dirichlet")])
+def test_odd_nx_dirichlet(bc):
+    nx, ny, nz = 45, 12, 10
+    yf = synth.tanh_faces(ny, 2.0)
+    f = np.random.default_rng(31).uniform(-1, 1, (ny, nz, nx))
+    phi, _ = gpu_solve(f, 1.9, 1.3, yf, bc=bc)
+    ref, _ = oracle.solve(f, 1.9, 1.3, yf, bc=bc)
+    assert rel(phi, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(63, 8, 16), (501, 5, 20)])
+def test_odd_nx_mixed_refinement(nx, ny, nz):
+    Lx, Lz = 1.9, 1.3
+    yf = synth.tanh_faces(ny, 2.0)
+    g = geometry(nx, ny, nz, Lx, Lz, yf)
+    u, v, w = synth.uniform_velocity(nx, ny, nz, seed=17)
+    f = divergence(u, v, w, g)
+    phi, info = gpu_solve(f, Lx, Lz, yf, precision="mixed", rtol=1e-10, max_iters=6)
+    r = residual(f, phi, Lx, Lz, yf)
+    assert info["converged"] == 1 and r <= 1e-10, (r, info)
+    ref, _ = oracle.solve(f, Lx, Lz, yf)
+    assert rel(phi, ref) <= 1e-8
+
+
+def test_odd_nx_rhs_assembled_in_first_pass():
+    """ibp_solve_divergence with the right-hand side built inside the first
+    x pass (single-value form for odd rows), with mass sources."""
+    nx, ny, nz, adt = 35, 9, 12, 0.02
+    Lx, Lz = 1.9, 1.3
+    yf = synth.tanh_faces(ny, 2.0)
+    g = geometry(nx, ny, nz, Lx, Lz, yf)
+    u, v, w = synth.uniform_velocity(nx, ny, nz, seed=18)
+    q = np.random.default_rng(19).uniform(-0.1, 0.1, (ny, nz, nx))
+    plan = ibp.Plan(nx, ny, nz, Lx, Lz, yf)
+    try:
+        phi = plan.solve_divergence(to_dev(u), to_dev(v), to_dev(w), adt, q=to_dev(q)).cpu().numpy()
+    finally:
+        plan.close()
+    ref, _ = oracle.solve(rhs_from_velocity(u, v, w, q, g, adt), Lx, Lz, yf)
+    assert rel(phi, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("where", ["cells", "yfaces"])
+def test_odd_nx_viscous(where):
+    nx, ny, nz, beta = 37, 11, 9, 0.03
+    Lx, Lz = 1.9, 1.3
+    yf = synth.tanh_faces(ny, 2.0)
+    g = geometry(nx, ny, nz, Lx, Lz, yf)
+    rows = ny if where == "cells" else ny + 1
+    f = np.random.default_rng(20).standard_normal((rows, nz, nx))
+    plan = ibp.Plan(nx, ny, nz, Lx, Lz, yf)
+    try:
+        plan.helmholtz_set(beta)
+        d = to_dev(f)
+        plan.helmholtz(d, where)
+        got = d.cpu().numpy()
+    finally:
+        plan.close()
+    want = oracle.factored_solve(f, g, beta, where)
+    assert float(np.abs(got - want).max()) <= 1e-12 * float(np.abs(f).max())
+
+
+MODES501 = [(0, 0), (1, 0), (0, 1), (3, 7), (167, 5), (250, 500), (100, 250), (250, 0)]
+
+
+def test_paper_size_501_sampled_modes():
+    """501 x 48 x 501 (the periodic directions of the paper's 501 x 501 x 1001
+    grid): sampled Fourier modes recomputed by the oracle's 1-D solves."""
+    nx, ny, nz = 501, 48, 501
+    Lx = Lz = 2 * np.pi
+    yf = synth.tanh_faces(ny, 2.0)
+    g = geometry(nx, ny, nz, Lx, Lz, yf)
+    u, v, w = synth.uniform_velocity(nx, ny, nz, seed=21)
+    f = divergence(u, v, w, g)
+    del u, v, w
+    plan = ibp.Plan(nx, ny, nz, Lx, Lz, yf)
+    try:
+        phi = plan.solve(to_dev(f)).cpu().numpy()
+    finally:
+        plan.close()
+    assert sampled_modes(f, phi, Lx, Lz, yf, MODES501) <= 1e-11
