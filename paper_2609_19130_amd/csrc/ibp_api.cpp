@@ -91,6 +91,8 @@ struct ibp_plan_s {
   long nb64 = 1, nb32 = 1;  // x-pass blocks (transform passes)
   long nbro = 1;            // blocks of the residual-only pass
   bool xfast = false, zfast = false;   // register-FFT kernels for power-of-two lengths
+  bool zsmall = false;                 // general z transform in the small tile
+  bool xsmall = false;                 // general x transform in the small tile
   // fused persistent x/z passes (nz = nx and both lengths register-FFT sizes)
   bool fused = false;
   int fblocks64 = 0, fblocks32 = 0;   // persistent blocks (FP64 / FP32 spectrum)
@@ -170,9 +172,18 @@ hipError_t reset_counters(ibp_plan_s* p) {
 // tiles, or half tiles when the length has a prime factor above 11 (the
 // direct-sum stage writes into the other half).
 int x_tile_rows(const ibp_plan_s* p, int tile) { return (p->fpx.any ? tile / 2 : tile) / p->h; }
+// Rows of this transform length fit the small x tile (FP64; FP32's is twice
+// as large).  Lengths with a direct-sum stage keep the large tile: its work
+// per block is the block's rows times h / 4 items, and one row of a half
+// small tile leaves most threads idle (measured slower at h = 316 and 501).
+bool x_small(const FftPlan& fpx, int h) { return !fpx.any && h <= kTileX64s; }
+int x_tile64(const ibp_plan_s* p) { return p->xsmall ? kTileX64s : kTileX64; }
+int x_tile32(const ibp_plan_s* p) { return p->xsmall ? kTileX32s : kTileX32; }
 int z_tile_cols(const ibp_plan_s* p, int tile) {
   return p->fpz.any ? (tile / 2) / (p->nz + 1) : tile / p->nz;
 }
+// Lines of this length fit the small z tile (FP64; the FP32 one is twice as large).
+bool z_small(const FftPlan& fpz, int nz) { return fpz.any ? nz + 1 <= kTileZ64s / 2 : nz <= kTileZ64s; }
 
 size_t spec_bytes(const ibp_plan_s* p) {
   const size_t b64 = (size_t)p->ny * spec_plane_stride<double>(p->hp, p->nz) * sizeof(Cx<double>);
@@ -541,12 +552,13 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     p->xfast = rfft::supported(p->h);
     p->zfast = rfft::supported(nz);
     const long nrows = (long)ny * nz;
-    p->nbro = (nrows + x_tile_rows(p, kTileX32) - 1) / x_tile_rows(p, kTileX32);
+    p->xsmall = x_small(p->fpx, p->h);
+    p->nbro = (nrows + x_tile_rows(p, x_tile32(p)) - 1) / x_tile_rows(p, x_tile32(p));
     if (p->xfast) {
       p->rb64 = p->rb32 = (int)fast_x_rows_per_block(p->h);
     } else {
-      p->rb64 = x_tile_rows(p, kTileX64);
-      p->rb32 = x_tile_rows(p, kTileX32);
+      p->rb64 = x_tile_rows(p, x_tile64(p));
+      p->rb32 = x_tile_rows(p, x_tile32(p));
     }
     p->nb64 = (nrows + p->rb64 - 1) / p->rb64;
     p->nb32 = (nrows + p->rb32 - 1) / p->rb32;
@@ -556,8 +568,9 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     p->fused = false;
     if (const char* e = getenv("IBP_FUSED")) p->fused = atoi(e) != 0 && p->xfast && p->zfast && fused_supported(p->h, nz);
     if (p->fused) p->nbf = nrows / fused_x_rows(p->h);
-    p->zc64 = z_tile_cols(p, kTileZ64);
-    p->zc32 = z_tile_cols(p, kTileZ32);
+    p->zsmall = z_small(p->fpz, nz);
+    p->zc64 = z_tile_cols(p, p->zsmall ? kTileZ64s : kTileZ64);
+    p->zc32 = z_tile_cols(p, p->zsmall ? kTileZ32s : kTileZ32);
     if (p->zc64 > 64) p->zc64 = 64;
     if (p->zc32 > 64) p->zc32 = 64;
     if (p->zc64 > p->hp) p->zc64 = p->hp;
@@ -1168,25 +1181,25 @@ hipError_t run_xr2c(const ibp_plan_s* p, int mode, const XArgs<T>& a, hipStream_
   if (p->xfast && mode != XM_RESID_ONLY) return launch_xr2c_fast<T>(mode, a, s);
   if (mode == XM_RESID_ONLY) {
     XArgs<T> b = a;
-    b.rows_per_block = x_tile_rows(p, kTileX32);
+    b.rows_per_block = x_tile_rows(p, x_tile32(p));
     b.row_begin = 0;
     b.nrows = (long)p->ny * p->nz;
     b.parts = 1;
-    return launch_xr2c<T>(mode, b, s);
+    return launch_xr2c<T>(mode, p->xsmall, b, s);
   }
-  return launch_xr2c<T>(mode, a, s);
+  return launch_xr2c<T>(mode, p->xsmall, a, s);
 }
 
 template <typename T>
 hipError_t run_xc2r(const ibp_plan_s* p, int mode, const XArgs<T>& a, hipStream_t s) {
   if (p->xfast) return launch_xc2r_fast<T>(mode, a, s);
-  return launch_xc2r<T>(mode, a, s);
+  return launch_xc2r<T>(mode, p->xsmall, a, s);
 }
 
 template <typename T>
 hipError_t run_zfft(const ibp_plan_s* p, bool inverse, const ZfArgs<T>& a, int nplanes, hipStream_t s) {
   if (p->zfast) return launch_zfft_fast<T>(inverse, a, nplanes, s);
-  return launch_zfft<T>(inverse, a, nplanes, s);
+  return launch_zfft<T>(inverse, p->zsmall, a, nplanes, s);
 }
 
 // Forward transforms of the whole grid: x R2C then z FFT.  With chunking,
@@ -1402,6 +1415,8 @@ struct ibp_batch_s {
   long nblk[3] = {0, 0, 0};  // blocks of the x, z and y stage launches
   int yP = 32, yK = 2, yM = 8;
   int xdiv = 1, zdiv = 1;    // x rows and z columns per block: the largest tile's, divided by these
+  bool zsmall = false;       // every grid's z lines fit the small tile
+  bool xsmall = false;       // every grid's x rows fit the small tile
   std::vector<long> hstart;
   std::vector<int> rbmax, zcmax;   // per grid: rows per block and z columns of the largest tile
   std::vector<BatchGrid<double>> h64;
@@ -1452,8 +1467,12 @@ hipError_t batch_reapply(ibp_batch_s* b) {
 template <typename T>
 ibp_status_t batch_build(ibp_batch_s* b) {
   constexpr bool kF64 = sizeof(T) == 8;
-  constexpr int TLX = kF64 ? kTileX64 : kTileX32;
-  constexpr int TLZ = kF64 ? kTileZ64 : kTileZ32;
+  b->xsmall = true;
+  for (ibp_plan_t p : b->plans) b->xsmall = b->xsmall && x_small(p->fpx, p->h);
+  const int TLX = b->xsmall ? (kF64 ? kTileX64s : kTileX32s) : (kF64 ? kTileX64 : kTileX32);
+  b->zsmall = true;
+  for (ibp_plan_t p : b->plans) b->zsmall = b->zsmall && z_small(p->fpz, p->nz);
+  const int TLZ = b->zsmall ? (kF64 ? kTileZ64s : kTileZ32s) : (kF64 ? kTileZ64 : kTileZ32);
   const int n = b->count;
   int maxny = 0;
   for (ibp_plan_t p : b->plans) maxny = p->ny > maxny ? p->ny : maxny;
@@ -1549,23 +1568,23 @@ ibp_status_t batch_enqueue(ibp_batch_s* b, const double* const* rhs, double* con
     p->solved = true;
   }
   BatchLaunch L{n, 0, 1, mixed ? 1 : 0, 0, 0};
-  IBP_HIP(launch_batch_xr2c<T>(XM_PLAIN, d, sx, b->nblk[0], P, L, s));
-  IBP_HIP(launch_batch_zfft<T>(false, d, sz, b->nblk[1], L, s));
+  IBP_HIP(launch_batch_xr2c<T>(XM_PLAIN, b->xsmall, d, sx, b->nblk[0], P, L, s));
+  IBP_HIP(launch_batch_zfft<T>(false, b->zsmall, d, sz, b->nblk[1], L, s));
   IBP_HIP(launch_batch_ytri<T>(b->yP, b->yK, b->yM, d, sy, b->nblk[2], L, s));
-  IBP_HIP(launch_batch_zfft<T>(true, d, sz, b->nblk[1], L, s));
-  IBP_HIP(launch_batch_xc2r<T>(CM_SET, d, sx, b->nblk[0], P, L, s));
+  IBP_HIP(launch_batch_zfft<T>(true, b->zsmall, d, sz, b->nblk[1], L, s));
+  IBP_HIP(launch_batch_xc2r<T>(CM_SET, b->xsmall, d, sx, b->nblk[0], P, L, s));
   if (!mixed) return IBP_SUCCESS;
   for (int k = 1; k <= b->max_iters; ++k) {
     L = BatchLaunch{n, k, 0, 1, 0, 1};
-    IBP_HIP(launch_batch_xr2c<T>(XM_RESID, d, sx, b->nblk[0], P, L, s));
+    IBP_HIP(launch_batch_xr2c<T>(XM_RESID, b->xsmall, d, sx, b->nblk[0], P, L, s));
     IBP_HIP(launch_batch_check<T>(d, L, s));
-    IBP_HIP(launch_batch_zfft<T>(false, d, sz, b->nblk[1], L, s));
+    IBP_HIP(launch_batch_zfft<T>(false, b->zsmall, d, sz, b->nblk[1], L, s));
     IBP_HIP(launch_batch_ytri<T>(b->yP, b->yK, b->yM, d, sy, b->nblk[2], L, s));
-    IBP_HIP(launch_batch_zfft<T>(true, d, sz, b->nblk[1], L, s));
-    IBP_HIP(launch_batch_xc2r<T>(CM_ADD, d, sx, b->nblk[0], P, L, s));
+    IBP_HIP(launch_batch_zfft<T>(true, b->zsmall, d, sz, b->nblk[1], L, s));
+    IBP_HIP(launch_batch_xc2r<T>(CM_ADD, b->xsmall, d, sx, b->nblk[0], P, L, s));
   }
   L = BatchLaunch{n, b->max_iters + 1, 0, 1, 1, 1};
-  IBP_HIP(launch_batch_xr2c<T>(XM_RESID_ONLY, d, sx, b->nblk[0], P, L, s));
+  IBP_HIP(launch_batch_xr2c<T>(XM_RESID_ONLY, b->xsmall, d, sx, b->nblk[0], P, L, s));
   IBP_HIP(launch_batch_check<T>(d, L, s));
   return IBP_SUCCESS;
 }

@@ -280,13 +280,13 @@ struct BatchLaunch {
 
 // Stages of a batched solve; each launcher covers every grid in one launch.
 template <typename T>
-hipError_t launch_batch_xr2c(int mode, const BatchGrid<T>* d, const long* start, long nblocks, const BatchPtrs& p,
+hipError_t launch_batch_xr2c(int mode, bool small, const BatchGrid<T>* d, const long* start, long nblocks, const BatchPtrs& p,
                              const BatchLaunch& l, hipStream_t s);
 template <typename T>
-hipError_t launch_batch_xc2r(int mode, const BatchGrid<T>* d, const long* start, long nblocks, const BatchPtrs& p,
+hipError_t launch_batch_xc2r(int mode, bool small, const BatchGrid<T>* d, const long* start, long nblocks, const BatchPtrs& p,
                              const BatchLaunch& l, hipStream_t s);
 template <typename T>
-hipError_t launch_batch_zfft(bool inverse, const BatchGrid<T>* d, const long* start, long nblocks,
+hipError_t launch_batch_zfft(bool inverse, bool small, const BatchGrid<T>* d, const long* start, long nblocks,
                              const BatchLaunch& l, hipStream_t s);
 template <typename T>
 hipError_t launch_batch_ytri(int P, int K, int M, const BatchGrid<T>* d, const long* start, long nblocks,
@@ -346,7 +346,12 @@ hipError_t launch_fill_zero(double* p, long n, hipStream_t s);
 
 // ---------------------------------------------------------------- launchers
 constexpr int kTileX64 = 2048, kTileX32 = 4096;   // complex elements per x-pass block
+constexpr int kTileX64s = 1024, kTileX32s = 2048; // small x tiles (as for z below)
 constexpr int kTileZ64 = 4096, kTileZ32 = 8192;   // complex elements per z-pass block
+// Small z tiles for short lines: the general transform's stage registers
+// scale with the tile (340 VGPRs at 4096 FP64, 167 at 1024), so lines that
+// fit run at two to three times the occupancy.
+constexpr int kTileZ64s = 1024, kTileZ32s = 2048;
 constexpr int kMaxNy = 1536;
 constexpr long kYTileBytes = 72 * 1024;           // staged line-solve tile per block
 
@@ -360,11 +365,11 @@ template <> inline int tile_z<float>() { return kTileZ32; }
 // x passes cover rows [a.row_begin, a.nrows); z passes cover planes
 // [a.plane0, a.plane0 + nplanes).
 template <typename T>
-hipError_t launch_xr2c(int mode, const XArgs<T>& a, hipStream_t s);
+hipError_t launch_xr2c(int mode, bool small, const XArgs<T>& a, hipStream_t s);
 template <typename T>
-hipError_t launch_xc2r(int mode, const XArgs<T>& a, hipStream_t s);
+hipError_t launch_xc2r(int mode, bool small, const XArgs<T>& a, hipStream_t s);
 template <typename T>
-hipError_t launch_zfft(bool inverse, const ZfArgs<T>& a, int nplanes, hipStream_t s);
+hipError_t launch_zfft(bool inverse, bool small, const ZfArgs<T>& a, int nplanes, hipStream_t s);
 // M columns per block: `want` (2, 4, 8 or 16) if given, else 128-byte rows;
 // capped by the LDS budget.
 template <typename T, typename U>

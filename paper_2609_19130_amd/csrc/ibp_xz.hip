@@ -330,11 +330,9 @@ __global__ __launch_bounds__(kThreads) void kb_zfft(const BatchGrid<T>* __restri
   zfft_gen_body<T, INV, TILE>(a, D[g].z.fp, (int)(local % ncb), local / ncb, buf);
 }
 
-template <typename T>
-hipError_t launch_batch_xr2c(int mode, const BatchGrid<T>* d, const long* start, long nblocks, const BatchPtrs& p,
-                             const BatchLaunch& l, hipStream_t s) {
-  constexpr int TL = (sizeof(T) == 8) ? kTileX64 : kTileX32;
-  if (nblocks <= 0) return hipSuccess;
+template <typename T, int TL>
+hipError_t batch_xr2c_tl(int mode, const BatchGrid<T>* d, const long* start, long nblocks, const BatchPtrs& p,
+                         const BatchLaunch& l, hipStream_t s) {
   const dim3 grid((unsigned)nblocks), block(kThreads);
   switch (mode) {
     case XM_PLAIN: hipLaunchKernelGGL((kb_xr2c<T, XM_PLAIN, TL>), grid, block, 0, s, d, start, p, l); break;
@@ -346,10 +344,16 @@ hipError_t launch_batch_xr2c(int mode, const BatchGrid<T>* d, const long* start,
 }
 
 template <typename T>
-hipError_t launch_batch_xc2r(int mode, const BatchGrid<T>* d, const long* start, long nblocks, const BatchPtrs& p,
-                             const BatchLaunch& l, hipStream_t s) {
-  constexpr int TL = (sizeof(T) == 8) ? kTileX64 : kTileX32;
+hipError_t launch_batch_xr2c(int mode, bool small, const BatchGrid<T>* d, const long* start, long nblocks,
+                             const BatchPtrs& p, const BatchLaunch& l, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
+  if (small) return batch_xr2c_tl<T, sizeof(T) == 8 ? kTileX64s : kTileX32s>(mode, d, start, nblocks, p, l, s);
+  return batch_xr2c_tl<T, sizeof(T) == 8 ? kTileX64 : kTileX32>(mode, d, start, nblocks, p, l, s);
+}
+
+template <typename T, int TL>
+hipError_t batch_xc2r_tl(int mode, const BatchGrid<T>* d, const long* start, long nblocks, const BatchPtrs& p,
+                         const BatchLaunch& l, hipStream_t s) {
   const dim3 grid((unsigned)nblocks), block(kThreads);
   switch (mode) {
     case CM_SET: hipLaunchKernelGGL((kb_xc2r<T, CM_SET, TL>), grid, block, 0, s, d, start, p, l); break;
@@ -360,35 +364,50 @@ hipError_t launch_batch_xc2r(int mode, const BatchGrid<T>* d, const long* start,
 }
 
 template <typename T>
-hipError_t launch_batch_zfft(bool inverse, const BatchGrid<T>* d, const long* start, long nblocks,
+hipError_t launch_batch_xc2r(int mode, bool small, const BatchGrid<T>* d, const long* start, long nblocks,
+                             const BatchPtrs& p, const BatchLaunch& l, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  if (small) return batch_xc2r_tl<T, sizeof(T) == 8 ? kTileX64s : kTileX32s>(mode, d, start, nblocks, p, l, s);
+  return batch_xc2r_tl<T, sizeof(T) == 8 ? kTileX64 : kTileX32>(mode, d, start, nblocks, p, l, s);
+}
+
+template <typename T>
+hipError_t launch_batch_zfft(bool inverse, bool small, const BatchGrid<T>* d, const long* start, long nblocks,
                              const BatchLaunch& l, hipStream_t s) {
   constexpr int TL = (sizeof(T) == 8) ? kTileZ64 : kTileZ32;
+  constexpr int TS = (sizeof(T) == 8) ? kTileZ64s : kTileZ32s;
   if (nblocks <= 0) return hipSuccess;
   const dim3 grid((unsigned)nblocks), block(kThreads);
-  if (inverse)
-    hipLaunchKernelGGL((kb_zfft<T, true, TL>), grid, block, 0, s, d, start, l);
-  else
-    hipLaunchKernelGGL((kb_zfft<T, false, TL>), grid, block, 0, s, d, start, l);
+  if (small) {
+    if (inverse)
+      hipLaunchKernelGGL((kb_zfft<T, true, TS>), grid, block, 0, s, d, start, l);
+    else
+      hipLaunchKernelGGL((kb_zfft<T, false, TS>), grid, block, 0, s, d, start, l);
+  } else {
+    if (inverse)
+      hipLaunchKernelGGL((kb_zfft<T, true, TL>), grid, block, 0, s, d, start, l);
+    else
+      hipLaunchKernelGGL((kb_zfft<T, false, TL>), grid, block, 0, s, d, start, l);
+  }
   return hipGetLastError();
 }
 
-template hipError_t launch_batch_xr2c<double>(int, const BatchGrid<double>*, const long*, long, const BatchPtrs&,
-                                              const BatchLaunch&, hipStream_t);
-template hipError_t launch_batch_xr2c<float>(int, const BatchGrid<float>*, const long*, long, const BatchPtrs&,
+template hipError_t launch_batch_xr2c<double>(int, bool, const BatchGrid<double>*, const long*, long,
+                                              const BatchPtrs&, const BatchLaunch&, hipStream_t);
+template hipError_t launch_batch_xr2c<float>(int, bool, const BatchGrid<float>*, const long*, long, const BatchPtrs&,
                                              const BatchLaunch&, hipStream_t);
-template hipError_t launch_batch_xc2r<double>(int, const BatchGrid<double>*, const long*, long, const BatchPtrs&,
-                                              const BatchLaunch&, hipStream_t);
-template hipError_t launch_batch_xc2r<float>(int, const BatchGrid<float>*, const long*, long, const BatchPtrs&,
+template hipError_t launch_batch_xc2r<double>(int, bool, const BatchGrid<double>*, const long*, long,
+                                              const BatchPtrs&, const BatchLaunch&, hipStream_t);
+template hipError_t launch_batch_xc2r<float>(int, bool, const BatchGrid<float>*, const long*, long, const BatchPtrs&,
                                              const BatchLaunch&, hipStream_t);
-template hipError_t launch_batch_zfft<double>(bool, const BatchGrid<double>*, const long*, long, const BatchLaunch&,
-                                              hipStream_t);
-template hipError_t launch_batch_zfft<float>(bool, const BatchGrid<float>*, const long*, long, const BatchLaunch&,
+template hipError_t launch_batch_zfft<double>(bool, bool, const BatchGrid<double>*, const long*, long,
+                                              const BatchLaunch&, hipStream_t);
+template hipError_t launch_batch_zfft<float>(bool, bool, const BatchGrid<float>*, const long*, long, const BatchLaunch&,
                                              hipStream_t);
 
 // ---------------------------------------------------------------- launchers
-template <typename T>
-hipError_t launch_xr2c(int mode, const XArgs<T>& a, hipStream_t s) {
-  constexpr int TL = (sizeof(T) == 8) ? kTileX64 : kTileX32;
+template <typename T, int TL>
+hipError_t xr2c_tl(int mode, const XArgs<T>& a, hipStream_t s) {
   const long nblocks = (a.nrows - a.row_begin + a.rows_per_block - 1) / a.rows_per_block;
   dim3 grid((unsigned)nblocks), block(kThreads);
   switch (mode) {
@@ -407,8 +426,13 @@ hipError_t launch_xr2c(int mode, const XArgs<T>& a, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_xc2r(int mode, const XArgs<T>& a, hipStream_t s) {
-  constexpr int TL = (sizeof(T) == 8) ? kTileX64 : kTileX32;
+hipError_t launch_xr2c(int mode, bool small, const XArgs<T>& a, hipStream_t s) {
+  if (small) return xr2c_tl<T, sizeof(T) == 8 ? kTileX64s : kTileX32s>(mode, a, s);
+  return xr2c_tl<T, sizeof(T) == 8 ? kTileX64 : kTileX32>(mode, a, s);
+}
+
+template <typename T, int TL>
+hipError_t xc2r_tl(int mode, const XArgs<T>& a, hipStream_t s) {
   const long nblocks = (a.nrows - a.row_begin + a.rows_per_block - 1) / a.rows_per_block;
   dim3 grid((unsigned)nblocks), block(kThreads);
   switch (mode) {
@@ -420,21 +444,35 @@ hipError_t launch_xc2r(int mode, const XArgs<T>& a, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_zfft(bool inverse, const ZfArgs<T>& a, int nplanes, hipStream_t s) {
+hipError_t launch_xc2r(int mode, bool small, const XArgs<T>& a, hipStream_t s) {
+  if (small) return xc2r_tl<T, sizeof(T) == 8 ? kTileX64s : kTileX32s>(mode, a, s);
+  return xc2r_tl<T, sizeof(T) == 8 ? kTileX64 : kTileX32>(mode, a, s);
+}
+
+template <typename T>
+hipError_t launch_zfft(bool inverse, bool small, const ZfArgs<T>& a, int nplanes, hipStream_t s) {
   constexpr int TL = (sizeof(T) == 8) ? kTileZ64 : kTileZ32;
+  constexpr int TS = (sizeof(T) == 8) ? kTileZ64s : kTileZ32s;
   dim3 grid((unsigned)((a.hp + a.cols - 1) / a.cols), (unsigned)nplanes), block(kThreads);
-  if (inverse)
-    hipLaunchKernelGGL((k_zfft<T, true, TL>), grid, block, 0, s, a);
-  else
-    hipLaunchKernelGGL((k_zfft<T, false, TL>), grid, block, 0, s, a);
+  if (small) {
+    if (inverse)
+      hipLaunchKernelGGL((k_zfft<T, true, TS>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_zfft<T, false, TS>), grid, block, 0, s, a);
+  } else {
+    if (inverse)
+      hipLaunchKernelGGL((k_zfft<T, true, TL>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_zfft<T, false, TL>), grid, block, 0, s, a);
+  }
   return hipGetLastError();
 }
 
-template hipError_t launch_xr2c<double>(int, const XArgs<double>&, hipStream_t);
-template hipError_t launch_xr2c<float>(int, const XArgs<float>&, hipStream_t);
-template hipError_t launch_xc2r<double>(int, const XArgs<double>&, hipStream_t);
-template hipError_t launch_xc2r<float>(int, const XArgs<float>&, hipStream_t);
-template hipError_t launch_zfft<double>(bool, const ZfArgs<double>&, int, hipStream_t);
-template hipError_t launch_zfft<float>(bool, const ZfArgs<float>&, int, hipStream_t);
+template hipError_t launch_xr2c<double>(int, bool, const XArgs<double>&, hipStream_t);
+template hipError_t launch_xr2c<float>(int, bool, const XArgs<float>&, hipStream_t);
+template hipError_t launch_xc2r<double>(int, bool, const XArgs<double>&, hipStream_t);
+template hipError_t launch_xc2r<float>(int, bool, const XArgs<float>&, hipStream_t);
+template hipError_t launch_zfft<double>(bool, bool, const ZfArgs<double>&, int, hipStream_t);
+template hipError_t launch_zfft<float>(bool, bool, const ZfArgs<float>&, int, hipStream_t);
 
 }  // namespace ibp
