@@ -353,7 +353,7 @@ constexpr int kTileZ64 = 4096, kTileZ32 = 8192;   // complex elements per z-pass
 // fit run at two to three times the occupancy.
 constexpr int kTileZ64s = 1024, kTileZ32s = 2048;
 constexpr int kMaxNy = 1536;
-constexpr long kYTileBytes = 72 * 1024;           // staged line-solve tile per block
+constexpr long kYTileBytes = 104 * 1024;          // staged line-solve tile per block (64 x 12 x 8 FP64: 99 KB)
 
 template <typename T> int tile_x();
 template <typename T> int tile_z();

@@ -467,7 +467,9 @@ static constexpr int kKs[] = {2, 4, 8, 12, 16, 24};
 
 bool ytri_shape(int ny, int* P, int* K) {
   if (ny < 2 || ny > kMaxNy) return false;
-  const int p = ny > 32 * 24 ? 64 : 32;
+  // 64 lanes once a column needs more than 12 rows per lane of 32: 24 rows
+  // per lane hold ~350 VGPRs (one wave per SIMD), 12 rows ~180 (two waves)
+  const int p = ny > 32 * 12 ? 64 : 32;
   const int need = (ny + p - 1) / p;
   for (int k : kKs) {
     if (k >= need) {
@@ -497,7 +499,7 @@ static int ytri_cols(int P, int K, int want) {
 
 template <typename T, typename U, int M, int P, int K>
 static hipError_t launch_ytri_mpk(const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s) {
-  // only shapes ytri_cols can select are instantiated (staged tile <= 72 KB)
+  // only shapes ytri_cols can select are instantiated (staged tile <= kYTileBytes)
   if constexpr (ytile_slots<M, P, K>() * (long)sizeof(Cx<T>) <= kYTileBytes && M * P <= 1024) {
     const long nb = (a.Q + M - 1) / M + a.ny;   // + the (0,0)-mode plane blocks
     hipLaunchKernelGGL((k_ytri<T, U, M, P, K>), dim3((unsigned)nb), dim3(M * P), 0, s, a, z);
