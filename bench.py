@@ -80,6 +80,28 @@ def traffic_for(kernel, workload):
     return d.get("bytes_per_launch")
 
 
+def copy_gbs(n_doubles):
+    """Device copy bandwidth (read + write) of an FP64 array half the dominant
+    kernel's bytes, measured live with torch's copy: the practical HBM ceiling
+    next to the 8 TB/s peak."""
+    import torch
+    a = torch.ones(n_doubles, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 20
+    del a, b
+    return 2.0 * n_doubles * 8 / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(args):
     """The oracle as it stands, on the host cores, on one full solve of the
     same workload (numpy FFTs and a numpy Thomas sweep: one thread)."""
@@ -105,7 +127,14 @@ def cpu_baseline(args):
         times.append(time.perf_counter() - t0)
     dt = float(np.median(times))
     scale = (nx * ny * nz) / float(args.nx * args.ny * args.nz)
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": scale / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "host": {"cpu": cpu, "logical_cpus": os.cpu_count(), "numpy": np.__version__},
             "sample": f"median of {len(times)} full oracle solves at {nx}x{ny}x{nz}: {dt:.2f} s each"
                       + ("" if scale == 1.0 else f"; rate scaled by the cell ratio {scale:.3f}")}
 
@@ -460,7 +489,9 @@ def main():
         name, p = dom
         avg = p["total_ms"] / p["launches"]
         ach = p["bytes_per_launch"] / (avg * 1e-3) / 1e9
+        copy = copy_gbs(int(p["bytes_per_launch"] // 16))
         out["roofline"] = {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                           "copy_gbs": copy, "frac_of_copy": ach / copy,
                            "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                            "bytes_per_launch": p["bytes_per_launch"], "avg_launch_ms": avg,
                            "traffic": traffic_for(name, workload)}
