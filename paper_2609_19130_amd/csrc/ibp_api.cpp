@@ -29,6 +29,9 @@ bool factorize(int n, FftPlan* fp) {
   fp->n = n;
   fp->nst = 0;
   fp->any = 0;
+  fp->blu = 0;
+  fp->m = 0;
+  fp->mst = 0;
   int m = n;
   auto push = [&](int r) {
     if (fp->nst >= 16) return false;
@@ -51,6 +54,81 @@ bool factorize(int n, FftPlan* fp) {
       if (!push(p)) return false;
   if (m > 1 && !push(m)) return false;   // the remaining prime
   return m == 1;
+}
+
+// Lengths whose largest prime factor exceeds kBluesteinPrime take Bluestein's
+// algorithm instead of a direct-sum stage, if the convolution length m (the
+// power of two >= 2n - 1) fits `max_m`.  Both move similar LDS traffic per
+// value at R ~ 100-200 (R/4 reads per output for the direct sum against two
+// padded length-m transforms), and the direct sum measured faster there on
+// MI355X (501 = 3 x 167 and 632 = 8 x 79 grids), so only larger primes switch.
+constexpr int kBluesteinPrime = 256;
+void plan_bluestein(FftPlan* fp, int max_m) {
+  int big = 1;
+  for (int s = 0; s < fp->nst; ++s) big = fp->radix[s] > big ? fp->radix[s] : big;
+  if (big <= kBluesteinPrime) return;
+  int m = 1;
+  while (m < 2 * fp->n - 1) m *= 2;
+  if (m > max_m) return;
+  fp->blu = 1;
+  fp->any = 0;
+  fp->m = m;
+  fp->mst = 0;
+  int r = m;
+  while (r % 8 == 0) { fp->mradix[fp->mst++] = 8; r /= 8; }
+  while (r % 4 == 0) { fp->mradix[fp->mst++] = 4; r /= 4; }
+  while (r % 2 == 0) { fp->mradix[fp->mst++] = 2; r /= 2; }
+}
+
+// Bluestein tables of length n (convolution length m), FP64 from long double:
+// chirp w_j = exp(-i pi j^2 / n) (angle reduced as j^2 mod 2n), and bhat =
+// DFT_m of the filter b with b_t = conj(w_|t|) at t mod m for |t| < n (a
+// radix-2 transform in long double).
+void bluestein_tables(int n, int m, std::vector<double>& chirp, std::vector<double>& bhat) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  chirp.assign(2 * (size_t)n, 0.0);
+  std::vector<long double> br(m, 0.0L), bi(m, 0.0L);
+  for (int j = 0; j < n; ++j) {
+    const long long r = ((long long)j * j) % (2LL * n);
+    const long double a = pi * (long double)r / (long double)n;
+    chirp[2 * j] = (double)cosl(a);
+    chirp[2 * j + 1] = (double)-sinl(a);
+    br[j] = cosl(a);   // conj(w_j)
+    bi[j] = sinl(a);
+    if (j > 0) {
+      br[m - j] = cosl(a);
+      bi[m - j] = sinl(a);
+    }
+  }
+  // iterative radix-2 DFT, exp(-2 pi i j k / m)
+  for (int i = 1, j = 0; i < m; ++i) {
+    int bit = m >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) {
+      std::swap(br[i], br[j]);
+      std::swap(bi[i], bi[j]);
+    }
+  }
+  for (int len = 2; len <= m; len <<= 1) {
+    const long double ang = -2.0L * pi / (long double)len;
+    for (int i = 0; i < m; i += len)
+      for (int k = 0; k < len / 2; ++k) {
+        const long double wr = cosl(ang * k), wi = sinl(ang * k);
+        const long double ur = br[i + k], ui = bi[i + k];
+        const long double vr = br[i + k + len / 2] * wr - bi[i + k + len / 2] * wi;
+        const long double vi = br[i + k + len / 2] * wi + bi[i + k + len / 2] * wr;
+        br[i + k] = ur + vr;
+        bi[i + k] = ui + vi;
+        br[i + k + len / 2] = ur - vr;
+        bi[i + k + len / 2] = ui - vi;
+      }
+  }
+  bhat.assign(2 * (size_t)m, 0.0);
+  for (int k = 0; k < m; ++k) {
+    bhat[2 * k] = (double)br[k];
+    bhat[2 * k + 1] = (double)bi[k];
+  }
 }
 
 // W_n^e = exp(-2 pi i e / n), e = 0..n-1, evaluated in long double and rounded.
@@ -104,6 +182,11 @@ struct ibp_plan_s {
   const float *ya32 = nullptr, *yc32 = nullptr, *lamx32 = nullptr, *lamz32 = nullptr;
   const Cx<double>*twx = nullptr, *twz = nullptr;
   const Cx<float>*twx32 = nullptr, *twz32 = nullptr;
+  // Bluestein tables (chirp, filter transform, length-m twiddles) of x and z
+  const Cx<double>* bx64[3] = {nullptr, nullptr, nullptr};
+  const Cx<double>* bz64[3] = {nullptr, nullptr, nullptr};
+  const Cx<float>* bx32[3] = {nullptr, nullptr, nullptr};
+  const Cx<float>* bz32[3] = {nullptr, nullptr, nullptr};
   // workspace
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -171,19 +254,26 @@ hipError_t reset_counters(ibp_plan_s* p) {
 // Rows (x) or columns (z) per block of the general LDS transforms: whole
 // tiles, or half tiles when the length has a prime factor above 11 (the
 // direct-sum stage writes into the other half).
-int x_tile_rows(const ibp_plan_s* p, int tile) { return (p->fpx.any ? tile / 2 : tile) / p->h; }
+int x_tile_rows(const ibp_plan_s* p, int tile) {
+  if (p->fpx.blu) return tile / p->fpx.m;
+  return (p->fpx.any ? tile / 2 : tile) / p->h;
+}
 // Rows of this transform length fit the small x tile (FP64; FP32's is twice
 // as large).  Lengths with a direct-sum stage keep the large tile: its work
 // per block is the block's rows times h / 4 items, and one row of a half
 // small tile leaves most threads idle (measured slower at h = 316 and 501).
-bool x_small(const FftPlan& fpx, int h) { return !fpx.any && h <= kTileX64s; }
+bool x_small(const FftPlan& fpx, int h) { return !fpx.any && !fpx.blu && h <= kTileX64s; }
 int x_tile64(const ibp_plan_s* p) { return p->xsmall ? kTileX64s : kTileX64; }
 int x_tile32(const ibp_plan_s* p) { return p->xsmall ? kTileX32s : kTileX32; }
 int z_tile_cols(const ibp_plan_s* p, int tile) {
+  if (p->fpz.blu) return tile / (p->fpz.m + 1);
   return p->fpz.any ? (tile / 2) / (p->nz + 1) : tile / p->nz;
 }
 // Lines of this length fit the small z tile (FP64; the FP32 one is twice as large).
-bool z_small(const FftPlan& fpz, int nz) { return fpz.any ? nz + 1 <= kTileZ64s / 2 : nz <= kTileZ64s; }
+bool z_small(const FftPlan& fpz, int nz) {
+  if (fpz.blu) return false;
+  return fpz.any ? nz + 1 <= kTileZ64s / 2 : nz <= kTileZ64s;
+}
 
 size_t spec_bytes(const ibp_plan_s* p) {
   const size_t b64 = (size_t)p->ny * spec_plane_stride<double>(p->hp, p->nz) * sizeof(Cx<double>);
@@ -232,6 +322,8 @@ ibp_status_t check_dims(int nx, int ny, int nz, FftPlan* fpx, FftPlan* fpz) {
   if (ny < 2 || ny > kMaxNy) return IBP_ERROR_UNSUPPORTED_SIZE;
   FftPlan a{}, b{};
   if (!factorize(hx, &a) || !factorize(nz, &b)) return IBP_ERROR_UNSUPPORTED_SIZE;
+  plan_bluestein(&a, kTileX64);          // rows of m values in the large x tile
+  plan_bluestein(&b, kTileZ64 / 2);      // columns of m + 1 values in the large z tile
   // a prime factor above 11 needs the spare half of the general tiles
   if (a.any && hx > kTileX64 / 2) return IBP_ERROR_UNSUPPORTED_SIZE;
   if (b.any && nz + 1 > kTileZ64 / 2) return IBP_ERROR_UNSUPPORTED_SIZE;
@@ -656,6 +748,26 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     const size_t o_lz32 = tof(lz);
     const size_t o_twx32 = put(cx32.data(), cx32.size() * sizeof(float));
     const size_t o_twz32 = put(cz32.data(), cz32.size() * sizeof(float));
+    // Bluestein tables: chirp, filter transform, length-m twiddles; FP64 and FP32
+    size_t o_bx[6] = {0, 0, 0, 0, 0, 0}, o_bz[6] = {0, 0, 0, 0, 0, 0};
+    auto put_blu = [&](const FftPlan& fp, size_t* o) {
+      std::vector<double> ch, bh, twr, twi;
+      bluestein_tables(fp.n, fp.m, ch, bh);
+      twiddles(fp.m, twr, twi);
+      std::vector<double> tw(2 * (size_t)fp.m);
+      for (int e = 0; e < fp.m; ++e) {
+        tw[2 * e] = twr[e];
+        tw[2 * e + 1] = twi[e];
+      }
+      o[0] = put(ch.data(), ch.size() * sizeof(double));
+      o[1] = put(bh.data(), bh.size() * sizeof(double));
+      o[2] = put(tw.data(), tw.size() * sizeof(double));
+      o[3] = tof(ch);
+      o[4] = tof(bh);
+      o[5] = tof(tw);
+    };
+    if (p->fpx.blu) put_blu(p->fpx, o_bx);
+    if (p->fpz.blu) put_blu(p->fpz, o_bz);
 
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess && p->fused) {
@@ -701,6 +813,16 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     p->lamx32 = reinterpret_cast<const float*>(d + o_lx32);
     p->lamz32 = reinterpret_cast<const float*>(d + o_lz32);
     p->twx32 = reinterpret_cast<const Cx<float>*>(d + o_twx32);
+    for (int t = 0; t < 3; ++t) {
+      if (p->fpx.blu) {
+        p->bx64[t] = reinterpret_cast<const Cx<double>*>(d + o_bx[t]);
+        p->bx32[t] = reinterpret_cast<const Cx<float>*>(d + o_bx[3 + t]);
+      }
+      if (p->fpz.blu) {
+        p->bz64[t] = reinterpret_cast<const Cx<double>*>(d + o_bz[t]);
+        p->bz32[t] = reinterpret_cast<const Cx<float>*>(d + o_bz[3 + t]);
+      }
+    }
     p->twz32 = reinterpret_cast<const Cx<float>*>(d + o_twz32);
 
     p->ws_bytes = workspace_bytes(p);
@@ -1101,6 +1223,18 @@ ibp_status_t ibp_helmholtz(ibp_plan_t p, double* field, ibp_location_t where, vo
 
 namespace {
 
+// Bluestein z transforms: column stride m + 1 and the tables.
+template <typename T>
+void zf_bluestein(const ibp_plan_s* p, ZfArgs<T>& z) {
+  if (!p->fpz.blu) return;
+  z.zss = p->fpz.m + 1;
+  if constexpr (sizeof(T) == 8) {
+    z.bc = p->bz64[0]; z.bb = p->bz64[1]; z.bt = p->bz64[2];
+  } else {
+    z.bc = p->bz32[0]; z.bb = p->bz32[1]; z.bt = p->bz32[2];
+  }
+}
+
 template <typename T>
 XArgs<T> xargs(ibp_plan_s* p, const double* rhs, const double* phi_in, double* phi_out, Cx<T>* spec,
                const Cx<T>* twx, int rb, int iter) {
@@ -1134,6 +1268,14 @@ XArgs<T> xargs(ibp_plan_s* p, const double* rhs, const double* phi_in, double* p
   a.out_scale = 1.0 / ((double)p->h * (double)p->nz);
   a.inv_nxnz = 1.0 / ((double)p->nx * (double)p->nz);
   a.iter = iter;
+  if (p->fpx.blu) {
+    a.hs = p->fpx.m;
+    if constexpr (sizeof(T) == 8) {
+      a.bc = p->bx64[0]; a.bb = p->bx64[1]; a.bt = p->bx64[2];
+    } else {
+      a.bc = p->bx32[0]; a.bb = p->bx32[1]; a.bt = p->bx32[2];
+    }
+  }
   return a;
 }
 
@@ -1333,6 +1475,7 @@ ibp_status_t enqueue_solve(ibp_plan_s* p, const double* rhs, double* phi, hipStr
   }
   ZfArgs<double> za{p->spec64, p->twz, p->ctl, p->fpz, p->nz, p->hp, p->zc64,
                     spec_row_stride<double>(p->hp), spec_plane_stride<double>(p->hp, p->nz), 0, 0};
+  zf_bluestein(p, za);
   ibp_status_t st = forward_xz<double>(p, xa, xmode, P_XR2C, za, s);
   if (st != IBP_SUCCESS) return st;
   YArgs<double, double> ya{p->spec64, p->lamx, p->lamz, p->ya, p->yc, p->ctl,
@@ -1362,6 +1505,7 @@ ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStr
   const long rs = spec_row_stride<float>(p->hp), ps = spec_plane_stride<float>(p->hp, p->nz);
   const long Q = (long)p->nz * rs;
   ZfArgs<float> za{p->spec32, p->twz32, p->ctl, p->fpz, p->nz, p->hp, p->zc32, rs, ps, 0, 0};
+  zf_bluestein(p, za);
   YArgs<float, U> ya{p->spec32, lx, lz, ca, cc, p->ctl, Q, rs, ps, p->ny, p->hp, 0, p->singular()};
 
   XArgs<float> xa = xargs<float>(p, rhs, phi, phi, p->spec32, p->twx32, p->rb32, 0);
@@ -1606,7 +1750,8 @@ ibp_status_t batch_eligible(const ibp_plan_t* plans, int count, int device) {
     if (plans[i]->prec == IBP_MIXED && plans[i]->max_iters != plans[0]->max_iters) return IBP_ERROR_INVALID_VALUE;
     // batches size every grid's general tiles whole (no direct-sum stages)
     // and split every row into pairs (even nx)
-    if (plans[i]->fpx.any || plans[i]->fpz.any || plans[i]->nx % 2) return IBP_ERROR_UNSUPPORTED_SIZE;
+    if (plans[i]->fpx.any || plans[i]->fpz.any || plans[i]->fpx.blu || plans[i]->fpz.blu || plans[i]->nx % 2)
+      return IBP_ERROR_UNSUPPORTED_SIZE;
   }
   if (plans[0]->prec != IBP_FP64 && plans[0]->prec != IBP_MIXED) return IBP_ERROR_UNSUPPORTED_SIZE;
   return IBP_SUCCESS;

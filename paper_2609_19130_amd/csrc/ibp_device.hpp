@@ -49,6 +49,10 @@ struct FftPlan {
   int nst;        // number of stages
   int radix[16];  // radices in stage order
   int any;        // 1: a radix above 11 (direct-sum stage; half tiles)
+  int blu;        // 1: Bluestein: the length-n DFT as a length-m cyclic convolution
+  int m;          // Bluestein convolution length (a power of two >= 2n - 1)
+  int mst;        // its stages
+  int mradix[8];  // its radices (8, 4, 2)
 };
 
 // ---------------------------------------------------------------- butterflies
@@ -290,17 +294,13 @@ __device__ __forceinline__ void fft_stage_any(Cx<T>* buf, Cx<T>* spare, int n, i
 
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-// nb sequences of length fp.n; sequence b starts at buf + b*ss.
-// TILE is the compile-time bound on nb * ss; a plan with a prime factor
-// above 11 (fp.any) keeps nb * ss <= TILE / 2 (the direct-sum stage's spare
-// half).
+// The Stockham stages of one factorisation over nb sequences of length n.
 template <int TILE, bool INV, typename T>
-__device__ __forceinline__ void lds_fft(Cx<T>* buf, int nb, int ss, const FftPlan& fp,
-                        const Cx<T>* __restrict__ tw, int twstride) {
-  const int n = fp.n;
+__device__ __forceinline__ void lds_stages(Cx<T>* buf, int nb, int ss, int n, int nst, const int* radix,
+                                           const Cx<T>* __restrict__ tw, int twstride) {
   int Ns = 1;
-  for (int s = 0; s < fp.nst; ++s) {
-    const int R = fp.radix[s];
+  for (int s = 0; s < nst; ++s) {
+    const int R = radix[s];
     switch (R) {
       case 8: fft_stage<8, cdiv(TILE, 8 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride); break;
       case 4: fft_stage<4, cdiv(TILE, 4 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride); break;
@@ -313,6 +313,63 @@ __device__ __forceinline__ void lds_fft(Cx<T>* buf, int nb, int ss, const FftPla
     }
     Ns *= R;
   }
+}
+
+// Bluestein's algorithm (the DFT as a chirp convolution): with
+// w_j = exp(-i pi j^2 / n), X_k = w_k sum_j (x_j w_j) conj(w_{k-j}), a cyclic
+// convolution of length m >= 2n - 1 done by two length-m transforms:
+//   a = x w zero-padded to m;  c = IFFT_m(FFT_m(a) * bhat) / m;  X = w c,
+// bhat = FFT_m of conj(w) laid out cyclically (host table).  The inverse DFT
+// is conj(forward(conj(x))).  Sequences sit at stride ss >= m.
+template <int TILE, bool INV, typename T>
+__device__ __forceinline__ void bluestein_fft(Cx<T>* buf, int nb, int ss, const FftPlan& fp,
+                                              const Cx<T>* __restrict__ chirp, const Cx<T>* __restrict__ bhat,
+                                              const Cx<T>* __restrict__ twm) {
+  const int n = fp.n, m = fp.m;
+  for (int t = threadIdx.x; t < nb * m; t += kThreads) {
+    const int b = t / m, j = t - b * m;
+    Cx<T> v{T(0), T(0)};
+    if (j < n) {
+      v = buf[b * ss + j];
+      if (INV) v = cconj(v);
+      v = cmul(v, chirp[j]);
+    }
+    buf[b * ss + j] = v;
+  }
+  __syncthreads();
+  lds_stages<TILE, false, T>(buf, nb, ss, m, fp.mst, fp.mradix, twm, 1);
+  for (int t = threadIdx.x; t < nb * m; t += kThreads) {
+    const int b = t / m, k = t - b * m;
+    buf[b * ss + k] = cmul(buf[b * ss + k], bhat[k]);
+  }
+  __syncthreads();
+  lds_stages<TILE, true, T>(buf, nb, ss, m, fp.mst, fp.mradix, twm, 1);
+  const T inv_m = T(1) / T(m);
+  for (int t = threadIdx.x; t < nb * n; t += kThreads) {
+    const int b = t / n, k = t - b * n;
+    Cx<T> v = cscale(cmul(buf[b * ss + k], chirp[k]), inv_m);
+    if (INV) v = cconj(v);
+    buf[b * ss + k] = v;
+  }
+  __syncthreads();
+}
+
+// nb sequences of length fp.n; sequence b starts at buf + b*ss.
+// TILE is the compile-time bound on nb * ss; a plan with a prime factor
+// above 11 (fp.any) keeps nb * ss <= TILE / 2 (the direct-sum stage's spare
+// half).  Bluestein plans (fp.blu) take the chirp, filter and length-m
+// twiddle tables.
+template <int TILE, bool INV, typename T>
+__device__ __forceinline__ void lds_fft(Cx<T>* buf, int nb, int ss, const FftPlan& fp,
+                                        const Cx<T>* __restrict__ tw, int twstride,
+                                        const Cx<T>* __restrict__ bchirp = nullptr,
+                                        const Cx<T>* __restrict__ bhat = nullptr,
+                                        const Cx<T>* __restrict__ btw = nullptr) {
+  if (fp.blu) {
+    bluestein_fft<TILE, INV, T>(buf, nb, ss, fp, bchirp, bhat, btw);
+    return;
+  }
+  lds_stages<TILE, INV, T>(buf, nb, ss, fp.n, fp.nst, fp.radix, tw, twstride);
 }
 
 // ---------------------------------------------------------------- reductions

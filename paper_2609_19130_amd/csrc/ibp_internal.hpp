@@ -81,6 +81,12 @@ struct XArgs {
   const double* w;
   const double* q;
   double idx, idz, rscale;
+  // Bluestein x transforms (fp.blu): LDS row stride hs (0: h) and the chirp,
+  // filter and length-m twiddle tables
+  int hs;
+  const Cx<T>* bc;
+  const Cx<T>* bb;
+  const Cx<T>* bt;
 };
 
 // f = (D u - q) * rscale for the two cells (2m, 2m+1) of row (j, k): the
@@ -135,6 +141,12 @@ struct ZfArgs {
   long rs, ps;           // spectrum row and plane strides (elements)
   int check_done;
   int plane0;            // first y plane of this launch
+  // Bluestein z transforms (fp.blu): LDS column stride zss (0: nz + 1) and
+  // the chirp, filter and length-m twiddle tables
+  int zss;
+  const Cx<T>* bc;
+  const Cx<T>* bb;
+  const Cx<T>* bt;
 };
 
 template <typename T, typename U>   // T: spectral storage, U: line-solve arithmetic
@@ -237,12 +249,18 @@ __device__ __forceinline__ void globalize(XArgs<T>& a) {
   a.ya = as_global(a.ya);
   a.yc = as_global(a.yc);
   a.dyf = as_global(a.dyf);
+  a.bc = as_global(a.bc);
+  a.bb = as_global(a.bb);
+  a.bt = as_global(a.bt);
 }
 template <typename T>
 __device__ __forceinline__ void globalize(ZfArgs<T>& a) {
   a.spec = as_global(a.spec);
   a.twz = as_global(a.twz);
   a.ctl = as_global(a.ctl);
+  a.bc = as_global(a.bc);
+  a.bb = as_global(a.bb);
+  a.bt = as_global(a.bt);
 }
 template <typename T, typename U>
 __device__ __forceinline__ void globalize(YArgs<T, U>& a) {

@@ -28,6 +28,7 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
   constexpr bool kRes = MODE == XM_RESID || MODE == XM_RESID_ONLY;
   if (kRes && __builtin_amdgcn_readfirstlane(A.ctl->done)) return;
   const int h = A.h, RB = A.rows_per_block, nx = A.nx, nz = A.nz, ny = A.ny;
+  const int hs = A.hs ? A.hs : h;   // LDS row stride (Bluestein: the convolution length)
   const bool odd = nx & 1;   // h = nx: single values, no split
   const long row0 = blk * RB;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -40,7 +41,7 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
     const long row = row0 + lr;
     if (row >= A.nrows) {
       if (MODE != XM_RESID_ONLY)
-        for (int m = lane; m < h; m += kWave) buf[lr * h + m] = Cx<T>{T(0), T(0)};
+        for (int m = lane; m < h; m += kWave) buf[lr * hs + m] = Cx<T>{T(0), T(0)};
       continue;
     }
     const double* frow = A.f + row * nx;
@@ -76,7 +77,7 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
         acc_in2 += v0 * v0;
         acc_max = fmax(acc_max, fabs(v0));
         if (!isfinite(v0)) acc_bad += 1.0;
-        if (MODE != XM_RESID_ONLY) buf[lr * h + m] = Cx<T>{T(v0 * s), T(0)};
+        if (MODE != XM_RESID_ONLY) buf[lr * hs + m] = Cx<T>{T(v0 * s), T(0)};
       }
     } else
     for (int m = lane; m < h; m += kWave) {
@@ -115,7 +116,7 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
       acc_in2 += v0 * v0 + v1 * v1;
       acc_max = fmax(acc_max, fmax(fabs(v0), fabs(v1)));
       if (!isfinite(v0) || !isfinite(v1)) acc_bad += 1.0;
-      if (MODE != XM_RESID_ONLY) buf[lr * h + m] = Cx<T>{T(v0 * s), T(v1 * s)};
+      if (MODE != XM_RESID_ONLY) buf[lr * hs + m] = Cx<T>{T(v0 * s), T(v1 * s)};
     }
     rs = wave_sum(rs);
     if (MODE != XM_RESID_ONLY && lane == 0) A.rowsum[row] = rs;
@@ -131,13 +132,13 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
   }
   if (MODE == XM_RESID_ONLY) return;
   __syncthreads();
-  lds_fft<TILE, false, T>(buf, RB, h, fp, A.twx, odd ? 1 : 2);
+  lds_fft<TILE, false, T>(buf, RB, hs, fp, A.twx, odd ? 1 : 2, A.bc, A.bb, A.bt);
 
   if (odd) {   // the first (nx+1)/2 coefficients, no split
     for (int e = threadIdx.x; e < RB * A.hp; e += kThreads) {
       const int lr = e / A.hp, kk = e - lr * A.hp;
       const long row = row0 + lr;
-      if (row < A.nrows) A.spec[row * A.rs + (row / nz) * (A.ps - (long)nz * A.rs) + kk] = buf[lr * h + kk];
+      if (row < A.nrows) A.spec[row * A.rs + (row / nz) * (A.ps - (long)nz * A.rs) + kk] = buf[lr * hs + kk];
     }
     __syncthreads();
     return;
@@ -147,8 +148,8 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
     const int lr = e / hh, k = e - lr * hh;
     const long row = row0 + lr;
     if (row >= A.nrows) continue;
-    const Cx<T> Zk = buf[lr * h + k % h];
-    const Cx<T> Zc = cconj(buf[lr * h + (h - k) % h]);
+    const Cx<T> Zk = buf[lr * hs + k % h];
+    const Cx<T> Zc = cconj(buf[lr * hs + (h - k) % h]);
     const Cx<T> E = cscale(cadd(Zk, Zc), T(0.5));
     const Cx<T> D = csub(Zk, Zc);
     const Cx<T> O = Cx<T>{T(0.5) * D.y, T(-0.5) * D.x};     // D / 2i
@@ -171,6 +172,7 @@ template <typename T, int MODE, int TILE>
 __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& fp, long blk, Cx<T>* buf) {
   if (MODE == CM_ADD && __builtin_amdgcn_readfirstlane(A.ctl->done)) return;
   const int h = A.h, RB = A.rows_per_block, nx = A.nx, nz = A.nz;
+  const int hs = A.hs ? A.hs : h;   // LDS row stride (Bluestein: the convolution length)
   const bool odd = nx & 1;   // h = nx: rebuild the full spectrum
   const long row0 = blk * RB;
   const int hh = odd ? 0 : h / 2 + 1;
@@ -181,8 +183,8 @@ __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& 
       Cx<T> X{T(0), T(0)};
       if (row < A.nrows) X = A.spec[row * A.rs + (row / nz) * (A.ps - (long)nz * A.rs) + k];
       if (k == 0) X.y = T(0);   // X[0] of a real sequence is real
-      buf[lr * h + k] = X;
-      if (k > 0) buf[lr * h + nx - k] = cconj(X);
+      buf[lr * hs + k] = X;
+      if (k > 0) buf[lr * hs + nx - k] = cconj(X);
     }
   }
   for (int e = threadIdx.x; e < RB * hh; e += kThreads) {
@@ -202,12 +204,12 @@ __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& 
     const Cx<T> E = cscale(cadd(Xk, Xmc), T(0.5));
     const Cx<T> D = cscale(csub(Xk, Xmc), T(0.5));
     const Cx<T> O = cmul(cconj(A.twx[k]), D);
-    buf[lr * h + k] = Cx<T>{E.x - O.y, E.y + O.x};               // E + i O
+    buf[lr * hs + k] = Cx<T>{E.x - O.y, E.y + O.x};               // E + i O
     const int km = (h - k) % h;
-    if (km != k) buf[lr * h + km] = Cx<T>{E.x + O.y, O.x - E.y};   // conj(E) + i conj(O)
+    if (km != k) buf[lr * hs + km] = Cx<T>{E.x + O.y, O.x - E.y};   // conj(E) + i conj(O)
   }
   __syncthreads();
-  lds_fft<TILE, true, T>(buf, RB, h, fp, A.twx, odd ? 1 : 2);
+  lds_fft<TILE, true, T>(buf, RB, hs, fp, A.twx, odd ? 1 : 2, A.bc, A.bb, A.bt);
 
   double cs = A.out_scale;
   if (MODE == CM_ADD) cs = cs / A.ctl->scale[A.iter & 1];
@@ -221,14 +223,14 @@ __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& 
     double* orow = A.out + row * nx;
     if (odd) {
       for (int m = lane; m < nx; m += kWave) {
-        double v0 = double(buf[lr * h + m].x) * cs + c00;
+        double v0 = double(buf[lr * hs + m].x) * cs + c00;
         if (MODE == CM_ADD) v0 += orow[m];
         orow[m] = v0;
       }
       continue;
     }
     for (int m = lane; m < h; m += kWave) {
-      const Cx<T> z = buf[lr * h + m];
+      const Cx<T> z = buf[lr * hs + m];
       double v0 = double(z.x) * cs + c00, v1 = double(z.y) * cs + c00;
       double2* o = reinterpret_cast<double2*>(orow + 2 * m);
       if (MODE == CM_ADD) {
@@ -252,7 +254,7 @@ template <typename T, bool INV, int TILE>
 __device__ __forceinline__ void zfft_gen_body(const ZfArgs<T>& A, const FftPlan& fp, int colblk, long plane_index,
                                               Cx<T>* buf) {
   if (A.check_done && __builtin_amdgcn_readfirstlane(A.ctl->done)) return;
-  const int nz = A.nz, C = A.cols, hp = A.hp, ss = nz + 1;
+  const int nz = A.nz, C = A.cols, hp = A.hp, ss = A.zss ? A.zss : nz + 1;
   const long rs = A.rs;
   const int c0 = colblk * C;
   Cx<T>* plane = A.spec + (size_t)plane_index * A.ps;
@@ -261,7 +263,7 @@ __device__ __forceinline__ void zfft_gen_body(const ZfArgs<T>& A, const FftPlan&
     buf[c * ss + z] = (c0 + c < hp) ? plane[(size_t)z * rs + c0 + c] : Cx<T>{T(0), T(0)};
   }
   __syncthreads();
-  lds_fft<TILE, INV, T>(buf, C, ss, fp, A.twz, 1);
+  lds_fft<TILE, INV, T>(buf, C, ss, fp, A.twz, 1, A.bc, A.bb, A.bt);
   for (int e = threadIdx.x; e < C * nz; e += kThreads) {
     const int z = e / C, c = e - z * C;
     if (c0 + c < hp) plane[(size_t)z * rs + c0 + c] = buf[c * ss + z];

@@ -191,3 +191,41 @@ def test_paper_size_501_sampled_modes():
     finally:
         plan.close()
     assert sampled_modes(f, phi, Lx, Lz, yf, MODES501) <= 1e-11
+
+
+# ---------------------------------------------------------------- Bluestein
+# prime factors above 256 take Bluestein's chirp convolution (x: nx/2 = 257,
+# odd nx = 521; z: 263), 1031 does not fit its convolution in a tile and
+# stays on the direct-sum stage
+BLU = [(514, 6, 263), (521, 5, 8), (16, 4, 1031), (514, 7, 12)]
+
+
+@pytest.mark.parametrize("nx,ny,nz", BLU)
+def test_bluestein_lengths_fp64_match_oracle(nx, ny, nz):
+    yf = synth.tanh_faces(ny, 2.0)
+    f = np.random.default_rng(nx + 11 * ny + nz).uniform(-1, 1, (ny, nz, nx))
+    phi, info = gpu_solve(f, 1.9, 1.3, yf)
+    ref, m = oracle.solve(f, 1.9, 1.3, yf)
+    assert abs(info["removed_mean"] - m) <= 1e-12 * max(1.0, abs(m))
+    assert rel(phi, ref) <= 1e-12, rel(phi, ref)
+
+
+def test_bluestein_mixed_and_inverse_round_trip():
+    """Mixed refinement (FP32 Bluestein tables) on x and z Bluestein lengths,
+    and the first-pass right-hand side assembly."""
+    nx, ny, nz = 514, 6, 263
+    Lx, Lz = 1.9, 1.3
+    yf = synth.tanh_faces(ny, 2.0)
+    g = geometry(nx, ny, nz, Lx, Lz, yf)
+    u, v, w = synth.uniform_velocity(nx, ny, nz, seed=23)
+    f = divergence(u, v, w, g)
+    phi, info = gpu_solve(f, Lx, Lz, yf, precision="mixed", rtol=1e-10, max_iters=6)
+    r = residual(f, phi, Lx, Lz, yf)
+    assert info["converged"] == 1 and r <= 1e-10, (r, info)
+    plan = ibp.Plan(nx, ny, nz, Lx, Lz, yf)
+    try:
+        phid = plan.solve_divergence(to_dev(u), to_dev(v), to_dev(w), 0.05).cpu().numpy()
+    finally:
+        plan.close()
+    ref, _ = oracle.solve(rhs_from_velocity(u, v, w, None, g, 0.05), Lx, Lz, yf)
+    assert rel(phid, ref) <= 1e-12
