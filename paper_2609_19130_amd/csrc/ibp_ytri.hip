@@ -493,14 +493,14 @@ static int ytri_cols(int P, int K, int want) {
   const int o = want ? want : ycol_override();
   if (o == 2 || o == 4 || o == 8 || o == 16) M = o;
   while (M > 2 && tile(M) > kYTileBytes) M /= 2;
-  while (M * P > 1024) M /= 2;
+  while (M * P > 512) M /= 2;   // 1024-thread blocks cap the solve at 128 VGPRs and spill
   return M;
 }
 
 template <typename T, typename U, int M, int P, int K>
 static hipError_t launch_ytri_mpk(const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s) {
   // only shapes ytri_cols can select are instantiated (staged tile <= kYTileBytes)
-  if constexpr (ytile_slots<M, P, K>() * (long)sizeof(Cx<T>) <= kYTileBytes && M * P <= 1024) {
+  if constexpr (ytile_slots<M, P, K>() * (long)sizeof(Cx<T>) <= kYTileBytes && M * P <= 512) {
     const long nb = (a.Q + M - 1) / M + a.ny;   // + the (0,0)-mode plane blocks
     hipLaunchKernelGGL((k_ytri<T, U, M, P, K>), dim3((unsigned)nb), dim3(M * P), 0, s, a, z);
     return hipGetLastError();
@@ -591,14 +591,14 @@ int batch_ytri_cols(int P, int K, int want) {
   auto tile = [&](int M) { return ytile_slots_host(M, P, K) * (long)sizeof(Cx<T>); };
   int M = (want == 2 || want == 4 || want == 8 || want == 16) ? want : 128 / (int)sizeof(Cx<T>);
   while (M > 2 && tile(M) > kYTileBytes) M /= 2;
-  while (M * P > 1024) M /= 2;
+  while (M * P > 512) M /= 2;   // 1024-thread blocks cap the solve at 128 VGPRs and spill
   return M;
 }
 
 template <typename T, int M, int P, int K>
 static hipError_t launch_kb_ytri(const BatchGrid<T>* d, const long* start, long nb, const BatchLaunch& l,
                                  hipStream_t s) {
-  if constexpr (ytile_slots<M, P, K>() * (long)sizeof(Cx<T>) <= kYTileBytes && M * P <= 1024) {
+  if constexpr (ytile_slots<M, P, K>() * (long)sizeof(Cx<T>) <= kYTileBytes && M * P <= 512) {
     hipLaunchKernelGGL((kb_ytri<T, M, P, K>), dim3((unsigned)nb), dim3(M * P), 0, s, d, start, l);
     return hipGetLastError();
   } else {
