@@ -1686,6 +1686,7 @@ ibp_status_t batch_build(ibp_batch_s* b) {
                       (long)p->nz * rs, rs, ps, p->ny, p->hp, 0, p->singular()};
     d.zero = zargs(p, 0, 0, 0, 0, 0);
     d.zero.part = part;
+    d.yk = batch_grid_rows_per_lane(p->ny, b->yP, b->yK);
   }
   e = hipMemcpy(dtab, tab.data(), tab.size() * sizeof(T), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = batch_apply<T>(b, hd);

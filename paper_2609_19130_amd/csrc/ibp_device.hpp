@@ -43,6 +43,25 @@ __device__ __forceinline__ Cx<T> mul_mi(Cx<T> a) {
   return INV ? Cx<T>{-a.y, a.x} : Cx<T>{a.y, -a.x};
 }
 
+// Exact quotient t / d of small non-negative integers (0 <= t < 2^19,
+// d >= 1) from a float reciprocal: r = (1/d rounded) * (1 + 1.5 * 2^-20)
+// rounded, and q = trunc(t * r rounded).  The three roundings move the
+// product by less than 2^-22 relative, so it lies in [t/d, t/d (1 + 2^-19));
+// that never reaches floor(t/d) + 1 while t < 2^19, and never falls below an
+// exact quotient, so truncation gives floor(t/d).  Three full-rate VALU
+// operations per quotient instead of the integer division sequence (whose
+// 32-bit multiplies issue at quarter rate); used for the index arithmetic of
+// the general LDS transforms, where t and d are tile offsets and lengths.
+struct QDiv {
+  float r;
+  int d;
+};
+constexpr float kQDivRaise = 1.000001430511474609375f;   // 1 + 1.5 * 2^-20, exact in FP32
+__device__ __forceinline__ QDiv qdiv(int d) { return QDiv{(1.0f / (float)d) * kQDivRaise, d}; }
+__device__ __forceinline__ int qquo(int t, QDiv q) { return (int)((float)t * q.r); }
+// t - d * (t / d)
+__device__ __forceinline__ int qrem(int t, QDiv q) { return t - __mul24(qquo(t, q), q.d); }
+
 // FFT factorisation handed to kernels by value.
 struct FftPlan {
   int n;          // sequence length
@@ -203,6 +222,7 @@ __device__ __forceinline__ void fft_stage(Cx<T>* buf, int n, int nb, int ss, int
   const int m = n / R;
   const int nbf = nb * m;
   const int twmul = (n / (Ns * R)) * twstride;
+  const QDiv qm = qdiv(m), qs = qdiv(Ns);
   Cx<T> v[MAXB][R];
   int dst[MAXB];
 #pragma unroll
@@ -210,22 +230,22 @@ __device__ __forceinline__ void fft_stage(Cx<T>* buf, int n, int nb, int ss, int
     const int t = threadIdx.x + q * kThreads;
     dst[q] = -1;
     if (t < nbf) {
-      const int b = t / m;
-      const int j = t - b * m;
-      const int k = j % Ns;
-      const Cx<T>* base = buf + b * ss;
+      const int b = qquo(t, qm);
+      const int j = t - __mul24(b, m);
+      const int k = qrem(j, qs);
+      const Cx<T>* base = buf + __mul24(b, ss);
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = base[j + r * m];
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          Cx<T> w = tw[r * k * twmul];
+          Cx<T> w = tw[__mul24(r * k, twmul)];
           if (INV) w.y = -w.y;
           v[q][r] = cmul(v[q][r], w);
         }
       }
       Bfly<R, INV, T>::run(v[q]);
-      dst[q] = b * ss + (j - k) * R + k;
+      dst[q] = __mul24(b, ss) + (j - k) * R + k;
     }
   }
   __syncthreads();
@@ -257,12 +277,13 @@ __device__ __forceinline__ void fft_stage_any(Cx<T>* buf, Cx<T>* spare, int n, i
   const int twmul = (n / (Ns * R)) * twstride;
   const int QB = (R + QA - 1) / QA;   // output groups per butterfly
   const int items = nb * m * QB;
+  const QDiv qmb = qdiv(m * QB), qm = qdiv(m), qs = qdiv(Ns), qn = qdiv(n);
   for (int t = threadIdx.x; t < items; t += kThreads) {
-    const int b = t / (m * QB);
-    const int w = t - b * (m * QB);
-    const int qb = w / m, j = w - qb * m;   // consecutive threads: consecutive butterflies
-    const int k = j % Ns;
-    const Cx<T>* base = buf + b * ss + j;
+    const int b = qquo(t, qmb);
+    const int w = t - __mul24(b, m * QB);
+    const int qb = qquo(w, qm), j = w - __mul24(qb, m);   // consecutive threads: consecutive butterflies
+    const int k = qrem(j, qs);
+    const Cx<T>* base = buf + __mul24(b, ss) + j;
     Cx<T> om[QA], y[QA];
     const Cx<T> top = base[(R - 1) * m];
 #pragma unroll
@@ -285,8 +306,8 @@ __device__ __forceinline__ void fft_stage_any(Cx<T>* buf, Cx<T>* spare, int n, i
   }
   __syncthreads();
   for (int t = threadIdx.x; t < nb * n; t += kThreads) {
-    const int b = t / n;
-    const int i = b * ss + (t - b * n);
+    const int b = qquo(t, qn);
+    const int i = __mul24(b, ss) + (t - __mul24(b, n));
     buf[i] = spare[i];
   }
   __syncthreads();
@@ -326,8 +347,9 @@ __device__ __forceinline__ void bluestein_fft(Cx<T>* buf, int nb, int ss, const 
                                               const Cx<T>* __restrict__ chirp, const Cx<T>* __restrict__ bhat,
                                               const Cx<T>* __restrict__ twm) {
   const int n = fp.n, m = fp.m;
+  const QDiv qm = qdiv(m), qn = qdiv(n);
   for (int t = threadIdx.x; t < nb * m; t += kThreads) {
-    const int b = t / m, j = t - b * m;
+    const int b = qquo(t, qm), j = t - __mul24(b, m);
     Cx<T> v{T(0), T(0)};
     if (j < n) {
       v = buf[b * ss + j];
@@ -339,14 +361,14 @@ __device__ __forceinline__ void bluestein_fft(Cx<T>* buf, int nb, int ss, const 
   __syncthreads();
   lds_stages<TILE, false, T>(buf, nb, ss, m, fp.mst, fp.mradix, twm, 1);
   for (int t = threadIdx.x; t < nb * m; t += kThreads) {
-    const int b = t / m, k = t - b * m;
+    const int b = qquo(t, qm), k = t - __mul24(b, m);
     buf[b * ss + k] = cmul(buf[b * ss + k], bhat[k]);
   }
   __syncthreads();
   lds_stages<TILE, true, T>(buf, nb, ss, m, fp.mst, fp.mradix, twm, 1);
   const T inv_m = T(1) / T(m);
   for (int t = threadIdx.x; t < nb * n; t += kThreads) {
-    const int b = t / n, k = t - b * n;
+    const int b = qquo(t, qn), k = t - __mul24(b, n);
     Cx<T> v = cscale(cmul(buf[b * ss + k], chirp[k]), inv_m);
     if (INV) v = cconj(v);
     buf[b * ss + k] = v;

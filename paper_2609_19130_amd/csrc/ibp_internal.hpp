@@ -225,6 +225,7 @@ struct BatchGrid {
   YArgs<T, T> y;   // check_done replaced at launch
   ZeroArgs zero;   // init, mixed, iter, final_pass replaced at launch
   int zcolblocks;  // z-pass column blocks per plane
+  int yk;          // line-solve rows per lane for this grid (the batch's K, K/2 or K/4)
 };
 
 // Pointers read from a device table are generic (flat) to the compiler;
@@ -314,6 +315,7 @@ hipError_t launch_batch_check(const BatchGrid<T>* d, const BatchLaunch& l, hipSt
 // Columns per block of the batched line solve for lanes P, rows per lane K.
 template <typename T>
 int batch_ytri_cols(int P, int K, int want);
+int batch_grid_rows_per_lane(int ny, int P, int K);
 
 struct DivArgs {          // f = (D u - q) * scale; q may be null
   const double* u;

@@ -31,6 +31,11 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
   const int hs = A.hs ? A.hs : h;   // LDS row stride (Bluestein: the convolution length)
   const bool odd = nx & 1;   // h = nx: single values, no split
   const long row0 = blk * RB;
+  // row = j nz + k: the block's first row splits once, later rows by exact
+  // small quotients (rows of a grid number below 2^31)
+  const int j0 = (int)row0 / nz, k0 = (int)row0 - j0 * nz;
+  const QDiv qnz = qdiv(nz);
+  const long pgap = A.ps - (long)nz * A.rs;   // spectral plane padding
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   double acc_in2 = 0.0, acc_f2 = 0.0, acc_max = 0.0, acc_bad = 0.0, acc_wphi = 0.0;
   double mean = 0.0, s = 1.0;
@@ -46,8 +51,9 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
     }
     const double* frow = A.f + row * nx;
     double rs = 0.0;
-    const int j = (int)(row / nz);
-    const int k = (int)(row - (long)j * nz);
+    const int jr = qquo(k0 + lr, qnz);
+    const int j = j0 + jr;
+    const int k = k0 + lr - __mul24(jr, nz);
     if (odd) {
       for (int m = lane; m < nx; m += kWave) {
         const double fv = MODE == XM_DIV ? assemble_one(A, row, j, k, m) : frow[m];
@@ -135,26 +141,29 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
   lds_fft<TILE, false, T>(buf, RB, hs, fp, A.twx, odd ? 1 : 2, A.bc, A.bb, A.bt);
 
   if (odd) {   // the first (nx+1)/2 coefficients, no split
+    const QDiv qhp = qdiv(A.hp);
     for (int e = threadIdx.x; e < RB * A.hp; e += kThreads) {
-      const int lr = e / A.hp, kk = e - lr * A.hp;
+      const int lr = qquo(e, qhp), kk = e - __mul24(lr, A.hp);
       const long row = row0 + lr;
-      if (row < A.nrows) A.spec[row * A.rs + (row / nz) * (A.ps - (long)nz * A.rs) + kk] = buf[lr * hs + kk];
+      if (row < A.nrows)
+        A.spec[row * A.rs + (j0 + qquo(k0 + lr, qnz)) * pgap + kk] = buf[__mul24(lr, hs) + kk];
     }
     __syncthreads();
     return;
   }
   const int hh = h / 2 + 1;
+  const QDiv qhh = qdiv(hh);
   for (int e = threadIdx.x; e < RB * hh; e += kThreads) {
-    const int lr = e / hh, k = e - lr * hh;
+    const int lr = qquo(e, qhh), k = e - __mul24(lr, hh);
     const long row = row0 + lr;
     if (row >= A.nrows) continue;
-    const Cx<T> Zk = buf[lr * hs + k % h];
-    const Cx<T> Zc = cconj(buf[lr * hs + (h - k) % h]);
+    const Cx<T> Zk = buf[__mul24(lr, hs) + k];   // k < hh <= h
+    const Cx<T> Zc = cconj(buf[__mul24(lr, hs) + (k ? h - k : 0)]);
     const Cx<T> E = cscale(cadd(Zk, Zc), T(0.5));
     const Cx<T> D = csub(Zk, Zc);
     const Cx<T> O = Cx<T>{T(0.5) * D.y, T(-0.5) * D.x};     // D / 2i
     const Cx<T> WO = cmul(A.twx[k], O);
-    Cx<T>* srow = A.spec + row * A.rs + (row / nz) * (A.ps - (long)nz * A.rs);
+    Cx<T>* srow = A.spec + row * A.rs + (j0 + qquo(k0 + lr, qnz)) * pgap;
     srow[k] = cadd(E, WO);
     if (h - k != k) srow[h - k] = cconj(csub(E, WO));
   }
@@ -176,23 +185,30 @@ __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& 
   const bool odd = nx & 1;   // h = nx: rebuild the full spectrum
   const long row0 = blk * RB;
   const int hh = odd ? 0 : h / 2 + 1;
+  // row = j nz + k: the block's first row splits once, later rows by exact
+  // small quotients (rows of a grid number below 2^31)
+  const int j0 = (int)row0 / nz, k0 = (int)row0 - j0 * nz;
+  const QDiv qnz = qdiv(nz);
+  const long pgap = A.ps - (long)nz * A.rs;   // spectral plane padding
   if (odd) {
+    const QDiv qhp = qdiv(A.hp);
     for (int e = threadIdx.x; e < RB * A.hp; e += kThreads) {
-      const int lr = e / A.hp, k = e - lr * A.hp;
+      const int lr = qquo(e, qhp), k = e - __mul24(lr, A.hp);
       const long row = row0 + lr;
       Cx<T> X{T(0), T(0)};
-      if (row < A.nrows) X = A.spec[row * A.rs + (row / nz) * (A.ps - (long)nz * A.rs) + k];
+      if (row < A.nrows) X = A.spec[row * A.rs + (j0 + qquo(k0 + lr, qnz)) * pgap + k];
       if (k == 0) X.y = T(0);   // X[0] of a real sequence is real
-      buf[lr * hs + k] = X;
-      if (k > 0) buf[lr * hs + nx - k] = cconj(X);
+      buf[__mul24(lr, hs) + k] = X;
+      if (k > 0) buf[__mul24(lr, hs) + nx - k] = cconj(X);
     }
   }
+  const QDiv qhh = qdiv(odd ? 1 : hh);
   for (int e = threadIdx.x; e < RB * hh; e += kThreads) {
-    const int lr = e / hh, k = e - lr * hh;
+    const int lr = qquo(e, qhh), k = e - __mul24(lr, hh);
     const long row = row0 + lr;
     Cx<T> Xk{T(0), T(0)}, Xm{T(0), T(0)};
     if (row < A.nrows) {
-      const Cx<T>* srow = A.spec + row * A.rs + (row / nz) * (A.ps - (long)nz * A.rs);
+      const Cx<T>* srow = A.spec + row * A.rs + (j0 + qquo(k0 + lr, qnz)) * pgap;
       Xk = srow[k];
       Xm = srow[h - k];
     }
@@ -204,9 +220,9 @@ __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& 
     const Cx<T> E = cscale(cadd(Xk, Xmc), T(0.5));
     const Cx<T> D = cscale(csub(Xk, Xmc), T(0.5));
     const Cx<T> O = cmul(cconj(A.twx[k]), D);
-    buf[lr * hs + k] = Cx<T>{E.x - O.y, E.y + O.x};               // E + i O
-    const int km = (h - k) % h;
-    if (km != k) buf[lr * hs + km] = Cx<T>{E.x + O.y, O.x - E.y};   // conj(E) + i conj(O)
+    buf[__mul24(lr, hs) + k] = Cx<T>{E.x - O.y, E.y + O.x};               // E + i O
+    const int km = k ? h - k : 0;                                            // (h - k) mod h, k < hh <= h
+    if (km != k) buf[__mul24(lr, hs) + km] = Cx<T>{E.x + O.y, O.x - E.y};   // conj(E) + i conj(O)
   }
   __syncthreads();
   lds_fft<TILE, true, T>(buf, RB, hs, fp, A.twx, odd ? 1 : 2, A.bc, A.bb, A.bt);
@@ -217,7 +233,7 @@ __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& 
   for (int lr = wave; lr < RB; lr += kThreads / kWave) {
     const long row = row0 + lr;
     if (row >= A.nrows) break;
-    const int j = (int)(row / nz);
+    const int j = j0 + qquo(k0 + lr, qnz);
     double c00 = A.phi00[j] * A.inv_nxnz;
     if (MODE == CM_ADD) c00 -= A.ctl->phimean;
     double* orow = A.out + row * nx;
@@ -258,14 +274,15 @@ __device__ __forceinline__ void zfft_gen_body(const ZfArgs<T>& A, const FftPlan&
   const long rs = A.rs;
   const int c0 = colblk * C;
   Cx<T>* plane = A.spec + (size_t)plane_index * A.ps;
+  const QDiv qc = qdiv(C);
   for (int e = threadIdx.x; e < C * nz; e += kThreads) {
-    const int z = e / C, c = e - z * C;
+    const int z = qquo(e, qc), c = e - __mul24(z, C);
     buf[c * ss + z] = (c0 + c < hp) ? plane[(size_t)z * rs + c0 + c] : Cx<T>{T(0), T(0)};
   }
   __syncthreads();
   lds_fft<TILE, INV, T>(buf, C, ss, fp, A.twz, 1, A.bc, A.bb, A.bt);
   for (int e = threadIdx.x; e < C * nz; e += kThreads) {
-    const int z = e / C, c = e - z * C;
+    const int z = qquo(e, qc), c = e - __mul24(z, C);
     if (c0 + c < hp) plane[(size_t)z * rs + c0 + c] = buf[c * ss + z];
   }
   __syncthreads();

@@ -387,17 +387,12 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
     const int mm = threadIdx.x % M, row0 = threadIdx.x / M;
     const long qs = q0 + mm;
     if (qs < Q && qs % A.rs < A.hp) {
-      Cx<T> st[K];
 #pragma unroll
       for (int i = 0; i < K; ++i) {
         const int row = row0 + P * i;
         const int pp = row / K;
-        st[i] = tile[pp * PS + (row - pp * K) * M + mm];
-      }
-#pragma unroll
-      for (int i = 0; i < K; ++i) {
-        const int row = row0 + P * i;
-        if (row < ny) A.spec[(long)row * A.ps + qs] = st[i];
+        const Cx<T> v = tile[pp * PS + (row - pp * K) * M + mm];
+        if (row < ny) A.spec[(long)row * A.ps + qs] = v;
       }
     }
   }
@@ -464,6 +459,9 @@ hipError_t launch_check(const ZeroArgs& z, hipStream_t s) {
 // from {2, 4, 8, 12, 16, 24}; M columns per block so that a row segment is
 // 128 bytes, reduced while the staged tile would exceed 64 KB.
 static constexpr int kKs[] = {2, 4, 8, 12, 16, 24};
+// (lanes, rows per lane) pairs ytri_shape returns: 32 lanes up to 12 rows,
+// 64 lanes from 8 rows (ny above 384 needs more than 6 rows of 64)
+constexpr bool ytri_pair_used(int P, int K) { return P == 32 ? K <= 12 : K >= 8; }
 
 bool ytri_shape(int ny, int* P, int* K) {
   if (ny < 2 || ny > kMaxNy) return false;
@@ -499,8 +497,9 @@ static int ytri_cols(int P, int K, int want) {
 
 template <typename T, typename U, int M, int P, int K>
 static hipError_t launch_ytri_mpk(const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s) {
-  // only shapes ytri_cols can select are instantiated (staged tile <= kYTileBytes)
-  if constexpr (ytile_slots<M, P, K>() * (long)sizeof(Cx<T>) <= kYTileBytes && M * P <= 512) {
+  // only shapes ytri_shape and ytri_cols can select are instantiated
+  if constexpr (ytile_slots<M, P, K>() * (long)sizeof(Cx<T>) <= kYTileBytes && M * P <= 512 &&
+                ytri_pair_used(P, K)) {
     const long nb = (a.Q + M - 1) / M + a.ny;   // + the (0,0)-mode plane blocks
     hipLaunchKernelGGL((k_ytri<T, U, M, P, K>), dim3((unsigned)nb), dim3(M * P), 0, s, a, z);
     return hipGetLastError();
@@ -571,7 +570,32 @@ void kb_ytri(const BatchGrid<T>* __restrict__ D, const long* __restrict__ start,
   z.final_pass = L.final_pass;
   globalize(a);
   globalize(z);
-  ytri_body<T, T, M, P, K>(a, z, (long)blockIdx.x - start[g], tile);
+  const long lb = (long)blockIdx.x - start[g];
+  // rows per lane of this grid: K, K/2 or K/4 (the smallest that holds its
+  // ny), so short columns of a batch with one tall grid skip the padding rows
+  const int kg = __builtin_amdgcn_readfirstlane(D[g].yk);
+  if constexpr (K % 4 == 0) {
+    if (kg == K / 4) {
+      ytri_body<T, T, M, P, K / 4>(a, z, lb, tile);
+      return;
+    }
+  }
+  if constexpr (K % 2 == 0) {
+    if (kg == K / 2) {
+      ytri_body<T, T, M, P, K / 2>(a, z, lb, tile);
+      return;
+    }
+  }
+  ytri_body<T, T, M, P, K>(a, z, lb, tile);
+}
+
+// Rows per lane for one grid of a batch whose line-solve shape is P lanes x
+// K rows: K/4 or K/2 when that still holds ny (the variants kb_ytri has).
+int batch_grid_rows_per_lane(int ny, int P, int K) {
+  const int need = (ny + P - 1) / P;
+  if (K % 4 == 0 && need <= K / 4) return K / 4;
+  if (K % 2 == 0 && need <= K / 2) return K / 2;
+  return K;
 }
 
 template <typename T>
@@ -598,7 +622,8 @@ int batch_ytri_cols(int P, int K, int want) {
 template <typename T, int M, int P, int K>
 static hipError_t launch_kb_ytri(const BatchGrid<T>* d, const long* start, long nb, const BatchLaunch& l,
                                  hipStream_t s) {
-  if constexpr (ytile_slots<M, P, K>() * (long)sizeof(Cx<T>) <= kYTileBytes && M * P <= 512) {
+  if constexpr (ytile_slots<M, P, K>() * (long)sizeof(Cx<T>) <= kYTileBytes && M * P <= 512 &&
+                ytri_pair_used(P, K)) {
     hipLaunchKernelGGL((kb_ytri<T, M, P, K>), dim3((unsigned)nb), dim3(M * P), 0, s, d, start, l);
     return hipGetLastError();
   } else {

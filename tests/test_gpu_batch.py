@@ -19,13 +19,23 @@ TOL64 = 1e-12
 REG_LENGTHS = {32, 64, 128, 256, 512, 1024}   # lengths the single-grid path transforms in registers
 
 
-def line_solve_rows(ny):
-    """Rows per lane of the line solve for ny (32 lanes up to ny = 768, then
-    64; rows from 2, 4, 8, 12, 16, 24): a batch uses the value of its largest
-    ny, so grids with another value compose their scans differently."""
-    lanes = 64 if ny > 768 else 32
+def line_solve_shape(ny):
+    """(lanes, rows per lane) of a single grid's line solve: 32 lanes up to
+    ny = 384, then 64; rows from 2, 4, 8, 12, 16, 24."""
+    lanes = 64 if ny > 384 else 32
     need = -(-ny // lanes)
-    return next(k for k in (2, 4, 8, 12, 16, 24) if k >= need)
+    return lanes, next(k for k in (2, 4, 8, 12, 16, 24) if k >= need)
+
+
+def batch_rows(ny, lanes, kmax):
+    """Rows per lane of one grid inside a batch whose largest ny gives
+    (lanes, kmax): kmax/4 or kmax/2 where that holds ny, else kmax."""
+    need = -(-ny // lanes)
+    if kmax % 4 == 0 and need <= kmax // 4:
+        return kmax // 4
+    if kmax % 2 == 0 and need <= kmax // 2:
+        return kmax // 2
+    return kmax
 
 
 @pytest.fixture(autouse=True)
@@ -62,13 +72,14 @@ def test_batched_fp64_matches_single_and_oracle(c4):
     phis = [torch.empty_like(r) for r in rhs]
     ibp.solve_batched(plans, rhs, phis)
     torch.cuda.synchronize()
-    kb = line_solve_rows(max(gd["ny"] for gd in grids))
+    lanes, kmax = line_solve_shape(max(gd["ny"] for gd in grids))
     same = 0
     for i, (p, r) in enumerate(zip(plans, rhs)):
         single = p.solve(r)
         gd = grids[i]
         assert float(torch.linalg.vector_norm(single - phis[i]) / torch.linalg.vector_norm(single)) <= TOL64, i
-        if gd["nx"] // 2 not in REG_LENGTHS and gd["nz"] not in REG_LENGTHS and line_solve_rows(gd["ny"]) == kb:
+        if (gd["nx"] // 2 not in REG_LENGTHS and gd["nz"] not in REG_LENGTHS
+                and line_solve_shape(gd["ny"]) == (lanes, batch_rows(gd["ny"], lanes, kmax))):
             same += 1
             assert torch.equal(single, phis[i]), f"grid {i}: batched differs from single"
     assert same >= 3
