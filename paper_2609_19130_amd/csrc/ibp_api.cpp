@@ -171,6 +171,7 @@ struct ibp_plan_s {
   bool xfast = false, zfast = false;   // register-FFT kernels for power-of-two lengths
   bool zsmall = false;                 // general z transform in the small tile
   bool xsmall = false;                 // general x transform in the small tile
+  bool xwide = true, zwide = true;     // general transform needs the wide kernel family
   // fused persistent x/z passes (nz = nx and both lengths register-FFT sizes)
   bool fused = false;
   int fblocks64 = 0, fblocks32 = 0;   // persistent blocks (FP64 / FP32 spectrum)
@@ -268,6 +269,17 @@ int x_tile32(const ibp_plan_s* p) { return p->xsmall ? kTileX32s : kTileX32; }
 int z_tile_cols(const ibp_plan_s* p, int tile) {
   if (p->fpz.blu) return tile / (p->fpz.m + 1);
   return p->fpz.any ? (tile / 2) / (p->nz + 1) : tile / p->nz;
+}
+// A factorisation with a radix other than 2, 3, 4, 5, 8 (or Bluestein's
+// convolution) needs the wide kernel family; the narrow one holds far fewer
+// registers.
+bool fft_wide(const FftPlan& fp) {
+  if (fp.blu || fp.any) return true;
+  for (int s = 0; s < fp.nst; ++s) {
+    const int r = fp.radix[s];
+    if (r != 2 && r != 3 && r != 4 && r != 5 && r != 8) return true;
+  }
+  return false;
 }
 // Lines of this length fit the small z tile (FP64; the FP32 one is twice as large).
 bool z_small(const FftPlan& fpz, int nz) {
@@ -645,6 +657,8 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     p->zfast = rfft::supported(nz);
     const long nrows = (long)ny * nz;
     p->xsmall = x_small(p->fpx, p->h);
+    p->xwide = fft_wide(p->fpx);
+    p->zwide = fft_wide(p->fpz);
     p->nbro = (nrows + x_tile_rows(p, x_tile32(p)) - 1) / x_tile_rows(p, x_tile32(p));
     if (p->xfast) {
       p->rb64 = p->rb32 = (int)fast_x_rows_per_block(p->h);
@@ -1327,21 +1341,21 @@ hipError_t run_xr2c(const ibp_plan_s* p, int mode, const XArgs<T>& a, hipStream_
     b.row_begin = 0;
     b.nrows = (long)p->ny * p->nz;
     b.parts = 1;
-    return launch_xr2c<T>(mode, p->xsmall, b, s);
+    return launch_xr2c<T>(mode, p->xsmall, p->xwide, b, s);
   }
-  return launch_xr2c<T>(mode, p->xsmall, a, s);
+  return launch_xr2c<T>(mode, p->xsmall, p->xwide, a, s);
 }
 
 template <typename T>
 hipError_t run_xc2r(const ibp_plan_s* p, int mode, const XArgs<T>& a, hipStream_t s) {
   if (p->xfast) return launch_xc2r_fast<T>(mode, a, s);
-  return launch_xc2r<T>(mode, p->xsmall, a, s);
+  return launch_xc2r<T>(mode, p->xsmall, p->xwide, a, s);
 }
 
 template <typename T>
 hipError_t run_zfft(const ibp_plan_s* p, bool inverse, const ZfArgs<T>& a, int nplanes, hipStream_t s) {
   if (p->zfast) return launch_zfft_fast<T>(inverse, a, nplanes, s);
-  return launch_zfft<T>(inverse, p->zsmall, a, nplanes, s);
+  return launch_zfft<T>(inverse, p->zsmall, p->zwide, a, nplanes, s);
 }
 
 // Forward transforms of the whole grid: x R2C then z FFT.  With chunking,
@@ -1555,8 +1569,11 @@ struct ibp_batch_s {
   std::vector<unsigned> gens;
   void* dmem = nullptr;
   void* desc = nullptr;      // BatchGrid<T>[count]
-  long* start = nullptr;     // [3][count + 1]: x, z, y stage prefix offsets
-  long nblk[3] = {0, 0, 0};  // blocks of the x, z and y stage launches
+  long* start = nullptr;     // [5][count + 1]: prefix offsets of the stage launches (nblk order)
+  // blocks of the x (narrow, wide family), z (narrow, wide) and y stage launches:
+  // each transform stage runs as two launches, grids whose factorisation
+  // needs the wide kernels and the rest (a grid has no blocks in the other)
+  long nblk[5] = {0, 0, 0, 0, 0};
   int yP = 32, yK = 2, yM = 8;
   int xdiv = 1, zdiv = 1;    // x rows and z columns per block: the largest tile's, divided by these
   bool zsmall = false;       // every grid's z lines fit the small tile
@@ -1578,10 +1595,9 @@ constexpr int kBatchDivMax = 4;   // finest x split the partial buffers are size
 template <typename T>
 hipError_t batch_apply(ibp_batch_s* b, std::vector<BatchGrid<T>>& hd) {
   const int n = b->count;
-  b->hstart.assign(3 * (n + 1), 0);
-  long* hx = b->hstart.data();
-  long* hz = hx + (n + 1);
-  long* hy = hz + (n + 1);
+  b->hstart.assign(5 * (n + 1), 0);
+  long* h[5];
+  for (int i = 0; i < 5; ++i) h[i] = b->hstart.data() + i * (n + 1);
   for (int g = 0; g < n; ++g) {
     BatchGrid<T>& d = hd[g];
     const int rb = b->rbmax[g] / b->xdiv > 0 ? b->rbmax[g] / b->xdiv : 1;
@@ -1591,13 +1607,15 @@ hipError_t batch_apply(ibp_batch_s* b, std::vector<BatchGrid<T>>& hd) {
     if (d.x.parts) d.zero.nparts = nxb;
     d.z.cols = zc;
     d.zcolblocks = (d.z.hp + zc - 1) / zc;
-    hx[g + 1] = hx[g] + nxb;
-    hz[g + 1] = hz[g] + (d.z.nz > 1 ? (long)d.zcolblocks * d.y.ny : 0);
-    hy[g + 1] = hy[g] + (d.y.Q + b->yM - 1) / b->yM + d.y.ny;
+    const long nzb = d.z.nz > 1 ? (long)d.zcolblocks * d.y.ny : 0;
+    const bool xw = b->plans[g]->xwide, zw = b->plans[g]->zwide;
+    h[0][g + 1] = h[0][g] + (xw ? 0 : nxb);
+    h[1][g + 1] = h[1][g] + (xw ? nxb : 0);
+    h[2][g + 1] = h[2][g] + (zw ? 0 : nzb);
+    h[3][g + 1] = h[3][g] + (zw ? nzb : 0);
+    h[4][g + 1] = h[4][g] + (d.y.Q + b->yM - 1) / b->yM + d.y.ny;
   }
-  b->nblk[0] = hx[n];
-  b->nblk[1] = hz[n];
-  b->nblk[2] = hy[n];
+  for (int i = 0; i < 5; ++i) b->nblk[i] = h[i][n];
   hipError_t e = hipMemcpy(b->desc, hd.data(), n * sizeof(BatchGrid<T>), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(b->start, b->hstart.data(), b->hstart.size() * sizeof(long), hipMemcpyHostToDevice);
@@ -1628,7 +1646,7 @@ ibp_status_t batch_build(ibp_batch_s* b) {
   // device memory: descriptors | prefix offsets | padded a, c tables | partials
   std::vector<size_t> o_part(n);
   const size_t o_start = align256(n * sizeof(BatchGrid<T>));
-  const size_t o_tab = o_start + align256(3 * (n + 1) * sizeof(long));
+  const size_t o_tab = o_start + align256(5 * (n + 1) * sizeof(long));
   size_t bytes = o_tab + align256((size_t)n * 2 * PK * sizeof(T));
   for (int g = 0; g < n; ++g) {
     const ibp_plan_s* p = b->plans[g];
@@ -1704,32 +1722,47 @@ ibp_status_t batch_enqueue(ibp_batch_s* b, const double* const* rhs, double* con
     P.phi[g] = phi[g];
   }
   const BatchGrid<T>* d = static_cast<const BatchGrid<T>*>(b->desc);
-  const long* sx = b->start;
-  const long* sz = sx + (n + 1);
-  const long* sy = sz + (n + 1);
+  const long* st[5];
+  for (int i = 0; i < 5; ++i) st[i] = b->start + i * (n + 1);
   const bool mixed = b->prec == IBP_MIXED;
   for (ibp_plan_t p : b->plans) {
     p->last_stream = s;
     p->solved = true;
   }
+  // each transform stage: the narrow-family launch, then the wide one
+  auto xr2c = [&](int mode, const BatchLaunch& l) {
+    hipError_t e = launch_batch_xr2c<T>(mode, b->xsmall, false, d, st[0], b->nblk[0], P, l, s);
+    return e == hipSuccess ? launch_batch_xr2c<T>(mode, b->xsmall, true, d, st[1], b->nblk[1], P, l, s) : e;
+  };
+  auto xc2r = [&](int mode, const BatchLaunch& l) {
+    hipError_t e = launch_batch_xc2r<T>(mode, b->xsmall, false, d, st[0], b->nblk[0], P, l, s);
+    return e == hipSuccess ? launch_batch_xc2r<T>(mode, b->xsmall, true, d, st[1], b->nblk[1], P, l, s) : e;
+  };
+  auto zfft = [&](bool inverse, const BatchLaunch& l) {
+    hipError_t e = launch_batch_zfft<T>(inverse, b->zsmall, false, d, st[2], b->nblk[2], l, s);
+    return e == hipSuccess ? launch_batch_zfft<T>(inverse, b->zsmall, true, d, st[3], b->nblk[3], l, s) : e;
+  };
+  auto ytri = [&](const BatchLaunch& l) {
+    return launch_batch_ytri<T>(b->yP, b->yK, b->yM, d, st[4], b->nblk[4], l, s);
+  };
   BatchLaunch L{n, 0, 1, mixed ? 1 : 0, 0, 0};
-  IBP_HIP(launch_batch_xr2c<T>(XM_PLAIN, b->xsmall, d, sx, b->nblk[0], P, L, s));
-  IBP_HIP(launch_batch_zfft<T>(false, b->zsmall, d, sz, b->nblk[1], L, s));
-  IBP_HIP(launch_batch_ytri<T>(b->yP, b->yK, b->yM, d, sy, b->nblk[2], L, s));
-  IBP_HIP(launch_batch_zfft<T>(true, b->zsmall, d, sz, b->nblk[1], L, s));
-  IBP_HIP(launch_batch_xc2r<T>(CM_SET, b->xsmall, d, sx, b->nblk[0], P, L, s));
+  IBP_HIP(xr2c(XM_PLAIN, L));
+  IBP_HIP(zfft(false, L));
+  IBP_HIP(ytri(L));
+  IBP_HIP(zfft(true, L));
+  IBP_HIP(xc2r(CM_SET, L));
   if (!mixed) return IBP_SUCCESS;
   for (int k = 1; k <= b->max_iters; ++k) {
     L = BatchLaunch{n, k, 0, 1, 0, 1};
-    IBP_HIP(launch_batch_xr2c<T>(XM_RESID, b->xsmall, d, sx, b->nblk[0], P, L, s));
+    IBP_HIP(xr2c(XM_RESID, L));
     IBP_HIP(launch_batch_check<T>(d, L, s));
-    IBP_HIP(launch_batch_zfft<T>(false, b->zsmall, d, sz, b->nblk[1], L, s));
-    IBP_HIP(launch_batch_ytri<T>(b->yP, b->yK, b->yM, d, sy, b->nblk[2], L, s));
-    IBP_HIP(launch_batch_zfft<T>(true, b->zsmall, d, sz, b->nblk[1], L, s));
-    IBP_HIP(launch_batch_xc2r<T>(CM_ADD, b->xsmall, d, sx, b->nblk[0], P, L, s));
+    IBP_HIP(zfft(false, L));
+    IBP_HIP(ytri(L));
+    IBP_HIP(zfft(true, L));
+    IBP_HIP(xc2r(CM_ADD, L));
   }
   L = BatchLaunch{n, b->max_iters + 1, 0, 1, 1, 1};
-  IBP_HIP(launch_batch_xr2c<T>(XM_RESID_ONLY, b->xsmall, d, sx, b->nblk[0], P, L, s));
+  IBP_HIP(xr2c(XM_RESID_ONLY, L));
   IBP_HIP(launch_batch_check<T>(d, L, s));
   return IBP_SUCCESS;
 }

@@ -316,7 +316,10 @@ __device__ __forceinline__ void fft_stage_any(Cx<T>* buf, Cx<T>* spare, int n, i
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 // The Stockham stages of one factorisation over nb sequences of length n.
-template <int TILE, bool INV, typename T>
+// WIDE = false leaves out the radix-7 and radix-11 butterflies and the
+// direct-sum stage, whose registers set the kernel's whole register count
+// (the caller guarantees radices 2, 3, 4, 5 and 8 only).
+template <int TILE, bool INV, typename T, bool WIDE = true>
 __device__ __forceinline__ void lds_stages(Cx<T>* buf, int nb, int ss, int n, int nst, const int* radix,
                                            const Cx<T>* __restrict__ tw, int twstride) {
   int Ns = 1;
@@ -328,9 +331,15 @@ __device__ __forceinline__ void lds_stages(Cx<T>* buf, int nb, int ss, int n, in
       case 2: fft_stage<2, cdiv(TILE, 2 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride); break;
       case 3: fft_stage<3, cdiv(TILE, 3 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride); break;
       case 5: fft_stage<5, cdiv(TILE, 5 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride); break;
-      case 7: fft_stage<7, cdiv(TILE, 7 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride); break;
-      case 11: fft_stage<11, cdiv(TILE, 11 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride); break;
-      default: fft_stage_any<INV, T>(buf, buf + TILE / 2, n, nb, ss, Ns, R, tw, twstride); break;
+      case 7:
+        if constexpr (WIDE) fft_stage<7, cdiv(TILE, 7 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride);
+        break;
+      case 11:
+        if constexpr (WIDE) fft_stage<11, cdiv(TILE, 11 * kThreads), INV, T>(buf, n, nb, ss, Ns, tw, twstride);
+        break;
+      default:
+        if constexpr (WIDE) fft_stage_any<INV, T>(buf, buf + TILE / 2, n, nb, ss, Ns, R, tw, twstride);
+        break;
     }
     Ns *= R;
   }
@@ -380,18 +389,20 @@ __device__ __forceinline__ void bluestein_fft(Cx<T>* buf, int nb, int ss, const 
 // TILE is the compile-time bound on nb * ss; a plan with a prime factor
 // above 11 (fp.any) keeps nb * ss <= TILE / 2 (the direct-sum stage's spare
 // half).  Bluestein plans (fp.blu) take the chirp, filter and length-m
-// twiddle tables.
-template <int TILE, bool INV, typename T>
+// twiddle tables.  WIDE = false: radices 2, 3, 4, 5, 8 only, no Bluestein.
+template <int TILE, bool INV, typename T, bool WIDE = true>
 __device__ __forceinline__ void lds_fft(Cx<T>* buf, int nb, int ss, const FftPlan& fp,
                                         const Cx<T>* __restrict__ tw, int twstride,
                                         const Cx<T>* __restrict__ bchirp = nullptr,
                                         const Cx<T>* __restrict__ bhat = nullptr,
                                         const Cx<T>* __restrict__ btw = nullptr) {
-  if (fp.blu) {
-    bluestein_fft<TILE, INV, T>(buf, nb, ss, fp, bchirp, bhat, btw);
-    return;
+  if constexpr (WIDE) {
+    if (fp.blu) {
+      bluestein_fft<TILE, INV, T>(buf, nb, ss, fp, bchirp, bhat, btw);
+      return;
+    }
   }
-  lds_stages<TILE, INV, T>(buf, nb, ss, fp.n, fp.nst, fp.radix, tw, twstride);
+  lds_stages<TILE, INV, T, WIDE>(buf, nb, ss, fp.n, fp.nst, fp.radix, tw, twstride);
 }
 
 // ---------------------------------------------------------------- reductions

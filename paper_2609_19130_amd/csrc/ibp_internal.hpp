@@ -299,13 +299,13 @@ struct BatchLaunch {
 
 // Stages of a batched solve; each launcher covers every grid in one launch.
 template <typename T>
-hipError_t launch_batch_xr2c(int mode, bool small, const BatchGrid<T>* d, const long* start, long nblocks, const BatchPtrs& p,
+hipError_t launch_batch_xr2c(int mode, bool small, bool wide, const BatchGrid<T>* d, const long* start, long nblocks, const BatchPtrs& p,
                              const BatchLaunch& l, hipStream_t s);
 template <typename T>
-hipError_t launch_batch_xc2r(int mode, bool small, const BatchGrid<T>* d, const long* start, long nblocks, const BatchPtrs& p,
+hipError_t launch_batch_xc2r(int mode, bool small, bool wide, const BatchGrid<T>* d, const long* start, long nblocks, const BatchPtrs& p,
                              const BatchLaunch& l, hipStream_t s);
 template <typename T>
-hipError_t launch_batch_zfft(bool inverse, bool small, const BatchGrid<T>* d, const long* start, long nblocks,
+hipError_t launch_batch_zfft(bool inverse, bool small, bool wide, const BatchGrid<T>* d, const long* start, long nblocks,
                              const BatchLaunch& l, hipStream_t s);
 template <typename T>
 hipError_t launch_batch_ytri(int P, int K, int M, const BatchGrid<T>* d, const long* start, long nblocks,
@@ -385,11 +385,11 @@ template <> inline int tile_z<float>() { return kTileZ32; }
 // x passes cover rows [a.row_begin, a.nrows); z passes cover planes
 // [a.plane0, a.plane0 + nplanes).
 template <typename T>
-hipError_t launch_xr2c(int mode, bool small, const XArgs<T>& a, hipStream_t s);
+hipError_t launch_xr2c(int mode, bool small, bool wide, const XArgs<T>& a, hipStream_t s);
 template <typename T>
-hipError_t launch_xc2r(int mode, bool small, const XArgs<T>& a, hipStream_t s);
+hipError_t launch_xc2r(int mode, bool small, bool wide, const XArgs<T>& a, hipStream_t s);
 template <typename T>
-hipError_t launch_zfft(bool inverse, bool small, const ZfArgs<T>& a, int nplanes, hipStream_t s);
+hipError_t launch_zfft(bool inverse, bool small, bool wide, const ZfArgs<T>& a, int nplanes, hipStream_t s);
 // M columns per block: `want` (2, 4, 8 or 16) if given, else 128-byte rows;
 // capped by the LDS budget.
 template <typename T, typename U>
