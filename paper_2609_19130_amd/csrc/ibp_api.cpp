@@ -1569,11 +1569,12 @@ struct ibp_batch_s {
   std::vector<unsigned> gens;
   void* dmem = nullptr;
   void* desc = nullptr;      // BatchGrid<T>[count]
-  long* start = nullptr;     // [5][count + 1]: prefix offsets of the stage launches (nblk order)
-  // blocks of the x (narrow, wide family), z (narrow, wide) and y stage launches:
-  // each transform stage runs as two launches, grids whose factorisation
-  // needs the wide kernels and the rest (a grid has no blocks in the other)
-  long nblk[5] = {0, 0, 0, 0, 0};
+  long* start = nullptr;     // [7][count + 1]: prefix offsets of the stage launches (nblk order)
+  // blocks of the x (narrow, wide family), z (narrow, wide) and y (rows per
+  // lane K, K/2, K/4) stage launches: each stage runs as several launches
+  // over the grids of one kind (a grid has no blocks in the others)
+  long nblk[7] = {0, 0, 0, 0, 0, 0, 0};
+  int yKc[3] = {0, 0, 0}, yMc[3] = {0, 0, 0};   // rows per lane and columns per block of the y launches
   int yP = 32, yK = 2, yM = 8;
   int xdiv = 1, zdiv = 1;    // x rows and z columns per block: the largest tile's, divided by these
   bool zsmall = false;       // every grid's z lines fit the small tile
@@ -1595,9 +1596,17 @@ constexpr int kBatchDivMax = 4;   // finest x split the partial buffers are size
 template <typename T>
 hipError_t batch_apply(ibp_batch_s* b, std::vector<BatchGrid<T>>& hd) {
   const int n = b->count;
-  b->hstart.assign(5 * (n + 1), 0);
-  long* h[5];
-  for (int i = 0; i < 5; ++i) h[i] = b->hstart.data() + i * (n + 1);
+  b->hstart.assign(7 * (n + 1), 0);
+  long* h[7];
+  for (int i = 0; i < 7; ++i) h[i] = b->hstart.data() + i * (n + 1);
+  // y launches: the base shape's K, K/2, K/4 rows per lane, with columns per
+  // block raised in proportion (same LDS tile, same bytes per block)
+  for (int c = 0; c < 3; ++c) {
+    const bool ok = b->yK % (1 << c) == 0;
+    b->yKc[c] = ok ? b->yK >> c : 0;
+    const int want = b->yM << c < 16 ? b->yM << c : 16;
+    b->yMc[c] = ok ? batch_ytri_cols<T>(b->yP, b->yKc[c], want) : 0;
+  }
   for (int g = 0; g < n; ++g) {
     BatchGrid<T>& d = hd[g];
     const int rb = b->rbmax[g] / b->xdiv > 0 ? b->rbmax[g] / b->xdiv : 1;
@@ -1613,9 +1622,12 @@ hipError_t batch_apply(ibp_batch_s* b, std::vector<BatchGrid<T>>& hd) {
     h[1][g + 1] = h[1][g] + (xw ? nxb : 0);
     h[2][g + 1] = h[2][g] + (zw ? 0 : nzb);
     h[3][g + 1] = h[3][g] + (zw ? nzb : 0);
-    h[4][g + 1] = h[4][g] + (d.y.Q + b->yM - 1) / b->yM + d.y.ny;
+    for (int c = 0; c < 3; ++c) {
+      const int M = b->yMc[c];
+      h[4 + c][g + 1] = h[4 + c][g] + (d.yk == b->yKc[c] ? (d.y.Q + M - 1) / M + zero_blocks(d.y.ny) : 0);
+    }
   }
-  for (int i = 0; i < 5; ++i) b->nblk[i] = h[i][n];
+  for (int i = 0; i < 7; ++i) b->nblk[i] = h[i][n];
   hipError_t e = hipMemcpy(b->desc, hd.data(), n * sizeof(BatchGrid<T>), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(b->start, b->hstart.data(), b->hstart.size() * sizeof(long), hipMemcpyHostToDevice);
@@ -1646,7 +1658,7 @@ ibp_status_t batch_build(ibp_batch_s* b) {
   // device memory: descriptors | prefix offsets | padded a, c tables | partials
   std::vector<size_t> o_part(n);
   const size_t o_start = align256(n * sizeof(BatchGrid<T>));
-  const size_t o_tab = o_start + align256(5 * (n + 1) * sizeof(long));
+  const size_t o_tab = o_start + align256(7 * (n + 1) * sizeof(long));
   size_t bytes = o_tab + align256((size_t)n * 2 * PK * sizeof(T));
   for (int g = 0; g < n; ++g) {
     const ibp_plan_s* p = b->plans[g];
@@ -1722,8 +1734,8 @@ ibp_status_t batch_enqueue(ibp_batch_s* b, const double* const* rhs, double* con
     P.phi[g] = phi[g];
   }
   const BatchGrid<T>* d = static_cast<const BatchGrid<T>*>(b->desc);
-  const long* st[5];
-  for (int i = 0; i < 5; ++i) st[i] = b->start + i * (n + 1);
+  const long* st[7];
+  for (int i = 0; i < 7; ++i) st[i] = b->start + i * (n + 1);
   const bool mixed = b->prec == IBP_MIXED;
   for (ibp_plan_t p : b->plans) {
     p->last_stream = s;
@@ -1743,7 +1755,10 @@ ibp_status_t batch_enqueue(ibp_batch_s* b, const double* const* rhs, double* con
     return e == hipSuccess ? launch_batch_zfft<T>(inverse, b->zsmall, true, d, st[3], b->nblk[3], l, s) : e;
   };
   auto ytri = [&](const BatchLaunch& l) {
-    return launch_batch_ytri<T>(b->yP, b->yK, b->yM, d, st[4], b->nblk[4], l, s);
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < 3 && e == hipSuccess; ++c)
+      if (b->nblk[4 + c] > 0) e = launch_batch_ytri<T>(b->yP, b->yKc[c], b->yMc[c], d, st[4 + c], b->nblk[4 + c], l, s);
+    return e;
   };
   BatchLaunch L{n, 0, 1, mixed ? 1 : 0, 0, 0};
   IBP_HIP(xr2c(XM_PLAIN, L));

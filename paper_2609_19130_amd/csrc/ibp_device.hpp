@@ -43,6 +43,30 @@ __device__ __forceinline__ Cx<T> mul_mi(Cx<T> a) {
   return INV ? Cx<T>{-a.y, a.x} : Cx<T>{a.y, -a.x};
 }
 
+// Global-address-space view of a base pointer: accesses through it compile
+// to global loads and stores.  Through a generic pointer read from memory
+// (the batched kernels' per-grid argument table) they compile to flat
+// accesses, which also count against the LDS wait counter, so a tile's
+// loads could not overlap its LDS writes; a cast back to a generic pointer
+// loses the address space again.  Kernel-argument pointers are global to
+// the compiler already.  Index the returned pointer (casting an offset
+// generic pointer instead has measured flat in the generated code).
+#define IBP_GLOBAL __attribute__((address_space(1)))
+template <typename P>
+__device__ __forceinline__ IBP_GLOBAL P* gbl(P* p) {
+  return (IBP_GLOBAL P*)p;
+}
+
+// Two consecutive doubles (16-byte aligned) through a global view, as one
+// 16-byte access.
+__device__ __forceinline__ double2 gld2(const IBP_GLOBAL double* p) {
+  const Cx<double> v = *reinterpret_cast<const IBP_GLOBAL Cx<double>*>(p);
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void gst2(IBP_GLOBAL double* p, double a, double b) {
+  *reinterpret_cast<IBP_GLOBAL Cx<double>*>(p) = Cx<double>{a, b};
+}
+
 // Exact quotient t / d of small non-negative integers (0 <= t < 2^19,
 // d >= 1) from a float reciprocal: r = (1/d rounded) * (1 + 1.5 * 2^-20)
 // rounded, and q = trunc(t * r rounded).  The three roundings move the
@@ -218,7 +242,7 @@ struct Bfly<11, INV, T> : BflyOdd<11, INV, T> {};
 // the host guarantees nb * n <= MAXB * R * kThreads.
 template <int R, int MAXB, bool INV, typename T>
 __device__ __forceinline__ void fft_stage(Cx<T>* buf, int n, int nb, int ss, int Ns,
-                                          const Cx<T>* __restrict__ tw, int twstride) {
+                                          const IBP_GLOBAL Cx<T>* __restrict__ tw, int twstride) {
   const int m = n / R;
   const int nbf = nb * m;
   const int twmul = (n / (Ns * R)) * twstride;
@@ -271,7 +295,7 @@ __device__ __forceinline__ void fft_stage(Cx<T>* buf, int n, int nb, int ss, int
 // the host leaves free for plans with such a factor), then are copied back.
 template <bool INV, typename T>
 __device__ __forceinline__ void fft_stage_any(Cx<T>* buf, Cx<T>* spare, int n, int nb, int ss, int Ns, int R,
-                                              const Cx<T>* __restrict__ tw, int twstride) {
+                                              const IBP_GLOBAL Cx<T>* __restrict__ tw, int twstride) {
   constexpr int QA = 4;
   const int m = n / R;
   const int twmul = (n / (Ns * R)) * twstride;
@@ -321,7 +345,7 @@ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 // (the caller guarantees radices 2, 3, 4, 5 and 8 only).
 template <int TILE, bool INV, typename T, bool WIDE = true>
 __device__ __forceinline__ void lds_stages(Cx<T>* buf, int nb, int ss, int n, int nst, const int* radix,
-                                           const Cx<T>* __restrict__ tw, int twstride) {
+                                           const IBP_GLOBAL Cx<T>* __restrict__ tw, int twstride) {
   int Ns = 1;
   for (int s = 0; s < nst; ++s) {
     const int R = radix[s];
@@ -353,8 +377,9 @@ __device__ __forceinline__ void lds_stages(Cx<T>* buf, int nb, int ss, int n, in
 // is conj(forward(conj(x))).  Sequences sit at stride ss >= m.
 template <int TILE, bool INV, typename T>
 __device__ __forceinline__ void bluestein_fft(Cx<T>* buf, int nb, int ss, const FftPlan& fp,
-                                              const Cx<T>* __restrict__ chirp, const Cx<T>* __restrict__ bhat,
-                                              const Cx<T>* __restrict__ twm) {
+                                              const IBP_GLOBAL Cx<T>* __restrict__ chirp,
+                                              const IBP_GLOBAL Cx<T>* __restrict__ bhat,
+                                              const IBP_GLOBAL Cx<T>* __restrict__ twm) {
   const int n = fp.n, m = fp.m;
   const QDiv qm = qdiv(m), qn = qdiv(n);
   for (int t = threadIdx.x; t < nb * m; t += kThreads) {
@@ -392,10 +417,10 @@ __device__ __forceinline__ void bluestein_fft(Cx<T>* buf, int nb, int ss, const 
 // twiddle tables.  WIDE = false: radices 2, 3, 4, 5, 8 only, no Bluestein.
 template <int TILE, bool INV, typename T, bool WIDE = true>
 __device__ __forceinline__ void lds_fft(Cx<T>* buf, int nb, int ss, const FftPlan& fp,
-                                        const Cx<T>* __restrict__ tw, int twstride,
-                                        const Cx<T>* __restrict__ bchirp = nullptr,
-                                        const Cx<T>* __restrict__ bhat = nullptr,
-                                        const Cx<T>* __restrict__ btw = nullptr) {
+                                        const IBP_GLOBAL Cx<T>* __restrict__ tw, int twstride,
+                                        const IBP_GLOBAL Cx<T>* __restrict__ bchirp = nullptr,
+                                        const IBP_GLOBAL Cx<T>* __restrict__ bhat = nullptr,
+                                        const IBP_GLOBAL Cx<T>* __restrict__ btw = nullptr) {
   if constexpr (WIDE) {
     if (fp.blu) {
       bluestein_fft<TILE, INV, T>(buf, nb, ss, fp, bchirp, bhat, btw);

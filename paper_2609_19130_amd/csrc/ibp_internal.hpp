@@ -166,7 +166,7 @@ struct YArgs {
 struct ZeroArgs {        // FP64 (0,0) mode and solve control
   const double* rowsum;
   double* ghat;          // [ny] plane sums
-  int* ticket;           // completion counter of the plane blocks (0 between launches)
+  int* ticket;           // completion counter of the (0,0)-mode blocks (0 between launches)
   double* phi00;
   const double* dyf;     // [ny]
   const double* dyc;     // [ny+1], entries 1..ny-1 used
@@ -228,61 +228,6 @@ struct BatchGrid {
   int yk;          // line-solve rows per lane for this grid (the batch's K, K/2 or K/4)
 };
 
-// Pointers read from a device table are generic (flat) to the compiler;
-// re-deriving them from a global-address-space cast lets it use global
-// loads and stores (as it does for kernel-argument pointers).
-template <typename P>
-__device__ __forceinline__ P* as_global(P* p) {
-  return (P*)((__attribute__((address_space(1))) P*)p);
-}
-
-template <typename T>
-__device__ __forceinline__ void globalize(XArgs<T>& a) {
-  a.f = as_global(a.f);
-  a.phi = as_global(a.phi);
-  a.out = as_global(a.out);
-  a.spec = as_global(a.spec);
-  a.rowsum = as_global(a.rowsum);
-  a.part = as_global(a.part);
-  a.phi00 = as_global(a.phi00);
-  a.ctl = as_global(a.ctl);
-  a.twx = as_global(a.twx);
-  a.ya = as_global(a.ya);
-  a.yc = as_global(a.yc);
-  a.dyf = as_global(a.dyf);
-  a.bc = as_global(a.bc);
-  a.bb = as_global(a.bb);
-  a.bt = as_global(a.bt);
-}
-template <typename T>
-__device__ __forceinline__ void globalize(ZfArgs<T>& a) {
-  a.spec = as_global(a.spec);
-  a.twz = as_global(a.twz);
-  a.ctl = as_global(a.ctl);
-  a.bc = as_global(a.bc);
-  a.bb = as_global(a.bb);
-  a.bt = as_global(a.bt);
-}
-template <typename T, typename U>
-__device__ __forceinline__ void globalize(YArgs<T, U>& a) {
-  a.spec = as_global(a.spec);
-  a.lamx = as_global(a.lamx);
-  a.lamz = as_global(a.lamz);
-  a.ya = as_global(a.ya);
-  a.yc = as_global(a.yc);
-  a.ctl = as_global(a.ctl);
-}
-__device__ __forceinline__ void globalize(ZeroArgs& z) {
-  z.rowsum = as_global(z.rowsum);
-  z.ghat = as_global(z.ghat);
-  z.ticket = as_global(z.ticket);
-  z.phi00 = as_global(z.phi00);
-  z.dyf = as_global(z.dyf);
-  z.dyc = as_global(z.dyc);
-  z.part = as_global(z.part);
-  z.ctl = as_global(z.ctl);
-}
-
 struct BatchPtrs {
   const double* f[kBatchMax];
   double* phi[kBatchMax];
@@ -316,6 +261,9 @@ hipError_t launch_batch_check(const BatchGrid<T>* d, const BatchLaunch& l, hipSt
 template <typename T>
 int batch_ytri_cols(int P, int K, int want);
 int batch_grid_rows_per_lane(int ny, int P, int K);
+// Blocks that run the FP64 (0,0) mode at the start of a grid's line-solve launch.
+constexpr int kZeroBlocks = 8;
+__host__ __device__ inline int zero_blocks(int ny) { return ny < kZeroBlocks ? ny : kZeroBlocks; }
 
 struct DivArgs {          // f = (D u - q) * scale; q may be null
   const double* u;

@@ -53,7 +53,7 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
         for (int m = lane; m < h; m += kWave) buf[lr * hs + m] = Cx<T>{T(0), T(0)};
       continue;
     }
-    const double* frow = A.f + row * nx;
+    const IBP_GLOBAL double* frow = gbl(A.f) + row * nx;
     double rs = 0.0;
     const int jr = qquo(k0 + lr, qnz);
     const int j = j0 + jr;
@@ -67,15 +67,15 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
           acc_f2 += v0 * v0;
         } else {
           // r = (f - m) - L_h phi, 7-point staggered stencil, FP64
-          const double* prow = A.phi + row * nx;
+          const IBP_GLOBAL double* prow = gbl(A.phi) + row * nx;
           const double pc = prow[m];
           const double pl = prow[m == 0 ? nx - 1 : m - 1];
           const double pr = prow[m + 1 == nx ? 0 : m + 1];
           const int kp = k + 1 == nz ? 0 : k + 1, km = k == 0 ? nz - 1 : k - 1;
-          const double zp = A.phi[((long)j * nz + kp) * nx + m];
-          const double zm = A.phi[((long)j * nz + km) * nx + m];
-          const double yp = j + 1 < ny ? A.phi[((long)(j + 1) * nz + k) * nx + m] : 0.0;
-          const double ym = j > 0 ? A.phi[((long)(j - 1) * nz + k) * nx + m] : 0.0;
+          const double zp = gbl(A.phi)[((long)j * nz + kp) * nx + m];
+          const double zm = gbl(A.phi)[((long)j * nz + km) * nx + m];
+          const double yp = j + 1 < ny ? gbl(A.phi)[((long)(j + 1) * nz + k) * nx + m] : 0.0;
+          const double ym = j > 0 ? gbl(A.phi)[((long)(j - 1) * nz + k) * nx + m] : 0.0;
           const double L0 = (pr - 2.0 * pc + pl) * A.idx2 + (zp + zm - 2.0 * pc) * A.idz2 + A.ya[j] * (ym - pc) +
                             A.yc[j] * (yp - pc);
           const double f0 = fv - mean;
@@ -92,7 +92,7 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
     } else
     for (int m = lane; m < h; m += kWave) {
       const double2 fv = MODE == XM_DIV ? assemble_pair(A, row, j, k, m)
-                                        : *reinterpret_cast<const double2*>(frow + 2 * m);
+                                        : gld2(frow + 2 * m);
       double v0, v1;
       if (!kRes) {
         v0 = fv.x;
@@ -100,16 +100,16 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
         acc_f2 += v0 * v0 + v1 * v1;
       } else {
         // r = (f - m) - L_h phi, 7-point staggered stencil, FP64
-        const double* prow = A.phi + row * nx;
-        const double2 pc = *reinterpret_cast<const double2*>(prow + 2 * m);
+        const IBP_GLOBAL double* prow = gbl(A.phi) + row * nx;
+        const double2 pc = gld2(prow + 2 * m);
         const double pl = prow[m == 0 ? nx - 1 : 2 * m - 1];
         const double pr = prow[2 * m + 2 == nx ? 0 : 2 * m + 2];
         const int kp = k + 1 == nz ? 0 : k + 1, km = k == 0 ? nz - 1 : k - 1;
-        const double2 zp = *reinterpret_cast<const double2*>(A.phi + ((long)j * nz + kp) * nx + 2 * m);
-        const double2 zm = *reinterpret_cast<const double2*>(A.phi + ((long)j * nz + km) * nx + 2 * m);
+        const double2 zp = gld2(gbl(A.phi) + ((long)j * nz + kp) * nx + 2 * m);
+        const double2 zm = gld2(gbl(A.phi) + ((long)j * nz + km) * nx + 2 * m);
         double2 yp = make_double2(0.0, 0.0), ym = make_double2(0.0, 0.0);
-        if (j + 1 < ny) yp = *reinterpret_cast<const double2*>(A.phi + ((long)(j + 1) * nz + k) * nx + 2 * m);
-        if (j > 0) ym = *reinterpret_cast<const double2*>(A.phi + ((long)(j - 1) * nz + k) * nx + 2 * m);
+        if (j + 1 < ny) yp = gld2(gbl(A.phi) + ((long)(j + 1) * nz + k) * nx + 2 * m);
+        if (j > 0) ym = gld2(gbl(A.phi) + ((long)(j - 1) * nz + k) * nx + 2 * m);
         // y part as a difference of face fluxes (a_0 = c_{ny-1} = 0)
         const double ca = A.ya[j], cc = A.yc[j];
         const double L0 = (pc.y - 2.0 * pc.x + pl) * A.idx2 + (zp.x + zm.x - 2.0 * pc.x) * A.idz2 +
@@ -129,7 +129,7 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
       if (MODE != XM_RESID_ONLY) buf[lr * hs + m] = Cx<T>{T(v0 * s), T(v1 * s)};
     }
     rs = wave_sum(rs);
-    if (MODE != XM_RESID_ONLY && lane == 0) A.rowsum[row] = rs;
+    if (MODE != XM_RESID_ONLY && lane == 0) gbl(A.rowsum)[row] = rs;
   }
   if (A.parts) {
     double vals[5] = {acc_in2, acc_f2, acc_max, acc_bad, acc_wphi};
@@ -137,12 +137,12 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
     block_reduce<5>(vals, ismax, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
-      for (int i = 0; i < kPartStride; ++i) A.part[blk * kPartStride + i] = vals[i];
+      for (int i = 0; i < kPartStride; ++i) gbl(A.part)[blk * kPartStride + i] = vals[i];
     }
   }
   if (MODE == XM_RESID_ONLY) return;
   __syncthreads();
-  lds_fft<TILE, false, T, WIDE>(buf, RB, hs, fp, A.twx, odd ? 1 : 2, A.bc, A.bb, A.bt);
+  lds_fft<TILE, false, T, WIDE>(buf, RB, hs, fp, gbl(A.twx), odd ? 1 : 2, gbl(A.bc), gbl(A.bb), gbl(A.bt));
 
   if (odd) {   // the first (nx+1)/2 coefficients, no split
     const QDiv qhp = qdiv(A.hp);
@@ -150,7 +150,7 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
       const int lr = qquo(e, qhp), kk = e - __mul24(lr, A.hp);
       const long row = row0 + lr;
       if (row < A.nrows)
-        A.spec[row * A.rs + (j0 + qquo(k0 + lr, qnz)) * pgap + kk] = buf[__mul24(lr, hs) + kk];
+        gbl(A.spec)[row * A.rs + (j0 + qquo(k0 + lr, qnz)) * pgap + kk] = buf[__mul24(lr, hs) + kk];
     }
     __syncthreads();
     return;
@@ -166,8 +166,8 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
     const Cx<T> E = cscale(cadd(Zk, Zc), T(0.5));
     const Cx<T> D = csub(Zk, Zc);
     const Cx<T> O = Cx<T>{T(0.5) * D.y, T(-0.5) * D.x};     // D / 2i
-    const Cx<T> WO = cmul(A.twx[k], O);
-    Cx<T>* srow = A.spec + row * A.rs + (j0 + qquo(k0 + lr, qnz)) * pgap;
+    const Cx<T> WO = cmul(gbl(A.twx)[k], O);
+    IBP_GLOBAL Cx<T>* srow = gbl(A.spec) + row * A.rs + (j0 + qquo(k0 + lr, qnz)) * pgap;
     srow[k] = cadd(E, WO);
     if (h - k != k) srow[h - k] = cconj(csub(E, WO));
   }
@@ -200,7 +200,7 @@ __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& 
       const int lr = qquo(e, qhp), k = e - __mul24(lr, A.hp);
       const long row = row0 + lr;
       Cx<T> X{T(0), T(0)};
-      if (row < A.nrows) X = A.spec[row * A.rs + (j0 + qquo(k0 + lr, qnz)) * pgap + k];
+      if (row < A.nrows) X = gbl(A.spec)[row * A.rs + (j0 + qquo(k0 + lr, qnz)) * pgap + k];
       if (k == 0) X.y = T(0);   // X[0] of a real sequence is real
       buf[__mul24(lr, hs) + k] = X;
       if (k > 0) buf[__mul24(lr, hs) + nx - k] = cconj(X);
@@ -212,7 +212,7 @@ __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& 
     const long row = row0 + lr;
     Cx<T> Xk{T(0), T(0)}, Xm{T(0), T(0)};
     if (row < A.nrows) {
-      const Cx<T>* srow = A.spec + row * A.rs + (j0 + qquo(k0 + lr, qnz)) * pgap;
+      const IBP_GLOBAL Cx<T>* srow = gbl(A.spec) + row * A.rs + (j0 + qquo(k0 + lr, qnz)) * pgap;
       Xk = srow[k];
       Xm = srow[h - k];
     }
@@ -223,13 +223,13 @@ __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& 
     const Cx<T> Xmc = cconj(Xm);
     const Cx<T> E = cscale(cadd(Xk, Xmc), T(0.5));
     const Cx<T> D = cscale(csub(Xk, Xmc), T(0.5));
-    const Cx<T> O = cmul(cconj(A.twx[k]), D);
+    const Cx<T> O = cmul(cconj(gbl(A.twx)[k]), D);
     buf[__mul24(lr, hs) + k] = Cx<T>{E.x - O.y, E.y + O.x};               // E + i O
     const int km = k ? h - k : 0;                                            // (h - k) mod h, k < hh <= h
     if (km != k) buf[__mul24(lr, hs) + km] = Cx<T>{E.x + O.y, O.x - E.y};   // conj(E) + i conj(O)
   }
   __syncthreads();
-  lds_fft<TILE, true, T, WIDE>(buf, RB, hs, fp, A.twx, odd ? 1 : 2, A.bc, A.bb, A.bt);
+  lds_fft<TILE, true, T, WIDE>(buf, RB, hs, fp, gbl(A.twx), odd ? 1 : 2, gbl(A.bc), gbl(A.bb), gbl(A.bt));
 
   double cs = A.out_scale;
   if (MODE == CM_ADD) cs = cs / A.ctl->scale[A.iter & 1];
@@ -238,9 +238,9 @@ __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& 
     const long row = row0 + lr;
     if (row >= A.nrows) break;
     const int j = j0 + qquo(k0 + lr, qnz);
-    double c00 = A.phi00[j] * A.inv_nxnz;
+    double c00 = gbl(A.phi00)[j] * A.inv_nxnz;
     if (MODE == CM_ADD) c00 -= A.ctl->phimean;
-    double* orow = A.out + row * nx;
+    IBP_GLOBAL double* orow = gbl(A.out) + row * nx;
     if (odd) {
       for (int m = lane; m < nx; m += kWave) {
         double v0 = double(buf[lr * hs + m].x) * cs + c00;
@@ -252,13 +252,13 @@ __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& 
     for (int m = lane; m < h; m += kWave) {
       const Cx<T> z = buf[lr * hs + m];
       double v0 = double(z.x) * cs + c00, v1 = double(z.y) * cs + c00;
-      double2* o = reinterpret_cast<double2*>(orow + 2 * m);
+      IBP_GLOBAL double* o = orow + 2 * m;
       if (MODE == CM_ADD) {
-        const double2 old = *o;
+        const double2 old = gld2(o);
         v0 += old.x;
         v1 += old.y;
       }
-      *o = make_double2(v0, v1);
+      gst2(o, v0, v1);
     }
   }
   __syncthreads();
@@ -277,14 +277,14 @@ __device__ __forceinline__ void zfft_gen_body(const ZfArgs<T>& A, const FftPlan&
   const int nz = A.nz, C = A.cols, hp = A.hp, ss = A.zss ? A.zss : nz + 1;
   const long rs = A.rs;
   const int c0 = colblk * C;
-  Cx<T>* plane = A.spec + (size_t)plane_index * A.ps;
+  IBP_GLOBAL Cx<T>* plane = gbl(A.spec) + (size_t)plane_index * A.ps;
   const QDiv qc = qdiv(C);
   for (int e = threadIdx.x; e < C * nz; e += kThreads) {
     const int z = qquo(e, qc), c = e - __mul24(z, C);
     buf[c * ss + z] = (c0 + c < hp) ? plane[(size_t)z * rs + c0 + c] : Cx<T>{T(0), T(0)};
   }
   __syncthreads();
-  lds_fft<TILE, INV, T, WIDE>(buf, C, ss, fp, A.twz, 1, A.bc, A.bb, A.bt);
+  lds_fft<TILE, INV, T, WIDE>(buf, C, ss, fp, gbl(A.twz), 1, gbl(A.bc), gbl(A.bb), gbl(A.bt));
   for (int e = threadIdx.x; e < C * nz; e += kThreads) {
     const int z = qquo(e, qc), c = e - __mul24(z, C);
     if (c0 + c < hp) plane[(size_t)z * rs + c0 + c] = buf[c * ss + z];
@@ -322,7 +322,6 @@ __global__ __launch_bounds__(kThreads) void kb_xr2c(const BatchGrid<T>* __restri
   a.phi = P.phi[g];
   a.out = P.phi[g];
   a.iter = L.iter;
-  globalize(a);
   xr2c_gen_body<T, MODE, TILE, WIDE>(a, D[g].x.fp, (long)blockIdx.x - start[g], buf, sh);
 }
 
@@ -336,7 +335,6 @@ __global__ __launch_bounds__(kThreads) void kb_xc2r(const BatchGrid<T>* __restri
   a.phi = P.phi[g];
   a.out = P.phi[g];
   a.iter = L.iter;
-  globalize(a);
   xc2r_gen_body<T, MODE, TILE, WIDE>(a, D[g].x.fp, (long)blockIdx.x - start[g], buf);
 }
 
@@ -347,7 +345,6 @@ __global__ __launch_bounds__(kThreads) void kb_zfft(const BatchGrid<T>* __restri
   const int g = batch_grid_of(start, L.count, blockIdx.x);
   ZfArgs<T> a = D[g].z;
   a.check_done = L.check_done;
-  globalize(a);
   const long local = (long)blockIdx.x - start[g];
   const int ncb = D[g].zcolblocks;
   zfft_gen_body<T, INV, TILE, WIDE>(a, D[g].z.fp, (int)(local % ncb), local / ncb, buf);

@@ -66,71 +66,67 @@ __device__ __forceinline__ double wave_excl_scan(double v) {
 
 // Scans of the (0,0) mode over the plane sums ghat[0..ny), run by one wave
 // (so the result does not depend on the size of the block that runs it).
-// `p`: reduced norm partials of the right-hand side pass (used when Z.init).
+// Lane l owns rows [l CH, l CH + CH).  Each sweep re-reads its rows' plane
+// sums (L2-resident) and recomputes the earlier sweeps' per-row values in the
+// same order instead of keeping ny / 64 values per lane in registers: those
+// registers would count for every block of the line-solve kernels that carry
+// this path.  `p`: reduced norm partials of the right-hand side pass (used
+// when Z.init).
 __device__ __forceinline__ void zero_mode_scans(const ZeroArgs& Z, const double (&p)[kPartStride]) {
   const int lane = threadIdx.x & (kWave - 1), ny = Z.ny;
-  constexpr int CHM = (kMaxNy + kWave - 1) / kWave;   // rows per lane at the largest ny
   const int CH = (ny + kWave - 1) / kWave;
   const int j0 = lane * CH;
+  const int j1 = j0 + CH < ny ? j0 + CH : ny;
   const volatile double* gh = Z.ghat;            // written by other blocks of this launch
-  double g[CHM];
   double wsum = 0.0, dsum = 0.0, bad = 0.0;
-#pragma unroll
-  for (int c = 0; c < CHM; ++c) {
-    g[c] = 0.0;
-    const int j = j0 + c;
-    if (c < CH && j < ny) {
-      const double v = gh[j];
-      g[c] = v;
-      wsum += Z.dyf[j] * v;
-      dsum += Z.dyf[j];
-      if (!isfinite(v)) bad += 1.0;
-    }
+  for (int j = j0; j < j1; ++j) {
+    const double v = gh[j];
+    wsum += Z.dyf[j] * v;
+    dsum += Z.dyf[j];
+    if (!isfinite(v)) bad += 1.0;
   }
   wsum = wave_total(wsum);
   dsum = wave_total(dsum);
   bad = wave_total(bad);
   const double nxnz = double(Z.nx) * double(Z.nz);
   const double m = Z.singular ? wsum / (dsum * nxnz) : 0.0;
-  // flux at the lower face of every cell of the chunk
+  const double mz = m * nxnz;
+  // g_j = ghat_j - m nx nz; flux at the lower face of every cell of the chunk
   double loc = 0.0;
-#pragma unroll
-  for (int c = 0; c < CHM; ++c) {
-    const int j = j0 + c;
-    if (c < CH && j < ny) {
-      g[c] -= m * nxnz;
-      loc += Z.dyf[j] * g[c];
-    }
-  }
-  double flux = wave_excl_scan(loc);
+  for (int j = j0; j < j1; ++j) loc += Z.dyf[j] * (gh[j] - mz);
+  const double flux0 = wave_excl_scan(loc);
+  // t_j = dyc_j flux_j (0 at the wall), summed per chunk
   double tl = 0.0;
-#pragma unroll
-  for (int c = 0; c < CHM; ++c) {      // g[c] <- dyc_j flux_j
-    const int j = j0 + c;
-    if (c < CH && j < ny) {
+  {
+    double flux = flux0;
+    for (int j = j0; j < j1; ++j) {
       const double fj = flux;
-      flux += Z.dyf[j] * g[c];
-      g[c] = j > 0 ? Z.dyc[j] * fj : 0.0;
-      tl += g[c];
+      flux += Z.dyf[j] * (gh[j] - mz);
+      tl += j > 0 ? Z.dyc[j] * fj : 0.0;
     }
   }
-  double X = wave_excl_scan(tl);
+  const double X0 = wave_excl_scan(tl);
+  // X_j = running sum of t; its dyf-weighted mean
   double xw = 0.0;
-#pragma unroll
-  for (int c = 0; c < CHM; ++c) {      // g[c] <- X_j
-    const int j = j0 + c;
-    if (c < CH && j < ny) {
-      X += g[c];
-      g[c] = X;
+  {
+    double flux = flux0, X = X0;
+    for (int j = j0; j < j1; ++j) {
+      const double fj = flux;
+      flux += Z.dyf[j] * (gh[j] - mz);
+      X += j > 0 ? Z.dyc[j] * fj : 0.0;
       xw += Z.dyf[j] * X;
     }
   }
   xw = wave_total(xw);
   const double xbar = xw / dsum;
-#pragma unroll
-  for (int c = 0; c < CHM; ++c) {   // with a Dirichlet wall (0,0) goes through the line solve
-    const int j = j0 + c;
-    if (c < CH && j < ny) Z.phi00[j] = Z.singular ? g[c] - xbar : 0.0;
+  {   // with a Dirichlet wall (0,0) goes through the line solve
+    double flux = flux0, X = X0;
+    for (int j = j0; j < j1; ++j) {
+      const double fj = flux;
+      flux += Z.dyf[j] * (gh[j] - mz);
+      X += j > 0 ? Z.dyc[j] * fj : 0.0;
+      Z.phi00[j] = Z.singular ? X - xbar : 0.0;
+    }
   }
   if (Z.init && lane == 0) {
     Ctl* c = Z.ctl;
@@ -149,27 +145,31 @@ __device__ __forceinline__ void zero_mode_scans(const ZeroArgs& Z, const double 
   }
 }
 
-// Block j < ny: plane sum ghat[j] of the FP64 row sums (wave 0, fixed
-// order); the block that finishes last (atomic ticket) then runs the scans
-// and re-arms the ticket for the next launch.
+// The (0,0) mode takes zero_blocks(ny) blocks at the start of each grid's
+// line-solve launch.  Block b sums planes j = b, b + nzb, ... (one wave per
+// plane: ghat[j] from the FP64 row sums in a fixed order); the block that
+// finishes last (atomic ticket) then runs the scans and re-arms the ticket
+// for the next launch.  A handful of blocks keeps the plane sums parallel
+// while each grid pays only a handful of device-scope fences (one per
+// plane, ny per launch, measured slower on batches of short grids).
 template <int NT>
-__device__ __forceinline__ void zero_mode_plane(const ZeroArgs& Z, int j) {
+__device__ __forceinline__ void zero_mode_part(const ZeroArgs& Z, int b) {
   __shared__ double sh[(NT / kWave) * kPartStride];
   __shared__ int last;
+  constexpr int NW = NT / kWave;
+  const int nzb = zero_blocks(Z.ny);
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x) / kWave;
   const int lane = threadIdx.x & (kWave - 1);
-  if (wave == 0) {
+  for (int j = b + nzb * wave; j < Z.ny; j += nzb * NW) {
     double s = 0.0;
     const double* rs = Z.rowsum + (long)j * Z.nz;
     for (int k = lane; k < Z.nz; k += kWave) s += rs[k];
     s = wave_total(s);
-    if (lane == 0) {
-      Z.ghat[j] = s;
-      __threadfence();
-      const int ticket = atomicAdd(Z.ticket, 1);
-      last = (ticket == Z.ny - 1);
-    }
+    if (lane == 0) Z.ghat[j] = s;
   }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(Z.ticket, 1) == nzb - 1);
   __syncthreads();
   if (!__builtin_amdgcn_readfirstlane(last)) return;
   __threadfence();
@@ -212,21 +212,22 @@ __device__ __forceinline__ U shfl_up_w(U v, int d, int w) { return __shfl_up(v, 
 template <typename U>
 __device__ __forceinline__ U shfl_down_w(U v, int d, int w) { return __shfl_down(v, d, w); }
 
-// Block `blk` of one grid's line-solve pass: blocks [0, ny) reduce the FP64
-// plane sums of the (0,0) mode, the rest own M consecutive columns each.
-// Every thread of the block calls it.
+// Block `blk` of one grid's line-solve pass: blocks [0, zero_blocks(ny))
+// run the FP64 (0,0) mode, the rest own M consecutive columns each.  Every
+// thread of the block calls it.
 template <typename T, typename U, int M, int P, int K>
 __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& Z, long blk, Cx<T>* tile) {
   constexpr int NT = M * P;
   constexpr int PS = K * M + 1;   // LDS slots per partition
   if (A.check_done && __builtin_amdgcn_readfirstlane(A.ctl->done)) return;
-  if (blk < A.ny) {   // the first ny blocks: FP64 (0,0) mode
-    zero_mode_plane<NT>(Z, (int)blk);
+  const int nzb = zero_blocks(A.ny);
+  if (blk < nzb) {   // the first blocks: FP64 (0,0) mode
+    zero_mode_part<NT>(Z, (int)blk);
     return;
   }
   const int ny = A.ny;
   const long Q = A.Q;
-  const long q0 = (blk - ny) * M;
+  const long q0 = (blk - nzb) * M;
   // ---- coalesced load of the [ny][M] tile into per-column partition slots:
   // thread (row0 = tid / M, m = tid % M) moves rows row0 + P*i, i < K; all K
   // loads are issued before the first LDS write (rows and columns past the
@@ -238,7 +239,7 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       const int row = row0 + P * i;
-      ld[i] = A.spec[(long)(row < ny ? row : ny - 1) * A.ps + qc];
+      ld[i] = gbl(A.spec)[(long)(row < ny ? row : ny - 1) * A.ps + qc];
     }
 #pragma unroll
     for (int i = 0; i < K; ++i) {
@@ -253,9 +254,9 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
   const int kz = q < Q ? (int)(q / A.rs) : 0;
   const int kx = q < Q ? (int)(q - (long)kz * A.rs) : 0;
   const bool valid = q < Q && kx < A.hp;   // row padding slots are not solved
-  U L = valid ? -(A.lamx[kx] + A.lamz[kz]) : U(1);
+  U L = valid ? -(gbl(A.lamx)[kx] + gbl(A.lamz)[kz]) : U(1);
   const bool zero = A.singular && q == 0;
-  if (zero) L = U(1);   // singular (0,0): solved in FP64 by the plane blocks, zeroed here
+  if (zero) L = U(1);   // singular (0,0): solved in FP64 by the (0,0)-mode blocks, zeroed here
   const int s = p * K;
   Cx<T>* my = tile + p * PS + m;   // row i of this lane's partition: my[i * M]
 
@@ -264,8 +265,8 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
   U ca[K], cc[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    ca[i] = A.ya[s + i];
-    cc[i] = A.yc[s + i];
+    ca[i] = gbl(A.ya)[s + i];
+    cc[i] = gbl(A.yc)[s + i];
   }
   Cx<U> d[K];
 #pragma unroll
@@ -392,7 +393,7 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
         const int row = row0 + P * i;
         const int pp = row / K;
         const Cx<T> v = tile[pp * PS + (row - pp * K) * M + mm];
-        if (row < ny) A.spec[(long)row * A.ps + qs] = v;
+        if (row < ny) gbl(A.spec)[(long)row * A.ps + qs] = v;
       }
     }
   }
@@ -500,7 +501,7 @@ static hipError_t launch_ytri_mpk(const YArgs<T, U>& a, const ZeroArgs& z, hipSt
   // only shapes ytri_shape and ytri_cols can select are instantiated
   if constexpr (ytile_slots<M, P, K>() * (long)sizeof(Cx<T>) <= kYTileBytes && M * P <= 512 &&
                 ytri_pair_used(P, K)) {
-    const long nb = (a.Q + M - 1) / M + a.ny;   // + the (0,0)-mode plane blocks
+    const long nb = (a.Q + M - 1) / M + zero_blocks(a.ny);   // + the (0,0)-mode blocks
     hipLaunchKernelGGL((k_ytri<T, U, M, P, K>), dim3((unsigned)nb), dim3(M * P), 0, s, a, z);
     return hipGetLastError();
   } else {
@@ -568,29 +569,13 @@ void kb_ytri(const BatchGrid<T>* __restrict__ D, const long* __restrict__ start,
   z.mixed = L.mixed;
   z.iter = L.iter;
   z.final_pass = L.final_pass;
-  globalize(a);
-  globalize(z);
-  const long lb = (long)blockIdx.x - start[g];
-  // rows per lane of this grid: K, K/2 or K/4 (the smallest that holds its
-  // ny), so short columns of a batch with one tall grid skip the padding rows
-  const int kg = __builtin_amdgcn_readfirstlane(D[g].yk);
-  if constexpr (K % 4 == 0) {
-    if (kg == K / 4) {
-      ytri_body<T, T, M, P, K / 4>(a, z, lb, tile);
-      return;
-    }
-  }
-  if constexpr (K % 2 == 0) {
-    if (kg == K / 2) {
-      ytri_body<T, T, M, P, K / 2>(a, z, lb, tile);
-      return;
-    }
-  }
-  ytri_body<T, T, M, P, K>(a, z, lb, tile);
+  ytri_body<T, T, M, P, K>(a, z, (long)blockIdx.x - start[g], tile);
 }
 
 // Rows per lane for one grid of a batch whose line-solve shape is P lanes x
-// K rows: K/4 or K/2 when that still holds ny (the variants kb_ytri has).
+// K rows: K/4 or K/2 when that still holds ny, so short columns of a batch
+// with one tall grid skip the padding rows.  The grids of each value run in
+// a launch of their own (a kernel's registers are those of its largest K).
 int batch_grid_rows_per_lane(int ny, int P, int K) {
   const int need = (ny + P - 1) / P;
   if (K % 4 == 0 && need <= K / 4) return K / 4;
@@ -606,7 +591,6 @@ __global__ __launch_bounds__(kThreads) void kb_check(const BatchGrid<T>* __restr
   z.mixed = L.mixed;
   z.iter = L.iter;
   z.final_pass = L.final_pass;
-  globalize(z);
   check_body(z, sh);
 }
 
@@ -619,11 +603,18 @@ int batch_ytri_cols(int P, int K, int want) {
   return M;
 }
 
+// (lanes, rows per lane) pairs a batch can launch: ytri_shape's pairs and
+// their halves and quarters
+constexpr bool ytri_batch_pair(int P, int K) {
+  return P == 32 ? (K == 1 || K == 2 || K == 3 || K == 4 || K == 6 || K == 8 || K == 12)
+                 : (K == 2 || K == 3 || K == 4 || K == 6 || K == 8 || K == 12 || K == 16 || K == 24);
+}
+
 template <typename T, int M, int P, int K>
 static hipError_t launch_kb_ytri(const BatchGrid<T>* d, const long* start, long nb, const BatchLaunch& l,
                                  hipStream_t s) {
   if constexpr (ytile_slots<M, P, K>() * (long)sizeof(Cx<T>) <= kYTileBytes && M * P <= 512 &&
-                ytri_pair_used(P, K)) {
+                ytri_batch_pair(P, K)) {
     hipLaunchKernelGGL((kb_ytri<T, M, P, K>), dim3((unsigned)nb), dim3(M * P), 0, s, d, start, l);
     return hipGetLastError();
   } else {
@@ -635,8 +626,11 @@ template <typename T, int M, int P>
 static hipError_t launch_kb_ytri_k(int K, const BatchGrid<T>* d, const long* start, long nb, const BatchLaunch& l,
                                    hipStream_t s) {
   switch (K) {
+    case 1: return launch_kb_ytri<T, M, P, 1>(d, start, nb, l, s);
     case 2: return launch_kb_ytri<T, M, P, 2>(d, start, nb, l, s);
+    case 3: return launch_kb_ytri<T, M, P, 3>(d, start, nb, l, s);
     case 4: return launch_kb_ytri<T, M, P, 4>(d, start, nb, l, s);
+    case 6: return launch_kb_ytri<T, M, P, 6>(d, start, nb, l, s);
     case 8: return launch_kb_ytri<T, M, P, 8>(d, start, nb, l, s);
     case 12: return launch_kb_ytri<T, M, P, 12>(d, start, nb, l, s);
     case 16: return launch_kb_ytri<T, M, P, 16>(d, start, nb, l, s);
