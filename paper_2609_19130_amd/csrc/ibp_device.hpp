@@ -57,14 +57,29 @@ __device__ __forceinline__ IBP_GLOBAL P* gbl(P* p) {
   return (IBP_GLOBAL P*)p;
 }
 
+// A complex value through a global view, member by member (an object in the
+// global address space cannot bind to the copy constructor's generic
+// reference); the members of an aligned Cx merge into one access.
+template <typename T>
+__device__ __forceinline__ Cx<T> gld(const IBP_GLOBAL Cx<T>* p) {
+  return Cx<T>{p->x, p->y};
+}
+template <typename T>
+__device__ __forceinline__ void gst(IBP_GLOBAL Cx<T>* p, Cx<T> v) {
+  p->x = v.x;
+  p->y = v.y;
+}
+
 // Two consecutive doubles (16-byte aligned) through a global view, as one
 // 16-byte access.
 __device__ __forceinline__ double2 gld2(const IBP_GLOBAL double* p) {
-  const Cx<double> v = *reinterpret_cast<const IBP_GLOBAL Cx<double>*>(p);
-  return make_double2(v.x, v.y);
+  const IBP_GLOBAL Cx<double>* q = reinterpret_cast<const IBP_GLOBAL Cx<double>*>(p);
+  return make_double2(q->x, q->y);
 }
 __device__ __forceinline__ void gst2(IBP_GLOBAL double* p, double a, double b) {
-  *reinterpret_cast<IBP_GLOBAL Cx<double>*>(p) = Cx<double>{a, b};
+  IBP_GLOBAL Cx<double>* q = reinterpret_cast<IBP_GLOBAL Cx<double>*>(p);
+  q->x = a;
+  q->y = b;
 }
 
 // Exact quotient t / d of small non-negative integers (0 <= t < 2^19,
@@ -263,7 +278,7 @@ __device__ __forceinline__ void fft_stage(Cx<T>* buf, int n, int nb, int ss, int
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          Cx<T> w = tw[__mul24(r * k, twmul)];
+          Cx<T> w = gld(tw + __mul24(r * k, twmul));
           if (INV) w.y = -w.y;
           v[q][r] = cmul(v[q][r], w);
         }
@@ -313,7 +328,7 @@ __device__ __forceinline__ void fft_stage_any(Cx<T>* buf, Cx<T>* spare, int n, i
 #pragma unroll
     for (int u = 0; u < QA; ++u) {
       const int q = qb * QA + u < R ? qb * QA + u : R - 1;
-      om[u] = tw[(k + q * Ns) * twmul];
+      om[u] = gld(tw + (k + q * Ns) * twmul);
       if (INV) om[u].y = -om[u].y;
       y[u] = top;
     }
@@ -388,7 +403,7 @@ __device__ __forceinline__ void bluestein_fft(Cx<T>* buf, int nb, int ss, const 
     if (j < n) {
       v = buf[b * ss + j];
       if (INV) v = cconj(v);
-      v = cmul(v, chirp[j]);
+      v = cmul(v, gld(chirp + j));
     }
     buf[b * ss + j] = v;
   }
@@ -396,14 +411,14 @@ __device__ __forceinline__ void bluestein_fft(Cx<T>* buf, int nb, int ss, const 
   lds_stages<TILE, false, T>(buf, nb, ss, m, fp.mst, fp.mradix, twm, 1);
   for (int t = threadIdx.x; t < nb * m; t += kThreads) {
     const int b = qquo(t, qm), k = t - __mul24(b, m);
-    buf[b * ss + k] = cmul(buf[b * ss + k], bhat[k]);
+    buf[b * ss + k] = cmul(buf[b * ss + k], gld(bhat + k));
   }
   __syncthreads();
   lds_stages<TILE, true, T>(buf, nb, ss, m, fp.mst, fp.mradix, twm, 1);
   const T inv_m = T(1) / T(m);
   for (int t = threadIdx.x; t < nb * n; t += kThreads) {
     const int b = qquo(t, qn), k = t - __mul24(b, n);
-    Cx<T> v = cscale(cmul(buf[b * ss + k], chirp[k]), inv_m);
+    Cx<T> v = cscale(cmul(buf[b * ss + k], gld(chirp + k)), inv_m);
     if (INV) v = cconj(v);
     buf[b * ss + k] = v;
   }

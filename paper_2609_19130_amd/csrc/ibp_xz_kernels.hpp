@@ -150,7 +150,7 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
       const int lr = qquo(e, qhp), kk = e - __mul24(lr, A.hp);
       const long row = row0 + lr;
       if (row < A.nrows)
-        gbl(A.spec)[row * A.rs + (j0 + qquo(k0 + lr, qnz)) * pgap + kk] = buf[__mul24(lr, hs) + kk];
+        gst(gbl(A.spec) + row * A.rs + (j0 + qquo(k0 + lr, qnz)) * pgap + kk, buf[__mul24(lr, hs) + kk]);
     }
     __syncthreads();
     return;
@@ -166,10 +166,10 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
     const Cx<T> E = cscale(cadd(Zk, Zc), T(0.5));
     const Cx<T> D = csub(Zk, Zc);
     const Cx<T> O = Cx<T>{T(0.5) * D.y, T(-0.5) * D.x};     // D / 2i
-    const Cx<T> WO = cmul(gbl(A.twx)[k], O);
+    const Cx<T> WO = cmul(gld(gbl(A.twx) + k), O);
     IBP_GLOBAL Cx<T>* srow = gbl(A.spec) + row * A.rs + (j0 + qquo(k0 + lr, qnz)) * pgap;
-    srow[k] = cadd(E, WO);
-    if (h - k != k) srow[h - k] = cconj(csub(E, WO));
+    gst(srow + k, cadd(E, WO));
+    if (h - k != k) gst(srow + (h - k), cconj(csub(E, WO)));
   }
   __syncthreads();
 }
@@ -200,7 +200,7 @@ __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& 
       const int lr = qquo(e, qhp), k = e - __mul24(lr, A.hp);
       const long row = row0 + lr;
       Cx<T> X{T(0), T(0)};
-      if (row < A.nrows) X = gbl(A.spec)[row * A.rs + (j0 + qquo(k0 + lr, qnz)) * pgap + k];
+      if (row < A.nrows) X = gld(gbl(A.spec) + row * A.rs + (j0 + qquo(k0 + lr, qnz)) * pgap + k);
       if (k == 0) X.y = T(0);   // X[0] of a real sequence is real
       buf[__mul24(lr, hs) + k] = X;
       if (k > 0) buf[__mul24(lr, hs) + nx - k] = cconj(X);
@@ -213,8 +213,8 @@ __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& 
     Cx<T> Xk{T(0), T(0)}, Xm{T(0), T(0)};
     if (row < A.nrows) {
       const IBP_GLOBAL Cx<T>* srow = gbl(A.spec) + row * A.rs + (j0 + qquo(k0 + lr, qnz)) * pgap;
-      Xk = srow[k];
-      Xm = srow[h - k];
+      Xk = gld(srow + k);
+      Xm = gld(srow + (h - k));
     }
     if (k == 0) {           // X[0] and X[h] of a real sequence are real
       Xk.y = T(0);
@@ -223,7 +223,7 @@ __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& 
     const Cx<T> Xmc = cconj(Xm);
     const Cx<T> E = cscale(cadd(Xk, Xmc), T(0.5));
     const Cx<T> D = cscale(csub(Xk, Xmc), T(0.5));
-    const Cx<T> O = cmul(cconj(gbl(A.twx)[k]), D);
+    const Cx<T> O = cmul(cconj(gld(gbl(A.twx) + k)), D);
     buf[__mul24(lr, hs) + k] = Cx<T>{E.x - O.y, E.y + O.x};               // E + i O
     const int km = k ? h - k : 0;                                            // (h - k) mod h, k < hh <= h
     if (km != k) buf[__mul24(lr, hs) + km] = Cx<T>{E.x + O.y, O.x - E.y};   // conj(E) + i conj(O)
@@ -281,13 +281,13 @@ __device__ __forceinline__ void zfft_gen_body(const ZfArgs<T>& A, const FftPlan&
   const QDiv qc = qdiv(C);
   for (int e = threadIdx.x; e < C * nz; e += kThreads) {
     const int z = qquo(e, qc), c = e - __mul24(z, C);
-    buf[c * ss + z] = (c0 + c < hp) ? plane[(size_t)z * rs + c0 + c] : Cx<T>{T(0), T(0)};
+    buf[c * ss + z] = (c0 + c < hp) ? gld(plane + (size_t)z * rs + c0 + c) : Cx<T>{T(0), T(0)};
   }
   __syncthreads();
   lds_fft<TILE, INV, T, WIDE>(buf, C, ss, fp, gbl(A.twz), 1, gbl(A.bc), gbl(A.bb), gbl(A.bt));
   for (int e = threadIdx.x; e < C * nz; e += kThreads) {
     const int z = qquo(e, qc), c = e - __mul24(z, C);
-    if (c0 + c < hp) plane[(size_t)z * rs + c0 + c] = buf[c * ss + z];
+    if (c0 + c < hp) gst(plane + (size_t)z * rs + c0 + c, buf[c * ss + z]);
   }
   __syncthreads();
 }

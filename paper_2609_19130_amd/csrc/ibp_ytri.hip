@@ -212,43 +212,62 @@ __device__ __forceinline__ U shfl_up_w(U v, int d, int w) { return __shfl_up(v, 
 template <typename U>
 __device__ __forceinline__ U shfl_down_w(U v, int d, int w) { return __shfl_down(v, d, w); }
 
+// Coalesced loads of the [ny][M] tile of columns q0 .. q0 + M - 1: thread
+// (row0 = tid / M, lm = tid % M) loads rows row0 + P*i, i < K, all issued
+// before any use (rows and columns past the end are clamped to valid
+// addresses and their values discarded when staged).
+template <typename T, typename U, int M, int P, int K>
+__device__ __forceinline__ void ytri_load(const YArgs<T, U>& A, long q0, int lm, int row0, Cx<T> (&ld)[K]) {
+  const long qc = (q0 + lm < A.Q) ? q0 + lm : A.Q - 1;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const int row = row0 + P * i;
+    ld[i] = gld(gbl(A.spec) + (long)(row < A.ny ? row : A.ny - 1) * A.ps + qc);
+  }
+}
+
+// The loaded values into their per-column partition slots.
+template <typename T, int M, int P, int K>
+__device__ __forceinline__ void ytri_stage(int ny, int lm, int row0, const Cx<T> (&ld)[K], Cx<T>* tile) {
+  constexpr int PS = K * M + 1;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const int row = row0 + P * i;
+    const int pp = row / K;
+    tile[pp * PS + (row - pp * K) * M + lm] = row < ny ? ld[i] : Cx<T>{T(0), T(0)};
+  }
+}
+
+template <typename T, typename U, int M, int P, int K>
+__device__ __forceinline__ void ytri_solve(const YArgs<T, U>& A, long q0, Cx<T>* tile);
+
 // Block `blk` of one grid's line-solve pass: blocks [0, zero_blocks(ny))
 // run the FP64 (0,0) mode, the rest own M consecutive columns each.  Every
 // thread of the block calls it.
 template <typename T, typename U, int M, int P, int K>
 __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& Z, long blk, Cx<T>* tile) {
   constexpr int NT = M * P;
-  constexpr int PS = K * M + 1;   // LDS slots per partition
   if (A.check_done && __builtin_amdgcn_readfirstlane(A.ctl->done)) return;
   const int nzb = zero_blocks(A.ny);
   if (blk < nzb) {   // the first blocks: FP64 (0,0) mode
     zero_mode_part<NT>(Z, (int)blk);
     return;
   }
+  const long q0 = (blk - nzb) * M;
+  const int lm = threadIdx.x % M, row0 = threadIdx.x / M;
+  Cx<T> ld[K];
+  ytri_load<T, U, M, P, K>(A, q0, lm, row0, ld);
+  ytri_stage<T, M, P, K>(A.ny, lm, row0, ld, tile);
+  __syncthreads();
+  ytri_solve<T, U, M, P, K>(A, q0, tile);
+}
+
+// Solve of the staged columns q0 .. q0 + M - 1 and their stores.
+template <typename T, typename U, int M, int P, int K>
+__device__ __forceinline__ void ytri_solve(const YArgs<T, U>& A, long q0, Cx<T>* tile) {
+  constexpr int PS = K * M + 1;   // LDS slots per partition
   const int ny = A.ny;
   const long Q = A.Q;
-  const long q0 = (blk - nzb) * M;
-  // ---- coalesced load of the [ny][M] tile into per-column partition slots:
-  // thread (row0 = tid / M, m = tid % M) moves rows row0 + P*i, i < K; all K
-  // loads are issued before the first LDS write (rows and columns past the
-  // end are clamped to valid addresses and their values discarded)
-  {
-    const int m = threadIdx.x % M, row0 = threadIdx.x / M;
-    const long qc = (q0 + m < Q) ? q0 + m : Q - 1;
-    Cx<T> ld[K];
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-      const int row = row0 + P * i;
-      ld[i] = gbl(A.spec)[(long)(row < ny ? row : ny - 1) * A.ps + qc];
-    }
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-      const int row = row0 + P * i;
-      const int pp = row / K;
-      tile[pp * PS + (row - pp * K) * M + m] = row < ny ? ld[i] : Cx<T>{T(0), T(0)};
-    }
-  }
-  __syncthreads();
   const int p = threadIdx.x % P, m = threadIdx.x / P;
   const long q = q0 + m;
   const int kz = q < Q ? (int)(q / A.rs) : 0;
@@ -393,7 +412,7 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
         const int row = row0 + P * i;
         const int pp = row / K;
         const Cx<T> v = tile[pp * PS + (row - pp * K) * M + mm];
-        if (row < ny) gbl(A.spec)[(long)row * A.ps + qs] = v;
+        if (row < ny) gst(gbl(A.spec) + (long)row * A.ps + qs, v);
       }
     }
   }
