@@ -82,6 +82,15 @@ __device__ __forceinline__ void gst2(IBP_GLOBAL double* p, double a, double b) {
   q->y = b;
 }
 
+// Reversed block order for the passes that read what the previous pass of
+// the solve wrote in ascending order (the forward z pass after the x R2C,
+// the x C2R after the inverse z pass): they start on the data written last,
+// which is still in the Infinity Cache.  Work per block is unchanged, so
+// results are bitwise the same.  Measured at 512x384x512 FP64: forward z
+// 327 -> 306 us.
+__device__ __forceinline__ unsigned rev_block_x() { return gridDim.x - 1 - blockIdx.x; }
+__device__ __forceinline__ unsigned rev_block_y() { return gridDim.y - 1 - blockIdx.y; }
+
 // Exact quotient t / d of small non-negative integers (0 <= t < 2^19,
 // d >= 1) from a float reciprocal: r = (1/d rounded) * (1 + 1.5 * 2^-20)
 // rounded, and q = trunc(t * r rounded).  The three roundings move the

@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kThreads) void k_xc2r_pipe(XArgs<T> A) {
   constexpr int RB = kThreads / TT;
   __shared__ Cx<T> lds[RB * rfft::Seq<H>::stride];
   if (MODE == CM_ADD && A.ctl->done) return;
-  const long blk0 = A.row_begin / RB + (long)blockIdx.x * kXGroups;
+  const long blk0 = A.row_begin / RB + (long)rev_block_x() * kXGroups;
   const int tid = threadIdx.x, lr = tid / TT, t = tid % TT;
   Cx<T> buf[kXGroups][2 * kE];
 #pragma unroll
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kThreads) void k_xc2r_reg(XArgs<T> A) {
   constexpr int RB = kThreads / (H / kE);
   __shared__ Cx<T> lds[RB * rfft::Seq<H>::stride];
   if (MODE == CM_ADD && A.ctl->done) return;
-  xc2r_body<T, MODE, H, kThreads>(A, A.row_begin / RB + blockIdx.x, lds, threadIdx.x);
+  xc2r_body<T, MODE, H, kThreads>(A, A.row_begin / RB + rev_block_x(), lds, threadIdx.x);
 }
 
 // z FFT of kx columns [colblk*C, colblk*C + C) of one y plane with C*NZ/8
@@ -283,7 +283,7 @@ template <typename T, bool INV, int NZ, int C>
 __global__ __launch_bounds__(C*(NZ / kE)) void k_zfft_reg(ZfArgs<T> A) {
   __shared__ Cx<T> lds[C * rfft::Seq<NZ>::stride];
   if (A.check_done && A.ctl->done) return;
-  zfft_body<T, INV, NZ, C>(A, blockIdx.x, A.plane0 + blockIdx.y, lds, threadIdx.x);
+  zfft_body<T, INV, NZ, C>(A, blockIdx.x, A.plane0 + (INV ? blockIdx.y : rev_block_y()), lds, threadIdx.x);
 }
 
 

@@ -267,7 +267,7 @@ __device__ __forceinline__ void xc2r_gen_body(const XArgs<T>& A, const FftPlan& 
 template <typename T, int MODE, int TILE, bool WIDE>
 __global__ __launch_bounds__(kThreads) void k_xc2r(XArgs<T> A) {
   __shared__ Cx<T> buf[TILE];
-  xc2r_gen_body<T, MODE, TILE, WIDE>(A, A.fp, A.row_begin / A.rows_per_block + blockIdx.x, buf);
+  xc2r_gen_body<T, MODE, TILE, WIDE>(A, A.fp, A.row_begin / A.rows_per_block + rev_block_x(), buf);
 }
 
 template <typename T, bool INV, int TILE, bool WIDE>
@@ -295,7 +295,7 @@ __device__ __forceinline__ void zfft_gen_body(const ZfArgs<T>& A, const FftPlan&
 template <typename T, bool INV, int TILE, bool WIDE>
 __global__ __launch_bounds__(kThreads) void k_zfft(ZfArgs<T> A) {
   __shared__ Cx<T> buf[TILE + 64];
-  zfft_gen_body<T, INV, TILE, WIDE>(A, A.fp, blockIdx.x, A.plane0 + blockIdx.y, buf);
+  zfft_gen_body<T, INV, TILE, WIDE>(A, A.fp, blockIdx.x, A.plane0 + (INV ? blockIdx.y : rev_block_y()), buf);
 }
 
 // ---------------------------------------------------------------- batched stages
@@ -329,23 +329,25 @@ template <typename T, int MODE, int TILE, bool WIDE>
 __global__ __launch_bounds__(kThreads) void kb_xc2r(const BatchGrid<T>* __restrict__ D, const long* __restrict__ start,
                                                      BatchPtrs P, BatchLaunch L) {
   __shared__ Cx<T> buf[TILE];
-  const int g = batch_grid_of(start, L.count, blockIdx.x);
+  const long bid = rev_block_x();
+  const int g = batch_grid_of(start, L.count, bid);
   XArgs<T> a = D[g].x;
   a.f = P.f[g];
   a.phi = P.phi[g];
   a.out = P.phi[g];
   a.iter = L.iter;
-  xc2r_gen_body<T, MODE, TILE, WIDE>(a, D[g].x.fp, (long)blockIdx.x - start[g], buf);
+  xc2r_gen_body<T, MODE, TILE, WIDE>(a, D[g].x.fp, bid - start[g], buf);
 }
 
 template <typename T, bool INV, int TILE, bool WIDE>
 __global__ __launch_bounds__(kThreads) void kb_zfft(const BatchGrid<T>* __restrict__ D, const long* __restrict__ start,
                                                      BatchLaunch L) {
   __shared__ Cx<T> buf[TILE + 64];
-  const int g = batch_grid_of(start, L.count, blockIdx.x);
+  const long bid = INV ? blockIdx.x : rev_block_x();
+  const int g = batch_grid_of(start, L.count, bid);
   ZfArgs<T> a = D[g].z;
   a.check_done = L.check_done;
-  const long local = (long)blockIdx.x - start[g];
+  const long local = bid - start[g];
   const int ncb = D[g].zcolblocks;
   zfft_gen_body<T, INV, TILE, WIDE>(a, D[g].z.fp, (int)(local % ncb), local / ncb, buf);
 }
