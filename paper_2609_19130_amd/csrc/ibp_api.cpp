@@ -1211,7 +1211,9 @@ ibp_status_t ibp_helmholtz(ibp_plan_t p, double* field, ibp_location_t where, vo
     double* base = cells ? field : field + plane;
     const ibp_plan_s::LineDir& hy = cells ? p->hyc : p->hyf;
     LineArgs ax{base, p->helm + p->hx.off, p->hx.npad, p->nx, p->hx.cyclic, p->hx.g, 0, 0, (long)planes * p->nz, 0};
-    LineArgs az{base, p->helm + p->hz.off, p->hz.npad, p->nz, p->hz.cyclic, p->hz.g, planes, plane, p->nx, p->nx};
+    // the z lines run in descending block order: the x pass wrote the last
+    // planes last, and they are still in the Infinity Cache
+    LineArgs az{base, p->helm + p->hz.off, p->hz.npad, p->nz, p->hz.cyclic, p->hz.g, planes, plane, p->nx, p->nx, 1};
     LineArgs ay{base, p->helm + hy.off, hy.npad, planes, 0, 0.0, 1, 0, plane, plane};
     if (!cells) {   // the increment vanishes on the wall faces
       e = launch_fill_zero(field, plane, s);

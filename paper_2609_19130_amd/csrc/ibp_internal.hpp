@@ -306,6 +306,7 @@ struct LineArgs {
   long ostride;
   long ncol;             // strided: columns per outer index; contiguous: number of lines
   long stride;           // strided: element stride along a line
+  int rev;               // 1: blocks in descending order (start on what the previous pass wrote last)
 };
 int line_shape(int n, int* P, int* K);   // lanes and rows per lane for lines of n (0: too long)
 hipError_t launch_lines_contig(int P, int K, const LineArgs& a, hipStream_t s);

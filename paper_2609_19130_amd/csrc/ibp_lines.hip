@@ -208,8 +208,9 @@ __global__ __launch_bounds__(M * P) void k_lines_strided(LineArgs A) {
   __shared__ double tile[P * PS];
   __shared__ double tab[NTAB];   // the tables, staged once per block with the data loads
   const long ncg = (A.ncol + M - 1) / M;
-  const long o = (long)blockIdx.x / ncg;
-  const long c0 = ((long)blockIdx.x - o * ncg) * M;
+  const long bid = A.rev ? (long)(gridDim.x - 1 - blockIdx.x) : (long)blockIdx.x;
+  const long o = bid / ncg;
+  const long c0 = (bid - o * ncg) * M;
   double* base = A.f + o * A.ostride + c0;
   const int n = A.n;
   {
