@@ -185,3 +185,38 @@ def test_autotune_is_bitwise_neutral(precision):
     torch.cuda.synchronize()
     assert all(torch.equal(x, y) for x, y in zip(before, after))
     b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_with_a_tall_grid_runs_every_line_solve_class(precision):
+    """One grid taller than 384 rows puts the whole batch on 64-lane line
+    solves (8 rows per lane); the others run 4 or 2 rows per lane in launches
+    of their own, and a grid of 6 rows takes fewer (0,0)-mode blocks than the
+    default.  Every grid against its single solve and the oracle."""
+    dims = [(48, 400, 40), (40, 130, 24), (32, 40, 48), (24, 6, 16), (30, 250, 20)]
+    assert line_solve_shape(max(d[1] for d in dims)) == (64, 8)
+    assert sorted({batch_rows(d[1], 64, 8) for d in dims}) == [2, 4, 8]
+    plans, rhs, fs = [], [], []
+    try:
+        for i, (nx, ny, nz) in enumerate(dims):
+            yf = synth.tanh_faces(ny, 2.0)
+            g = geometry(nx, ny, nz, 2 * np.pi, 1.3, yf)
+            u, v, w = synth.uniform_velocity(nx, ny, nz, seed=60 + i)
+            f = divergence(u, v, w, g)
+            fs.append((f, yf))
+            plans.append(ibp.Plan(nx, ny, nz, 2 * np.pi, 1.3, yf, precision=precision, max_iters=6))
+            rhs.append(to_dev(f))
+        outs = ibp.solve_batched(plans, rhs, [torch.empty_like(r) for r in rhs])
+        torch.cuda.synchronize()
+        tol = TOL64 if precision == "fp64" else 1e-8
+        for i, (p, r) in enumerate(zip(plans, rhs)):
+            if precision == "mixed":
+                assert p.info()["converged"] == 1
+            single = p.solve(r)
+            assert float(torch.linalg.vector_norm(single - outs[i]) / torch.linalg.vector_norm(single)) <= tol, i
+            f, yf = fs[i]
+            ref, _ = oracle.solve(f, 2 * np.pi, 1.3, yf)
+            assert rel(outs[i].cpu().numpy(), ref) <= tol, (i, dims[i])
+    finally:
+        for p in plans:
+            p.close()
