@@ -283,7 +283,15 @@ template <typename T, bool INV, int NZ, int C>
 __global__ __launch_bounds__(C*(NZ / kE)) void k_zfft_reg(ZfArgs<T> A) {
   __shared__ Cx<T> lds[C * rfft::Seq<NZ>::stride];
   if (A.check_done && A.ctl->done) return;
-  zfft_body<T, INV, NZ, C>(A, blockIdx.x, A.plane0 + (INV ? blockIdx.y : rev_block_y()), lds, threadIdx.x);
+  // forward: planes in descending order (the x R2C wrote the last planes
+  // last); inverse of an FP64 spectrum: grid (planes, column groups), column
+  // groups in descending order (its line solve wrote the last kx groups last)
+  if (INV && sizeof(T) == 8)
+    zfft_body<T, INV, NZ, C>(A, rev_block_y(), A.plane0 + blockIdx.x, lds, threadIdx.x);
+  else if (INV)
+    zfft_body<T, INV, NZ, C>(A, blockIdx.x, A.plane0 + blockIdx.y, lds, threadIdx.x);
+  else
+    zfft_body<T, INV, NZ, C>(A, blockIdx.x, A.plane0 + rev_block_y(), lds, threadIdx.x);
 }
 
 
@@ -604,7 +612,8 @@ static hipError_t zfft_n(const ZfArgs<T>& a, int nplanes, hipStream_t s) {
   const int C = fast_z_cols<T>(a.nz);
   // (two planes per block with both loaded up front was measured slower: the
   // preloaded columns double the VGPRs and halve the occupancy)
-  const dim3 grid((unsigned)((a.hp + C - 1) / C), (unsigned)nplanes);
+  const unsigned ncb = (unsigned)((a.hp + C - 1) / C);
+  const dim3 grid = (INV && sizeof(T) == 8) ? dim3((unsigned)nplanes, ncb) : dim3(ncb, (unsigned)nplanes);
   auto go = [&](auto kern, int threads) {
     hipLaunchKernelGGL(kern, grid, dim3(threads), 0, s, a);
     return hipGetLastError();

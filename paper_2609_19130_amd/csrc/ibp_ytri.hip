@@ -242,10 +242,15 @@ template <typename T, typename U, int M, int P, int K>
 __device__ __forceinline__ void ytri_solve(const YArgs<T, U>& A, long q0, Cx<T>* tile);
 
 // Block `blk` of one grid's line-solve pass: blocks [0, zero_blocks(ny))
-// run the FP64 (0,0) mode, the rest own M consecutive columns each.  Every
-// thread of the block calls it.
+// run the FP64 (0,0) mode, the rest own M consecutive columns each.  With
+// `kx_major` (and M dividing the row stride) the column blocks go kx group
+// by kx group, all kz of one group of M kx columns before the next: the
+// inverse z pass, which transforms all kz of one kx group per block and runs
+// its groups in descending order, then starts on the groups written last,
+// still in the Infinity Cache.  Every thread of the block calls it.
 template <typename T, typename U, int M, int P, int K>
-__device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& Z, long blk, Cx<T>* tile) {
+__device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& Z, long blk, Cx<T>* tile,
+                                          bool kx_major = false) {
   constexpr int NT = M * P;
   if (A.check_done && __builtin_amdgcn_readfirstlane(A.ctl->done)) return;
   const int nzb = zero_blocks(A.ny);
@@ -253,7 +258,11 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
     zero_mode_part<NT>(Z, (int)blk);
     return;
   }
-  const long q0 = (blk - nzb) * M;
+  long q0 = (blk - nzb) * M;
+  if (kx_major && A.rs % M == 0) {
+    const long lb = blk - nzb, nkz = A.Q / A.rs;
+    q0 = (lb % nkz) * A.rs + (lb / nkz) * M;
+  }
   const int lm = threadIdx.x % M, row0 = threadIdx.x / M;
   Cx<T> ld[K];
   ytri_load<T, U, M, P, K>(A, q0, lm, row0, ld);
@@ -429,7 +438,9 @@ template <typename T, typename U, int M, int P, int K>
 __global__ __launch_bounds__(M * P) __attribute__((amdgpu_waves_per_eu(ytri_waves<T, U>())))
 void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
   __shared__ Cx<T> tile[ytile_slots<M, P, K>()];
-  ytri_body<T, U, M, P, K>(A, Z, blockIdx.x, tile);
+  // kx-major column order for FP64 spectra (measured 1.7% slower on the
+  // mixed form's FP32 spectra, which keep the plain order)
+  ytri_body<T, U, M, P, K>(A, Z, blockIdx.x, tile, sizeof(T) == 8);
 }
 
 // ---------------------------------------------------------------- control
