@@ -102,9 +102,25 @@ def copy_gbs(n_doubles):
     return 2.0 * n_doubles * 8 / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(args):
-    """The oracle as it stands, on the host cores, on one full solve of the
-    same workload (numpy FFTs and a numpy Thomas sweep: one thread)."""
+def cpu_threads():
+    """Host threads this process may use: the CPU affinity set, capped at the
+    share of one GPU's host (16 threads)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    env = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    if env > 0:
+        n = min(n, env)
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(args, keep=None, uvw=None):
+    """The oracle as it stands, on the host cores, on full solves of the same
+    workload: numpy FFTs (one thread) and scipy.fft with `workers` threads
+    (the FFT steps only; the Thomas sweep is single-threaded numpy in both).
+    `keep`, if a dict, receives the oracle's solution of the full workload
+    (`phi`) for the GPU forms' error against it."""
     import numpy as np
 
     import oracle
@@ -117,15 +133,28 @@ def cpu_baseline(args):
         nx, nz = nx // 2, nz // 2
     yf = synth.tanh_faces(ny, args.beta)
     g = geometry(nx, ny, nz, 2 * np.pi, 2 * np.pi, yf)
-    u, v, w = synth.kolmogorov_velocity(nx, ny, nz, seed=3, kmax=64)
+    if uvw is not None and args.cpu_sample == "full":
+        u, v, w = uvw
+    else:
+        u, v, w = synth.kolmogorov_velocity(nx, ny, nz, seed=3, kmax=64)
     f = divergence(u, v, w, g)
     del u, v, w
-    times = []
-    while len(times) < 3 and sum(times) < 30.0:
-        t0 = time.perf_counter()
-        oracle.solve(f, 2 * np.pi, 2 * np.pi, yf)
-        times.append(time.perf_counter() - t0)
-    dt = float(np.median(times))
+    threads = cpu_threads()
+
+    def timed(workers):
+        times = []
+        phi = None
+        while len(times) < 3 and sum(times) < 30.0:
+            t0 = time.perf_counter()
+            phi, _ = oracle.solve(f, 2 * np.pi, 2 * np.pi, yf, workers=workers)
+            times.append(time.perf_counter() - t0)
+        return float(np.median(times)), len(times), phi
+
+    dt, n1, phi = timed(None)
+    dtm, nm, _ = timed(threads)
+    if keep is not None and args.cpu_sample == "full":
+        keep["phi"] = phi
+        keep["f"] = f
     scale = (nx * ny * nz) / float(args.nx * args.ny * args.nz)
     cpu = "unknown"
     try:
@@ -133,10 +162,15 @@ def cpu_baseline(args):
             cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
     except (OSError, StopIteration):
         pass
+    import scipy
     return {"value": scale / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "host": {"cpu": cpu, "logical_cpus": os.cpu_count(), "numpy": np.__version__},
-            "sample": f"median of {len(times)} full oracle solves at {nx}x{ny}x{nz}: {dt:.2f} s each"
-                      + ("" if scale == 1.0 else f"; rate scaled by the cell ratio {scale:.3f}")}
+            "host": {"cpu": cpu, "logical_cpus": os.cpu_count(), "numpy": np.__version__,
+                     "scipy": scipy.__version__},
+            "sample": f"median of {n1} full oracle solves at {nx}x{ny}x{nz}: {dt:.2f} s each (numpy FFTs, 1 thread)"
+                      + ("" if scale == 1.0 else f"; rate scaled by the cell ratio {scale:.3f}"),
+            "threaded": {"value": scale / dtm, "unit": "solves/s", "cores": threads,
+                         "sample": f"median of {nm} full oracle solves: {dtm:.2f} s each (scipy.fft with "
+                                   f"workers={threads}; the Thomas sweep stays one thread)"}}
 
 
 def run_c4(args):
@@ -210,10 +244,10 @@ def run_c4(args):
         out["value"] = out["fp64"]["batched_autotuned"]["grid_solves_per_s"]
         out["ms_per_step"] = out["fp64"]["batched_autotuned"]["ms_per_step"]
     out["source_hash"] = source_hash()
-    print(json.dumps(out), flush=True)
+    return out
 
 
-def run_c5(args):
+def run_c5(args, steps=None):
     """One GPU's share at paper scale: 1024 x 768 x 1024 cells, beta = 3.  A
     bank of 4 right-hand sides (divergences of seeded k^-5/3 velocity fields,
     drawn on the GPU) feeds an AR(1) sequence f_{t+1} = 0.95 f_t +
@@ -227,7 +261,7 @@ def run_c5(args):
     from paper_2609_19130_amd import synth
 
     nx, ny, nz, beta, seed, nbank = 1024, 768, 1024, 3.0, 5, 4
-    steps = args.seq
+    steps = args.seq if steps is None else steps
     workload = f"poisson_{nx}x{ny}x{nz}_beta{beta:g}_ar1_kolmogorov_graph{steps}"
     Lx = Lz = 2 * np.pi
     yf = synth.tanh_faces(ny, beta)
@@ -276,7 +310,7 @@ def run_c5(args):
     g_adv.replay()
     adv_ms = replay_ms(g_adv, 3)
     del g_adv
-    forms = [s for s in args.forms.split(",") if s in ("fp64", "mixed", "mixed_f64sweep")]
+    forms = [s for s in args.forms.split(",") if s in ("fp64", "mixed", "mixed_f64sweep", "mixed_f64inv")]
     res = {}
     finals = {}
     for form in forms:
@@ -320,10 +354,12 @@ def run_c5(args):
         mixed[form] = {"solves_per_s": 1000.0 / r["solve_ms"], "ms_per_step": r["solve_ms"],
                        "iterations_last": r["info"]["iterations"], "converged_last": r["info"]["converged"],
                        "rel_residual_last": r["info"]["rel_residual"], "rel_diff_vs_fp64_last": d,
+                       "backward_error_last": r["info"]["backward_error"],
+                       "residual_history_last": r["info"]["residual_history"],
                        "vs_fp64": (r64["solve_ms"] / r["solve_ms"]) if r64 else None}
     out["mixed"] = mixed
     out["source_hash"] = source_hash()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -335,8 +371,10 @@ def main():
     ap.add_argument("--ny", type=int, default=384)
     ap.add_argument("--nz", type=int, default=512)
     ap.add_argument("--beta", type=float, default=2.0)
-    ap.add_argument("--mixed-iters", type=int, default=6)
-    ap.add_argument("--forms", default="fp64,mixed,mixed_f64sweep")
+    ap.add_argument("--mixed-iters", type=int, default=4,
+                    help="refinement corrections allowed after the initial FP32 solve (each form reports how "
+                         "many it took)")
+    ap.add_argument("--forms", default="fp64,mixed,mixed_f64sweep,mixed_f64inv")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-substep", action="store_true", help="skip the fractional-step substep timing")
     ap.add_argument("--no-profile", action="store_true",
@@ -346,16 +384,19 @@ def main():
                     help="c3: the 512x384x512 solve (default, the headline line); "
                          "c5: a captured graph of --seq solves at 1024x768x1024, beta 3, AR(1) right-hand sides")
     ap.add_argument("--seq", type=int, default=100, help="solves per captured sequence (c5)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="c3 only: skip the batched and paper-scale summaries appended to the line")
+    ap.add_argument("--extra-seq", type=int, default=20, help="solves per captured sequence of the c5 summary")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
     if args.config == "c5":
-        run_c5(args)
+        print(json.dumps(run_c5(args)), flush=True)
         return
     if args.config == "c4":
-        run_c4(args)
+        print(json.dumps(run_c4(args)), flush=True)
         return
 
     import numpy as np
@@ -375,6 +416,7 @@ def main():
     log(f"[bench] generated in {time.perf_counter() - t0:.1f} s; uploading")
     plan = ibp.Plan(nx, ny, nz, Lx, Lz, yf)
     ud, vd, wd = (torch.from_numpy(a).cuda() for a in (u, v, w))
+    host_uvw = (u, v, w) if not args.no_cpu_baseline else None   # the oracle leg's input
     del u, v, w
     f = plan.divergence(ud, vd, wd)
     phi = torch.empty_like(f)
@@ -503,14 +545,59 @@ def main():
         mixed[form] = {"solves_per_s": 1000.0 / r["ms"], "ms_per_step": r["ms"],
                        "iterations": r["info"]["iterations"], "converged": r["info"]["converged"],
                        "rel_residual": r["info"]["rel_residual"],
+                       "rel_residual_vw": r["info"]["rel_residual_vw"],
+                       "backward_error": r["info"]["backward_error"],
+                       "residual_history": r["info"]["residual_history"],
                        "vs_fp64": (r64["ms"] / r["ms"]) if r64 else None}
+        if r["prof"]:
+            mixed[form]["passes"] = {
+                name: {"avg_ms": p["total_ms"] / p["launches"], "launches": p["launches"],
+                       "gbs": p["bytes_per_launch"] / (p["total_ms"] / p["launches"] * 1e-3) / 1e9}
+                for name, p in r["prof"].items()}
     out["mixed"] = mixed
     if substep is not None:
         out["substep_fp64"] = substep
     out["source_hash"] = source_hash()
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline: oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(args)
+        keep = {}
+        out["cpu_baseline"] = cpu_baseline(args, keep, host_uvw)
+        del host_uvw
+        if "phi" in keep:
+            # each form's error against the oracle: the oracle's right-hand
+            # side solved by every form, ||phi - phi_oracle|| / ||phi_oracle||
+            ref = keep["phi"]
+            fo = torch.from_numpy(keep["f"]).cuda()
+            errs = {}
+            for form in forms:
+                plan.set_precision(form, 1e-10, args.mixed_iters)
+                po = plan.solve(fo).cpu().numpy()
+                errs[form] = float(np.linalg.norm(po - ref) / np.linalg.norm(ref))
+            del fo, keep
+            log(f"[bench] error against the oracle: {errs}")
+            out["err_vs_oracle"] = errs
+            if "fp64" in errs:
+                out["err_vs_oracle_fp64"] = errs["fp64"]
+            for form in mixed:
+                mixed[form]["err_vs_oracle"] = errs.get(form)
+    del plan, f, phi
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        # the batched (64 uneven grids) and paper-scale (1024x768x1024 graph
+        # sequence) workloads, summarised; `--config c4` / `--config c5` give
+        # their full records
+        log("[bench] c4: 64-grid batch")
+        c4 = run_c4(args)
+        out["c4"] = {k: c4[k] for k in ("config", "value", "unit", "ms_per_step") if k in c4}
+        for form in ("fp64", "mixed"):
+            if form in c4:
+                out["c4"][form] = {k: c4[form][k] for k in c4[form] if k != "autotune"}
+        torch.cuda.empty_cache()
+        log(f"[bench] c5: {args.extra_seq}-solve graph sequence at 1024x768x1024")
+        c5 = run_c5(args, steps=args.extra_seq)
+        out["c5"] = {k: c5[k] for k in ("config", "value", "unit", "ms_per_step", "hbm_gbs_stage_model",
+                                         "roofline_frac_stage_model", "mixed") if k in c5}
     print(json.dumps(out), flush=True)
 
 

@@ -28,8 +28,8 @@
  * coordinates passed to ibp_plan_create.
  *
  * Execution: argument checks are synchronous and happen before anything is
- * enqueued.  Solves are asynchronous on the given stream (a hipStream_t;
- * NULL = the device's default stream); they never synchronise, allocate or
+ * enqueued.  Solves are asynchronous on the given stream (NULL = the
+ * device's default stream); they never synchronise, allocate or
  * copy to the host, so a solve sequence can be captured in a hipGraph.  A
  * plan owns one workspace: solves with one plan must not overlap on two
  * streams.  Nothing aborts, exits or throws across this interface.
@@ -38,6 +38,8 @@
 #define IBPOISSON_H
 
 #include <stddef.h>
+
+#include <hip/hip_runtime_api.h>   /* hipStream_t */
 
 #ifdef __cplusplus
 extern "C" {
@@ -58,19 +60,39 @@ typedef enum {
   IBP_FP64 = 0,            /* FP64 transforms and line solves: the direct solve */
   IBP_MIXED = 1,           /* FP32 transforms and FP32 line solves, FP64 (0,0) mode, FP64
                               residual and update, iterative refinement to rtol */
-  IBP_MIXED_F64SWEEP = 2   /* as IBP_MIXED, but the line-solve arithmetic is FP64 on the
+  IBP_MIXED_F64SWEEP = 2,  /* as IBP_MIXED, but the line-solve arithmetic is FP64 on the
                               FP32 spectral data (storage and transforms stay FP32) */
+  IBP_MIXED_F64INV = 3     /* FP32 forward transforms (FP32 half spectrum); the line solve
+                              reads it and solves in FP64 into an FP64 half spectrum, and
+                              the inverse transforms run in FP64.  Rounding at or after the
+                              line solve is what the wall rows of the stencil amplify most;
+                              without it one correction reaches 1e-10 where IBP_MIXED needs
+                              two (single plans only: ibp_solve_batched solves such plans
+                              one after another) */
 } ibp_precision_t;
+
+#define IBP_HISTORY_MAX 16
 
 typedef struct {
   int iterations;       /* refinement corrections applied after the initial solve (0 for FP64) */
-  int converged;        /* FP64: 1; mixed: rel_residual <= rtol was reached */
+  int converged;        /* FP64: 1.  Mixed: 1 = rel_residual <= rtol reached; 2 = stopped before
+                           rtol because the iterate reached the FP64 floor (backward_error <=
+                           8 unit roundoffs: no further correction can lower the residual, as on
+                           strongly stretched grids whose FP64 residual floor lies above rtol);
+                           0 = max_iters corrections did neither */
   int nonfinite_input;  /* a NaN/Inf (or FP64 overflow) was met in rhs or in a residual */
   int reserved;
   double rel_residual;  /* ||rhs - m - L_h phi||_2 / ||rhs - m||_2 in FP64 (NaN for FP64 solves) */
   double removed_mean;  /* m, the removed volume-weighted mean of rhs */
   double rhs_norm;      /* ||rhs - m||_2 (mixed) */
   double residual_norm; /* ||rhs - m - L_h phi||_2 (mixed) */
+  /* Mixed forms (NaN for FP64 solves), all of the returned iterate: */
+  double rel_residual_vw;  /* volume-weighted ||V r||_2 / ||V (rhs - m)||_2, V the cell volumes */
+  double backward_error;   /* ||r||_inf / (||L_h||_inf ||phi||_inf + ||rhs - m||_inf) */
+  int history_len;         /* entries of residual_history */
+  int reserved2;
+  double residual_history[IBP_HISTORY_MAX];   /* rel_residual after k = 0, 1, ... corrections
+                                                 (k = 0: the initial FP32 solve) */
 } ibp_info_t;
 
 /* Host-only size check (touches no GPU).  Even nx <= 4096 (transformed as
@@ -133,9 +155,9 @@ ibp_status_t ibp_plan_set_workspace(ibp_plan_t plan, void* device_ptr, size_t by
  * nx*ny*nz doubles, [ny][nz][nx], 16-byte aligned.  rhs is read-only.
  * phi may alias rhs (in-place) for IBP_FP64 only; in the mixed forms rhs is
  * read again by every refinement pass, so any overlap returns
- * IBP_ERROR_INVALID_VALUE.  Enqueued on `stream` (hipStream_t or NULL); call
+ * IBP_ERROR_INVALID_VALUE.  Enqueued on `stream` (NULL: the default stream); call
  * on the device the plan was created on. */
-ibp_status_t ibp_solve(ibp_plan_t plan, const double* rhs, double* phi, void* stream);
+ibp_status_t ibp_solve(ibp_plan_t plan, const double* rhs, double* phi, hipStream_t stream);
 
 /* Solve `count` independent problems, problem i with plans[i], rhs[i],
  * phi[i] (each as in ibp_solve; HOST arrays of plans and device pointers).
@@ -156,7 +178,7 @@ ibp_status_t ibp_solve(ibp_plan_t plan, const double* rhs, double* phi, void* st
  * last bits for grids that ibp_solve transforms with its power-of-two
  * kernels. */
 ibp_status_t ibp_solve_batched(const ibp_plan_t* plans, int count, const double* const* rhs,
-                               double* const* phi, void* stream);
+                               double* const* phi, hipStream_t stream);
 
 /* ---------------------------------------------------------------- batches
  * Many uneven grids solved together (one launch per stage covering every
@@ -177,7 +199,7 @@ ibp_status_t ibp_batch_create(const ibp_plan_t* plans, int count, ibp_batch_t* o
  * pointers, as in ibp_solve).  Asynchronous on `stream`; never allocates,
  * synchronises or copies to the host, so it can be captured in a graph.
  * Per-grid state is read with ibp_get_info on the grid's plan. */
-ibp_status_t ibp_batch_solve(ibp_batch_t batch, const double* const* rhs, double* const* phi, void* stream);
+ibp_status_t ibp_batch_solve(ibp_batch_t batch, const double* const* rhs, double* const* phi, hipStream_t stream);
 
 /* Line-solve columns per block of the batch's stage launches (2, 4, 8 or 16;
  * capped by the LDS budget).  Used by the batch autotuner. */
@@ -202,12 +224,12 @@ typedef struct {
 /* Time solves of rhs into phi (device pointers as in ibp_solve; phi is
  * overwritten with the solution) over the plan's tunable splits and keep
  * the fastest.  Synchronises `stream`; not for use under graph capture. */
-ibp_status_t ibp_plan_autotune(ibp_plan_t plan, const double* rhs, double* phi, void* stream, ibp_tune_t* out);
+ibp_status_t ibp_plan_autotune(ibp_plan_t plan, const double* rhs, double* phi, hipStream_t stream, ibp_tune_t* out);
 
 /* The same for a batch (x rows, z columns and line-solve columns per block
  * of its stage launches; the x split is tuned for IBP_FP64 batches only,
  * because the mixed forms' norm partials follow it). */
-ibp_status_t ibp_batch_autotune(ibp_batch_t batch, const double* const* rhs, double* const* phi, void* stream,
+ibp_status_t ibp_batch_autotune(ibp_batch_t batch, const double* const* rhs, double* const* phi, hipStream_t stream,
                                 ibp_tune_t* out);
 
 /* Wait for the plan's last solve and report its state (iterations,
@@ -221,7 +243,7 @@ ibp_status_t ibp_get_info(ibp_plan_t plan, ibp_info_t* out);
  * v: [ny+1][nz][nx] on the y faces (rows 0 and ny are the walls); f:
  * [ny][nz][nx].  Device pointers, asynchronous on `stream`. */
 ibp_status_t ibp_divergence(ibp_plan_t plan, const double* u, const double* v, const double* w,
-                            double* f, void* stream);
+                            double* f, hipStream_t stream);
 
 /* One substep of the fractional-step method around the solve (paper, eqs.
  * ``elliptic``, ``velsolen`` and ``pressure``).
@@ -236,7 +258,7 @@ ibp_status_t ibp_divergence(ibp_plan_t plan, const double* u, const double* v, c
  * refinement passes read it again) and solved as by ibp_solve.  Device
  * pointers, 16-byte aligned; asynchronous on `stream`. */
 ibp_status_t ibp_solve_divergence(ibp_plan_t plan, const double* u, const double* v, const double* w,
-                                  const double* q, double alpha_dt, double* rhs_out, double* phi, void* stream);
+                                  const double* q, double alpha_dt, double* rhs_out, double* phi, hipStream_t stream);
 
 /* Projection and pressure update in one pass over the cells:
  *   u -= alpha_dt * G phi (x, y and z faces; at a Neumann wall the normal
@@ -246,7 +268,7 @@ ibp_status_t ibp_solve_divergence(ibp_plan_t plan, const double* u, const double
  *   viscous terms, 0 with explicit ones; p may be NULL to skip it).
  * u, v, w, p are updated in place; phi is read.  Asynchronous on `stream`. */
 ibp_status_t ibp_project(ibp_plan_t plan, const double* phi, double alpha_dt, double visc, double* u, double* v,
-                         double* w, double* p, void* stream);
+                         double* w, double* p, hipStream_t stream);
 
 /* Factored implicit viscous solve (paper: eq. ``nstime_discr`` with
  * Crank-Nicolson viscous terms, split into direction-wise tridiagonal solves,
@@ -281,7 +303,7 @@ ibp_status_t ibp_helmholtz_set(ibp_plan_t plan, double beta);
  * capturable).  IBP_ERROR_INVALID_VALUE if ibp_helmholtz_set has not been
  * called since the plan's last change of wall conditions, or for
  * IBP_AT_YFACES without prescribed velocity at both walls. */
-ibp_status_t ibp_helmholtz(ibp_plan_t plan, double* field, ibp_location_t where, void* stream);
+ibp_status_t ibp_helmholtz(ibp_plan_t plan, double* field, ibp_location_t where, hipStream_t stream);
 
 /* Per-pass timing.  While enabled, every kernel launch of ibp_solve is
  * bracketed by two HIP events recorded on the solve's stream (a few

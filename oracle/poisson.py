@@ -102,7 +102,7 @@ def solve_modes(g, F):
     return X
 
 
-def solve(f, Lx, Lz, yf, bc=("neumann", "neumann")):
+def solve(f, Lx, Lz, yf, bc=("neumann", "neumann"), workers=None):
     """Solve L_h phi = f - m with zero volume-weighted mean (Neumann walls),
     or L_h phi = f when a wall is Dirichlet (``bc`` = (lower, upper), each
     "neumann" or "dirichlet"; m = 0 then).
@@ -111,6 +111,8 @@ def solve(f, Lx, Lz, yf, bc=("neumann", "neumann")):
     coordinates; x and z are periodic with lengths Lx and Lz.  Returns
     ``(phi, m)`` where m is the removed volume-weighted mean of f.
     Any nx >= 1, nz >= 1, ny >= 2 is accepted (odd sizes included).
+    ``workers``: None takes numpy's FFTs (one thread); an integer takes
+    scipy.fft's with that many threads (the same transforms; timing only).
     """
     f = np.asarray(f, dtype=np.float64)
     if f.ndim != 3:
@@ -121,7 +123,14 @@ def solve(f, Lx, Lz, yf, bc=("neumann", "neumann")):
     g = geometry(nx, ny, nz, Lx, Lz, yf, bc=bc)
     w = g.dyf.reshape(-1, 1, 1)
     m = float((w * f).sum() / (g.dyf.sum() * nx * nz)) if g.singular else 0.0
-    F = np.fft.fft(np.fft.rfft(f - m, axis=2), axis=1)
+    if workers is None:
+        F = np.fft.fft(np.fft.rfft(f - m, axis=2), axis=1)
+    else:
+        import scipy.fft as sfft
+        F = sfft.fft(sfft.rfft(f - m, axis=2, workers=workers), axis=1, workers=workers)
     X = solve_modes(g, F)
-    phi = np.fft.irfft(np.fft.ifft(X, axis=1), n=nx, axis=2)
+    if workers is None:
+        phi = np.fft.irfft(np.fft.ifft(X, axis=1), n=nx, axis=2)
+    else:
+        phi = sfft.irfft(sfft.ifft(X, axis=1, workers=workers), n=nx, axis=2, workers=workers)
     return phi, m

@@ -20,7 +20,7 @@ using namespace ibp;
 
 namespace {
 
-constexpr int kVersion = 100;  // 0.1.0
+constexpr int kVersion = 200;  // 0.2.0
 
 // Radix factorisation for the LDS FFT: eights first, then fours, twos, the
 // odd primes with butterflies of their own (3, 5, 7, 11), then any larger
@@ -203,10 +203,12 @@ struct ibp_plan_s {
   signed char xcc_queue[kMaxXcc] = {0};     // hardware XCC id -> queue
   double* part = nullptr;
   Ctl* ctl = nullptr;
+  const Ctl* info_ctl = nullptr;   // control block of the last solve
   hipStream_t last_stream = nullptr;
   bool solved = false;
   unsigned gen = 0;   // bumped when the precision, workspace or wall conditions change (batches check it)
   ibp_bc_t bc_lo = IBP_BC_NEUMANN, bc_hi = IBP_BC_NEUMANN;
+  double lnorm = 0.0;   // ||L_h||_inf with the current wall conditions
   std::vector<double> ya_host, yc_host, dyf_host;   // Neumann face coefficients and cell widths
   std::vector<double> dyc_host;                      // centre distances, entries 1..ny-1
   // factored viscous solve (ibp_helmholtz_set): device factor tables per direction
@@ -237,6 +239,17 @@ namespace {
 
 // fused-pass counter block: queues, exit count, error flag, padding, done[ny]
 constexpr int kFctlQueue = 0, kFctlExit = kMaxXcc, kFctlError = kMaxXcc + 1, kFctlHead = kMaxXcc + 4;
+
+// Largest absolute row sum of L_h: 4/dx^2 and 4/dz^2 from the periodic
+// second differences (none for a single cell), 2 (a_j + c_j) from row j of
+// the y operator (a, c are the face coefficients, wall terms included).
+double operator_inf_norm(const ibp_plan_s* p, const std::vector<double>& a, const std::vector<double>& c) {
+  double y = 0.0;
+  for (int j = 0; j < p->ny; ++j) y = std::max(y, 2.0 * (a[j] + c[j]));
+  const double x = p->nx > 1 ? 4.0 / (p->dx * p->dx) : 0.0;
+  const double z = p->nz > 1 ? 4.0 / (p->dz * p->dz) : 0.0;
+  return x + z + y;
+}
 
 long max_parts(const ibp_plan_s* p) {
   long nb = p->nb64 > p->nb32 ? p->nb64 : p->nb32;
@@ -287,14 +300,17 @@ bool z_small(const FftPlan& fpz, int nz) {
   return fpz.any ? nz + 1 <= kTileZ64s / 2 : nz <= kTileZ64s;
 }
 
-size_t spec_bytes(const ibp_plan_s* p) {
-  const size_t b64 = (size_t)p->ny * spec_plane_stride<double>(p->hp, p->nz) * sizeof(Cx<double>);
-  const size_t b32 = (size_t)p->ny * spec_plane_stride<float>(p->hp, p->nz) * sizeof(Cx<float>);
-  return b64 > b32 ? b64 : b32;
+// The FP64 and FP32 half spectra are separate regions: the FP64 inverse
+// passes of IBP_MIXED_F64INV read the FP32 one and write the FP64 one.
+size_t spec64_bytes(const ibp_plan_s* p) {
+  return (size_t)p->ny * spec_plane_stride<double>(p->hp, p->nz) * sizeof(Cx<double>);
+}
+size_t spec32_bytes(const ibp_plan_s* p) {
+  return (size_t)p->ny * spec_plane_stride<float>(p->hp, p->nz) * sizeof(Cx<float>);
 }
 
 size_t workspace_bytes(const ibp_plan_s* p) {
-  size_t b = align256(spec_bytes(p));
+  size_t b = align256(spec64_bytes(p)) + align256(spec32_bytes(p));
   b += align256((size_t)p->ny * p->nz * sizeof(double));
   b += align256((size_t)p->ny * sizeof(double));   // phi00
   b += align256((size_t)p->ny * sizeof(double));   // ghat
@@ -308,8 +324,9 @@ size_t workspace_bytes(const ibp_plan_s* p) {
 void carve_workspace(ibp_plan_s* p) {
   char* c = static_cast<char*>(p->ws);
   p->spec64 = reinterpret_cast<Cx<double>*>(c);
+  c += align256(spec64_bytes(p));
   p->spec32 = reinterpret_cast<Cx<float>*>(c);
-  c += align256(spec_bytes(p));
+  c += align256(spec32_bytes(p));
   p->rowsum = reinterpret_cast<double*>(c);
   c += align256((size_t)p->ny * p->nz * sizeof(double));
   p->phi00 = reinterpret_cast<double*>(c);
@@ -447,20 +464,23 @@ const char* const kPassName[P_COUNT] = {"x_r2c",  "z_fwd",      "y_solve",    "z
 
 // Algorithmic bytes of one launch of each pass (each input element read
 // once, each output element written once).  N = nx ny nz cells, Nh =
-// (nx/2+1) ny nz half-spectrum coefficients of `cb` bytes.
+// (nx/2+1) ny nz half-spectrum coefficients of `cb` bytes (IBP_MIXED_F64INV:
+// the line solve reads 8-byte and writes 16-byte coefficients, the z inverse
+// and the x C2R move 16-byte ones).
 double pass_bytes(const ibp_plan_s* p, int pass) {
   const double N = (double)p->nx * p->ny * p->nz;
   const double Nh = (double)p->hp * p->ny * p->nz;
   const double cb = (p->prec == IBP_FP64) ? 16.0 : 8.0;
+  const bool up = p->prec == IBP_MIXED_F64INV;
   switch (pass) {
     case P_XR2C: return 8.0 * N + cb * Nh;
-    case P_ZFWD:
-    case P_ZINV:
-    case P_Y: return 2.0 * cb * Nh;
-    case P_XC2R: return cb * Nh + 8.0 * N;
+    case P_Y: return up ? 24.0 * Nh : 2.0 * cb * Nh;
+    case P_ZINV: return up ? 32.0 * Nh : 2.0 * cb * Nh;
+    case P_ZFWD: return 2.0 * cb * Nh;
+    case P_XC2R: return (up ? 16.0 : cb) * Nh + 8.0 * N;
     case P_XRES: return 16.0 * N + cb * Nh;        // f and phi in, spectrum out
     case P_XRESONLY: return 16.0 * N;
-    case P_XC2R_ADD: return cb * Nh + 16.0 * N;    // spectrum and phi in, phi out
+    case P_XC2R_ADD: return (up ? 16.0 : cb) * Nh + 16.0 * N;    // spectrum and phi in, phi out
     case P_DIV: return 32.0 * N;                   // u, v, w in, f out
     case P_XZF: return 8.0 * N + cb * Nh;          // fused: the spectrum makes one trip
     case P_ZXI: return cb * Nh + 8.0 * N;
@@ -702,6 +722,7 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     p->yc_host = c;
     p->dyf_host = dyf;
     p->dyc_host = dyc;
+    p->lnorm = operator_inf_norm(p, a, c);
     // ---- closed-form eigenvalues of the periodic second differences
     const long double pi = 3.141592653589793238462643383279502884L;
     std::vector<double> lx(p->hp), lz(nz);
@@ -874,7 +895,8 @@ ibp_status_t ibp_plan_destroy(ibp_plan_t p) {
 
 ibp_status_t ibp_plan_set_precision(ibp_plan_t p, ibp_precision_t prec, double rtol, int max_iters) {
   if (!valid_plan(p)) return IBP_ERROR_INVALID_VALUE;
-  if (prec != IBP_FP64 && prec != IBP_MIXED && prec != IBP_MIXED_F64SWEEP) return IBP_ERROR_INVALID_VALUE;
+  if (prec != IBP_FP64 && prec != IBP_MIXED && prec != IBP_MIXED_F64SWEEP && prec != IBP_MIXED_F64INV)
+    return IBP_ERROR_INVALID_VALUE;
   if (prec != IBP_FP64) {
     if (!(rtol > 0.0) || !std::isfinite(rtol)) return IBP_ERROR_INVALID_VALUE;
     if (max_iters < 0 || max_iters > 64) return IBP_ERROR_INVALID_VALUE;
@@ -906,6 +928,7 @@ ibp_status_t ibp_plan_set_bc(ibp_plan_t p, ibp_bc_t lower, ibp_bc_t upper) {
     if (e != hipSuccess) return from_hip(e);
     p->bc_lo = lower;
     p->bc_hi = upper;
+    p->lnorm = operator_inf_norm(p, a, c);
     ++p->gen;
     return IBP_SUCCESS;
   } catch (...) {
@@ -947,7 +970,7 @@ ibp_status_t ibp_plan_set_workspace(ibp_plan_t p, void* ptr, size_t bytes) {
   }
 }
 
-ibp_status_t ibp_solve(ibp_plan_t p, const double* rhs, double* phi, void* stream) {
+ibp_status_t ibp_solve(ibp_plan_t p, const double* rhs, double* phi, hipStream_t stream) {
   if (!valid_plan(p) || rhs == nullptr || phi == nullptr) return IBP_ERROR_INVALID_VALUE;
   if ((reinterpret_cast<uintptr_t>(rhs) & 15) != 0 || (reinterpret_cast<uintptr_t>(phi) & 15) != 0)
     return IBP_ERROR_INVALID_VALUE;
@@ -969,7 +992,7 @@ ibp_status_t ibp_solve(ibp_plan_t p, const double* rhs, double* phi, void* strea
 }
 
 ibp_status_t ibp_solve_batched(const ibp_plan_t* plans, int count, const double* const* rhs,
-                               double* const* phi, void* stream) {
+                               double* const* phi, hipStream_t stream) {
   if (count < 0) return IBP_ERROR_INVALID_VALUE;
   if (count == 0) return IBP_SUCCESS;
   if (plans == nullptr || rhs == nullptr || phi == nullptr) return IBP_ERROR_INVALID_VALUE;
@@ -991,11 +1014,14 @@ ibp_status_t ibp_get_info(ibp_plan_t p, ibp_info_t* out) {
     std::memset(out, 0, sizeof(*out));
     if (!p->solved) {
       out->rel_residual = NAN;
+      out->rel_residual_vw = NAN;
+      out->backward_error = NAN;
       return IBP_SUCCESS;
     }
     hipError_t e = hipStreamSynchronize(p->last_stream);
     Ctl c{};
-    if (e == hipSuccess) e = hipMemcpy(&c, p->ctl, sizeof(Ctl), hipMemcpyDeviceToHost);
+    const Ctl* src = p->info_ctl ? p->info_ctl : p->ctl;
+    if (e == hipSuccess) e = hipMemcpy(&c, src, sizeof(Ctl), hipMemcpyDeviceToHost);
     int dep_error = 0;
     if (e == hipSuccess) e = hipMemcpy(&dep_error, p->fctl + kFctlError, sizeof(int), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return from_hip(e);
@@ -1010,6 +1036,10 @@ ibp_status_t ibp_get_info(ibp_plan_t p, ibp_info_t* out) {
     out->removed_mean = c.removed_mean;
     out->rhs_norm = std::sqrt(c.fnorm2);
     out->residual_norm = std::sqrt(c.rnorm2);
+    out->rel_residual_vw = c.rel_residual_vw;
+    out->backward_error = c.backward_error;
+    out->history_len = std::min(std::max(c.nhist, 0), std::min(kHistMax, IBP_HISTORY_MAX));
+    for (int k = 0; k < out->history_len; ++k) out->residual_history[k] = c.hist[k];
     return IBP_SUCCESS;
   } catch (...) {
     return IBP_ERROR_INTERNAL;
@@ -1057,7 +1087,7 @@ ibp_status_t ibp_plan_get_profile(ibp_plan_t p, int max, int* count, ibp_pass_st
 }
 
 ibp_status_t ibp_divergence(ibp_plan_t p, const double* u, const double* v, const double* w, double* f,
-                            void* stream) {
+                            hipStream_t stream) {
   if (!valid_plan(p) || !u || !v || !w || !f) return IBP_ERROR_INVALID_VALUE;
   try {
     DivArgs a{u, v, w, nullptr, f, p->dyf, p->nx, p->ny, p->nz, 1.0 / p->dx, 1.0 / p->dz, 1.0};
@@ -1076,7 +1106,7 @@ bool aligned16(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15)
 }  // namespace
 
 ibp_status_t ibp_solve_divergence(ibp_plan_t p, const double* u, const double* v, const double* w, const double* q,
-                                  double alpha_dt, double* rhs_out, double* phi, void* stream) {
+                                  double alpha_dt, double* rhs_out, double* phi, hipStream_t stream) {
   if (!valid_plan(p) || !u || !v || !w || !phi) return IBP_ERROR_INVALID_VALUE;
   if (!(alpha_dt > 0.0) || !std::isfinite(alpha_dt)) return IBP_ERROR_INVALID_VALUE;
   if (!aligned16(u) || !aligned16(v) || !aligned16(w) || !aligned16(phi) || (q && !aligned16(q)) ||
@@ -1105,7 +1135,7 @@ ibp_status_t ibp_solve_divergence(ibp_plan_t p, const double* u, const double* v
 }
 
 ibp_status_t ibp_project(ibp_plan_t p, const double* phi, double alpha_dt, double visc, double* u, double* v,
-                         double* w, double* pr, void* stream) {
+                         double* w, double* pr, hipStream_t stream) {
   if (!valid_plan(p) || !phi || !u || !v || !w) return IBP_ERROR_INVALID_VALUE;
   if (!std::isfinite(alpha_dt) || !std::isfinite(visc)) return IBP_ERROR_INVALID_VALUE;
   try {
@@ -1194,7 +1224,7 @@ ibp_status_t ibp_helmholtz_set(ibp_plan_t p, double beta) {
   }
 }
 
-ibp_status_t ibp_helmholtz(ibp_plan_t p, double* field, ibp_location_t where, void* stream) {
+ibp_status_t ibp_helmholtz(ibp_plan_t p, double* field, ibp_location_t where, hipStream_t stream) {
   if (!valid_plan(p) || field == nullptr || !aligned16(field)) return IBP_ERROR_INVALID_VALUE;
   if (where != IBP_AT_CELLS && where != IBP_AT_YFACES) return IBP_ERROR_INVALID_VALUE;
   if (!p->helm_ready || p->helm_lo != p->bc_lo || p->helm_hi != p->bc_hi) return IBP_ERROR_INVALID_VALUE;
@@ -1316,6 +1346,7 @@ ZeroArgs zargs(ibp_plan_s* p, long nparts, int init, int mixed, int iter, int fi
   z.rtol = p->rtol;
   z.dyf_sum = p->dyf_sum;
   z.singular = p->singular();
+  z.lnorm = p->lnorm;
   return z;
 }
 
@@ -1467,14 +1498,16 @@ ibp_status_t inverse_zx(ibp_plan_s* p, XArgs<T> xa, int cmode, int xpass, ZfArgs
 }
 
 template <typename U>
-ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStream_t s);
+ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStream_t s, bool f64inv);
 
 ibp_status_t enqueue_solve(ibp_plan_s* p, const double* rhs, double* phi, hipStream_t s,
                            const RhsFromVelocity* from_u) {
   p->last_stream = s;
   p->solved = true;
-  if (p->prec == IBP_MIXED) return enqueue_mixed<float>(p, rhs, phi, s);
-  if (p->prec == IBP_MIXED_F64SWEEP) return enqueue_mixed<double>(p, rhs, phi, s);
+  p->info_ctl = p->ctl;
+  if (p->prec == IBP_MIXED) return enqueue_mixed<float>(p, rhs, phi, s, false);
+  if (p->prec == IBP_MIXED_F64SWEEP) return enqueue_mixed<double>(p, rhs, phi, s, false);
+  if (p->prec == IBP_MIXED_F64INV) return enqueue_mixed<double>(p, rhs, phi, s, true);
   // FP64 direct solve: x R2C, z FFT, y line solves + FP64 (0,0), z inverse, x C2R
   XArgs<double> xa = xargs<double>(p, rhs, nullptr, phi, p->spec64, p->twx, p->rb64, 0);
   xa.parts = 0;   // no norms needed: non-finite input shows up in the FP64 plane sums
@@ -1501,15 +1534,31 @@ ibp_status_t enqueue_solve(ibp_plan_s* p, const double* rhs, double* phi, hipStr
   return inverse_zx<double>(p, xa, CM_SET, P_XC2R, za, s);
 }
 
+// FP64 inverse passes of IBP_MIXED_F64INV: the FP64 z inverse and x C2R (set
+// or add into phi) on the FP64 half spectrum the line solve wrote.
+ibp_status_t inverse_f64(ibp_plan_s* p, const double* rhs, double* phi, int cmode, int iter, int check_done,
+                         hipStream_t s) {
+  ZfArgs<double> za{p->spec64, p->twz, p->ctl, p->fpz, p->nz, p->hp, p->zc64,
+                    spec_row_stride<double>(p->hp), spec_plane_stride<double>(p->hp, p->nz), check_done, 0};
+  zf_bluestein(p, za);
+  if (p->nz > 1) IBP_LAUNCH(P_ZINV, run_zfft<double>(p, true, za, p->ny, s));
+  XArgs<double> xd = xargs<double>(p, rhs, phi, phi, p->spec64, p->twx, p->rb64, iter);
+  xd.parts = 0;
+  IBP_LAUNCH(cmode == CM_SET ? P_XC2R : P_XC2R_ADD, run_xc2r<double>(p, cmode, xd, s));
+  return IBP_SUCCESS;
+}
+
 // Mixed forms: FP32 spectral passes wrapped in FP64 iterative refinement.
 //   pass 0: phi = solve32(f)                      (rows summed in FP64 for (0,0))
 //   pass k: r = f - m - L_h phi (FP64), stop if ||r|| <= rtol ||f - m||,
 //           else phi += solve32(r * s_k) / s_k   (s_k a power of two)
 //   final : residual of the last iterate.
 // Every pass is enqueued; once the control block marks the solve done the
-// remaining kernels return immediately.
+// remaining kernels return immediately.  f64inv (U = double): the line
+// solve of every solve32 writes its FP64 solution to the FP64 half spectrum
+// and the inverse z and x passes run in FP64 (inverse_f64).
 template <typename U>
-ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStream_t s) {
+ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStream_t s, bool f64inv) {
   const U* lx = nullptr;
   const U* lz = nullptr;
   const U *ca = nullptr, *cc = nullptr;
@@ -1529,8 +1578,19 @@ ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStr
   if (st != IBP_SUCCESS) return st;
   // partials of the initial pass: one per x-row block of whichever x kernel ran
   const long np0 = (p->fused && p->chunk <= 0) ? p->nbf : p->nb32;
-  IBP_LAUNCH(P_Y, launch_ytri<float, U>(p->yP, p->yK, p->ycols, ya, zargs(p, np0, 1, 1, 0, 0), s));
-  st = inverse_zx<float>(p, xa, CM_SET, P_XC2R, za, s);
+  if constexpr (sizeof(U) == 8) {
+    ya.out64 = p->spec64;
+    ya.out_rs = spec_row_stride<double>(p->hp);
+    ya.out_ps = spec_plane_stride<double>(p->hp, p->nz);
+  }
+  auto ysolve = [&](const ZeroArgs& z) {
+    if constexpr (sizeof(U) == 8) {
+      if (f64inv) return launch_ytri_out64(p->yP, p->yK, ya, z, s);
+    }
+    return launch_ytri<float, U>(p->yP, p->yK, p->ycols, ya, z, s);
+  };
+  IBP_LAUNCH(P_Y, ysolve(zargs(p, np0, 1, 1, 0, 0)));
+  st = f64inv ? inverse_f64(p, rhs, phi, CM_SET, 0, 0, s) : inverse_zx<float>(p, xa, CM_SET, P_XC2R, za, s);
   if (st != IBP_SUCCESS) return st;
 
   za.check_done = 1;
@@ -1545,8 +1605,8 @@ ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStr
     ZfArgs<float> zf = za;
     zf.plane0 = 0;
     if (p->nz > 1) IBP_LAUNCH(P_ZFWD, run_zfft<float>(p, false, zf, p->ny, s));
-    IBP_LAUNCH(P_Y, launch_ytri<float, U>(p->yP, p->yK, p->ycols, ya, zargs(p, p->nb32, 0, 1, k, 0), s));
-    st = inverse_zx<float>(p, xa, CM_ADD, P_XC2R_ADD, za, s);
+    IBP_LAUNCH(P_Y, ysolve(zargs(p, p->nb32, 0, 1, k, 0)));
+    st = f64inv ? inverse_f64(p, rhs, phi, CM_ADD, k, 1, s) : inverse_zx<float>(p, xa, CM_ADD, P_XC2R_ADD, za, s);
     if (st != IBP_SUCCESS) return st;
   }
   xa.iter = p->max_iters + 1;
@@ -1742,6 +1802,7 @@ ibp_status_t batch_enqueue(ibp_batch_s* b, const double* const* rhs, double* con
   for (ibp_plan_t p : b->plans) {
     p->last_stream = s;
     p->solved = true;
+    p->info_ctl = p->ctl;
   }
   // each transform stage: the narrow-family launch, then the wide one
   auto xr2c = [&](int mode, const BatchLaunch& l) {
@@ -1948,7 +2009,7 @@ ibp_status_t ibp_batch_create(const ibp_plan_t* plans, int count, ibp_batch_t* o
   }
 }
 
-ibp_status_t ibp_batch_solve(ibp_batch_t batch, const double* const* rhs, double* const* phi, void* stream) {
+ibp_status_t ibp_batch_solve(ibp_batch_t batch, const double* const* rhs, double* const* phi, hipStream_t stream) {
   if (batch == nullptr) return IBP_ERROR_INVALID_VALUE;
   try {
     return batch_solve(batch, rhs, phi, static_cast<hipStream_t>(stream));
@@ -2033,7 +2094,7 @@ ibp_status_t autotune(const std::vector<TuneCfg>& cands, Apply apply, Run run, h
 
 extern "C" {
 
-ibp_status_t ibp_plan_autotune(ibp_plan_t p, const double* rhs, double* phi, void* stream, ibp_tune_t* out) {
+ibp_status_t ibp_plan_autotune(ibp_plan_t p, const double* rhs, double* phi, hipStream_t stream, ibp_tune_t* out) {
   if (!valid_plan(p) || rhs == nullptr || phi == nullptr) return IBP_ERROR_INVALID_VALUE;
   try {
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -2057,7 +2118,7 @@ ibp_status_t ibp_plan_autotune(ibp_plan_t p, const double* rhs, double* phi, voi
   }
 }
 
-ibp_status_t ibp_batch_autotune(ibp_batch_t b, const double* const* rhs, double* const* phi, void* stream,
+ibp_status_t ibp_batch_autotune(ibp_batch_t b, const double* const* rhs, double* const* phi, hipStream_t stream,
                                 ibp_tune_t* out) {
   if (b == nullptr || rhs == nullptr || phi == nullptr) return IBP_ERROR_INVALID_VALUE;
   try {

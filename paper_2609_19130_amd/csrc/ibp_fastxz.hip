@@ -38,12 +38,18 @@ __device__ __forceinline__ void xr2c_body(const XArgs<T>& A, long blk, Cx<T>* ld
   const int j = live ? (int)(row / nz) : 0;
   const int k = live ? (int)(row - (long)j * nz) : 0;
   constexpr bool kRes = MODE == XM_RESID || MODE == XM_RESID_ONLY;
+  // norm partials: residual passes and FP32-spectrum passes (the mixed forms'
+  // first pass); an FP64-spectrum right-hand-side pass (the direct solve)
+  // never needs them and carries none of their registers
+  constexpr bool kParts = kRes || sizeof(T) == 4;
   double mean = 0.0, s = 1.0;
   if (kRes) mean = A.ctl->removed_mean;
   if (MODE == XM_RESID) s = A.ctl->scale[A.iter & 1];
 
   Cx<T> v[kE];
-  double rs = 0.0, acc_in2 = 0.0, acc_f2 = 0.0, acc_max = 0.0, acc_bad = 0.0, acc_wphi = 0.0;
+  double rs = 0.0;
+  NormAcc acc;
+  const double dyfj = kRes && live ? A.dyf[j] : 0.0;
 #pragma unroll
   for (int i = 0; i < kE; ++i) {
     const int m = t + TT * i;
@@ -55,7 +61,7 @@ __device__ __forceinline__ void xr2c_body(const XArgs<T>& A, long blk, Cx<T>* ld
       if (!kRes) {
         v0 = fv.x;
         v1 = fv.y;
-        acc_f2 += v0 * v0 + v1 * v1;
+        if (kParts && A.parts) acc.rhs_pair(v0, v1);
       } else {
         const double* prow = A.phi + row * nx;
         const double2 pc = *reinterpret_cast<const double2*>(prow + 2 * m);
@@ -75,13 +81,10 @@ __device__ __forceinline__ void xr2c_body(const XArgs<T>& A, long blk, Cx<T>* ld
         const double f0 = fv.x - mean, f1 = fv.y - mean;
         v0 = f0 - L0;
         v1 = f1 - L1;
-        acc_f2 += f0 * f0 + f1 * f1;
-        acc_wphi += A.dyf[j] * (pc.x + pc.y);
+        acc.pair(v0, v1, f0, f1, dyfj * dyfj);
+        acc.phi_pair(pc.x, pc.y, dyfj);
       }
       rs += v0 + v1;
-      acc_in2 += v0 * v0 + v1 * v1;
-      acc_max = fmax(acc_max, fmax(fabs(v0), fabs(v1)));
-      if (!isfinite(v0) || !isfinite(v1)) acc_bad += 1.0;
     }
     v[i] = Cx<T>{T(v0 * s), T(v1 * s)};
   }
@@ -89,15 +92,7 @@ __device__ __forceinline__ void xr2c_body(const XArgs<T>& A, long blk, Cx<T>* ld
 #pragma unroll
   for (int off = TT / 2; off > 0; off >>= 1) rs += __shfl_xor(rs, off, kWave);
   if (live && t == 0) A.rowsum[row] = rs;
-  if (A.parts) {
-    double vals[5] = {acc_in2, acc_f2, acc_max, acc_bad, acc_wphi};
-    const bool ismax[5] = {false, false, true, false, false};
-    block_reduce<5, NT>(vals, ismax, sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int q = 0; q < kPartStride; ++q) A.part[blk * kPartStride + q] = vals[q];
-    }
-  }
+  if (kParts && A.parts) acc.write<NT, kRes>(A.part, blk, sh);
   Cx<T>* my = lds + lr * SS;
   P::run(v, t, my, A.twx, 2);
 #pragma unroll
@@ -123,7 +118,7 @@ template <typename T, int MODE, int H>
 __global__ __launch_bounds__(kThreads) void k_xr2c_reg(XArgs<T> A) {
   constexpr int RB = kThreads / (H / kE);
   __shared__ Cx<T> lds[RB * rfft::Seq<H>::stride];
-  __shared__ double sh[(kThreads / kWave) * 5];
+  __shared__ double sh[(kThreads / kWave) * kPartStride];
   if ((MODE == XM_RESID || MODE == XM_RESID_ONLY) && A.ctl->done) return;
   xr2c_body<T, MODE, H, kThreads>(A, A.row_begin / RB + blockIdx.x, lds, sh, threadIdx.x);
 }
@@ -139,7 +134,7 @@ __global__ __launch_bounds__(kThreads) void k_xr2c_pipe(XArgs<T> A) {
   constexpr int TT = H / kE;
   constexpr int RB = kThreads / TT;
   __shared__ Cx<T> lds[RB * rfft::Seq<H>::stride];
-  __shared__ double sh[(kThreads / kWave) * 5];
+  __shared__ double sh[(kThreads / kWave) * kPartStride];
   const long blk0 = A.row_begin / RB + (long)blockIdx.x * kXGroups;
   const int tid = threadIdx.x, lr = tid / TT, t = tid % TT;
   double2 buf[kXGroups][kE];
@@ -389,7 +384,7 @@ __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4
   constexpr int RBX = NT / (H / kE), CZ = NT / (NZ / kE);
   constexpr int LX = RBX * rfft::Seq<H>::stride, LZ = CZ * rfft::Seq<NZ>::stride;
   __shared__ Cx<T> lds[LX > LZ ? LX : LZ];
-  __shared__ double sh[(NT / kWave) * 5];
+  __shared__ double sh[(NT / kWave) * kPartStride];
   __shared__ int item;
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x) / kWave;   // uniform
   const int lane = (int)threadIdx.x % kWave;

@@ -26,10 +26,11 @@ inline long spec_plane_stride(int hp, int nz) {
 // Solve state kept in device memory.  The iteration-0 (0,0)-mode block
 // re-initialises it at the start of every solve, before any kernel reads it,
 // so no memset is ever enqueued (solves stay graph-capturable).
+constexpr int kHistMax = 16;   // refinement residuals kept per solve
 struct alignas(64) Ctl {
   int done;           // refinement finished: later kernels of the solve return at once
   int iters;          // refinement corrections applied after the initial solve
-  int converged;
+  int converged;      // 1: rel_residual <= rtol; 2: stopped at the FP64 floor (backward error); 0: not
   int nonfinite;      // non-finite value met in the right-hand side (or residual)
   double scale[2];    // FP32 input scale of refinement pass k is scale[k & 1]
   double fnorm2;      // ||f - m||_2^2
@@ -38,7 +39,18 @@ struct alignas(64) Ctl {
   double removed_mean;
   double rel_residual;
   double phimean;     // volume-weighted mean of the iterate read by the latest residual pass
+  double rel_residual_vw;   // ||V r||_2 / ||V (f - m)||_2, V the cell volumes
+  double backward_error;    // ||r||_inf / (||L_h||_inf ||phi||_inf + ||f - m||_inf)
+  int nhist;                // entries of hist
+  int pad_;
+  double hist[kHistMax];    // rel_residual of the iterate after k corrections, k = 0, 1, ...
 };
+
+// Normwise backward error at which the refinement stops although rtol is
+// not reached: the iterate is then as accurate as its FP64 representation
+// allows (FP64 direct solutions measure 1.5-2.5 unit roundoffs on the
+// benchmark grids), and further corrections cannot lower the residual.
+constexpr double kEtaFloor = 8.0 * 1.1102230246251565e-16;
 
 // x R2C input: f itself (PLAIN), the FP64 residual of the current iterate
 // (RESID; RESID_ONLY reduces it without transforming), or f assembled on the
@@ -46,8 +58,83 @@ struct alignas(64) Ctl {
 enum XMode { XM_PLAIN = 0, XM_RESID = 1, XM_RESID_ONLY = 2, XM_DIV = 3 };
 enum CMode { CM_SET = 0, CM_ADD = 1 };
 
-// per-block partials: sum in^2, sum (f-m)^2, max |in|, #non-finite, sum_j dyf_j * (row sums of phi)
-constexpr int kPartStride = 5;
+// Per-block norm partials of an x pass; `in` is what the pass transforms (f,
+// or the residual r = f - m - L_h phi in the residual modes) and `fm` the
+// right-hand side with its mean removed (residual modes; f otherwise):
+//   [0] sum in^2          [1] sum fm^2          [2] max |in|
+//   [3] non-finite count  [4] sum_j dyf_j phi   [5] sum dyf_j^2 in^2
+//   [6] sum dyf_j^2 fm^2  [7] max |phi|         [8] max |fm|
+// Slots 4, 5, 6 and 7 are filled by the residual modes only.
+constexpr int kPartStride = 9;
+#define IBP_PART_IS_MAX {false, false, true, false, false, false, false, true, true}
+
+struct NormAcc {
+  double in2 = 0.0, f2 = 0.0, imax = 0.0, bad = 0.0, wphi = 0.0, win2 = 0.0, wf2 = 0.0, pmax = 0.0, fmx = 0.0;
+  // one residual or right-hand-side pair (in0, in1) with its (f - m) pair; w2 = dyf_j^2
+  __device__ __forceinline__ void pair(double in0, double in1, double fm0, double fm1, double w2) {
+    in2 += in0 * in0 + in1 * in1;
+    f2 += fm0 * fm0 + fm1 * fm1;
+    imax = fmax(imax, fmax(fabs(in0), fabs(in1)));
+    if (!isfinite(in0) || !isfinite(in1)) bad += 1.0;
+    win2 += w2 * (in0 * in0 + in1 * in1);
+    wf2 += w2 * (fm0 * fm0 + fm1 * fm1);
+    fmx = fmax(fmx, fmax(fabs(fm0), fabs(fm1)));
+  }
+  // a right-hand-side pair of a non-residual pass (in = f): only the plain
+  // norms (sum, max, non-finite count); write<NT, false> derives the rest
+  __device__ __forceinline__ void rhs_pair(double in0, double in1) {
+    in2 += in0 * in0 + in1 * in1;
+    imax = fmax(imax, fmax(fabs(in0), fabs(in1)));
+    if (!isfinite(in0) || !isfinite(in1)) bad += 1.0;
+  }
+  __device__ __forceinline__ void rhs_one(double in0) {
+    in2 += in0 * in0;
+    imax = fmax(imax, fabs(in0));
+    if (!isfinite(in0)) bad += 1.0;
+  }
+  __device__ __forceinline__ void one(double in0, double fm0, double w2) {
+    in2 += in0 * in0;
+    f2 += fm0 * fm0;
+    imax = fmax(imax, fabs(in0));
+    if (!isfinite(in0)) bad += 1.0;
+    win2 += w2 * (in0 * in0);
+    wf2 += w2 * (fm0 * fm0);
+    fmx = fmax(fmx, fabs(fm0));
+  }
+  // the iterate's values at the cells of a residual pair (dyf = dyf_j)
+  __device__ __forceinline__ void phi_pair(double p0, double p1, double dyf) {
+    wphi += dyf * (p0 + p1);
+    pmax = fmax(pmax, fmax(fabs(p0), fabs(p1)));
+  }
+  __device__ __forceinline__ void phi_one(double p0, double dyf) {
+    wphi += dyf * p0;
+    pmax = fmax(pmax, fabs(p0));
+  }
+  // block-reduce and write the block's partials (thread 0); every thread
+  // calls it.  RESID: all slots; otherwise only the right-hand side's
+  // (fm = in, no phi, no weighted sums).
+  template <int NT, bool RESID, typename Ptr>
+  __device__ __forceinline__ void write(Ptr part, long blk, double* sh) {
+    if constexpr (RESID) {
+      double v[kPartStride] = {in2, f2, imax, bad, wphi, win2, wf2, pmax, fmx};
+      const bool ism[kPartStride] = IBP_PART_IS_MAX;
+      block_reduce<kPartStride, NT>(v, ism, sh);
+      if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < kPartStride; ++q) part[blk * kPartStride + q] = v[q];
+      }
+    } else {
+      double v[3] = {in2, imax, bad};
+      const bool ism[3] = {false, true, false};
+      block_reduce<3, NT>(v, ism, sh);
+      if (threadIdx.x == 0) {
+        const double w[kPartStride] = {v[0], v[0], v[1], v[2], 0.0, 0.0, 0.0, 0.0, v[1]};
+#pragma unroll
+        for (int q = 0; q < kPartStride; ++q) part[blk * kPartStride + q] = w[q];
+      }
+    }
+  }
+};
 
 template <typename T>
 struct XArgs {
@@ -161,6 +248,10 @@ struct YArgs {
   long rs, ps;           // spectrum row and plane strides (elements)
   int ny, hp, check_done;
   int singular;          // Neumann at both walls: column (0,0) is left to the FP64 (0,0) path
+  // IBP_MIXED_F64INV: the solution goes to this FP64 half spectrum (row and
+  // plane strides out_rs, out_ps) instead of back into `spec`
+  Cx<double>* out64;
+  long out_rs, out_ps;
 };
 
 struct ZeroArgs {        // FP64 (0,0) mode and solve control
@@ -181,6 +272,7 @@ struct ZeroArgs {        // FP64 (0,0) mode and solve control
   double rtol;
   double dyf_sum;        // sum_j dyf_j
   int singular;          // Neumann at both walls: remove the mean, solve (0,0) by flux integration
+  double lnorm;          // ||L_h||_inf (largest absolute row sum of the operator)
 };
 
 // Fused x/z pass (persistent).  The y planes are dealt out to one work
@@ -343,6 +435,8 @@ hipError_t launch_zfft(bool inverse, bool small, bool wide, const ZfArgs<T>& a, 
 // capped by the LDS budget.
 template <typename T, typename U>
 hipError_t launch_ytri(int P, int K, int want, const YArgs<T, U>& a, const ZeroArgs& z, hipStream_t s);
+// FP32 half spectrum in, FP64 arithmetic, FP64 half spectrum a.out64 out.
+hipError_t launch_ytri_out64(int P, int K, const YArgs<float, double>& a, const ZeroArgs& z, hipStream_t s);
 hipError_t launch_check(const ZeroArgs& z, hipStream_t s);
 
 // Register-FFT kernels for power-of-two lengths 32..1024 (ibp_fastxz.hip).

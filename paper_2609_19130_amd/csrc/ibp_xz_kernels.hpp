@@ -30,6 +30,7 @@ template <typename T, int MODE, int TILE, bool WIDE>
 __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& fp, long blk, Cx<T>* buf,
                                               double* sh) {
   constexpr bool kRes = MODE == XM_RESID || MODE == XM_RESID_ONLY;
+  constexpr bool kParts = kRes || sizeof(T) == 4;   // as in the register kernels
   if (kRes && __builtin_amdgcn_readfirstlane(A.ctl->done)) return;
   const int h = A.h, RB = A.rows_per_block, nx = A.nx, nz = A.nz, ny = A.ny;
   const int hs = A.hs ? A.hs : h;   // LDS row stride (Bluestein: the convolution length)
@@ -41,7 +42,7 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
   const QDiv qnz = qdiv(nz);
   const long pgap = A.ps - (long)nz * A.rs;   // spectral plane padding
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  double acc_in2 = 0.0, acc_f2 = 0.0, acc_max = 0.0, acc_bad = 0.0, acc_wphi = 0.0;
+  NormAcc acc;
   double mean = 0.0, s = 1.0;
   if (kRes) mean = A.ctl->removed_mean;
   if (MODE == XM_RESID) s = A.ctl->scale[A.iter & 1];
@@ -58,13 +59,14 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
     const int jr = qquo(k0 + lr, qnz);
     const int j = j0 + jr;
     const int k = k0 + lr - __mul24(jr, nz);
+    const double dyfj = kRes ? gbl(A.dyf)[j] : 0.0;
     if (odd) {
       for (int m = lane; m < nx; m += kWave) {
         const double fv = MODE == XM_DIV ? assemble_one(A, row, j, k, m) : frow[m];
         double v0;
         if (!kRes) {
           v0 = fv;
-          acc_f2 += v0 * v0;
+          if (kParts && A.parts) acc.rhs_one(v0);
         } else {
           // r = (f - m) - L_h phi, 7-point staggered stencil, FP64
           const IBP_GLOBAL double* prow = gbl(A.phi) + row * nx;
@@ -80,13 +82,10 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
                             A.yc[j] * (yp - pc);
           const double f0 = fv - mean;
           v0 = f0 - L0;
-          acc_f2 += f0 * f0;
-          acc_wphi += A.dyf[j] * pc;
+          acc.one(v0, f0, dyfj * dyfj);
+          acc.phi_one(pc, dyfj);
         }
         rs += v0;
-        acc_in2 += v0 * v0;
-        acc_max = fmax(acc_max, fabs(v0));
-        if (!isfinite(v0)) acc_bad += 1.0;
         if (MODE != XM_RESID_ONLY) buf[lr * hs + m] = Cx<T>{T(v0 * s), T(0)};
       }
     } else
@@ -97,7 +96,7 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
       if (!kRes) {
         v0 = fv.x;
         v1 = fv.y;
-        acc_f2 += v0 * v0 + v1 * v1;
+        if (kParts && A.parts) acc.rhs_pair(v0, v1);
       } else {
         // r = (f - m) - L_h phi, 7-point staggered stencil, FP64
         const IBP_GLOBAL double* prow = gbl(A.phi) + row * nx;
@@ -119,27 +118,16 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
         const double f0 = fv.x - mean, f1 = fv.y - mean;
         v0 = f0 - L0;
         v1 = f1 - L1;
-        acc_f2 += f0 * f0 + f1 * f1;
-        acc_wphi += A.dyf[j] * (pc.x + pc.y);
+        acc.pair(v0, v1, f0, f1, dyfj * dyfj);
+        acc.phi_pair(pc.x, pc.y, dyfj);
       }
       rs += v0 + v1;
-      acc_in2 += v0 * v0 + v1 * v1;
-      acc_max = fmax(acc_max, fmax(fabs(v0), fabs(v1)));
-      if (!isfinite(v0) || !isfinite(v1)) acc_bad += 1.0;
       if (MODE != XM_RESID_ONLY) buf[lr * hs + m] = Cx<T>{T(v0 * s), T(v1 * s)};
     }
     rs = wave_sum(rs);
     if (MODE != XM_RESID_ONLY && lane == 0) gbl(A.rowsum)[row] = rs;
   }
-  if (A.parts) {
-    double vals[5] = {acc_in2, acc_f2, acc_max, acc_bad, acc_wphi};
-    const bool ismax[5] = {false, false, true, false, false};
-    block_reduce<5>(vals, ismax, sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int i = 0; i < kPartStride; ++i) gbl(A.part)[blk * kPartStride + i] = vals[i];
-    }
-  }
+  if (kParts && A.parts) acc.write<kThreads, kRes>(gbl(A.part), blk, sh);
   if (MODE == XM_RESID_ONLY) return;
   __syncthreads();
   lds_fft<TILE, false, T, WIDE>(buf, RB, hs, fp, gbl(A.twx), odd ? 1 : 2, gbl(A.bc), gbl(A.bb), gbl(A.bt));
@@ -177,7 +165,7 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
 template <typename T, int MODE, int TILE, bool WIDE>
 __global__ __launch_bounds__(kThreads) void k_xr2c(XArgs<T> A) {
   __shared__ Cx<T> buf[TILE];
-  __shared__ double sh[4 * 5];
+  __shared__ double sh[4 * kPartStride];
   xr2c_gen_body<T, MODE, TILE, WIDE>(A, A.fp, A.row_begin / A.rows_per_block + blockIdx.x, buf, sh);
 }
 
@@ -315,7 +303,7 @@ template <typename T, int MODE, int TILE, bool WIDE>
 __global__ __launch_bounds__(kThreads) void kb_xr2c(const BatchGrid<T>* __restrict__ D, const long* __restrict__ start,
                                                      BatchPtrs P, BatchLaunch L) {
   __shared__ Cx<T> buf[TILE];
-  __shared__ double sh[4 * 5];
+  __shared__ double sh[4 * kPartStride];
   const int g = batch_grid_of(start, L.count, blockIdx.x);
   XArgs<T> a = D[g].x;
   a.f = P.f[g];

@@ -11,6 +11,7 @@
 // one wave own one column, K consecutive rows each (rows past ny are
 // decoupled padding).
 #include <cstdlib>
+#include <type_traits>
 
 #include "ibp_internal.hpp"
 
@@ -29,16 +30,15 @@ namespace ibp {
 // given NT).
 template <int NT>
 __device__ __forceinline__ void reduce_parts(const ZeroArgs& Z, double* sh, double out[kPartStride]) {
-  double v[kPartStride] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const bool ism[kPartStride] = IBP_PART_IS_MAX;
+  double v[kPartStride];
+#pragma unroll
+  for (int q = 0; q < kPartStride; ++q) v[q] = 0.0;
   for (long b = threadIdx.x; b < Z.nparts; b += NT) {
     const double* p = Z.part + b * kPartStride;
-    v[0] += p[0];
-    v[1] += p[1];
-    v[2] = fmax(v[2], p[2]);
-    v[3] += p[3];
-    v[4] += p[4];
+#pragma unroll
+    for (int q = 0; q < kPartStride; ++q) v[q] = ism[q] ? fmax(v[q], p[q]) : v[q] + p[q];
   }
-  const bool ism[kPartStride] = {false, false, true, false, false};
   block_reduce<kPartStride, NT>(v, ism, sh);
   for (int i = 0; i < kPartStride; ++i) out[i] = v[i];
 }
@@ -142,6 +142,9 @@ __device__ __forceinline__ void zero_mode_scans(const ZeroArgs& Z, const double 
     c->removed_mean = m;
     c->rel_residual = __builtin_nan("");
     c->phimean = 0.0;
+    c->rel_residual_vw = __builtin_nan("");
+    c->backward_error = __builtin_nan("");
+    c->nhist = 0;
   }
 }
 
@@ -173,7 +176,9 @@ __device__ __forceinline__ void zero_mode_part(const ZeroArgs& Z, int b) {
   __syncthreads();
   if (!__builtin_amdgcn_readfirstlane(last)) return;
   __threadfence();
-  double p[kPartStride] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double p[kPartStride];
+#pragma unroll
+  for (int q = 0; q < kPartStride; ++q) p[q] = 0.0;
   if (Z.init) reduce_parts<NT>(Z, sh, p);
   if (wave == 0) zero_mode_scans(Z, p);
   if (threadIdx.x == 0) atomicExch(Z.ticket, 0);
@@ -238,7 +243,7 @@ __device__ __forceinline__ void ytri_stage(int ny, int lm, int row0, const Cx<T>
   }
 }
 
-template <typename T, typename U, int M, int P, int K>
+template <typename T, typename U, int M, int P, int K, bool OUT64 = false>
 __device__ __forceinline__ void ytri_solve(const YArgs<T, U>& A, long q0, Cx<T>* tile);
 
 // Block `blk` of one grid's line-solve pass: blocks [0, zero_blocks(ny))
@@ -248,7 +253,7 @@ __device__ __forceinline__ void ytri_solve(const YArgs<T, U>& A, long q0, Cx<T>*
 // inverse z pass, which transforms all kz of one kx group per block and runs
 // its groups in descending order, then starts on the groups written last,
 // still in the Infinity Cache.  Every thread of the block calls it.
-template <typename T, typename U, int M, int P, int K>
+template <typename T, typename U, int M, int P, int K, bool OUT64 = false>
 __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& Z, long blk, Cx<T>* tile,
                                           bool kx_major = false) {
   constexpr int NT = M * P;
@@ -268,11 +273,14 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
   ytri_load<T, U, M, P, K>(A, q0, lm, row0, ld);
   ytri_stage<T, M, P, K>(A.ny, lm, row0, ld, tile);
   __syncthreads();
-  ytri_solve<T, U, M, P, K>(A, q0, tile);
+  ytri_solve<T, U, M, P, K, OUT64>(A, q0, tile);
 }
 
-// Solve of the staged columns q0 .. q0 + M - 1 and their stores.
-template <typename T, typename U, int M, int P, int K>
+// Solve of the staged columns q0 .. q0 + M - 1 and their stores.  OUT64:
+// the solution is written in FP64 to A.out64; `tile` is then the first half
+// of an LDS buffer of ytile_slots FP64 entries, re-used as their FP64 staging
+// once every lane has read its staged rows.
+template <typename T, typename U, int M, int P, int K, bool OUT64>
 __device__ __forceinline__ void ytri_solve(const YArgs<T, U>& A, long q0, Cx<T>* tile) {
   constexpr int PS = K * M + 1;   // LDS slots per partition
   const int ny = A.ny;
@@ -299,6 +307,7 @@ __device__ __forceinline__ void ytri_solve(const YArgs<T, U>& A, long q0, Cx<T>*
   Cx<U> d[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) d[i] = Cx<U>{U(my[i * M].x), U(my[i * M].y)};
+  if constexpr (OUT64) __syncthreads();   // the FP64 staging overwrites the FP32 slots
 #define IBP_COEF(i, a_, c_, l_) \
   const U a_ = ca[i];           \
   const U c_ = cc[i];           \
@@ -409,6 +418,26 @@ __device__ __forceinline__ void ytri_solve(const YArgs<T, U>& A, long q0, Cx<T>*
     }
   }
 #undef IBP_COEF
+  if constexpr (OUT64) {
+    Cx<double>* t64 = reinterpret_cast<Cx<double>*>(tile);
+    Cx<double>* my64 = t64 + p * PS + m;
+#pragma unroll
+    for (int i = 0; i < K; ++i) my64[i * M] = zero ? Cx<double>{0.0, 0.0} : Cx<double>{double(d[i].x), double(d[i].y)};
+    __syncthreads();
+    const int mm = threadIdx.x % M, row0 = threadIdx.x / M;
+    const long qs = q0 + mm;
+    const long kz = qs / A.rs, kx = qs - kz * A.rs;
+    if (qs < Q && kx < A.hp) {
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const int row = row0 + P * i;
+        const int pp = row / K;
+        const Cx<double> v = t64[pp * PS + (row - pp * K) * M + mm];
+        if (row < ny) gst(gbl(A.out64) + (long)row * A.out_ps + kz * A.out_rs + kx, v);
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < K; ++i) my[i * M] = zero ? Cx<T>{T(0), T(0)} : Cx<T>{T(d[i].x), T(d[i].y)};
   __syncthreads();
@@ -443,6 +472,12 @@ void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
   ytri_body<T, U, M, P, K>(A, Z, blockIdx.x, tile, sizeof(T) == 8);
 }
 
+template <int M, int P, int K>
+__global__ __launch_bounds__(M * P) void k_ytri_out64(YArgs<float, double> A, ZeroArgs Z) {
+  __shared__ Cx<double> tile[ytile_slots<M, P, K>()];
+  ytri_body<float, double, M, P, K, true>(A, Z, blockIdx.x, reinterpret_cast<Cx<float>*>(tile), false);
+}
+
 // ---------------------------------------------------------------- control
 // Convergence test of a refinement pass (one block): reduce the partials of
 // the residual pass, record ||r||/||f - m||, and either stop the refinement or
@@ -453,22 +488,36 @@ __device__ __forceinline__ void check_body(const ZeroArgs& Z, double* sh) {
   reduce_parts<kThreads>(Z, sh, p);
   if (threadIdx.x != 0) return;
   Ctl* c = Z.ctl;
-  double rel;
-  if (p[1] > 0.0)
-    rel = sqrt(p[0] / p[1]);
-  else
-    rel = (p[0] == 0.0) ? 0.0 : __builtin_inf();
+  auto ratio = [](double num2, double den2) {
+    if (den2 > 0.0) return sqrt(num2 / den2);
+    return num2 == 0.0 ? 0.0 : __builtin_inf();
+  };
+  const double rel = ratio(p[0], p[1]);
+  // normwise backward error: ||r||_inf / (||L_h||_inf ||phi||_inf + ||f - m||_inf)
+  const double den = Z.lnorm * p[7] + p[8];
+  const double eta = den > 0.0 ? p[2] / den : (p[2] == 0.0 ? 0.0 : __builtin_inf());
   c->rnorm2 = p[0];
   c->fnorm2 = p[1];
   c->rmax = p[2];
   c->rel_residual = rel;
+  c->rel_residual_vw = ratio(p[5], p[6]);
+  c->backward_error = eta;
+  // the residual of the iterate after iter - 1 corrections
+  if (Z.iter - 1 < kHistMax) c->hist[Z.iter - 1] = rel;
+  c->nhist = Z.iter < kHistMax ? Z.iter : kHistMax;
   // the mean of a Neumann-Neumann iterate is fixed to zero; with a
   // Dirichlet wall the solution's mean is part of it
   c->phimean = Z.singular ? p[4] / (Z.dyf_sum * double(Z.nx) * double(Z.nz)) : 0.0;
   if (p[3] > 0.0) c->nonfinite = 1;
-  if (Z.final_pass || !(rel > Z.rtol)) {
+  if (rel <= Z.rtol) {
     c->done = 1;
-    c->converged = (rel <= Z.rtol) ? 1 : 0;
+    c->converged = 1;
+  } else if (eta <= kEtaFloor) {   // at the FP64 floor: corrections cannot lower the residual
+    c->done = 1;
+    c->converged = 2;
+  } else if (Z.final_pass || !(rel > Z.rtol)) {   // last pass, or a NaN residual
+    c->done = 1;
+    c->converged = 0;
   } else {
     c->iters = Z.iter;
     c->scale[(Z.iter + 1) & 1] = next_scale(p[2]);
@@ -573,6 +622,49 @@ hipError_t launch_ytri(int P, int K, int want, const YArgs<T, U>& a, const ZeroA
       default: return hipErrorInvalidValue;
     }
   }
+  return hipErrorInvalidValue;
+}
+
+// FP32 in, FP64 out: the FP64 line solve's columns per block (128-byte
+// output segments, the same LDS tile)
+template <int M, int P>
+static hipError_t launch_out64_mp(int K, const YArgs<float, double>& a, const ZeroArgs& z, hipStream_t s) {
+  auto go = [&](auto kk) {
+    constexpr int KK = decltype(kk)::value;
+    // only tiles within the LDS budget are instantiated
+    if constexpr (ytile_slots<M, P, KK>() * (long)sizeof(Cx<double>) <= kYTileBytes) {
+      const long nb = (a.Q + M - 1) / M + zero_blocks(a.ny);
+      hipLaunchKernelGGL((k_ytri_out64<M, P, KK>), dim3((unsigned)nb), dim3(M * P), 0, s, a, z);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  };
+  if constexpr (P == 32) {
+    switch (K) {
+      case 2: return go(std::integral_constant<int, 2>{});
+      case 4: return go(std::integral_constant<int, 4>{});
+      case 8: return go(std::integral_constant<int, 8>{});
+      case 12: return go(std::integral_constant<int, 12>{});
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (K) {
+      case 8: return go(std::integral_constant<int, 8>{});
+      case 12: return go(std::integral_constant<int, 12>{});
+      case 16: return go(std::integral_constant<int, 16>{});
+      case 24: return go(std::integral_constant<int, 24>{});
+      default: return hipErrorInvalidValue;
+    }
+  }
+}
+
+hipError_t launch_ytri_out64(int P, int K, const YArgs<float, double>& a, const ZeroArgs& z, hipStream_t s) {
+  int M = 8;
+  while (M > 2 && ytile_slots_host(M, P, K) * (long)sizeof(Cx<double>) > kYTileBytes) M /= 2;
+  if (P == 32 && M == 8) return launch_out64_mp<8, 32>(K, a, z, s);
+  if (P == 64 && M == 8) return launch_out64_mp<8, 64>(K, a, z, s);
+  if (P == 64 && M == 4) return launch_out64_mp<4, 64>(K, a, z, s);
   return hipErrorInvalidValue;
 }
 

@@ -10,8 +10,8 @@ first call raises: there is no fallback implementation.
 import ctypes
 import os
 
-FP64, MIXED, MIXED_F64SWEEP = 0, 1, 2
-PRECISIONS = {"fp64": FP64, "mixed": MIXED, "mixed_f64sweep": MIXED_F64SWEEP}
+FP64, MIXED, MIXED_F64SWEEP, MIXED_F64INV = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "mixed": MIXED, "mixed_f64sweep": MIXED_F64SWEEP, "mixed_f64inv": MIXED_F64INV}
 LOCATIONS = {"cells": 0, "yfaces": 1}   # ibp_location_t
 
 SUCCESS, INVALID_VALUE, UNSUPPORTED_SIZE, OUT_OF_MEMORY, HIP_ERROR, INTERNAL = range(6)
@@ -27,14 +27,23 @@ class IbpError(RuntimeError):
         super().__init__(f"{what}: {status_string(status)} ({status})")
 
 
+HISTORY_MAX = 16
+
+
 class Info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int),
                 ("nonfinite_input", ctypes.c_int), ("reserved", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("removed_mean", ctypes.c_double),
-                ("rhs_norm", ctypes.c_double), ("residual_norm", ctypes.c_double)]
+                ("rhs_norm", ctypes.c_double), ("residual_norm", ctypes.c_double),
+                ("rel_residual_vw", ctypes.c_double), ("backward_error", ctypes.c_double),
+                ("history_len", ctypes.c_int), ("reserved2", ctypes.c_int),
+                ("residual_history", ctypes.c_double * HISTORY_MAX)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        d = {name: getattr(self, name) for name, _ in self._fields_
+             if name not in ("reserved", "reserved2", "residual_history", "history_len")}
+        d["residual_history"] = [float(self.residual_history[k]) for k in range(self.history_len)]
+        return d
 
 
 class PassStat(ctypes.Structure):

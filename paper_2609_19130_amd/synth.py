@@ -164,6 +164,15 @@ def kolmogorov_velocity_device(nx, ny, nz, seed, kmax=64, device="cuda"):
     return u, v, w
 
 
+def kolmogorov_scalar_device(nx, ny, nz, seed, kmax=64, device="cuda"):
+    """One scalar field [ny][nz][nx] with the same k^(-5/3) recipe, drawn on
+    the GPU (torch.Generator seeded with `seed`); unit RMS, not mean-free."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    return _spectral_scalar_device((ny, nz, nx), gen, kmax, device)
+
+
 def ar1_schedule(seed, steps, nx, nz, bank=4):
     """Per-step innovation draws for an AR(1) sequence of right-hand sides:
     step t uses bank member t mod `bank`, rolled by (dz, dx) planes/columns

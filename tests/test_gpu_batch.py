@@ -12,6 +12,7 @@ from paper_2609_19130_amd import ibpoisson as ibp
 from paper_2609_19130_amd import synth
 
 from gpu_helpers import rel, require_gpu, to_dev
+from test_gpu_parity import TOL_MIXED_VS_FP64, residual
 
 pytestmark = pytest.mark.gpu
 
@@ -127,6 +128,9 @@ def test_batch_object_graph_and_ycols(c4):
 
 
 def test_batched_mixed_converges_per_grid():
+    """Every grid of a mixed batch: converged, its residual recomputed here
+    with the oracle's operator (<= 1e-10 and equal to the reported one), and
+    its solution against the oracle within the mixed error bound."""
     grids, plans, rhs, fs = batch_case(count=24, seed=9, precision="mixed", max_iters=6)
     phis = [torch.empty_like(r) for r in rhs]
     ibp.solve_batched(plans, rhs, phis)
@@ -134,11 +138,14 @@ def test_batched_mixed_converges_per_grid():
     for i, p in enumerate(plans):
         info = p.info()
         assert info["converged"] == 1 and info["rel_residual"] <= 1e-10, (i, info)
-    for i in range(0, 24, 6):
         f, yf = fs[i]
         gd = grids[i]
+        phi = phis[i].cpu().numpy()
+        r = residual(f, phi, gd["Lx"], gd["Lz"], yf)
+        assert r <= 1e-10, (i, r)
+        assert abs(info["rel_residual"] - r) <= 0.05 * r + 1e-15, (i, r, info["rel_residual"])
         ref, _ = oracle.solve(f, gd["Lx"], gd["Lz"], yf)
-        assert rel(phis[i].cpu().numpy(), ref) <= 1e-8, (i, gd)
+        assert rel(phi, ref) <= TOL_MIXED_VS_FP64, (i, gd, rel(phi, ref), r)
 
 
 def test_batched_more_than_max_and_stale_batch():

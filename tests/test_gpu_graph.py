@@ -23,7 +23,7 @@ def _gpu():
     require_gpu()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_f64inv"])
 @pytest.mark.parametrize("nx,ny,nz", [(64, 33, 64), (48, 20, 40)])
 def test_graph_replay_matches_eager(precision, nx, ny, nz):
     """A captured solve replayed on new inputs (written into the captured rhs
@@ -51,11 +51,11 @@ def test_graph_replay_matches_eager(precision, nx, ny, nz):
         torch.cuda.synchronize()
         assert torch.equal(phi, expect), f"replay {k}"
         del other
-    if precision == "mixed":
+    if precision != "fp64":
         assert cap.info()["converged"] == 1
 
 
-C5 = dict(nx=1024, ny=768, nz=1024, beta=3.0, seed=5, bank=4, steps=3)
+C5 = dict(nx=1024, ny=768, nz=1024, beta=3.0, seed=5, bank=4, steps=100)
 
 
 @pytest.fixture(scope="module")
@@ -75,10 +75,11 @@ def c5_bank():
 
 
 def test_c5_graph_sequence(c5_bank):
-    """Three AR(1) steps captured as one graph (advance the rhs, solve), FP64
-    and mixed: graph replay is bitwise the eager sequence; the final mixed
-    solution is within 1e-10 of the FP64 one; the final FP64 solution
-    matches the oracle's 1-D solves on sampled modes."""
+    """The benchmark's sequence of 100 AR(1) steps captured as one graph
+    (advance the rhs, solve), FP64 and mixed: graph replay is bitwise the
+    eager sequence; the final mixed solution is within 1e-10 of the FP64 one;
+    the final FP64 solution matches the oracle's 1-D solves on sampled
+    modes."""
     yf, bank = c5_bank
     nx, ny, nz = C5["nx"], C5["ny"], C5["nz"]
     Lx = Lz = 2 * np.pi
@@ -128,3 +129,79 @@ def test_c5_graph_sequence(c5_bank):
     assert d <= 1e-10, d
     modes = [(0, 0), (1, 0), (0, 1), (5, 1000), (64, 3), (300, 200)]
     assert sampled_modes(fh, p64.cpu().numpy(), Lx, Lz, yf, modes) <= 1e-11
+
+
+def residual_torch(f, phi, Lx, Lz, yf):
+    """||f - m - L_h phi|| / ||f - m|| on the GPU with plain torch float64
+    array operations (the oracle's stencil: periodic second differences in x
+    and z, the difference of the two face fluxes in y, no wall flux), for
+    grids too large for a CPU pass within a test's time."""
+    ny = phi.shape[0]
+    yf = np.asarray(yf, dtype=np.float64)
+    dyf = np.diff(yf)
+    yc = 0.5 * (yf[1:] + yf[:-1])
+    a = np.zeros(ny)
+    c = np.zeros(ny)
+    a[1:] = 1.0 / (dyf[1:] * (yc[1:] - yc[:-1]))
+    c[:-1] = 1.0 / (dyf[:-1] * (yc[1:] - yc[:-1]))
+    dx, dz = Lx / phi.shape[2], Lz / phi.shape[1]
+    w = torch.from_numpy(dyf).to(phi.device).view(-1, 1, 1)
+    m = float((f * w).sum() / (w.sum() * phi.shape[1] * phi.shape[2]))
+    num = 0.0
+    den = 0.0
+    for j in range(ny):   # plane by plane keeps the temporaries small
+        p = phi[j]
+        lap = (torch.roll(p, -1, 1) - 2 * p + torch.roll(p, 1, 1)) / (dx * dx)
+        lap += (torch.roll(p, -1, 0) - 2 * p + torch.roll(p, 1, 0)) / (dz * dz)
+        if j > 0:
+            lap += a[j] * (phi[j - 1] - p)
+        if j < ny - 1:
+            lap += c[j] * (phi[j + 1] - p)
+        r = (f[j] - m) - lap
+        num += float((r * r).sum())
+        den += float(((f[j] - m) ** 2).sum())
+    return (num / den) ** 0.5
+
+
+def test_c5_scalar_field_innovations():
+    """The paper-scale share with the innovations read literally: an AR(1)
+    blend (rho 0.95) of four scalar k^-5/3 fields (rolled, sign-flipped),
+    not of divergences.  On this input (beta = 3, ny = 768) the FP64 direct
+    solve's own relative residual is ~1e-8: a 1e-10 residual target is below
+    the FP64 floor.  Accepted when the mixed form stops at that floor
+    (converged = 1 or 2, backward error <= 8 unit roundoffs), its residual is
+    at most max(1e-10, 2 x the FP64 solve's residual), and its solution is
+    within 1e-10 of the FP64 one; the FP64 solution also matches the
+    oracle's 1-D solves on sampled modes."""
+    nx, ny, nz, beta, seed = C5["nx"], C5["ny"], C5["nz"], C5["beta"], C5["seed"]
+    Lx = Lz = 2 * np.pi
+    yf = synth.tanh_faces(ny, beta)
+    bank = [synth.kolmogorov_scalar_device(nx, ny, nz, seed=7000 + b) for b in range(C5["bank"])]
+    steps = 4
+    sched = synth.ar1_schedule(seed + 1, steps, nx, nz, C5["bank"])
+    f = bank[0] * sched[0][3]
+    gbuf = torch.empty_like(f)
+    for t in range(1, steps):
+        synth.ar1_advance(f, gbuf, bank, sched[t])
+    del bank, gbuf
+    torch.cuda.empty_cache()
+    plan = ibp.Plan(nx, ny, nz, Lx, Lz, yf)
+    phi64 = plan.solve(f)
+    plan.set_precision("mixed", 1e-10, 8)
+    phim = plan.solve(f)
+    info = plan.info()
+    torch.cuda.synchronize()
+    d = float(torch.linalg.vector_norm(phim - phi64) / torch.linalg.vector_norm(phi64))
+    r64 = residual_torch(f, phi64, Lx, Lz, yf)
+    rm = residual_torch(f, phim, Lx, Lz, yf)
+    print(f"c5 scalar: fp64 residual {r64:.3e}, mixed residual {rm:.3e} (reported {info['rel_residual']:.3e}), "
+          f"mixed vs fp64 {d:.3e}, info {info}")
+    assert info["converged"] in (1, 2), info
+    assert info["backward_error"] <= 8 * 2.0 ** -53 or info["rel_residual"] <= 1e-10, info
+    assert abs(info["rel_residual"] - rm) <= 0.05 * rm, (rm, info)
+    assert rm <= max(1e-10, 2 * r64), (rm, r64)
+    assert d <= 1e-10, d
+    fh = f.cpu().numpy()
+    modes = [(0, 0), (1, 0), (0, 1), (3, 2), (64, 3), (300, 200)]
+    assert sampled_modes(fh, phi64.cpu().numpy(), Lx, Lz, yf, modes) <= 1e-11
+    plan.close()

@@ -37,6 +37,22 @@ def residual(f, phi, Lx, Lz, yf):
     return float(np.linalg.norm(r.ravel()) / np.linalg.norm((f - m).ravel()))
 
 
+def residual_vw_and_eta(f, phi, Lx, Lz, yf):
+    """Volume-weighted relative residual ||V r|| / ||V (f - m)|| and the
+    normwise backward error ||r||_inf / (||L_h||_inf ||phi||_inf + ||f - m||_inf),
+    with the oracle's operator; ||L_h||_inf is the largest absolute row sum
+    of the stencil, 4/dx^2 + 4/dz^2 + max_j 2 (a_j + c_j)."""
+    ny, nz, nx = f.shape
+    g = geometry(nx, ny, nz, Lx, Lz, yf)
+    m = weighted_mean(f, g)
+    r = (f - m) - laplacian(phi, g)
+    w = g.dyf.reshape(-1, 1, 1)
+    rvw = float(np.linalg.norm((w * r).ravel()) / np.linalg.norm((w * (f - m)).ravel()))
+    lnorm = (4 / g.dx ** 2 if nx > 1 else 0.0) + (4 / g.dz ** 2 if nz > 1 else 0.0) + float(np.max(2 * (g.a + g.c)))
+    eta = float(np.abs(r).max() / (lnorm * np.abs(phi).max() + np.abs(f - m).max()))
+    return rvw, eta
+
+
 # ---------------------------------------------------------------- FP64 parity
 SHAPES = [  # (nx, ny, nz, beta): several tiles, ragged tails, every radix
     (2, 2, 1, 1.0), (4, 3, 2, 2.0), (6, 5, 3, 2.0), (8, 7, 5, 2.5), (12, 9, 6, 3.0),
@@ -50,8 +66,18 @@ SHAPES = [  # (nx, ny, nz, beta): several tiles, ragged tails, every radix
     (32, 5, 32, 2.0), (64, 19, 64, 2.5), (128, 40, 128, 2.0), (256, 11, 256, 3.0),
 ]
 
+# every line-solve shape the dispatcher picks (lanes x rows per lane): 32 x 12
+# for 257 <= ny <= 384 (the 512x384x512 benchmark's instance, FP64 8 and FP32
+# 16 columns per block), 64 x 12 for 513..768 (the 1024x768x1024 one), 64 x 16
+# and 64 x 24 up to the 1536-row limit, each at the bottom and the top of its
+# range
+LINE_SHAPES = [
+    (64, 300, 48, 2.0), (48, 384, 40, 2.5), (32, 600, 16, 3.0), (16, 768, 24, 2.0),
+    (12, 1024, 10, 2.0), (10, 1100, 6, 3.0), (8, 1536, 4, 2.0),
+]
 
-@pytest.mark.parametrize("nx,ny,nz,beta", SHAPES)
+
+@pytest.mark.parametrize("nx,ny,nz,beta", SHAPES + LINE_SHAPES)
 def test_fp64_matches_oracle(nx, ny, nz, beta):
     rng = np.random.default_rng(nx * 1000 + ny * 10 + nz)
     Lx, Lz = 2 * np.pi, 1.7
@@ -200,8 +226,24 @@ def test_nonfinite_input_flagged():
 
 
 # ---------------------------------------------------------------- mixed forms
-@pytest.mark.parametrize("precision", ["mixed", "mixed_f64sweep"])
-@pytest.mark.parametrize("nx,ny,nz,beta", [(64, 64, 64, 2.0), (40, 100, 14, 3.0), (176, 33, 30, 2.5)])
+# Mixed against FP64 at the same input: the refinement's target is the
+# residual (<= 1e-10); the error it leaves depends on where the residual sits
+# in the spectrum.  Read as for the paper-scale sequence, mixed agrees with
+# FP64 to 1e-10 relative.  Measured on MI355X: at most 6.7e-11 (32x600x16,
+# beta 3, the most stretched small grid), 2.8e-15 to 6.3e-15 at 512x384x512,
+# where the FP64 tolerance 1e-12 is held as well.
+TOL_MIXED_VS_FP64 = 1e-10
+TOL_MIXED_VS_FP64_C3 = 1e-12
+
+
+MIXED_FORMS = ["mixed", "mixed_f64sweep", "mixed_f64inv"]
+
+
+@pytest.mark.parametrize("precision", MIXED_FORMS)
+@pytest.mark.parametrize("nx,ny,nz,beta", [(64, 64, 64, 2.0), (40, 100, 14, 3.0), (176, 33, 30, 2.5),
+                                           (96, 40, 1, 2.0), (26, 50, 22, 2.0), (30, 60, 263, 2.0),
+                                           (64, 300, 48, 2.0), (48, 384, 40, 2.5), (32, 600, 16, 3.0),
+                                           (16, 768, 24, 2.0)])
 def test_mixed_refinement(precision, nx, ny, nz, beta):
     Lx = Lz = 2 * np.pi
     yf = synth.tanh_faces(ny, beta)
@@ -214,13 +256,20 @@ def test_mixed_refinement(precision, nx, ny, nz, beta):
     assert r <= RTOL_MIXED, (r, info)
     assert abs(info["rel_residual"] - r) <= 0.05 * r + 1e-14
     assert 1 <= info["iterations"] <= 6
-    # the criterion is the residual; the error it implies depends on the
-    # conditioning of the grid, so the error is only sanity-bounded here
+    assert len(info["residual_history"]) == info["iterations"] + 1
+    assert abs(info["residual_history"][-1] - info["rel_residual"]) <= 1e-15 + 1e-12 * r
+    rvw, eta = residual_vw_and_eta(f, phi, Lx, Lz, yf)
+    assert abs(info["rel_residual_vw"] - rvw) <= 0.05 * rvw + 1e-15, (info["rel_residual_vw"], rvw)
+    assert abs(info["backward_error"] - eta) <= 0.05 * eta + 1e-18, (info["backward_error"], eta)
     ref, _ = oracle.solve(f, Lx, Lz, yf)
-    assert rel(phi, ref) <= 1e-8
+    phi64, _ = gpu_solve(f, Lx, Lz, yf)
+    print(f"mixed vs fp64 {rel(phi, phi64):.3e}, vs oracle {rel(phi, ref):.3e}, residual {r:.3e}, "
+          f"history {info['residual_history']}")
+    assert rel(phi, phi64) <= TOL_MIXED_VS_FP64, rel(phi, phi64)
+    assert rel(phi, ref) <= TOL_MIXED_VS_FP64
 
 
-@pytest.mark.parametrize("precision", ["mixed", "mixed_f64sweep"])
+@pytest.mark.parametrize("precision", MIXED_FORMS)
 def test_mixed_tight_rtol_reaches_fp64_accuracy(precision):
     nx, ny, nz = 176, 33, 30
     Lx = Lz = 2 * np.pi
@@ -232,6 +281,11 @@ def test_mixed_tight_rtol_reaches_fp64_accuracy(precision):
     ref, _ = oracle.solve(f, Lx, Lz, yf)
     assert info["rel_residual"] <= 1e-13, info
     assert rel(phi, ref) <= 1e-11
+    # below the FP64 floor of this grid the refinement stops there (backward
+    # error <= 8 unit roundoffs) instead of running to max_iters
+    assert info["converged"] in (1, 2) and info["iterations"] < 8, info
+    if info["converged"] == 2:
+        assert info["backward_error"] <= 8 * 2.0 ** -53
 
 
 def test_mixed_rejects_aliasing():
@@ -309,17 +363,35 @@ MODES = [(0, 0), (1, 0), (0, 1), (1, 1), (3, 7), (40, 5), (7, 500), (64, 0), (17
 
 
 def test_c3_fullsize_fp64_and_mixed(c3_case):
+    """512 x 384 x 512 in the benchmark's launch configuration (its line solve
+    is the 32-lane, 12-row instance): the whole FP64 field against the
+    oracle's full solve, each sampled mode against the oracle's 1-D solve,
+    and both mixed forms' residuals recomputed here."""
     f, Lx, Lz, yf = c3_case
     ny, nz, nx = f.shape
+    ref, m = oracle.solve(f, Lx, Lz, yf)
     plan = ibp.Plan(nx, ny, nz, Lx, Lz, yf)
     fd = to_dev(f)
     phi64 = plan.solve(fd)
+    info64 = plan.info()
     p64 = phi64.cpu().numpy()
+    err64 = rel(p64, ref)
+    print(f"c3 fp64 vs oracle {err64:.3e}")
+    assert err64 <= TOL64, err64
+    assert abs(info64["removed_mean"] - m) <= 1e-14 * max(1.0, abs(m))
     assert sampled_modes(f, p64, Lx, Lz, yf, MODES) <= 1e-11
-    plan.set_precision("mixed", RTOL_MIXED, 6)
-    phim = plan.solve(fd)
-    info = plan.info()
-    pm = phim.cpu().numpy()
-    r = residual(f, pm, Lx, Lz, yf)
-    assert info["converged"] == 1 and r <= RTOL_MIXED, (r, info)
-    assert rel(pm, p64) <= 1e-8   # error <= condition x residual: a sanity bound, as for the small mixed cases
+    for form in MIXED_FORMS:
+        plan.set_precision(form, RTOL_MIXED, 6)
+        phim = plan.solve(fd)
+        info = plan.info()
+        pm = phim.cpu().numpy()
+        r = residual(f, pm, Lx, Lz, yf)
+        d = rel(pm, p64)
+        print(f"c3 {form}: residual {r:.3e} (reported {info['rel_residual']:.3e}), vs fp64 {d:.3e}, "
+              f"vs oracle {rel(pm, ref):.3e}, history {info['residual_history']}")
+        assert info["converged"] == 1 and r <= RTOL_MIXED, (r, info)
+        assert abs(info["rel_residual"] - r) <= 0.05 * r + 1e-15
+        assert d <= TOL_MIXED_VS_FP64_C3, d
+        assert rel(pm, ref) <= TOL_MIXED_VS_FP64_C3
+        if form == "mixed_f64inv":   # FP64 inverse passes: one correction reaches 1e-10 here
+            assert info["iterations"] == 1, info

@@ -370,3 +370,15 @@ def _geom_dyf_mutant(g):
     c[:-1] = 1 / (g.dyf[:-1] * g.dyf[:-1])
     g.a, g.c, g.b = a, c, -(a + c)
     return g
+
+
+def test_threaded_fft_route_matches():
+    """The multi-threaded scipy.fft route of oracle.solve (used only to time
+    the oracle on many cores) gives the numpy route's solution."""
+    nx, ny, nz = 24, 13, 10
+    yf = synth.tanh_faces(ny, 2.0)
+    f = np.random.default_rng(17).standard_normal((ny, nz, nx))
+    a, ma = oracle.solve(f, 2.0, 1.5, yf)
+    b, mb = oracle.solve(f, 2.0, 1.5, yf, workers=4)
+    assert ma == mb
+    assert rel(b, a) <= 1e-14
