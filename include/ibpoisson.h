@@ -159,6 +159,23 @@ ibp_status_t ibp_plan_set_workspace(ibp_plan_t plan, void* device_ptr, size_t by
  * on the device the plan was created on. */
 ibp_status_t ibp_solve(ibp_plan_t plan, const double* rhs, double* phi, hipStream_t stream);
 
+/* ibp_solve for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid allocation):
+ * the same solve, but its workspace (half spectrum, row and plane sums, norm
+ * partials, control block) is a static device array of the library, 32 MiB
+ * per GPU, held from the library's first use of that GPU until the process
+ * ends, instead of the plan's own workspace.  Calls no hipMalloc, hipFree or
+ * other allocating routine (the array's address is looked up once per
+ * device).  Plans whose workspace (ibp_plan_workspace_size) exceeds 32 MiB
+ * return IBP_ERROR_UNSUPPORTED_SIZE: FP64 grids up to about 2 million
+ * half-spectrum coefficients, e.g. 128 x 128 x 128.  Every such call on one
+ * GPU uses the same array and leaves its contents there: calls that overlap
+ * on one GPU (two streams or threads) race, and ibp_get_info after this call
+ * reports the state the array holds, valid until the next such call on the
+ * GPU.  Always the separate-pass schedule, without per-pass profiling
+ * events.  Arguments, layout and errors as ibp_solve. */
+ibp_status_t ibp_solve_scratch(ibp_plan_t plan, const double* rhs, double* phi, hipStream_t stream);
+
 /* Solve `count` independent problems, problem i with plans[i], rhs[i],
  * phi[i] (each as in ibp_solve; HOST arrays of plans and device pointers).
  * The plans must be distinct (each owns its workspace).  All work is

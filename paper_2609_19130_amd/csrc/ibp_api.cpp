@@ -2144,3 +2144,113 @@ ibp_status_t ibp_batch_autotune(ibp_batch_t b, const double* const* rhs, double*
 }
 
 }  // extern "C"
+
+// ======================================================================
+// Solves that allocate nothing: the workspace comes from one static device
+// array per GPU (`scratch`, kScratchBytes) instead of the plan's own.  Its
+// device address is looked up once per device with hipGetSymbolAddress; the
+// array's name is only a host-side stand-in and is never handed to a kernel
+// or a copy.  Every such solve on one GPU shares the array: the last call's
+// contents stay there, and calls that overlap on one GPU (two streams, two
+// threads) race.
+namespace {
+
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (the device must be current).
+ibp_status_t scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return IBP_ERROR_INVALID_VALUE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return from_hip(e);
+    if (ptr == nullptr || (reinterpret_cast<uintptr_t>(ptr) & 255) != 0) return IBP_ERROR_INTERNAL;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return IBP_SUCCESS;
+}
+
+// The plan's workspace views, saved while a scratch solve borrows the plan.
+struct WorkspaceViews {
+  void* ws;
+  Cx<double>* spec64;
+  Cx<float>* spec32;
+  double *rowsum, *phi00, *ghat, *part;
+  int *ticket, *fctl;
+  Ctl* ctl;
+  bool fused, profiling;
+  int chunk;
+};
+
+WorkspaceViews save_views(const ibp_plan_s* p) {
+  return WorkspaceViews{p->ws,    p->spec64, p->spec32, p->rowsum, p->phi00,    p->ghat,  p->part,
+                        p->ticket, p->fctl,  p->ctl,    p->fused,  p->profiling, p->chunk};
+}
+
+void restore_views(ibp_plan_s* p, const WorkspaceViews& v) {
+  p->ws = v.ws;
+  p->spec64 = v.spec64;
+  p->spec32 = v.spec32;
+  p->rowsum = v.rowsum;
+  p->phi00 = v.phi00;
+  p->ghat = v.ghat;
+  p->part = v.part;
+  p->ticket = v.ticket;
+  p->fctl = v.fctl;
+  p->ctl = v.ctl;
+  p->fused = v.fused;
+  p->profiling = v.profiling;
+  p->chunk = v.chunk;
+}
+
+}  // namespace
+
+extern "C" {
+
+ibp_status_t ibp_solve_scratch(ibp_plan_t p, const double* rhs, double* phi, hipStream_t stream) {
+  if (!valid_plan(p) || rhs == nullptr || phi == nullptr) return IBP_ERROR_INVALID_VALUE;
+  if ((reinterpret_cast<uintptr_t>(rhs) & 15) != 0 || (reinterpret_cast<uintptr_t>(phi) & 15) != 0)
+    return IBP_ERROR_INVALID_VALUE;
+  const size_t n = (size_t)p->nx * p->ny * p->nz;
+  if (p->prec != IBP_FP64) {
+    const uintptr_t r0 = reinterpret_cast<uintptr_t>(rhs), r1 = r0 + n * sizeof(double);
+    const uintptr_t q0 = reinterpret_cast<uintptr_t>(phi), q1 = q0 + n * sizeof(double);
+    if (r0 < q1 && q0 < r1) return IBP_ERROR_INVALID_VALUE;
+  }
+  if (workspace_bytes(p) > kScratchBytes) return IBP_ERROR_UNSUPPORTED_SIZE;
+  try {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return from_hip(e);
+    if (dev != p->device) return IBP_ERROR_INVALID_VALUE;
+    void* base = nullptr;
+    ibp_status_t st = scratch_address(dev, &base);
+    if (st != IBP_SUCCESS) return st;
+    const WorkspaceViews saved = save_views(p);
+    p->ws = base;
+    carve_workspace(p);
+    // the separate-pass schedule (no fused-pass queues, no second stream)
+    // and no profiling events
+    p->fused = false;
+    p->chunk = 0;
+    p->profiling = false;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // the (0,0)-mode ticket starts every solve at zero (a fill kernel, not a
+    // memset node, so the call stays capturable)
+    e = launch_fill_zero(reinterpret_cast<double*>(p->ticket), 256 / sizeof(double), s);
+    st = e == hipSuccess ? enqueue_solve(p, rhs, phi, s, nullptr) : from_hip(e);
+    restore_views(p, saved);
+    return st;
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
+}
+
+}  // extern "C"

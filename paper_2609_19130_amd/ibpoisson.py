@@ -77,6 +77,7 @@ def lib():
         "ibp_plan_workspace_size": (ci, [vp, ctypes.POINTER(cs)]),
         "ibp_plan_set_workspace": (ci, [vp, vp, cs]),
         "ibp_solve": (ci, [vp, vp, vp, vp]),
+        "ibp_solve_scratch": (ci, [vp, vp, vp, vp]),
         "ibp_solve_batched": (ci, [ctypes.POINTER(vp), ci, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]),
         "ibp_get_info": (ci, [vp, ctypes.POINTER(Info)]),
         "ibp_divergence": (ci, [vp, vp, vp, vp, vp, vp]),
@@ -200,6 +201,14 @@ class Plan:
             phi = torch.empty(self.shape, dtype=torch.float64, device=rhs.device)
         p = _field(phi, self.shape, "phi")
         _check(lib().ibp_solve(self.handle, r, p, _stream_ptr(stream)), "ibp_solve")
+        return phi
+
+    def solve_scratch(self, rhs, phi, stream=None):
+        """Enqueue a solve whose workspace is the library's static per-GPU
+        array (ibp_solve_scratch; allocates nothing, phi must be given)."""
+        r = _field(rhs, self.shape, "rhs")
+        p = _field(phi, self.shape, "phi")
+        _check(lib().ibp_solve_scratch(self.handle, r, p, _stream_ptr(stream)), "ibp_solve_scratch")
         return phi
 
     def autotune(self, rhs, phi=None, stream=None):
