@@ -31,7 +31,8 @@ if ROOT not in sys.path:
 METRIC = "Poisson solves/s + HBM GB/s at 512x384x512, mixed vs FP64 at 1e-10 resid"
 HBM_PEAK_GBS = 8000.0
 SOURCES = ["ibp_api.cpp", "ibp_xz.hip", "ibp_xz_narrow.hip", "ibp_xz_kernels.hpp", "ibp_fastxz.hip", "ibp_ytri.hip",
-           "ibp_misc.hip", "ibp_lines.hip", "ibp_device.hpp", "ibp_internal.hpp", "ibp_regfft.hpp"]
+           "ibp_ytri_body.hpp", "ibp_misc.hip", "ibp_lines.hip", "ibp_persist.hip", "ibp_device.hpp",
+           "ibp_internal.hpp", "ibp_regfft.hpp"]
 
 
 def source_hash():
@@ -210,6 +211,21 @@ def run_c4(args):
         def batched():
             ibp.solve_batched(plans, fs, phis)
 
+        staged_b = ibp.Batch(plans)
+        staged_b.set_persistent(False)
+        persist_b = ibp.Batch(plans)
+        try:
+            persist_b.set_persistent(True)
+            has_persist = True
+        except ibp.IbpError:
+            has_persist = False
+
+        def staged():
+            staged_b.solve(fs, phis)
+
+        def persistent():
+            persist_b.solve(fs, phis)
+
         batch = ibp.Batch(plans)
         tune = batch.autotune(fs, phis)
         log(f"[bench c4] {form} autotuned batch: {tune}")
@@ -218,7 +234,11 @@ def run_c4(args):
             batch.solve(fs, phis)
 
         res = {"autotune": tune}
-        for name, fn in (("per_grid_loop", loop), ("batched", batched), ("batched_autotuned", tuned)):
+        variants = [("per_grid_loop", loop), ("batched", batched), ("batched_staged", staged)]
+        if has_persist:
+            variants.append(("batched_persistent", persistent))
+        variants.append(("batched_autotuned", tuned))
+        for name, fn in variants:
             for _ in range(args.warmup):
                 fn()
             torch.cuda.synchronize()
@@ -238,6 +258,8 @@ def run_c4(args):
         res["autotuned_vs_loop"] = res["per_grid_loop"]["ms_per_step"] / res["batched_autotuned"]["ms_per_step"]
         out[form] = res
         batch.close()
+        staged_b.close()
+        persist_b.close()
         for p in plans:
             p.close()
     if "fp64" in out:

@@ -222,6 +222,19 @@ ibp_status_t ibp_batch_solve(ibp_batch_t batch, const double* const* rhs, double
  * capped by the LDS budget).  Used by the batch autotuner. */
 ibp_status_t ibp_batch_set_ycols(ibp_batch_t batch, int cols);
 
+/* Schedule of the batch's solves.  1: the whole batched solve (every stage
+ * of every grid, and for IBP_MIXED every refinement pass) is one persistent
+ * launch: each grid is pinned to one XCD, whose blocks take the stages'
+ * blocks from a queue in dependency order and overlap the stages of
+ * different grids.  0 (the default): one launch per stage covering every
+ * grid, measured faster on MI355X for batches of 32..192-point grids.  The
+ * persistent schedule is available when every grid's x and z lines fit the
+ * small transform tiles (nx/2 and nz up to 1024) and the tallest grid has at
+ * most 384 rows (512 with 64-lane line solves of 8 rows); otherwise
+ * IBP_ERROR_UNSUPPORTED_SIZE for enable = 1.  ibp_batch_autotune times both.
+ * Results are bitwise the same under both. */
+ibp_status_t ibp_batch_set_persistent(ibp_batch_t batch, int enable);
+
 /* Free the batch's device table (the plans are untouched).  NULL accepted. */
 ibp_status_t ibp_batch_destroy(ibp_batch_t batch);
 
@@ -236,6 +249,10 @@ typedef struct {
   int tried;         /* configurations timed */
   double ms;         /* time of one solve with the chosen configuration (HIP events) */
   double ms_before;  /* time of one solve with the configuration in place before tuning */
+  int persistent;    /* batches: 1 = the persistent schedule was chosen (ibp_batch_set_persistent) */
+  int lag;           /* batches, persistent: diagonal interleave of the grids' stages in a queue */
+  int chunk;         /* batches, persistent: work items a block claims at once */
+  int reserved;
 } ibp_tune_t;
 
 /* Time solves of rhs into phi (device pointers as in ibp_solve; phi is

@@ -1645,6 +1645,15 @@ struct ibp_batch_s {
   std::vector<int> rbmax, zcmax;   // per grid: rows per block and z columns of the largest tile
   std::vector<BatchGrid<double>> h64;
   std::vector<BatchGrid<float>> h32;
+  // persistent schedule: the whole solve in one launch (ibp_persist.hip)
+  bool persist_ok = false;   // small tiles and a line-solve shape the persistent kernel is built for
+  bool persist = false;      // solve with it
+  bool wide = false;         // some grid needs the wide transform family
+  int persist_blocks = 0;    // blocks of the persistent launch
+  int lag = 1;               // diagonal interleave of the grids' stages in a queue
+  int smax = 0;              // stages per grid (counters per grid)
+  void* pmem = nullptr;      // segments | queue offsets | items per queue | claim heads | counters | exit count
+  PersistArgs pargs{};
 };
 
 namespace {
@@ -1655,6 +1664,9 @@ constexpr int kBatchDivMax = 4;   // finest x split the partial buffers are size
 // solve columns per block) to the per-grid arguments and prefix offsets and
 // upload them (synchronous).  The split changes which block does what, not
 // the arithmetic: results are bitwise the same for every split.
+template <typename T>
+hipError_t persist_schedule(ibp_batch_s* b, const std::vector<BatchGrid<T>>& hd);
+
 template <typename T>
 hipError_t batch_apply(ibp_batch_s* b, std::vector<BatchGrid<T>>& hd) {
   const int n = b->count;
@@ -1693,11 +1705,173 @@ hipError_t batch_apply(ibp_batch_s* b, std::vector<BatchGrid<T>>& hd) {
   hipError_t e = hipMemcpy(b->desc, hd.data(), n * sizeof(BatchGrid<T>), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(b->start, b->hstart.data(), b->hstart.size() * sizeof(long), hipMemcpyHostToDevice);
+  if (e == hipSuccess && b->persist_ok) e = persist_schedule<T>(b, hd);
+  return e;
+}
+
+// The per-XCD work queues of the persistent schedule for the current work
+// split.  Stages of one grid run in order, each waiting for the previous
+// one to complete; a grid's stages all go to one queue (grids dealt to the
+// queues by decreasing size, each to the least loaded).  In a queue the
+// segments follow diagonals: stage s of the i-th grid has key s + lag i.
+template <typename T>
+hipError_t persist_schedule(ibp_batch_s* b, const std::vector<BatchGrid<T>>& hd) {
+  const int n = b->count;
+  const bool mixed = b->prec == IBP_MIXED;
+  const int M = kThreads / b->yP;
+  struct St {
+    int kind, iter, flags;
+    long count;
+  };
+  std::vector<std::vector<St>> stages(n);
+  std::vector<double> work(n, 0.0);
+  for (int g = 0; g < n; ++g) {
+    const BatchGrid<T>& d = hd[g];
+    const long nxb = (d.x.nrows + d.x.rows_per_block - 1) / d.x.rows_per_block;
+    const long nzb = d.z.nz > 1 ? (long)d.zcolblocks * d.y.ny : 0;
+    const long nyb = (d.y.Q + M - 1) / M + zero_blocks(d.y.ny);
+    const int yk = d.yk == b->yK ? PK_Y0 : (d.yk == b->yK / 2 ? PK_Y1 : PK_Y2);
+    auto& v = stages[g];
+    v.push_back({PK_XR2C, 0, 0, nxb});
+    v.push_back({PK_ZF, 0, 0, nzb});
+    v.push_back({yk, 0, PF_INIT, nyb});
+    v.push_back({PK_ZI, 0, 0, nzb});
+    v.push_back({PK_XC2R, 0, 0, nxb});
+    if (mixed) {
+      for (int k = 1; k <= b->max_iters; ++k) {
+        v.push_back({PK_XRES, k, 0, nxb});
+        v.push_back({PK_CHECK, k, 0, 1});
+        v.push_back({PK_ZF, k, PF_CHECK_DONE, nzb});
+        v.push_back({yk, k, PF_CHECK_DONE, nyb});
+        v.push_back({PK_ZI, k, PF_CHECK_DONE, nzb});
+        v.push_back({PK_XC2R_ADD, k, 0, nxb});
+      }
+      v.push_back({PK_XRESONLY, b->max_iters + 1, 0, nxb});
+      v.push_back({PK_CHECK, b->max_iters + 1, PF_FINAL, 1});
+    }
+    v.erase(std::remove_if(v.begin(), v.end(), [](const St& x) { return x.count == 0; }), v.end());
+    work[g] = (double)b->plans[g]->nx * b->plans[g]->ny * b->plans[g]->nz;
+  }
+  const int nq = b->pargs.nq;
+  std::vector<int> order(n);
+  for (int g = 0; g < n; ++g) order[g] = g;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return work[a] > work[c]; });
+  std::vector<std::vector<int>> qgrids(nq);
+  std::vector<double> load(nq, 0.0);
+  for (int g : order) {
+    const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    qgrids[q].push_back(g);
+    load[q] += work[g];
+  }
+  std::vector<PersistSeg> segs;
+  std::vector<int> qseg(nq + 1, 0);
+  std::vector<long> qitems(nq, 0);
+  for (int q = 0; q < nq; ++q) {
+    qseg[q] = (int)segs.size();
+    struct Key {
+      int key, pos, stage;
+    };
+    std::vector<Key> keys;
+    for (int i = 0; i < (int)qgrids[q].size(); ++i)
+      for (int st = 0; st < (int)stages[qgrids[q][i]].size(); ++st) keys.push_back({st + b->lag * i, i, st});
+    std::stable_sort(keys.begin(), keys.end(),
+                     [](const Key& a, const Key& c) { return a.key != c.key ? a.key < c.key : a.pos < c.pos; });
+    long first = 0;
+    for (const Key& k : keys) {
+      const int g = qgrids[q][k.pos];
+      const St& x = stages[g][k.stage];
+      PersistSeg sg{};
+      sg.first = first;
+      sg.g = g;
+      sg.kind = x.kind;
+      sg.iter = x.iter;
+      sg.flags = x.flags;
+      sg.done = g * b->smax + k.stage;
+      sg.dep = k.stage > 0 ? g * b->smax + k.stage - 1 : -1;
+      sg.need = k.stage > 0 ? (int)stages[g][k.stage - 1].count : 0;
+      segs.push_back(sg);
+      first += x.count;
+    }
+    qitems[q] = first;
+  }
+  qseg[nq] = (int)segs.size();
+  // device layout: segments | qseg | qitems (sized for the largest schedule at build)
+  char* base = static_cast<char*>(b->pmem);
+  const size_t o_qseg = align256((size_t)b->count * b->smax * sizeof(PersistSeg));
+  const size_t o_qitems = o_qseg + align256((kMaxXcc + 1) * sizeof(int));
+  hipError_t e = hipMemcpy(base, segs.data(), segs.size() * sizeof(PersistSeg), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(base + o_qseg, qseg.data(), qseg.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(base + o_qitems, qitems.data(), qitems.size() * sizeof(long), hipMemcpyHostToDevice);
   return e;
 }
 
 hipError_t batch_reapply(ibp_batch_s* b) {
   return b->prec == IBP_FP64 ? batch_apply<double>(b, b->h64) : batch_apply<float>(b, b->h32);
+}
+
+// Persistent schedule of a batch: available when every grid fits the small
+// transform tiles and the line-solve shape is one the persistent kernel is
+// built for (off with IBP_PERSIST=0).  Allocates the queue tables and the
+// counters (zeroed here; each launch re-arms them before it ends) and sizes
+// the launch to the resident blocks of the device.
+template <typename T>
+hipError_t persist_setup(ibp_batch_s* b) {
+  b->wide = false;
+  for (ibp_plan_t p : b->plans) b->wide = b->wide || p->xwide || p->zwide;
+  b->persist_ok = b->xsmall && b->zsmall && persist_shape_supported(b->yP, b->yK);
+  if (const char* e = getenv("IBP_PERSIST")) b->persist_ok = b->persist_ok && atoi(e) != 0;
+  b->persist = false;
+  if (!b->persist_ok) return hipSuccess;
+  XccMap m;
+  hipError_t e = xcc_map(b->device, &m);
+  if (e != hipSuccess) return e;
+  if (m.nq < 1 || m.nq > kMaxXcc) {
+    b->persist_ok = false;
+    return hipSuccess;
+  }
+  int per_cu = 0, ncu = 0;
+  e = persist_blocks_per_cu<T>(b->wide, b->yP, b->yK, &per_cu);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1 || ncu < 1) {
+    b->persist_ok = false;
+    return hipSuccess;
+  }
+  b->persist_blocks = std::max(m.nq, (per_cu * ncu) / m.nq * m.nq);
+  const bool mixed = b->prec == IBP_MIXED;
+  b->smax = 5 + (mixed ? 6 * b->max_iters + 2 : 0);
+  const size_t nseg = (size_t)b->count * b->smax;
+  const size_t o_qseg = align256(nseg * sizeof(PersistSeg));
+  const size_t o_qitems = o_qseg + align256((kMaxXcc + 1) * sizeof(int));
+  const size_t o_head = o_qitems + align256(kMaxXcc * sizeof(long));
+  const size_t o_cnt = o_head + align256(kMaxXcc * sizeof(int));
+  const size_t o_exit = o_cnt + align256(nseg * sizeof(int));
+  const size_t bytes = o_exit + align256(sizeof(int));
+  e = hipMalloc(&b->pmem, bytes);
+  if (e == hipSuccess) e = hipMemset(b->pmem, 0, bytes);
+  if (e != hipSuccess) return e;
+  char* base = static_cast<char*>(b->pmem);
+  PersistArgs& a = b->pargs;
+  a = PersistArgs{};
+  a.grids = b->desc;
+  a.seg = reinterpret_cast<const PersistSeg*>(base);
+  a.qseg = reinterpret_cast<const int*>(base + o_qseg);
+  a.qitems = reinterpret_cast<const long*>(base + o_qitems);
+  a.head = reinterpret_cast<int*>(base + o_head);
+  a.cnt = reinterpret_cast<int*>(base + o_cnt);
+  a.exit_count = reinterpret_cast<int*>(base + o_exit);
+  a.ncnt = (int)nseg;
+  a.nq = m.nq;
+  a.mixed = mixed ? 1 : 0;
+  a.chunk = 8;
+  for (int i = 0; i < kMaxXcc; ++i) a.xcc_queue[i] = m.queue[i];
+  for (int g = 0; g < b->count; ++g) a.err[g] = b->plans[g]->fctl + kFctlError;
+  // measured slower than one launch per stage on the 64-grid batch (4.6 ms
+  // against 2.9 ms FP64): opt-in (ibp_batch_set_persistent) or chosen by the
+  // batch autotuner when it is faster
+  b->persist = false;
+  return hipSuccess;
 }
 
 template <typename T>
@@ -1781,6 +1955,8 @@ ibp_status_t batch_build(ibp_batch_s* b) {
     d.yk = batch_grid_rows_per_lane(p->ny, b->yP, b->yK);
   }
   e = hipMemcpy(dtab, tab.data(), tab.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return from_hip(e);
+  e = persist_setup<T>(b);
   if (e == hipSuccess) e = batch_apply<T>(b, hd);
   if (e != hipSuccess) return from_hip(e);
   if constexpr (kF64) b->h64 = std::move(hd); else b->h32 = std::move(hd);
@@ -1803,6 +1979,10 @@ ibp_status_t batch_enqueue(ibp_batch_s* b, const double* const* rhs, double* con
     p->last_stream = s;
     p->solved = true;
     p->info_ctl = p->ctl;
+  }
+  if (b->persist) {   // every stage of every grid in one launch
+    IBP_HIP(launch_persist<T>(b->wide, b->yP, b->yK, b->pargs, P, b->persist_blocks, s));
+    return IBP_SUCCESS;
   }
   // each transform stage: the narrow-family launch, then the wide one
   auto xr2c = [&](int mode, const BatchLaunch& l) {
@@ -1848,6 +2028,7 @@ ibp_status_t batch_enqueue(ibp_batch_s* b, const double* const* rhs, double* con
 void batch_free(ibp_batch_s* b) {
   if (b == nullptr) return;
   if (b->dmem) hipFree(b->dmem);
+  if (b->pmem) hipFree(b->pmem);
   delete b;
 }
 
@@ -2029,6 +2210,13 @@ ibp_status_t ibp_batch_set_ycols(ibp_batch_t b, int cols) {
   }
 }
 
+ibp_status_t ibp_batch_set_persistent(ibp_batch_t b, int enable) {
+  if (b == nullptr) return IBP_ERROR_INVALID_VALUE;
+  if (enable && !b->persist_ok) return IBP_ERROR_UNSUPPORTED_SIZE;
+  b->persist = enable != 0;
+  return IBP_SUCCESS;
+}
+
 ibp_status_t ibp_batch_destroy(ibp_batch_t b) {
   try {
     batch_free(b);
@@ -2048,6 +2236,9 @@ namespace {
 
 struct TuneCfg {
   int xdiv, zdiv, ycols;
+  int persist = 0;   // batches: the persistent schedule
+  int lag = 1;       // its diagonal interleave
+  int chunk = 8;     // and the items its blocks claim at once
 };
 
 template <class Apply, class Run>
@@ -2086,6 +2277,9 @@ ibp_status_t autotune(const std::vector<TuneCfg>& cands, Apply apply, Run run, h
     out->tried = (int)cands.size();
     out->ms = best;
     out->ms_before = before;
+    out->persistent = bestc.persist;
+    out->lag = bestc.lag;
+    out->chunk = bestc.chunk;
   }
   return st;
 }
@@ -2123,17 +2317,25 @@ ibp_status_t ibp_batch_autotune(ibp_batch_t b, const double* const* rhs, double*
   if (b == nullptr || rhs == nullptr || phi == nullptr) return IBP_ERROR_INVALID_VALUE;
   try {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    std::vector<TuneCfg> cands{{b->xdiv, b->zdiv, b->yM}};
+    std::vector<TuneCfg> cands{{b->xdiv, b->zdiv, b->yM, b->persist ? 1 : 0, b->lag, b->pargs.chunk}};
     for (int xd : {1, 2, 4}) {
       if (b->prec != IBP_FP64 && xd > 1) continue;   // the mixed forms' partials follow the x split
-      for (int zd : {1, 2, 4})
-        for (int yc : {2, 4, 8, 16}) cands.push_back(TuneCfg{xd, zd, yc});
+      for (int zd : {1, 2, 4}) {
+        for (int yc : {2, 4, 8, 16}) cands.push_back(TuneCfg{xd, zd, yc, 0, 1, 8});
+        // persistent: the line solve's columns per block follow from its block size
+        if (b->persist_ok)
+          for (int lag : {1, 2})
+            for (int ch : {4, 16}) cands.push_back(TuneCfg{xd, zd, b->yM, 1, lag, ch});
+      }
     }
     auto apply = [&](const TuneCfg& c) {
       b->xdiv = c.xdiv;
       b->zdiv = c.zdiv;
       b->yM = b->prec == IBP_FP64 ? batch_ytri_cols<double>(b->yP, b->yK, c.ycols)
                                   : batch_ytri_cols<float>(b->yP, b->yK, c.ycols);
+      b->persist = c.persist != 0 && b->persist_ok;
+      b->lag = c.lag;
+      b->pargs.chunk = c.chunk;
       return from_hip(batch_reapply(b));
     };
     auto run = [&]() { return batch_solve(b, rhs, phi, s); };

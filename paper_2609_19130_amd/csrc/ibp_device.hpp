@@ -489,4 +489,32 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], const bool (&is_ma
   __syncthreads();
 }
 
+// ---------------------------------------------------------------- XCD-local scheduling
+// Hardware id of the XCD (accelerator complex die) this wave runs on: bits
+// [3:0] of the XCC_ID hardware register (register 20 on CDNA3/CDNA4).
+__device__ __forceinline__ int xcc_id() {
+  constexpr int kXccIdReg = 20, kSize = 4, kOffset = 0;
+  return __builtin_amdgcn_readfirstlane(
+      __builtin_amdgcn_s_getreg(((kSize - 1) << 11) | (kOffset << 6) | kXccIdReg) & 15);
+}
+
+// Wave 0 waits until `counter` reaches `need`; bounded (max_spins polls) so
+// that a broken dependency raises the error flag instead of hanging the device.
+__device__ __forceinline__ void wave_wait_count(int* counter, int need, int* error, int max_spins = 1 << 20) {
+  for (int spins = 0;; ++spins) {
+    const int v = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (v >= need) break;
+    if (spins >= max_spins) {
+      __hip_atomic_store(error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+// s_waitcnt immediate for vmcnt(0) with expcnt and lgkmcnt left free
+// (gfx9 encoding: vmcnt [3:0] and [15:14], expcnt [6:4], lgkmcnt [11:8]).
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 }  // namespace ibp

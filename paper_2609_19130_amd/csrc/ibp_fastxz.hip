@@ -331,14 +331,6 @@ __device__ __forceinline__ void decode_item(long g, int ny, int D, int n1, int n
 // steps the compiler may thread the branches across the loop's barriers so
 // that the other lanes loop back before lane 0 has claimed the next item.
 
-// Hardware id of the XCD (accelerator complex die) this wave runs on: bits
-// [3:0] of the XCC_ID hardware register (register 20 on CDNA3/CDNA4).
-__device__ __forceinline__ int xcc_id() {
-  constexpr int kXccIdReg = 20, kSize = 4, kOffset = 0;
-  return __builtin_amdgcn_readfirstlane(
-      __builtin_amdgcn_s_getreg(((kSize - 1) << 11) | (kOffset << 6) | kXccIdReg) & 15);
-}
-
 __global__ void k_xcc_probe(int* out) {
   const int x = xcc_id();
   if (threadIdx.x == 0) out[blockIdx.x] = x;
@@ -348,25 +340,6 @@ hipError_t launch_xcc_probe(int* out, int nblocks, hipStream_t s) {
   hipLaunchKernelGGL(k_xcc_probe, dim3((unsigned)nblocks), dim3(64), 0, s, out);
   return hipGetLastError();
 }
-
-// Wave 0 waits until `counter` reaches `need`; bounded so that a broken
-// dependency raises the error flag instead of hanging the device.
-__device__ __forceinline__ void wave_wait_count(int* counter, int need, int* error) {
-  for (int spins = 0;; ++spins) {
-    const int v = __builtin_amdgcn_readfirstlane(
-        __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    if (v >= need) break;
-    if (spins >= (1 << 20)) {
-      __hip_atomic_store(error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      break;
-    }
-    __builtin_amdgcn_s_sleep(2);
-  }
-}
-
-// s_waitcnt immediate for vmcnt(0) with expcnt and lgkmcnt left free
-// (gfx9 encoding: vmcnt [3:0] and [15:14], expcnt [6:4], lgkmcnt [11:8]).
-constexpr int kWaitVmcnt0 = 0x0F70;
 
 // Planes of queue q: q, q + nq, q + 2 nq, ... below ny.
 __device__ __forceinline__ int queue_planes(int q, int nq, int ny) { return q < ny ? (ny - q + nq - 1) / nq : 0; }

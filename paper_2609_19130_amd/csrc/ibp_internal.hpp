@@ -334,6 +334,54 @@ struct BatchLaunch {
   int check_done;
 };
 
+// ---------------------------------------------------------------- persistent batches
+// One launch for the whole batched solve (ibp_persist.hip).  The items of a
+// queue (one queue per XCD) are grouped in segments: the blocks of one stage
+// of one grid, in queue order.  An item of a segment waits until counter
+// `dep` reaches `need` (the grid's previous stage complete) and counts itself
+// in counter `done`.
+enum PersistKind {
+  PK_XR2C = 0, PK_XRES = 1, PK_XRESONLY = 2, PK_XC2R = 3, PK_XC2R_ADD = 4,
+  PK_ZF = 5, PK_ZI = 6, PK_Y0 = 7, PK_Y1 = 8, PK_Y2 = 9, PK_CHECK = 10
+};
+constexpr int PF_INIT = 1, PF_FINAL = 2, PF_CHECK_DONE = 4;   // segment flags
+
+struct PersistSeg {
+  long first;   // queue position of the segment's first item
+  int g;        // grid
+  int kind;     // PersistKind; PK_Y0/1/2: the line solve with K, K/2 or K/4 rows per lane
+  int iter;     // refinement pass of the stage
+  int flags;    // PF_*
+  int done;     // counter the items increment
+  int dep;      // counter the items wait on (-1: none)
+  int need;     // value of `dep` that releases them
+  int pad;
+};
+
+struct PersistArgs {
+  const void* grids;        // BatchGrid<T>[count]
+  const PersistSeg* seg;    // the queues' segments, queue q at [qseg[q], qseg[q + 1])
+  const int* qseg;          // [nq + 1]
+  const long* qitems;       // [nq] items per queue
+  int* head;                // [kMaxXcc] claim counters (zero between launches)
+  int* cnt;                 // [ncnt] completion counters (zero between launches)
+  int* exit_count;          // (zero between launches)
+  int ncnt;
+  int nq;
+  int mixed;
+  int chunk;                // items a block claims at once
+  signed char xcc_queue[kMaxXcc];   // hardware XCC id -> queue (-1: none)
+  int* err[kBatchMax];      // per grid: 1 = a wait gave up, 2 = its queue had no block
+};
+
+// Lanes and rows per lane the persistent kernel is built for.
+bool persist_shape_supported(int P, int K);
+template <typename T>
+hipError_t persist_blocks_per_cu(bool wide, int P, int K, int* per_cu);
+template <typename T>
+hipError_t launch_persist(bool wide, int P, int K, const PersistArgs& a, const BatchPtrs& p, int blocks,
+                          hipStream_t s);
+
 // Stages of a batched solve; each launcher covers every grid in one launch.
 template <typename T>
 hipError_t launch_batch_xr2c(int mode, bool small, bool wide, const BatchGrid<T>* d, const long* start, long nblocks, const BatchPtrs& p,

@@ -53,10 +53,11 @@ class PassStat(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("xdiv", ctypes.c_int), ("zdiv", ctypes.c_int), ("ycols", ctypes.c_int), ("tried", ctypes.c_int),
-                ("ms", ctypes.c_double), ("ms_before", ctypes.c_double)]
+                ("ms", ctypes.c_double), ("ms_before", ctypes.c_double), ("persistent", ctypes.c_int),
+                ("lag", ctypes.c_int), ("chunk", ctypes.c_int), ("reserved", ctypes.c_int)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 def lib():
@@ -90,6 +91,7 @@ def lib():
         "ibp_batch_create": (ci, [ctypes.POINTER(vp), ci, ctypes.POINTER(vp)]),
         "ibp_batch_solve": (ci, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]),
         "ibp_batch_set_ycols": (ci, [vp, ci]),
+        "ibp_batch_set_persistent": (ci, [vp, ci]),
         "ibp_batch_destroy": (ci, [vp]),
         "ibp_plan_autotune": (ci, [vp, vp, vp, vp, ctypes.POINTER(Tune)]),
         "ibp_batch_autotune": (ci, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.POINTER(Tune)]),
@@ -339,6 +341,11 @@ class Batch:
 
     def set_ycols(self, cols):
         _check(lib().ibp_batch_set_ycols(self.handle, int(cols)), "ibp_batch_set_ycols")
+
+    def set_persistent(self, enable=True):
+        """One persistent launch for the whole batched solve (True) or one
+        launch per stage (False); ibp_batch_set_persistent."""
+        _check(lib().ibp_batch_set_persistent(self.handle, 1 if enable else 0), "ibp_batch_set_persistent")
 
     def _ptrs(self, rhs, phi):
         n = len(self.plans)

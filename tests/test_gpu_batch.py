@@ -227,3 +227,67 @@ def test_batch_with_a_tall_grid_runs_every_line_solve_class(precision):
     finally:
         for p in plans:
             p.close()
+
+
+TALL_DIMS = [(48, 400, 40), (40, 130, 24), (32, 40, 48), (24, 6, 16), (30, 250, 20), (64, 20, 1)]
+
+
+def tall_case(precision):
+    plans, rhs = [], []
+    for i, (nx, ny, nz) in enumerate(TALL_DIMS):
+        yf = synth.tanh_faces(ny, 2.0)
+        f = np.random.default_rng(80 + i).standard_normal((ny, nz, nx))
+        plans.append(ibp.Plan(nx, ny, nz, 2 * np.pi, 1.3, yf, precision=precision, max_iters=4))
+        rhs.append(to_dev(f))
+    return plans, rhs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", ["c4", "tall"])
+def test_persistent_schedule_matches_staged(precision, case):
+    """The whole batched solve as one persistent launch (grids pinned to XCD
+    queues, stages overlapped across grids) gives bitwise the results of one
+    launch per stage, on every grid, on repeated solves (the queue counters
+    re-arm at the end of each launch) and under graph capture: the 64-grid
+    workload (32-lane line solves, 8 rows) and a batch with a 400-row grid
+    (64 lanes, the K, K/2 and K/4 classes, a 6-row grid, one nz = 1 grid)."""
+    if case == "c4":
+        _, plans, rhs, _ = batch_case(count=64 if precision == "fp64" else 24, seed=4 if precision == "fp64" else 9,
+                                      precision=precision, max_iters=4)
+    else:
+        plans, rhs = tall_case(precision)
+    b = ibp.Batch(plans)
+    b.set_persistent(False)
+    staged = b.solve(rhs)
+    torch.cuda.synchronize()
+    b.set_persistent(True)
+    for rep in range(3):
+        out = b.solve(rhs)
+        torch.cuda.synchronize()
+        for i in range(len(rhs)):
+            assert torch.equal(out[i], staged[i]), (rep, i)
+        for p in plans:
+            info = p.info()   # raises if a queue wait gave up
+            if precision == "mixed":
+                assert info["converged"] == 1, info
+    inp = [r.clone() for r in rhs]
+    outg = [torch.empty_like(r) for r in rhs]
+    b.solve(inp, outg)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.solve(inp, outg)
+    for k in range(3):
+        scale = float(2 ** (k + 1))
+        for a, r in zip(inp, rhs):
+            a.copy_(r * scale)
+        for o in outg:
+            o.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(rhs)):
+            assert torch.equal(outg[i], staged[i] * scale), (k, i)
+    b.close()
+    for p in plans:
+        p.close()
