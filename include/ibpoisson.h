@@ -252,12 +252,26 @@ typedef struct {
   int persistent;    /* batches: 1 = the persistent schedule was chosen (ibp_batch_set_persistent) */
   int lag;           /* batches, persistent: diagonal interleave of the grids' stages in a queue */
   int chunk;         /* batches, persistent: work items a block claims at once */
+  int xsmall;        /* plans: general x transform in the small (1) or large (0) LDS tile; -1: no choice */
+  int zsmall;        /* plans: the same for the general z transform */
   int reserved;
 } ibp_tune_t;
 
 /* Time solves of rhs into phi (device pointers as in ibp_solve; phi is
- * overwritten with the solution) over the plan's tunable splits and keep
- * the fastest.  Synchronises `stream`; not for use under graph capture. */
+ * overwritten with the solution) over the plan's tunable configurations and
+ * keep the fastest: the LDS tile (small or large) of the general x and z
+ * transforms, z columns and line-solve columns per block.  Synchronises
+ * `stream`; not for use under graph capture.
+ *
+ * Tuning cache: when the environment variable IBP_TUNE_CACHE names a file,
+ * every tuned choice is appended to it as one JSON line keyed by the device
+ * architecture, the grid dimensions and the precision form, e.g.
+ *   {"key": "gfx950/plan/512x384x512/0", "xdiv": 1, "zdiv": 1, "ycols": 8,
+ *    "xsmall": -1, "zsmall": -1, "persistent": 0, "lag": 1, "chunk": 8, "ms": 1.67}
+ * (batches: "gfx950/batch/<precision>.<max_iters>/<nx>x<ny>x<nz>,..." over
+ * their grids in order).  A key found there is applied without a search
+ * (tried = 0), and ibp_plan_create, ibp_plan_set_precision and
+ * ibp_batch_create apply it by themselves.  The last line of a key wins. */
 ibp_status_t ibp_plan_autotune(ibp_plan_t plan, const double* rhs, double* phi, hipStream_t stream, ibp_tune_t* out);
 
 /* The same for a batch (x rows, z columns and line-solve columns per block

@@ -2,14 +2,17 @@
 // workspace management and the enqueue order of the solve passes.  Every
 // entry point is extern "C", returns a status and catches C++ exceptions.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/ibpoisson.h"
@@ -251,10 +254,14 @@ double operator_inf_norm(const ibp_plan_s* p, const std::vector<double>& a, cons
   return x + z + y;
 }
 
+// Norm partials: one per x-pass block; one per row bounds every x split and
+// tile the tuner may choose.
 long max_parts(const ibp_plan_s* p) {
   long nb = p->nb64 > p->nb32 ? p->nb64 : p->nb32;
   nb = nb > p->nbf ? nb : p->nbf;
-  return nb > p->nbro ? nb : p->nbro;
+  nb = nb > p->nbro ? nb : p->nbro;
+  const long nrows = (long)p->ny * p->nz;
+  return nb > nrows ? nb : nrows;
 }
 
 // Counters that kernels expect at zero between launches (each kernel that
@@ -302,6 +309,31 @@ bool z_small(const FftPlan& fpz, int nz) {
 
 // The FP64 and FP32 half spectra are separate regions: the FP64 inverse
 // passes of IBP_MIXED_F64INV read the FP32 one and write the FP64 one.
+// x-pass rows per block and block counts for the plan's x tile (small or
+// large LDS tile of the general kernels; the register kernels' rows are fixed).
+void set_x_split(ibp_plan_s* p) {
+  const long nrows = (long)p->ny * p->nz;
+  p->nbro = (nrows + x_tile_rows(p, x_tile32(p)) - 1) / x_tile_rows(p, x_tile32(p));
+  if (p->xfast) {
+    p->rb64 = p->rb32 = (int)fast_x_rows_per_block(p->h);
+  } else {
+    p->rb64 = x_tile_rows(p, x_tile64(p));
+    p->rb32 = x_tile_rows(p, x_tile32(p));
+  }
+  p->nb64 = (nrows + p->rb64 - 1) / p->rb64;
+  p->nb32 = (nrows + p->rb32 - 1) / p->rb32;
+}
+
+// z-pass columns per block for the plan's z tile, divided by zdiv.
+void set_z_split(ibp_plan_s* p, int zdiv) {
+  p->zc64max = z_tile_cols(p, p->zsmall ? kTileZ64s : kTileZ64);
+  p->zc32max = z_tile_cols(p, p->zsmall ? kTileZ32s : kTileZ32);
+  p->zc64max = std::min(std::min(p->zc64max, 64), p->hp);
+  p->zc32max = std::min(std::min(p->zc32max, 64), p->hp);
+  p->zc64 = std::max(1, p->zc64max / zdiv);
+  p->zc32 = std::max(1, p->zc32max / zdiv);
+}
+
 size_t spec64_bytes(const ibp_plan_s* p) {
   return (size_t)p->ny * spec_plane_stride<double>(p->hp, p->nz) * sizeof(Cx<double>);
 }
@@ -408,6 +440,8 @@ struct RhsFromVelocity {
 ibp_status_t enqueue_solve(ibp_plan_s* p, const double* rhs, double* phi, hipStream_t s,
                            const RhsFromVelocity* from_u);
 void purge_batch_cache(const ibp_plan_s* p);
+// Tuned configurations from the tuning cache (IBP_TUNE_CACHE), if any.
+void apply_cached_plan(ibp_plan_s* p);
 ibp_status_t batched_or_loop(const ibp_plan_t* plans, int count, const double* const* rhs, double* const* phi,
                              hipStream_t s);
 
@@ -679,15 +713,7 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     p->xsmall = x_small(p->fpx, p->h);
     p->xwide = fft_wide(p->fpx);
     p->zwide = fft_wide(p->fpz);
-    p->nbro = (nrows + x_tile_rows(p, x_tile32(p)) - 1) / x_tile_rows(p, x_tile32(p));
-    if (p->xfast) {
-      p->rb64 = p->rb32 = (int)fast_x_rows_per_block(p->h);
-    } else {
-      p->rb64 = x_tile_rows(p, x_tile64(p));
-      p->rb32 = x_tile_rows(p, x_tile32(p));
-    }
-    p->nb64 = (nrows + p->rb64 - 1) / p->rb64;
-    p->nb32 = (nrows + p->rb32 - 1) / p->rb32;
+    set_x_split(p);
     // Fused persistent x/z passes: opt-in (IBP_FUSED=1).  Measured on MI355X
     // at 512x384x512 they move the same HBM bytes as the separate passes
     // (a plane's intermediate does not stay in its XCD's L2) and run slower.
@@ -695,14 +721,7 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     if (const char* e = getenv("IBP_FUSED")) p->fused = atoi(e) != 0 && p->xfast && p->zfast && fused_supported(p->h, nz);
     if (p->fused) p->nbf = nrows / fused_x_rows(p->h);
     p->zsmall = z_small(p->fpz, nz);
-    p->zc64 = z_tile_cols(p, p->zsmall ? kTileZ64s : kTileZ64);
-    p->zc32 = z_tile_cols(p, p->zsmall ? kTileZ32s : kTileZ32);
-    if (p->zc64 > 64) p->zc64 = 64;
-    if (p->zc32 > 64) p->zc32 = 64;
-    if (p->zc64 > p->hp) p->zc64 = p->hp;
-    if (p->zc32 > p->hp) p->zc32 = p->hp;
-    p->zc64max = p->zc64;
-    p->zc32max = p->zc32;
+    set_z_split(p, 1);
 
     // ---- FP64 geometry of the y operator (staggered, Neumann walls)
     // face coefficients a_j, c_j; the diagonal -(a_j + c_j) is never formed:
@@ -875,6 +894,7 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
       release(p);
       return from_hip(e);
     }
+    apply_cached_plan(p);
     *out = p;
     return IBP_SUCCESS;
   } catch (...) {
@@ -905,6 +925,11 @@ ibp_status_t ibp_plan_set_precision(ibp_plan_t p, ibp_precision_t prec, double r
   }
   p->prec = prec;
   ++p->gen;
+  try {
+    apply_cached_plan(p);
+  } catch (...) {
+    return IBP_ERROR_INTERNAL;
+  }
   return IBP_SUCCESS;
 }
 
@@ -985,7 +1010,10 @@ ibp_status_t ibp_solve(ibp_plan_t p, const double* rhs, double* phi, hipStream_t
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return from_hip(e);
     if (dev != p->device) return IBP_ERROR_INVALID_VALUE;
-    return enqueue_solve(p, rhs, phi, static_cast<hipStream_t>(stream), nullptr);
+    roctxRangePushA("ibp_solve");
+    const ibp_status_t st = enqueue_solve(p, rhs, phi, static_cast<hipStream_t>(stream), nullptr);
+    roctxRangePop();
+    return st;
   } catch (...) {
     return IBP_ERROR_INTERNAL;
   }
@@ -1351,11 +1379,15 @@ ZeroArgs zargs(ibp_plan_s* p, long nparts, int init, int mixed, int iter, int fi
 }
 
 // Launch `call` on `strm` with optional profiling events around it.
+// Each launch is also a roctx range named after its pass (visible to
+// rocprofv3 --marker-trace; a no-op without a profiler).
 #define IBP_LAUNCH_ON(pass, strm, ...)                         \
   do {                                                         \
+    roctxRangePushA(kPassName[(pass)]);                        \
     hipError_t e_ = prof_mark(p, (pass), (strm), true);        \
     if (e_ == hipSuccess) e_ = (__VA_ARGS__);                  \
     if (e_ == hipSuccess) e_ = prof_mark(p, (pass), (strm), false); \
+    roctxRangePop();                                           \
     if (e_ != hipSuccess) return from_hip(e_);                 \
   } while (0)
 #define IBP_LAUNCH(pass, ...) IBP_LAUNCH_ON(pass, s, __VA_ARGS__)
@@ -2025,6 +2057,8 @@ ibp_status_t batch_enqueue(ibp_batch_s* b, const double* const* rhs, double* con
   return IBP_SUCCESS;
 }
 
+ibp_status_t apply_cached_batch(ibp_batch_s* b);
+
 void batch_free(ibp_batch_s* b) {
   if (b == nullptr) return;
   if (b->dmem) hipFree(b->dmem);
@@ -2065,6 +2099,7 @@ ibp_status_t batch_create(const ibp_plan_t* plans, int count, ibp_batch_s** out)
   b->plans.assign(plans, plans + count);
   for (int i = 0; i < count; ++i) b->gens.push_back(plans[i]->gen);
   st = b->prec == IBP_FP64 ? batch_build<double>(b) : batch_build<float>(b);
+  if (st == IBP_SUCCESS) st = apply_cached_batch(b);
   if (st != IBP_SUCCESS) {
     batch_free(b);
     return st;
@@ -2097,7 +2132,11 @@ ibp_status_t batch_solve(ibp_batch_s* b, const double* const* rhs, double* const
       if (r0 < q0 + n && q0 < r0 + n) return IBP_ERROR_INVALID_VALUE;
     }
   }
-  return b->prec == IBP_FP64 ? batch_enqueue<double>(b, rhs, phi, s) : batch_enqueue<float>(b, rhs, phi, s);
+  roctxRangePushA(b->persist ? "ibp_batch_solve_persistent" : "ibp_batch_solve_staged");
+  const ibp_status_t st =
+      b->prec == IBP_FP64 ? batch_enqueue<double>(b, rhs, phi, s) : batch_enqueue<float>(b, rhs, phi, s);
+  roctxRangePop();
+  return st;
 }
 
 // Batches built by ibp_solve_batched, keyed by the exact plan sequence.
@@ -2229,9 +2268,9 @@ ibp_status_t ibp_batch_destroy(ibp_batch_t b) {
 }  // extern "C"
 
 // ======================================================================
-// Autotuning: time each candidate work split with HIP events on the
+// Autotuning: time each candidate configuration with HIP events on the
 // caller's stream (one warm-up solve, then the mean of a few) and keep the
-// fastest.
+// fastest.  Choices persist across processes in a cache file (IBP_TUNE_CACHE).
 namespace {
 
 struct TuneCfg {
@@ -2239,10 +2278,138 @@ struct TuneCfg {
   int persist = 0;   // batches: the persistent schedule
   int lag = 1;       // its diagonal interleave
   int chunk = 8;     // and the items its blocks claim at once
+  int xsmall = -1;   // plans: general x transform in the small (1) or large (0) LDS tile; -1: keep
+  int zsmall = -1;   // plans: the same for the general z transform
 };
 
+// ---- tuning cache
+// A text file of JSON lines, one per tuned configuration:
+//   {"key": "<arch>/plan/<nx>x<ny>x<nz>/<precision>", "xdiv": 1, "zdiv": 1, "ycols": 4,
+//    "xsmall": 1, "zsmall": 1, "persistent": 0, "lag": 1, "chunk": 8, "ms": 1.23}
+// Batch keys are "<arch>/batch/<precision>.<max_iters>/<nx>x<ny>x<nz>,..." over
+// the batch's grids in order.  The last line of a key wins.  <arch> is the
+// device's gfx architecture name (e.g. gfx950).
+std::mutex g_tune_mu;
+
+std::string tune_cache_path() {
+  const char* e = getenv("IBP_TUNE_CACHE");
+  return (e && *e) ? std::string(e) : std::string();
+}
+
+std::string device_arch(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+std::string plan_key(const ibp_plan_s* p) {
+  char buf[160];
+  snprintf(buf, sizeof buf, "%s/plan/%dx%dx%d/%d", device_arch(p->device).c_str(), p->nx, p->ny, p->nz, (int)p->prec);
+  return buf;
+}
+
+std::string batch_key(const ibp_batch_s* b) {
+  std::string k = device_arch(b->device) + "/batch/" + std::to_string((int)b->prec) + "." +
+                  std::to_string(b->prec == IBP_FP64 ? 0 : b->max_iters) + "/";
+  for (int g = 0; g < b->count; ++g) {
+    const ibp_plan_s* p = b->plans[g];
+    if (g) k += ",";
+    k += std::to_string(p->nx) + "x" + std::to_string(p->ny) + "x" + std::to_string(p->nz);
+  }
+  return k;
+}
+
+int json_int(const std::string& line, const char* name, int dflt) {
+  const std::string pat = std::string("\"") + name + "\":";
+  const size_t at = line.find(pat);
+  if (at == std::string::npos) return dflt;
+  return (int)strtol(line.c_str() + at + pat.size(), nullptr, 10);
+}
+
+// The cached configuration of `key`, if the cache file has one.
+bool tune_cache_get(const std::string& key, TuneCfg* out) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return false;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  FILE* f = fopen(path.c_str(), "r");
+  if (!f) return false;
+  const std::string want = "\"key\": \"" + key + "\"";
+  bool found = false;
+  std::string line;
+  char chunk[4096];
+  while (fgets(chunk, sizeof chunk, f)) {
+    line += chunk;
+    if (line.empty() || line.back() != '\n') continue;   // a line longer than the buffer
+    if (line.find(want) != std::string::npos) {
+      TuneCfg c{};
+      c.xdiv = json_int(line, "xdiv", 1);
+      c.zdiv = json_int(line, "zdiv", 1);
+      c.ycols = json_int(line, "ycols", 0);
+      c.persist = json_int(line, "persistent", 0);
+      c.lag = json_int(line, "lag", 1);
+      c.chunk = json_int(line, "chunk", 8);
+      c.xsmall = json_int(line, "xsmall", -1);
+      c.zsmall = json_int(line, "zsmall", -1);
+      *out = c;
+      found = true;   // keep reading: the last line of a key wins
+    }
+    line.clear();
+  }
+  fclose(f);
+  return found;
+}
+
+void tune_cache_put(const std::string& key, const TuneCfg& c, double ms) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  FILE* f = fopen(path.c_str(), "a");
+  if (!f) return;
+  fprintf(f,
+          "{\"key\": \"%s\", \"xdiv\": %d, \"zdiv\": %d, \"ycols\": %d, \"xsmall\": %d, \"zsmall\": %d, "
+          "\"persistent\": %d, \"lag\": %d, \"chunk\": %d, \"ms\": %.6f}\n",
+          key.c_str(), c.xdiv, c.zdiv, c.ycols, c.xsmall, c.zsmall, c.persist, c.lag, c.chunk, ms);
+  fclose(f);
+}
+
+// Plans: whether the general x / z transforms may take either LDS tile.
+bool plan_x_tile_choice(const ibp_plan_s* p) {
+  return !p->xfast && x_small(p->fpx, p->h) && p->chunk == 0 && !p->fused;
+}
+bool plan_z_tile_choice(const ibp_plan_s* p) { return !p->zfast && p->nz > 1 && z_small(p->fpz, p->nz); }
+
+// A plan configuration: x and z tiles (where the plan may choose), z columns
+// per block, line-solve columns per block.  None changes the arithmetic.
+void apply_plan_cfg(ibp_plan_s* p, const TuneCfg& c) {
+  if (c.xsmall >= 0 && plan_x_tile_choice(p)) {
+    p->xsmall = c.xsmall != 0;
+    set_x_split(p);
+  }
+  if (c.zsmall >= 0 && plan_z_tile_choice(p)) p->zsmall = c.zsmall != 0;
+  set_z_split(p, c.zdiv > 0 ? c.zdiv : 1);
+  p->ycols = c.ycols == 2 || c.ycols == 4 || c.ycols == 8 || c.ycols == 16 ? c.ycols : 0;
+}
+
+hipError_t apply_batch_cfg(ibp_batch_s* b, const TuneCfg& c) {
+  b->xdiv = c.xdiv >= 1 && c.xdiv <= kBatchDivMax ? c.xdiv : 1;
+  if (b->prec != IBP_FP64) b->xdiv = 1;   // the mixed forms' partials are sized for the finest split only
+  b->zdiv = c.zdiv >= 1 ? c.zdiv : 1;
+  const int want = c.ycols == 2 || c.ycols == 4 || c.ycols == 8 || c.ycols == 16 ? c.ycols : 0;
+  b->yM = b->prec == IBP_FP64 ? batch_ytri_cols<double>(b->yP, b->yK, want)
+                              : batch_ytri_cols<float>(b->yP, b->yK, want);
+  b->persist = c.persist != 0 && b->persist_ok;
+  b->lag = c.lag >= 1 ? c.lag : 1;
+  b->pargs.chunk = c.chunk >= 1 && c.chunk <= 64 ? c.chunk : 8;
+  return batch_reapply(b);
+}
+
+// cached: a configuration read from the tuning cache, applied and timed once
+// (tried = 0); otherwise the fastest is stored under `key`.
 template <class Apply, class Run>
-ibp_status_t autotune(const std::vector<TuneCfg>& cands, Apply apply, Run run, hipStream_t s, ibp_tune_t* out) {
+ibp_status_t autotune(const std::vector<TuneCfg>& cands, Apply apply, Run run, hipStream_t s, ibp_tune_t* out,
+                      bool cached = false, const std::string& key = std::string()) {
   constexpr int kReps = 3;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
@@ -2270,11 +2437,14 @@ ibp_status_t autotune(const std::vector<TuneCfg>& cands, Apply apply, Run run, h
   if (st == IBP_SUCCESS) st = apply(bestc);
   if (e0) hipEventDestroy(e0);
   if (e1) hipEventDestroy(e1);
+  if (st == IBP_SUCCESS && !cached && !key.empty()) tune_cache_put(key, bestc, best);
   if (st == IBP_SUCCESS && out) {
     out->xdiv = bestc.xdiv;
     out->zdiv = bestc.zdiv;
     out->ycols = bestc.ycols;
-    out->tried = (int)cands.size();
+    out->tried = cached ? 0 : (int)cands.size();
+    out->xsmall = bestc.xsmall;
+    out->zsmall = bestc.zsmall;
     out->ms = best;
     out->ms_before = before;
     out->persistent = bestc.persist;
@@ -2282,6 +2452,19 @@ ibp_status_t autotune(const std::vector<TuneCfg>& cands, Apply apply, Run run, h
     out->chunk = bestc.chunk;
   }
   return st;
+}
+
+void apply_cached_plan(ibp_plan_s* p) {
+  if (tune_cache_path().empty()) return;
+  TuneCfg c;
+  if (tune_cache_get(plan_key(p), &c)) apply_plan_cfg(p, c);
+}
+
+ibp_status_t apply_cached_batch(ibp_batch_s* b) {
+  if (tune_cache_path().empty()) return IBP_SUCCESS;
+  TuneCfg c;
+  if (!tune_cache_get(batch_key(b), &c)) return IBP_SUCCESS;
+  return from_hip(apply_batch_cfg(b, c));
 }
 
 }  // namespace
@@ -2292,21 +2475,31 @@ ibp_status_t ibp_plan_autotune(ibp_plan_t p, const double* rhs, double* phi, hip
   if (!valid_plan(p) || rhs == nullptr || phi == nullptr) return IBP_ERROR_INVALID_VALUE;
   try {
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool can_x = plan_x_tile_choice(p), can_z = plan_z_tile_choice(p);
     const int zd0 = p->zc64max / (p->zc64 > 0 ? p->zc64 : 1);
-    std::vector<TuneCfg> cands{{1, zd0 > 0 ? zd0 : 1, p->ycols}};   // the configuration in place first
-    const bool zgen = !p->zfast && p->nz > 1;
-    for (int zd : {1, 2, 4}) {
-      if (!zgen && zd > 1) continue;
-      for (int yc : {2, 4, 8, 16}) cands.push_back(TuneCfg{1, zd, yc});
-    }
+    const TuneCfg now{1, zd0 > 0 ? zd0 : 1, p->ycols, 0, 1, 8, p->xsmall ? 1 : 0, p->zsmall ? 1 : 0};
     auto apply = [&](const TuneCfg& c) {
-      p->ycols = c.ycols;
-      p->zc64 = p->zc64max / c.zdiv > 0 ? p->zc64max / c.zdiv : 1;
-      p->zc32 = p->zc32max / c.zdiv > 0 ? p->zc32max / c.zdiv : 1;
+      apply_plan_cfg(p, c);
       return IBP_SUCCESS;
     };
     auto run = [&]() { return ibp_solve(p, rhs, phi, stream); };
-    return autotune(cands, apply, run, s, out);
+    const std::string key = plan_key(p);
+    TuneCfg cached;
+    if (tune_cache_get(key, &cached)) return autotune({cached}, apply, run, s, out, true);
+    std::vector<TuneCfg> cands{now};   // the configuration in place first
+    const bool zgen = !p->zfast && p->nz > 1;
+    for (int xs : {1, 0}) {
+      if (!can_x && xs != now.xsmall) continue;
+      for (int zs : {1, 0}) {
+        if (!can_z && zs != now.zsmall) continue;
+        for (int zd : {1, 2, 4}) {
+          if (!zgen && zd > 1) continue;
+          for (int yc : {2, 4, 8, 16}) cands.push_back(TuneCfg{1, zd, yc, 0, 1, 8, xs, zs});
+        }
+      }
+    }
+    ibp_status_t st = autotune(cands, apply, run, s, out, false, key);
+    return st;
   } catch (...) {
     return IBP_ERROR_INTERNAL;
   }
@@ -2317,6 +2510,11 @@ ibp_status_t ibp_batch_autotune(ibp_batch_t b, const double* const* rhs, double*
   if (b == nullptr || rhs == nullptr || phi == nullptr) return IBP_ERROR_INVALID_VALUE;
   try {
     hipStream_t s = static_cast<hipStream_t>(stream);
+    auto apply = [&](const TuneCfg& c) { return from_hip(apply_batch_cfg(b, c)); };
+    auto run = [&]() { return batch_solve(b, rhs, phi, s); };
+    const std::string key = batch_key(b);
+    TuneCfg cached;
+    if (tune_cache_get(key, &cached)) return autotune({cached}, apply, run, s, out, true);
     std::vector<TuneCfg> cands{{b->xdiv, b->zdiv, b->yM, b->persist ? 1 : 0, b->lag, b->pargs.chunk}};
     for (int xd : {1, 2, 4}) {
       if (b->prec != IBP_FP64 && xd > 1) continue;   // the mixed forms' partials follow the x split
@@ -2328,18 +2526,7 @@ ibp_status_t ibp_batch_autotune(ibp_batch_t b, const double* const* rhs, double*
             for (int ch : {4, 16}) cands.push_back(TuneCfg{xd, zd, b->yM, 1, lag, ch});
       }
     }
-    auto apply = [&](const TuneCfg& c) {
-      b->xdiv = c.xdiv;
-      b->zdiv = c.zdiv;
-      b->yM = b->prec == IBP_FP64 ? batch_ytri_cols<double>(b->yP, b->yK, c.ycols)
-                                  : batch_ytri_cols<float>(b->yP, b->yK, c.ycols);
-      b->persist = c.persist != 0 && b->persist_ok;
-      b->lag = c.lag;
-      b->pargs.chunk = c.chunk;
-      return from_hip(batch_reapply(b));
-    };
-    auto run = [&]() { return batch_solve(b, rhs, phi, s); };
-    return autotune(cands, apply, run, s, out);
+    return autotune(cands, apply, run, s, out, false, key);
   } catch (...) {
     return IBP_ERROR_INTERNAL;
   }

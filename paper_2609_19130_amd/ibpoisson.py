@@ -54,7 +54,8 @@ class PassStat(ctypes.Structure):
 class Tune(ctypes.Structure):
     _fields_ = [("xdiv", ctypes.c_int), ("zdiv", ctypes.c_int), ("ycols", ctypes.c_int), ("tried", ctypes.c_int),
                 ("ms", ctypes.c_double), ("ms_before", ctypes.c_double), ("persistent", ctypes.c_int),
-                ("lag", ctypes.c_int), ("chunk", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("lag", ctypes.c_int), ("chunk", ctypes.c_int), ("xsmall", ctypes.c_int), ("zsmall", ctypes.c_int),
+                ("reserved", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

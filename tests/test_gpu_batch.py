@@ -291,3 +291,45 @@ def test_persistent_schedule_matches_staged(precision, case):
     b.close()
     for p in plans:
         p.close()
+
+
+def test_tuning_cache(monkeypatch, tmp_path):
+    """Tuned choices persist in the IBP_TUNE_CACHE file (one JSON line per
+    key: architecture, dimensions, precision): a second plan or batch of the
+    same dimensions takes the cached choice without a search, plans pick it
+    up when created, and the bits do not change."""
+    import json
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("IBP_TUNE_CACHE", str(cache))
+    nx, ny, nz = 96, 40, 48   # general (LDS) x and z transforms: the tile choice applies
+    yf = synth.tanh_faces(ny, 2.0)
+    f = to_dev(np.random.default_rng(21).standard_normal((ny, nz, nx)))
+    a = ibp.Plan(nx, ny, nz, 2 * np.pi, 1.0, yf)
+    ref = a.solve(f).clone()
+    t1 = a.autotune(f)
+    assert t1["tried"] >= 8 and t1["xsmall"] in (0, 1) and t1["zsmall"] in (0, 1), t1
+    lines = [json.loads(l) for l in cache.read_text().splitlines()]
+    assert len(lines) == 1 and lines[0]["key"].endswith(f"/plan/{nx}x{ny}x{nz}/0"), lines
+    assert lines[0]["ycols"] == t1["ycols"] and lines[0]["zdiv"] == t1["zdiv"]
+    b = ibp.Plan(nx, ny, nz, 2 * np.pi, 1.0, yf)   # created with the cached choice
+    assert torch.equal(b.solve(f), ref)
+    t2 = b.autotune(f)
+    assert t2["tried"] == 0 and all(t2[k] == t1[k] for k in ("zdiv", "ycols", "xsmall", "zsmall")), (t1, t2)
+    assert torch.equal(b.solve(f), ref)
+    # batches
+    grids, plans, rhs, _ = batch_case(count=6, seed=17)
+    bt = ibp.Batch(plans)
+    base = bt.solve(rhs)
+    t3 = bt.autotune(rhs)
+    assert t3["tried"] >= 13
+    bt2 = ibp.Batch(plans)
+    t4 = bt2.autotune(rhs)
+    assert t4["tried"] == 0 and all(t4[k] == t3[k] for k in ("xdiv", "zdiv", "persistent")), (t3, t4)
+    out = bt2.solve(rhs)
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(base, out))
+    assert len(cache.read_text().splitlines()) == 2
+    for o in (bt, bt2):
+        o.close()
+    for p in plans + [a, b]:
+        p.close()
