@@ -2,27 +2,105 @@
 // the elliptic problem is (div u* - q) / (alpha dt) (paper, eq. ``elliptic``).
 // u[j][k][i] sits on the x face at x = i dx, w[j][k][i] on the z face at
 // z = k dz (both periodic), v[j][k][i] on the y face yf[j] (ny+1 rows).
+#include <algorithm>
+
 #include "ibp_internal.hpp"
 
 namespace ibp {
 
-__global__ __launch_bounds__(kThreads) void k_divergence(DivArgs A) {
-  const long n = (long)A.nx * A.ny * A.nz;
-  const long plane = (long)A.nx * A.nz;
-  for (long e = (long)blockIdx.x * kThreads + threadIdx.x; e < n; e += (long)gridDim.x * kThreads) {
-    const long j = e / plane;
-    const long rem = e - j * plane;
-    const int k = (int)(rem / A.nx);
-    const int i = (int)(rem - (long)k * A.nx);
-    const int ip = i + 1 == A.nx ? 0 : i + 1;
-    const int kp = k + 1 == A.nz ? 0 : k + 1;
-    const long rowb = e - i;
-    const double du = A.u[rowb + ip] - A.u[e];
-    const double dw = A.w[j * plane + (long)kp * A.nx + i] - A.w[e];
-    const double dv = A.v[e + plane] - A.v[e];
-    double d = du * A.idx + dv / A.dyf[j] + dw * A.idz;
-    if (A.q) d -= A.q[e];
-    A.f[e] = d * A.scale;
+// Both kernels march along y: a block owns a tile of KR consecutive z rows
+// (all nx columns) and walks NJ consecutive y planes of it, keeping the
+// values it needs from the planes below and above in registers, so every
+// field is read from memory once (plus one z halo row per tile and one y
+// halo plane per walk).  Tiles of a plane follow each other in block order,
+// so the z neighbours of a tile's edge rows are read by blocks running at
+// the same time.  NT threads own TILE / NT cells each: cell c of the tile
+// (c = t + NT m) is row c / nx, column c % nx.  Two shapes: 512 threads over
+// 2048-cell tiles (nx <= 2048; the faster of the shapes measured), and 1024
+// threads over 4096-cell tiles for wider rows.
+constexpr int kMarchThreads = 512, kMarchTile = 2048;
+constexpr int kMarchThreadsWide = 1024, kMarchTileWide = 4096;
+// LDS of the projection: (kr + 2) rows of nx, at most three times the tile
+constexpr int kProjLds = 3 * kMarchTile, kProjLdsWide = 3 * kMarchTileWide;
+// blocks per launch to aim for, and the longest walk along y
+constexpr int kMarchBlocks = 1024, kMarchMaxPlanes = 32;
+
+struct MarchShape {
+  int kr;     // z rows per tile
+  int ntk;    // tiles per plane
+  int nj;     // y planes per block
+  int nbj;    // blocks along y
+};
+
+// Blocks of a launch go to the XCDs in turn (block b to XCD b mod 8), and
+// each XCD has its own L2.  The march kernels renumber blocks so that every
+// XCD takes a contiguous range of tiles: neighbouring tiles of one plane,
+// which read each other's edge rows, then share an L2.  Only the speed
+// depends on the dispatch order; any order computes the same result.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb / kXcds, r = nb % kXcds;
+  const int x = b % kXcds, i = b / kXcds;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+inline MarchShape march_shape(int nx, int ny, int nz, int tile) {
+  MarchShape m;
+  m.kr = std::max(1, std::min(nz, tile / nx));
+  m.ntk = (nz + m.kr - 1) / m.kr;
+  // enough blocks to fill the device with at least 4 planes each
+  m.nj = std::max(4, std::min(kMarchMaxPlanes, (int)((long)ny * m.ntk / kMarchBlocks)));
+  m.nj = std::min(m.nj, ny);
+  m.nbj = (ny + m.nj - 1) / m.nj;
+  return m;
+}
+
+// Discrete divergence: v(j + 1) of a plane is v(j) of the next one; the
+// x and z neighbours u(i + 1), w(k + 1) come from the same or the next row
+// (cache hits, apart from each tile's last row).
+template <int NT, int TILE>
+__global__ __launch_bounds__(NT) void k_divergence(DivArgs A, MarchShape S) {
+  constexpr int kMarchCells = TILE / NT;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int tk = blk % S.ntk, bj = blk / S.ntk;
+  const int j0 = bj * S.nj, j1 = min(A.ny, j0 + S.nj);
+  const int k0 = tk * S.kr, nx = A.nx;
+  const long plane = (long)nx * A.nz;
+  const int ncell = min(S.kr, A.nz - k0) * nx;
+  int off[kMarchCells], offu[kMarchCells], offw[kMarchCells];   // within a plane (< 2^24)
+  bool live[kMarchCells];
+  double vb[kMarchCells];
+#pragma unroll
+  for (int m = 0; m < kMarchCells; ++m) {
+    const int c = threadIdx.x + NT * m;
+    live[m] = c < ncell;
+    const int kk = live[m] ? c / nx : 0, i = live[m] ? c - kk * nx : 0;
+    const int k = k0 + kk;
+    off[m] = k * nx + i;
+    offu[m] = k * nx + (i + 1 == nx ? 0 : i + 1);
+    offw[m] = (k + 1 == A.nz ? 0 : k + 1) * nx + i;
+    vb[m] = live[m] ? A.v[(long)j0 * plane + off[m]] : 0.0;
+  }
+  for (int j = j0; j < j1; ++j) {
+    const long pj = (long)j * plane;
+    const double* u = A.u + pj;
+    const double* w = A.w + pj;
+    const double* vt_row = A.v + pj + plane;
+    const double* q = A.q ? A.q + pj : nullptr;
+    double* f = A.f + pj;
+    const double rdyf = A.dyf[j];
+#pragma unroll
+    for (int m = 0; m < kMarchCells; ++m) {
+      if (!live[m]) continue;
+      const double vt = vt_row[off[m]];
+      const double du = u[offu[m]] - u[off[m]];
+      const double dw = w[offw[m]] - w[off[m]];
+      const double dv = vt - vb[m];
+      double d = du * A.idx + dv / rdyf + dw * A.idz;
+      if (q) d -= q[off[m]];
+      f[off[m]] = d * A.scale;
+      vb[m] = vt;
+    }
   }
 }
 
@@ -34,51 +112,132 @@ __global__ __launch_bounds__(kThreads) void k_divergence(DivArgs A) {
 // Wall faces of v: unchanged at a Neumann wall; at a Dirichlet wall (phi = 0
 // on the face) the one-sided gradient over the half cell.  Cell (j,k,i)
 // updates the faces west, south and below it (plus the upper wall face when
-// j = ny-1), so every face has one writer.
-__global__ __launch_bounds__(kThreads) void k_project(ProjArgs A) {
-  const long plane = (long)A.nx * A.nz;
-  const long n = plane * A.ny;
-  for (long e = (long)blockIdx.x * kThreads + threadIdx.x; e < n; e += (long)gridDim.x * kThreads) {
-    const long j = e / plane;
-    const long rem = e - j * plane;
-    const int k = (int)(rem / A.nx);
-    const int i = (int)(rem - (long)k * A.nx);
-    const long rowb = e - i;
-    const int im = i == 0 ? A.nx - 1 : i - 1, ip = i + 1 == A.nx ? 0 : i + 1;
-    const int km = k == 0 ? A.nz - 1 : k - 1, kp = k + 1 == A.nz ? 0 : k + 1;
-    const double c0 = A.phi[e];
-    const double xm = A.phi[rowb + im], xp = A.phi[rowb + ip];
-    const double zm = A.phi[j * plane + (long)km * A.nx + i], zp = A.phi[j * plane + (long)kp * A.nx + i];
-    const double ym = j > 0 ? A.phi[e - plane] : 0.0;          // wall value 0 beyond a wall
-    const double yp = j + 1 < A.ny ? A.phi[e + plane] : 0.0;
-    A.u[e] -= A.adt * (c0 - xm) * A.idx;
-    A.w[e] -= A.adt * (c0 - zm) * A.idz;
-    if (j > 0)
-      A.v[e] -= A.adt * (c0 - ym) / A.dyc[j];
-    else if (A.dir_lo)
-      A.v[e] -= A.adt * (c0 - 0.0) / (0.5 * A.dyf[0]);
-    if (j + 1 == A.ny && A.dir_hi) A.v[e + plane] -= A.adt * (0.0 - c0) / (0.5 * A.dyf[j]);
-    if (A.p) {
-      const double lap = (xp - 2.0 * c0 + xm) * A.idx * A.idx + (zp - 2.0 * c0 + zm) * A.idz * A.idz +
-                         A.ya[j] * (ym - c0) + A.yc[j] * (yp - c0);
-      A.p[e] += c0 - A.visc * lap;
+// j = ny-1), so every face has one writer.  The phi tile of the current
+// plane, with one halo row on each z side, sits in LDS for the x and z
+// neighbours; phi of the planes below and above, at the thread's own cells,
+// in registers.
+// LDS: capacity in doubles, at least (kr + 2) nx.
+template <int NT, int TILE, int LDS>
+__global__ __launch_bounds__(NT) void k_project(ProjArgs A, MarchShape S) {
+  constexpr int kMarchCells = TILE / NT;
+  __shared__ double tile[LDS];   // (kr + 2) rows of nx: z rows k0 - 1 .. k0 + kr
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int tk = blk % S.ntk, bj = blk / S.ntk;
+  const int j0 = bj * S.nj, j1 = min(A.ny, j0 + S.nj);
+  const int k0 = tk * S.kr, nx = A.nx, nz = A.nz;
+  const int kr = min(S.kr, nz - k0);
+  const long plane = (long)nx * nz;
+  const int ncell = kr * nx;
+  int tc[kMarchCells], txm[kMarchCells], txp[kMarchCells];   // tile index of the cell and its x neighbours
+  int off[kMarchCells];                                      // within a plane (< 2^24)
+  bool live[kMarchCells];
+#pragma unroll
+  for (int m = 0; m < kMarchCells; ++m) {
+    const int c = threadIdx.x + NT * m;
+    live[m] = c < ncell;
+    const int kk = live[m] ? c / nx : 0, i = live[m] ? c - kk * nx : 0;
+    off[m] = (k0 + kk) * nx + i;
+    tc[m] = (kk + 1) * nx + i;
+    txm[m] = (kk + 1) * nx + (i == 0 ? nx - 1 : i - 1);
+    txp[m] = (kk + 1) * nx + (i + 1 == nx ? 0 : i + 1);
+  }
+  // Tile row r holds z row (k0 - 1 + r) mod nz.  Each thread writes its own
+  // cells (rows 1..kr) from registers; the two halo rows come from memory.
+  auto fill = [&](int j, const double* own) {
+#pragma unroll
+    for (int m = 0; m < kMarchCells; ++m)
+      if (live[m]) tile[tc[m]] = own[m];
+    const double* src = A.phi + (long)j * plane;
+    const int klo = k0 == 0 ? nz - 1 : k0 - 1, khi = k0 + kr == nz ? 0 : k0 + kr;
+    for (int e = threadIdx.x; e < 2 * nx; e += NT) {
+      const int hi = e >= nx, i = e - hi * nx;
+      tile[hi ? (kr + 1) * nx + i : i] = src[(hi ? khi : klo) * nx + i];
     }
+  };
+  double pm[kMarchCells], pc[kMarchCells], pp[kMarchCells];
+#pragma unroll
+  for (int m = 0; m < kMarchCells; ++m) {
+    pm[m] = (live[m] && j0 > 0) ? A.phi[(long)(j0 - 1) * plane + off[m]] : 0.0;   // wall value 0 beyond a wall
+    pc[m] = live[m] ? A.phi[(long)j0 * plane + off[m]] : 0.0;
+  }
+  fill(j0, pc);
+  const double ax = A.adt * A.idx, az = A.adt * A.idz;
+  const double cxx = A.idx * A.idx, czz = A.idz * A.idz;
+  for (int j = j0; j < j1; ++j) {
+    const long pj = (long)j * plane;
+    const double* phin = A.phi + pj + plane;
+    double* u = A.u + pj;
+    double* v = A.v + pj;
+    double* w = A.w + pj;
+    double* p = A.p ? A.p + pj : nullptr;
+    const bool wall_hi = j + 1 == A.ny && A.dir_hi;
+    // every global load of the plane is issued before the barrier
+    double uo[kMarchCells], vo[kMarchCells], wo[kMarchCells], po[kMarchCells], vh[kMarchCells];
+#pragma unroll
+    for (int m = 0; m < kMarchCells; ++m) {
+      pp[m] = (live[m] && j + 1 < A.ny) ? phin[off[m]] : 0.0;
+      uo[m] = live[m] ? u[off[m]] : 0.0;
+      wo[m] = live[m] ? w[off[m]] : 0.0;
+      vo[m] = live[m] ? v[off[m]] : 0.0;
+      po[m] = (live[m] && p) ? p[off[m]] : 0.0;
+      vh[m] = (live[m] && wall_hi) ? v[off[m] + plane] : 0.0;
+    }
+    const double gy = j > 0 ? A.adt / A.dyc[j] : (A.dir_lo ? A.adt / (0.5 * A.dyf[0]) : 0.0);
+    const double gyh = wall_hi ? A.adt / (0.5 * A.dyf[j]) : 0.0;
+    const double ya = A.ya[j], yc = A.yc[j];
+    __syncthreads();   // the tile of plane j is complete
+#pragma unroll
+    for (int m = 0; m < kMarchCells; ++m) {
+      if (!live[m]) continue;
+      const int o = off[m];
+      const double c0 = pc[m];
+      const double xm = tile[txm[m]], xp = tile[txp[m]];
+      const double zm = tile[tc[m] - nx], zp = tile[tc[m] + nx];
+      const double ym = pm[m], yp = pp[m];
+      u[o] = uo[m] - ax * (c0 - xm);
+      w[o] = wo[m] - az * (c0 - zm);
+      if (j > 0 || A.dir_lo) v[o] = vo[m] - gy * (c0 - ym);   // ym = 0 on a Dirichlet wall face
+      if (wall_hi) v[o + plane] = vh[m] - gyh * (0.0 - c0);
+      if (p) {
+        const double lap = (xp - 2.0 * c0 + xm) * cxx + (zp - 2.0 * c0 + zm) * czz + ya * (ym - c0) + yc * (yp - c0);
+        p[o] = po[m] + (c0 - A.visc * lap);
+      }
+    }
+    __syncthreads();   // every read of the tile is done
+#pragma unroll
+    for (int m = 0; m < kMarchCells; ++m) {
+      pm[m] = pc[m];
+      pc[m] = pp[m];
+    }
+    if (j + 1 < j1) fill(j + 1, pc);
   }
 }
 
 hipError_t launch_project(const ProjArgs& a, hipStream_t s) {
-  const long n = (long)a.nx * a.ny * a.nz;
-  long nb = (n + kThreads - 1) / kThreads;
-  if (nb > 65536) nb = 65536;
-  hipLaunchKernelGGL(k_project, dim3((unsigned)nb), dim3(kThreads), 0, s, a);
+  if (a.nx > kMarchTileWide || (long)a.nx * a.nz >= (1L << 30)) return hipErrorInvalidValue;
+  if (a.nx <= kMarchTile) {
+    const MarchShape S = march_shape(a.nx, a.ny, a.nz, kMarchTile);
+    hipLaunchKernelGGL((k_project<kMarchThreads, kMarchTile, kProjLds>), dim3((unsigned)(S.ntk * S.nbj)),
+                       dim3(kMarchThreads), 0, s, a, S);
+  } else {
+    const MarchShape S = march_shape(a.nx, a.ny, a.nz, kMarchTileWide);
+    hipLaunchKernelGGL((k_project<kMarchThreadsWide, kMarchTileWide, kProjLdsWide>), dim3((unsigned)(S.ntk * S.nbj)),
+                       dim3(kMarchThreadsWide), 0, s, a, S);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_divergence(const DivArgs& a, hipStream_t s) {
-  const long n = (long)a.nx * a.ny * a.nz;
-  long nb = (n + kThreads - 1) / kThreads;
-  if (nb > 65536) nb = 65536;
-  hipLaunchKernelGGL(k_divergence, dim3((unsigned)nb), dim3(kThreads), 0, s, a);
+  if (a.nx > kMarchTileWide || (long)a.nx * a.nz >= (1L << 30)) return hipErrorInvalidValue;
+  if (a.nx <= kMarchTile) {
+    const MarchShape S = march_shape(a.nx, a.ny, a.nz, kMarchTile);
+    hipLaunchKernelGGL((k_divergence<kMarchThreads, kMarchTile>), dim3((unsigned)(S.ntk * S.nbj)),
+                       dim3(kMarchThreads), 0, s, a, S);
+  } else {
+    const MarchShape S = march_shape(a.nx, a.ny, a.nz, kMarchTileWide);
+    hipLaunchKernelGGL((k_divergence<kMarchThreadsWide, kMarchTileWide>), dim3((unsigned)(S.ntk * S.nbj)),
+                       dim3(kMarchThreadsWide), 0, s, a, S);
+  }
   return hipGetLastError();
 }
 

@@ -18,7 +18,9 @@ from gpu_helpers import rel, require_gpu, to_dev
 pytestmark = pytest.mark.gpu
 
 CASES = [(64, 40, 32, ("neumann", "neumann")), (48, 33, 20, ("neumann", "neumann")),
-         (256, 17, 128, ("neumann", "dirichlet")), (30, 25, 18, ("dirichlet", "dirichlet"))]
+         (256, 17, 128, ("neumann", "dirichlet")), (30, 25, 18, ("dirichlet", "dirichlet")),
+         # rows wider than the standard march tile take the 4096-cell tiles
+         (2304, 6, 5, ("dirichlet", "neumann"))]
 
 
 @pytest.fixture(autouse=True)
