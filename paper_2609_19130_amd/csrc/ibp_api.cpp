@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/ibpoisson.h"
+#include "ibp_host.hpp"
 #include "ibp_internal.hpp"
 #include "ibp_regfft.hpp"
 
@@ -24,127 +25,6 @@ using namespace ibp;
 namespace {
 
 constexpr int kVersion = 200;  // 0.2.0
-
-// Radix factorisation for the LDS FFT: eights first, then fours, twos, the
-// odd primes with butterflies of their own (3, 5, 7, 11), then any larger
-// prime factors (direct-sum stages).  Returns false only past 16 stages.
-bool factorize(int n, FftPlan* fp) {
-  fp->n = n;
-  fp->nst = 0;
-  fp->any = 0;
-  fp->blu = 0;
-  fp->m = 0;
-  fp->mst = 0;
-  int m = n;
-  auto push = [&](int r) {
-    if (fp->nst >= 16) return false;
-    fp->radix[fp->nst++] = r;
-    if (r > 11) fp->any = 1;
-    m /= r;
-    return true;
-  };
-  while (m % 8 == 0)
-    if (!push(8)) return false;
-  while (m % 4 == 0)
-    if (!push(4)) return false;
-  while (m % 2 == 0)
-    if (!push(2)) return false;
-  for (int p : {3, 5, 7, 11})
-    while (m % p == 0)
-      if (!push(p)) return false;
-  for (int p = 13; p * p <= m; p += 2)
-    while (m % p == 0)
-      if (!push(p)) return false;
-  if (m > 1 && !push(m)) return false;   // the remaining prime
-  return m == 1;
-}
-
-// Lengths whose largest prime factor exceeds kBluesteinPrime take Bluestein's
-// algorithm instead of a direct-sum stage, if the convolution length m (the
-// power of two >= 2n - 1) fits `max_m`.  Both move similar LDS traffic per
-// value at R ~ 100-200 (R/4 reads per output for the direct sum against two
-// padded length-m transforms), and the direct sum measured faster there on
-// MI355X (501 = 3 x 167 and 632 = 8 x 79 grids), so only larger primes switch.
-constexpr int kBluesteinPrime = 256;
-void plan_bluestein(FftPlan* fp, int max_m) {
-  int big = 1;
-  for (int s = 0; s < fp->nst; ++s) big = fp->radix[s] > big ? fp->radix[s] : big;
-  if (big <= kBluesteinPrime) return;
-  int m = 1;
-  while (m < 2 * fp->n - 1) m *= 2;
-  if (m > max_m) return;
-  fp->blu = 1;
-  fp->any = 0;
-  fp->m = m;
-  fp->mst = 0;
-  int r = m;
-  while (r % 8 == 0) { fp->mradix[fp->mst++] = 8; r /= 8; }
-  while (r % 4 == 0) { fp->mradix[fp->mst++] = 4; r /= 4; }
-  while (r % 2 == 0) { fp->mradix[fp->mst++] = 2; r /= 2; }
-}
-
-// Bluestein tables of length n (convolution length m), FP64 from long double:
-// chirp w_j = exp(-i pi j^2 / n) (angle reduced as j^2 mod 2n), and bhat =
-// DFT_m of the filter b with b_t = conj(w_|t|) at t mod m for |t| < n (a
-// radix-2 transform in long double).
-void bluestein_tables(int n, int m, std::vector<double>& chirp, std::vector<double>& bhat) {
-  const long double pi = 3.141592653589793238462643383279502884L;
-  chirp.assign(2 * (size_t)n, 0.0);
-  std::vector<long double> br(m, 0.0L), bi(m, 0.0L);
-  for (int j = 0; j < n; ++j) {
-    const long long r = ((long long)j * j) % (2LL * n);
-    const long double a = pi * (long double)r / (long double)n;
-    chirp[2 * j] = (double)cosl(a);
-    chirp[2 * j + 1] = (double)-sinl(a);
-    br[j] = cosl(a);   // conj(w_j)
-    bi[j] = sinl(a);
-    if (j > 0) {
-      br[m - j] = cosl(a);
-      bi[m - j] = sinl(a);
-    }
-  }
-  // iterative radix-2 DFT, exp(-2 pi i j k / m)
-  for (int i = 1, j = 0; i < m; ++i) {
-    int bit = m >> 1;
-    for (; j & bit; bit >>= 1) j ^= bit;
-    j ^= bit;
-    if (i < j) {
-      std::swap(br[i], br[j]);
-      std::swap(bi[i], bi[j]);
-    }
-  }
-  for (int len = 2; len <= m; len <<= 1) {
-    const long double ang = -2.0L * pi / (long double)len;
-    for (int i = 0; i < m; i += len)
-      for (int k = 0; k < len / 2; ++k) {
-        const long double wr = cosl(ang * k), wi = sinl(ang * k);
-        const long double ur = br[i + k], ui = bi[i + k];
-        const long double vr = br[i + k + len / 2] * wr - bi[i + k + len / 2] * wi;
-        const long double vi = br[i + k + len / 2] * wi + bi[i + k + len / 2] * wr;
-        br[i + k] = ur + vr;
-        bi[i + k] = ui + vi;
-        br[i + k + len / 2] = ur - vr;
-        bi[i + k + len / 2] = ui - vi;
-      }
-  }
-  bhat.assign(2 * (size_t)m, 0.0);
-  for (int k = 0; k < m; ++k) {
-    bhat[2 * k] = (double)br[k];
-    bhat[2 * k + 1] = (double)bi[k];
-  }
-}
-
-// W_n^e = exp(-2 pi i e / n), e = 0..n-1, evaluated in long double and rounded.
-void twiddles(int n, std::vector<double>& re, std::vector<double>& im) {
-  re.resize(n);
-  im.resize(n);
-  const long double two_pi = 6.283185307179586476925286766559005768L;
-  for (int e = 0; e < n; ++e) {
-    const long double a = two_pi * (long double)e / (long double)n;
-    re[e] = (double)cosl(a);
-    im[e] = (double)-sinl(a);
-  }
-}
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -375,24 +255,11 @@ void carve_workspace(ibp_plan_s* p) {
 }
 
 ibp_status_t check_dims(int nx, int ny, int nz, FftPlan* fpx, FftPlan* fpz) {
-  if (nx < 1 || nz < 1 || ny < 1) return IBP_ERROR_INVALID_VALUE;
-  // x transform length: nx/2 complex pairs, or nx complex values for odd nx
-  const int hx = nx % 2 ? nx : nx / 2;
-  if (hx > kTileX64) return IBP_ERROR_UNSUPPORTED_SIZE;
-  if (nz > kTileZ64) return IBP_ERROR_UNSUPPORTED_SIZE;
-  if (ny < 2 || ny > kMaxNy) return IBP_ERROR_UNSUPPORTED_SIZE;
-  FftPlan a{}, b{};
-  if (!factorize(hx, &a) || !factorize(nz, &b)) return IBP_ERROR_UNSUPPORTED_SIZE;
-  plan_bluestein(&a, kTileX64);          // rows of m values in the large x tile
-  plan_bluestein(&b, kTileZ64 / 2);      // columns of m + 1 values in the large z tile
-  // a prime factor above 11 needs the spare half of the general tiles
-  if (a.any && hx > kTileX64 / 2) return IBP_ERROR_UNSUPPORTED_SIZE;
-  if (b.any && nz + 1 > kTileZ64 / 2) return IBP_ERROR_UNSUPPORTED_SIZE;
-  int M, K;
-  if (!ytri_shape(ny, &M, &K)) return IBP_ERROR_UNSUPPORTED_SIZE;
-  if (fpx) *fpx = a;
-  if (fpz) *fpz = b;
-  return IBP_SUCCESS;
+  switch (dims_status(nx, ny, nz, fpx, fpz)) {
+    case kDimsOk: return IBP_SUCCESS;
+    case kDimsInvalid: return IBP_ERROR_INVALID_VALUE;
+    default: return IBP_ERROR_UNSUPPORTED_SIZE;
+  }
 }
 
 // XCD map of a device: the hardware XCC ids that blocks of a wide launch
@@ -557,60 +424,6 @@ namespace {
 // -di_0, u = (gamma, 0.., up_{n-1}), v = (1, 0.., lo_0 / gamma); B is
 // factored by Thomas and B^-1 u folds into w = B^-1 u / (1 + v.B^-1 u), so
 // that x = y - w (y_0 + g y_{n-1}) with y = B^-1 d and g = lo_0 / gamma.
-struct LineLu {
-  std::vector<double> m, s, t, w;
-  double g = 0.0;
-  int cyclic = 0;
-};
-
-LineLu line_lu(std::vector<double> lo, std::vector<double> di, std::vector<double> up, bool cyclic) {
-  const int n = (int)di.size();
-  LineLu L;
-  if (cyclic && n == 1) {   // both neighbours are the point itself
-    di[0] += lo[0] + up[0];
-    cyclic = false;
-  } else if (cyclic && n == 2) {   // both neighbours are the other point
-    up[0] += lo[0];
-    lo[1] += up[1];
-    cyclic = false;
-  }
-  std::vector<double> u;
-  if (cyclic) {
-    const double gamma = -di[0];
-    const double clo = lo[0], cup = up[n - 1];
-    di[0] -= gamma;
-    di[n - 1] -= clo * cup / gamma;
-    u.assign(n, 0.0);
-    u[0] = gamma;
-    u[n - 1] = cup;
-    L.g = clo / gamma;
-    L.cyclic = 1;
-  }
-  lo[0] = 0.0;
-  up[n - 1] = 0.0;
-  L.m.assign(n, 0.0);
-  L.s.assign(n, 0.0);
-  L.t.assign(n, 0.0);
-  L.w.assign(n, 0.0);
-  double den = 0.0;
-  for (int i = 0; i < n; ++i) {
-    den = i == 0 ? di[0] : di[i] - lo[i] * up[i - 1] / den;
-    L.s[i] = 1.0 / den;
-    L.m[i] = -lo[i] / den;
-    L.t[i] = -up[i] / den;
-  }
-  if (cyclic) {
-    std::vector<double> z(n);
-    double prev = 0.0;
-    for (int i = 0; i < n; ++i) prev = z[i] = L.m[i] * prev + L.s[i] * u[i];
-    double nxt = 0.0;
-    for (int i = n - 1; i >= 0; --i) nxt = z[i] = z[i] + L.t[i] * nxt;
-    const double vz = z[0] + L.g * z[n - 1];
-    for (int i = 0; i < n; ++i) L.w[i] = z[i] / (1.0 + vz);
-  }
-  return L;
-}
-
 // Appends the four padded tables of `L` to `buf` and fills `d`.
 void pack_line(ibp_plan_s::LineDir& d, const LineLu& L, int P, int K, std::vector<double>& buf) {
   d.P = P;
@@ -1785,31 +1598,16 @@ hipError_t persist_schedule(ibp_batch_s* b, const std::vector<BatchGrid<T>>& hd)
     work[g] = (double)b->plans[g]->nx * b->plans[g]->ny * b->plans[g]->nz;
   }
   const int nq = b->pargs.nq;
-  std::vector<int> order(n);
-  for (int g = 0; g < n; ++g) order[g] = g;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return work[a] > work[c]; });
-  std::vector<std::vector<int>> qgrids(nq);
-  std::vector<double> load(nq, 0.0);
-  for (int g : order) {
-    const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    qgrids[q].push_back(g);
-    load[q] += work[g];
-  }
+  const std::vector<std::vector<int>> qgrids = lpt_queues(work, nq);
   std::vector<PersistSeg> segs;
   std::vector<int> qseg(nq + 1, 0);
   std::vector<long> qitems(nq, 0);
   for (int q = 0; q < nq; ++q) {
     qseg[q] = (int)segs.size();
-    struct Key {
-      int key, pos, stage;
-    };
-    std::vector<Key> keys;
-    for (int i = 0; i < (int)qgrids[q].size(); ++i)
-      for (int st = 0; st < (int)stages[qgrids[q][i]].size(); ++st) keys.push_back({st + b->lag * i, i, st});
-    std::stable_sort(keys.begin(), keys.end(),
-                     [](const Key& a, const Key& c) { return a.key != c.key ? a.key < c.key : a.pos < c.pos; });
+    std::vector<int> nstages;
+    for (int g : qgrids[q]) nstages.push_back((int)stages[g].size());
     long first = 0;
-    for (const Key& k : keys) {
+    for (const DiagItem& k : diagonal_order(nstages, b->lag)) {
       const int g = qgrids[q][k.pos];
       const St& x = stages[g][k.stage];
       PersistSeg sg{};
@@ -2273,15 +2071,6 @@ ibp_status_t ibp_batch_destroy(ibp_batch_t b) {
 // fastest.  Choices persist across processes in a cache file (IBP_TUNE_CACHE).
 namespace {
 
-struct TuneCfg {
-  int xdiv, zdiv, ycols;
-  int persist = 0;   // batches: the persistent schedule
-  int lag = 1;       // its diagonal interleave
-  int chunk = 8;     // and the items its blocks claim at once
-  int xsmall = -1;   // plans: general x transform in the small (1) or large (0) LDS tile; -1: keep
-  int zsmall = -1;   // plans: the same for the general z transform
-};
-
 // ---- tuning cache
 // A text file of JSON lines, one per tuned configuration:
 //   {"key": "<arch>/plan/<nx>x<ny>x<nz>/<precision>", "xdiv": 1, "zdiv": 1, "ycols": 4,
@@ -2321,57 +2110,19 @@ std::string batch_key(const ibp_batch_s* b) {
   return k;
 }
 
-int json_int(const std::string& line, const char* name, int dflt) {
-  const std::string pat = std::string("\"") + name + "\":";
-  const size_t at = line.find(pat);
-  if (at == std::string::npos) return dflt;
-  return (int)strtol(line.c_str() + at + pat.size(), nullptr, 10);
-}
-
 // The cached configuration of `key`, if the cache file has one.
 bool tune_cache_get(const std::string& key, TuneCfg* out) {
   const std::string path = tune_cache_path();
   if (path.empty()) return false;
   std::lock_guard<std::mutex> lock(g_tune_mu);
-  FILE* f = fopen(path.c_str(), "r");
-  if (!f) return false;
-  const std::string want = "\"key\": \"" + key + "\"";
-  bool found = false;
-  std::string line;
-  char chunk[4096];
-  while (fgets(chunk, sizeof chunk, f)) {
-    line += chunk;
-    if (line.empty() || line.back() != '\n') continue;   // a line longer than the buffer
-    if (line.find(want) != std::string::npos) {
-      TuneCfg c{};
-      c.xdiv = json_int(line, "xdiv", 1);
-      c.zdiv = json_int(line, "zdiv", 1);
-      c.ycols = json_int(line, "ycols", 0);
-      c.persist = json_int(line, "persistent", 0);
-      c.lag = json_int(line, "lag", 1);
-      c.chunk = json_int(line, "chunk", 8);
-      c.xsmall = json_int(line, "xsmall", -1);
-      c.zsmall = json_int(line, "zsmall", -1);
-      *out = c;
-      found = true;   // keep reading: the last line of a key wins
-    }
-    line.clear();
-  }
-  fclose(f);
-  return found;
+  return tune_file_get(path, key, out);
 }
 
 void tune_cache_put(const std::string& key, const TuneCfg& c, double ms) {
   const std::string path = tune_cache_path();
   if (path.empty()) return;
   std::lock_guard<std::mutex> lock(g_tune_mu);
-  FILE* f = fopen(path.c_str(), "a");
-  if (!f) return;
-  fprintf(f,
-          "{\"key\": \"%s\", \"xdiv\": %d, \"zdiv\": %d, \"ycols\": %d, \"xsmall\": %d, \"zsmall\": %d, "
-          "\"persistent\": %d, \"lag\": %d, \"chunk\": %d, \"ms\": %.6f}\n",
-          key.c_str(), c.xdiv, c.zdiv, c.ycols, c.xsmall, c.zsmall, c.persist, c.lag, c.chunk, ms);
-  fclose(f);
+  tune_file_put(path, key, c, ms);
 }
 
 // Plans: whether the general x / z transforms may take either LDS tile.

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ibp_host.hpp"
+
 namespace ibp {
 
 constexpr int kThreads = 256;   // every kernel uses 256-thread blocks (4 waves)
@@ -110,17 +112,6 @@ __device__ __forceinline__ int qquo(int t, QDiv q) { return (int)((float)t * q.r
 // t - d * (t / d)
 __device__ __forceinline__ int qrem(int t, QDiv q) { return t - __mul24(qquo(t, q), q.d); }
 
-// FFT factorisation handed to kernels by value.
-struct FftPlan {
-  int n;          // sequence length
-  int nst;        // number of stages
-  int radix[16];  // radices in stage order
-  int any;        // 1: a radix above 11 (direct-sum stage; half tiles)
-  int blu;        // 1: Bluestein: the length-n DFT as a length-m cyclic convolution
-  int m;          // Bluestein convolution length (a power of two >= 2n - 1)
-  int mst;        // its stages
-  int mradix[8];  // its radices (8, 4, 2)
-};
 
 // ---------------------------------------------------------------- butterflies
 template <int R, bool INV, typename T>

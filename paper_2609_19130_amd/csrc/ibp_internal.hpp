@@ -454,14 +454,6 @@ hipError_t launch_lines_strided(int P, int K, const LineArgs& a, hipStream_t s);
 hipError_t launch_fill_zero(double* p, long n, hipStream_t s);
 
 // ---------------------------------------------------------------- launchers
-constexpr int kTileX64 = 2048, kTileX32 = 4096;   // complex elements per x-pass block
-constexpr int kTileX64s = 1024, kTileX32s = 2048; // small x tiles (as for z below)
-constexpr int kTileZ64 = 4096, kTileZ32 = 8192;   // complex elements per z-pass block
-// Small z tiles for short lines: the general transform's stage registers
-// scale with the tile (340 VGPRs at 4096 FP64, 167 at 1024), so lines that
-// fit run at two to three times the occupancy.
-constexpr int kTileZ64s = 1024, kTileZ32s = 2048;
-constexpr int kMaxNy = 1536;
 constexpr long kYTileBytes = 104 * 1024;          // staged line-solve tile per block (64 x 12 x 8 FP64: 99 KB)
 
 template <typename T> int tile_x();
@@ -516,8 +508,5 @@ template <typename T>
 int fast_z_cols(int nz);
 hipError_t launch_divergence(const DivArgs& a, hipStream_t s);
 
-// Host-side choice of the y-pass shape: lanes per column P and rows per
-// lane K with P * K >= ny.  Returns false when ny is too large.
-bool ytri_shape(int ny, int* P, int* K);
 
 }  // namespace ibp

@@ -51,29 +51,14 @@ hipError_t launch_check(const ZeroArgs& z, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- dispatch
-// Shapes: P = 32 lanes per column (P = 64 when ny > 768), K rows per lane
-// from {2, 4, 8, 12, 16, 24}; M columns per block so that a row segment is
-// 128 bytes, reduced while the staged tile would exceed 64 KB.
-static constexpr int kKs[] = {2, 4, 8, 12, 16, 24};
+// Shapes (ytri_shape): P = 32 lanes per column (P = 64 when ny > 384), K
+// rows per lane from {2, 4, 8, 12, 16, 24}; M columns per block so that a
+// row segment is 128 bytes, reduced while the staged tile would exceed the
+// LDS budget.
 // (lanes, rows per lane) pairs ytri_shape returns: 32 lanes up to 12 rows,
 // 64 lanes from 8 rows (ny above 384 needs more than 6 rows of 64)
 constexpr bool ytri_pair_used(int P, int K) { return P == 32 ? K <= 12 : K >= 8; }
 
-bool ytri_shape(int ny, int* P, int* K) {
-  if (ny < 2 || ny > kMaxNy) return false;
-  // 64 lanes once a column needs more than 12 rows per lane of 32: 24 rows
-  // per lane hold ~350 VGPRs (one wave per SIMD), 12 rows ~180 (two waves)
-  const int p = ny > 32 * 12 ? 64 : 32;
-  const int need = (ny + p - 1) / p;
-  for (int k : kKs) {
-    if (k >= need) {
-      *P = p;
-      *K = k;
-      return true;
-    }
-  }
-  return false;
-}
 
 static int ycol_override() {
   const char* e = getenv("IBP_YCOLS");   // tuning knob: columns per line-solve block
