@@ -393,7 +393,7 @@ def main():
     ap.add_argument("--ny", type=int, default=384)
     ap.add_argument("--nz", type=int, default=512)
     ap.add_argument("--beta", type=float, default=2.0)
-    ap.add_argument("--mixed-iters", type=int, default=4,
+    ap.add_argument("--mixed-iters", type=int, default=2,
                     help="refinement corrections allowed after the initial FP32 solve (each form reports how "
                          "many it took)")
     ap.add_argument("--forms", default="fp64,mixed,mixed_f64sweep,mixed_f64inv")

@@ -228,7 +228,7 @@ size_t workspace_bytes(const ibp_plan_s* p) {
   b += align256((size_t)p->ny * sizeof(double));   // ghat
   b += align256(sizeof(int));                      // ticket
   b += align256((size_t)(kFctlHead + p->ny) * sizeof(int)); // fused-pass counters
-  b += align256((size_t)max_parts(p) * kPartStride * sizeof(double));
+  b += align256((size_t)(max_parts(p) + kCheckSplitMax) * kPartStride * sizeof(double));
   b += align256(sizeof(Ctl));
   return b;
 }
@@ -249,8 +249,8 @@ void carve_workspace(ibp_plan_s* p) {
   c += align256(sizeof(int));
   p->fctl = reinterpret_cast<int*>(c);
   c += align256((size_t)(kFctlHead + p->ny) * sizeof(int));
-  p->part = reinterpret_cast<double*>(c);
-  c += align256((size_t)max_parts(p) * kPartStride * sizeof(double));
+  p->part = reinterpret_cast<double*>(c);   // partials, then the check's first-level sums
+  c += align256((size_t)(max_parts(p) + kCheckSplitMax) * kPartStride * sizeof(double));
   p->ctl = reinterpret_cast<Ctl*>(c);
 }
 
@@ -1175,6 +1175,7 @@ ZeroArgs zargs(ibp_plan_s* p, long nparts, int init, int mixed, int iter, int fi
   z.dyf = p->dyf;
   z.dyc = p->dyc;
   z.part = p->part;
+  z.part2 = p->part + max_parts(p) * kPartStride;
   z.nparts = nparts;
   z.ctl = p->ctl;
   z.nx = p->nx;
@@ -1445,6 +1446,14 @@ ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStr
     // the residual pass is not chunked: the convergence test needs all of it
     xa.row_begin = 0;
     xa.nrows = (long)p->ny * p->nz;
+    if (k >= 2) {   // residual-only probe of the corrected iterate (runs when predicted to converge)
+      XArgs<float> xp = xa;
+      xp.probe = 1;
+      IBP_LAUNCH(P_XRESONLY, run_xr2c<float>(p, XM_RESID_ONLY, xp, s));
+      ZeroArgs zp = zargs(p, p->nbro, 0, 1, k, 0);
+      zp.probe = 1;
+      IBP_LAUNCH(P_CHECK, launch_check(zp, s));
+    }
     IBP_LAUNCH(P_XRES, run_xr2c<float>(p, XM_RESID, xa, s));
     IBP_LAUNCH(P_CHECK, launch_check(zargs(p, p->nb32, 0, 1, k, 0), s));
     ZfArgs<float> zf = za;

@@ -120,6 +120,7 @@ __global__ __launch_bounds__(kThreads) void k_xr2c_reg(XArgs<T> A) {
   __shared__ Cx<T> lds[RB * rfft::Seq<H>::stride];
   __shared__ double sh[(kThreads / kWave) * kPartStride];
   if ((MODE == XM_RESID || MODE == XM_RESID_ONLY) && A.ctl->done) return;
+  if (MODE == XM_RESID_ONLY && A.probe && !A.ctl->probe) return;
   xr2c_body<T, MODE, H, kThreads>(A, A.row_begin / RB + blockIdx.x, lds, sh, threadIdx.x);
 }
 

@@ -42,7 +42,7 @@ struct alignas(64) Ctl {
   double rel_residual_vw;   // ||V r||_2 / ||V (f - m)||_2, V the cell volumes
   double backward_error;    // ||r||_inf / (||L_h||_inf ||phi||_inf + ||f - m||_inf)
   int nhist;                // entries of hist
-  int pad_;
+  int probe;                // 1: the next pass first tests the iterate with a residual-only pass
   double hist[kHistMax];    // rel_residual of the iterate after k corrections, k = 0, 1, ...
 };
 
@@ -174,6 +174,9 @@ struct XArgs {
   const Cx<T>* bc;
   const Cx<T>* bb;
   const Cx<T>* bt;
+  // XM_RESID_ONLY as a probe: runs only when the latest check predicted
+  // convergence (ctl->probe)
+  int probe = 0;
 };
 
 // f = (D u - q) * rscale for the two cells (2m, 2m+1) of row (j, k): the
@@ -234,6 +237,9 @@ struct ZfArgs {
   const Cx<T>* bc;
   const Cx<T>* bb;
   const Cx<T>* bt;
+  // XM_RESID_ONLY as a probe: runs only when the latest check predicted
+  // convergence (ctl->probe)
+  int probe = 0;
 };
 
 template <typename T, typename U>   // T: spectral storage, U: line-solve arithmetic
@@ -273,7 +279,14 @@ struct ZeroArgs {        // FP64 (0,0) mode and solve control
   double dyf_sum;        // sum_j dyf_j
   int singular;          // Neumann at both walls: remove the mean, solve (0,0) by flux integration
   double lnorm;          // ||L_h||_inf (largest absolute row sum of the operator)
+  int probe = 0;         // check of a probe pass: stops on convergence, else leaves the state to the next check
+  double* part2 = nullptr;   // [kCheckSplitMax][kPartStride]: first-level sums of the check's split reduction
 };
+// The convergence check reduces its partials in two launches once there are
+// more than kCheckSplitMin of them: up to kCheckSplitMax blocks each sum a
+// contiguous slice (in order), then one block reduces those sums.
+constexpr long kCheckSplitMin = 2048;
+constexpr int kCheckSplitMax = 256;
 
 // Fused x/z pass (persistent).  The y planes are dealt out to one work
 // queue per XCD (plane p to queue p % nq) and a block only serves the queue

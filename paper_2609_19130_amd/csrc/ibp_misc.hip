@@ -16,10 +16,11 @@ namespace ibp {
 // so the z neighbours of a tile's edge rows are read by blocks running at
 // the same time.  NT threads own TILE / NT cells each: cell c of the tile
 // (c = t + NT m) is row c / nx, column c % nx.  Two shapes: 512 threads over
-// 2048-cell tiles (nx <= 2048; the faster of the shapes measured), and 1024
-// threads over 4096-cell tiles for wider rows.
+// 2048-cell tiles (nx <= 2048; the faster of the shapes measured), and 512
+// threads over 4096-cell tiles for wider rows (1024-thread blocks would cap
+// the registers at 128 and spill).
 constexpr int kMarchThreads = 512, kMarchTile = 2048;
-constexpr int kMarchThreadsWide = 1024, kMarchTileWide = 4096;
+constexpr int kMarchThreadsWide = 512, kMarchTileWide = 4096;
 // LDS of the projection: (kr + 2) rows of nx, at most three times the tile
 constexpr int kProjLds = 3 * kMarchTile, kProjLdsWide = 3 * kMarchTileWide;
 // blocks per launch to aim for, and the longest walk along y

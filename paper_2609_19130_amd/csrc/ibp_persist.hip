@@ -99,7 +99,7 @@ __device__ __forceinline__ void pb_check(const BatchGrid<T>* D, int g, int flags
   zr.mixed = 1;
   zr.iter = iter;
   zr.final_pass = (flags & PF_FINAL) ? 1 : 0;
-  check_body(zr, sh);
+  check_body<kThreads>(zr, sh);
 }
 
 template <typename T, bool W, int P, int K0>

@@ -32,6 +32,7 @@ __device__ __forceinline__ void xr2c_gen_body(const XArgs<T>& A, const FftPlan& 
   constexpr bool kRes = MODE == XM_RESID || MODE == XM_RESID_ONLY;
   constexpr bool kParts = kRes || sizeof(T) == 4;   // as in the register kernels
   if (kRes && __builtin_amdgcn_readfirstlane(A.ctl->done)) return;
+  if (MODE == XM_RESID_ONLY && A.probe && !__builtin_amdgcn_readfirstlane(A.ctl->probe)) return;
   const int h = A.h, RB = A.rows_per_block, nx = A.nx, nz = A.nz, ny = A.ny;
   const int hs = A.hs ? A.hs : h;   // LDS row stride (Bluestein: the convolution length)
   const bool odd = nx & 1;   // h = nx: single values, no split

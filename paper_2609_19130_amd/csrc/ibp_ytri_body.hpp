@@ -25,10 +25,22 @@ __device__ __forceinline__ void reduce_parts(const ZeroArgs& Z, double* sh, doub
   double v[kPartStride];
 #pragma unroll
   for (int q = 0; q < kPartStride; ++q) v[q] = 0.0;
-  for (long b = threadIdx.x; b < Z.nparts; b += NT) {
-    const double* p = Z.part + b * kPartStride;
+  // records b, b + NT, b + 2 NT, ... in that order; four loaded at a time
+  constexpr int kU = 4;
+  for (long b0 = threadIdx.x; b0 < Z.nparts; b0 += kU * NT) {
+    double r[kU][kPartStride];
 #pragma unroll
-    for (int q = 0; q < kPartStride; ++q) v[q] = ism[q] ? fmax(v[q], p[q]) : v[q] + p[q];
+    for (int u = 0; u < kU; ++u) {
+      const long b = b0 + (long)u * NT < Z.nparts ? b0 + (long)u * NT : b0;
+#pragma unroll
+      for (int q = 0; q < kPartStride; ++q) r[u][q] = Z.part[b * kPartStride + q];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (b0 + (long)u * NT >= Z.nparts) break;
+#pragma unroll
+      for (int q = 0; q < kPartStride; ++q) v[q] = ism[q] ? fmax(v[q], r[u][q]) : v[q] + r[u][q];
+    }
   }
   block_reduce<kPartStride, NT>(v, ism, sh);
   for (int i = 0; i < kPartStride; ++i) out[i] = v[i];
@@ -136,6 +148,7 @@ __device__ __forceinline__ void zero_mode_scans(const ZeroArgs& Z, const double 
     c->rel_residual_vw = __builtin_nan("");
     c->backward_error = __builtin_nan("");
     c->nhist = 0;
+    c->probe = 0;
   }
 }
 
@@ -202,6 +215,27 @@ template <int M, int P, int K>
 __host__ __device__ constexpr long ytile_slots() { return (long)P * (K * M + 1); }
 
 inline long ytile_slots_host(int M, int P, int K) { return (long)P * (K * M + 1); }
+
+// Reciprocal by the hardware estimate refined with Newton's iteration
+// y <- y + y (1 - x y) (two steps in FP64, one in FP32): within an ulp or
+// so of 1/x for the positive, normal pivots of the line solves, at a
+// fraction of the latency of a correctly rounded division.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ float rcp_nr(float x) {
+  const float y = __builtin_amdgcn_rcpf(x);
+  return fmaf(y, fmaf(-x, y, 1.0f), y);
+}
+// Exponent e of x = mant 2^e, 0.5 <= mant < 1, and exact scaling by 2^k.
+__device__ __forceinline__ int exp2_of(double x) { return __builtin_amdgcn_frexp_exp(x); }
+__device__ __forceinline__ int exp2_of(float x) { return __builtin_amdgcn_frexp_expf(x); }
+__device__ __forceinline__ double scale2(double x, int k) { return __builtin_amdgcn_ldexp(x, k); }
+__device__ __forceinline__ float scale2(float x, int k) { return __builtin_amdgcn_ldexpf(x, k); }
 
 template <typename U>
 __device__ __forceinline__ U shfl_up_w(U v, int d, int w) { return __shfl_up(v, d, w); }
@@ -305,20 +339,22 @@ __device__ __forceinline__ void ytri_solve(const YArgs<T, U>& A, long q0, Cx<T>*
   const U l_ = (s + (i) < ny) ? L : U(1);
 
   // ---- scan 1: eps_out = (mA eps_in + mB) / (mC eps_in + mD) over the
-  // partition, all entries >= 0, normalised to mC + mD = 1 (the denominator
-  // at eps_in = 1, positive for every row; the constant term mD alone can
-  // vanish, e.g. rows with shift 0 under a Neumann upper wall)
+  // partition, all entries >= 0, rescaled by a power of two (exact) so that
+  // mC + mD, the denominator at eps_in = 1 and positive for every row, lies
+  // in [1/2, 1) (the constant term mD alone can vanish, e.g. rows with
+  // shift 0 under a Neumann upper wall); a Moebius map is unchanged by a
+  // common factor of its four entries
   U mA = U(1), mB = U(0), mC = U(0), mD = U(1);
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     IBP_COEF(i, a, c, l)
     const U n00 = a * mA + l * mC, n01 = a * mB + l * mD;
     const U n10 = a * mA + (c + l) * mC, n11 = a * mB + (c + l) * mD;
-    const U inv = U(1) / (n10 + n11);
-    mA = n00 * inv;
-    mB = n01 * inv;
-    mC = n10 * inv;
-    mD = n11 * inv;
+    const int ex = -exp2_of(n10 + n11);
+    mA = scale2(n00, ex);
+    mB = scale2(n01, ex);
+    mC = scale2(n10, ex);
+    mD = scale2(n11, ex);
   }
 #pragma unroll
   for (int off = 1; off < P; off <<= 1) {   // inclusive prefix: mine after the earlier ones
@@ -327,11 +363,11 @@ __device__ __forceinline__ void ytri_solve(const YArgs<T, U>& A, long q0, Cx<T>*
     if (p >= off) {
       const U n00 = mA * pA + mB * pC, n01 = mA * pB + mB * pD;
       const U n10 = mC * pA + mD * pC, n11 = mC * pB + mD * pD;
-      const U inv = U(1) / (n10 + n11);
-      mA = n00 * inv;
-      mB = n01 * inv;
-      mC = n10 * inv;
-      mD = n11 * inv;
+      const int ex = -exp2_of(n10 + n11);
+      mA = scale2(n00, ex);
+      mB = scale2(n01, ex);
+      mC = scale2(n10, ex);
+      mD = scale2(n11, ex);
     }
   }
   {
@@ -347,7 +383,7 @@ __device__ __forceinline__ void ytri_solve(const YArgs<T, U>& A, long q0, Cx<T>*
     for (int i = 0; i < K; ++i) {
       IBP_COEF(i, a, c, l)
       const U n = l + a * e;
-      const U r = U(1) / (c + n);
+      const U r = rcp_nr(c + n);
       e = n * r;
       ca[i] = a * r;
       cc[i] = c * r;
@@ -451,10 +487,12 @@ __device__ __forceinline__ void ytri_solve(const YArgs<T, U>& A, long q0, Cx<T>*
 // Convergence test of a refinement pass (one block): reduce the partials of
 // the residual pass, record ||r||/||f - m||, and either stop the refinement or
 // set the FP32 input scale of the next pass.
+template <int NT>
 __device__ __forceinline__ void check_body(const ZeroArgs& Z, double* sh) {
   if (__builtin_amdgcn_readfirstlane(Z.ctl->done)) return;
+  if (Z.probe && !__builtin_amdgcn_readfirstlane(Z.ctl->probe)) return;
   double p[kPartStride];
-  reduce_parts<kThreads>(Z, sh, p);
+  reduce_parts<NT>(Z, sh, p);
   if (threadIdx.x != 0) return;
   Ctl* c = Z.ctl;
   auto ratio = [](double num2, double den2) {
@@ -484,12 +522,23 @@ __device__ __forceinline__ void check_body(const ZeroArgs& Z, double* sh) {
   } else if (eta <= kEtaFloor) {   // at the FP64 floor: corrections cannot lower the residual
     c->done = 1;
     c->converged = 2;
+  } else if (Z.probe) {
+    // not converged: the full residual pass of the same iterate follows and
+    // its check decides the next step
   } else if (Z.final_pass || !(rel > Z.rtol)) {   // last pass, or a NaN residual
     c->done = 1;
     c->converged = 0;
   } else {
     c->iters = Z.iter;
     c->scale[(Z.iter + 1) & 1] = next_scale(p[2]);
+    // Predict the residual after this correction from the contraction so
+    // far (the first correction: the initial solve's own relative
+    // residual); when it should meet rtol, the next pass tests the
+    // corrected iterate with a residual-only pass first and skips the
+    // residual transform if it has converged.
+    const double prev = Z.iter >= 2 && Z.iter - 2 < kHistMax ? c->hist[Z.iter - 2] : 1.0;
+    const double pred = rel * (rel / prev);
+    c->probe = pred <= Z.rtol ? 1 : 0;
   }
 }
 
