@@ -222,13 +222,13 @@ size_t spec32_bytes(const ibp_plan_s* p) {
 }
 
 size_t workspace_bytes(const ibp_plan_s* p) {
-  size_t b = align256(spec64_bytes(p)) + align256(spec32_bytes(p));
-  b += align256((size_t)p->ny * p->nz * sizeof(double));
+  size_t b = align256(spec64_bytes(p)) + align256(2 * spec32_bytes(p));
+  b += align256(2 * (size_t)p->ny * p->nz * sizeof(double));
   b += align256((size_t)p->ny * sizeof(double));   // phi00
   b += align256((size_t)p->ny * sizeof(double));   // ghat
   b += align256(sizeof(int));                      // ticket
   b += align256((size_t)(kFctlHead + p->ny) * sizeof(int)); // fused-pass counters
-  b += align256((size_t)(max_parts(p) + kCheckSplitMax) * kPartStride * sizeof(double));
+  b += align256((size_t)(2 * max_parts(p) + kCheckSplitMax) * kPartStride * sizeof(double));
   b += align256(sizeof(Ctl));
   return b;
 }
@@ -237,10 +237,10 @@ void carve_workspace(ibp_plan_s* p) {
   char* c = static_cast<char*>(p->ws);
   p->spec64 = reinterpret_cast<Cx<double>*>(c);
   c += align256(spec64_bytes(p));
-  p->spec32 = reinterpret_cast<Cx<float>*>(c);
-  c += align256(spec32_bytes(p));
-  p->rowsum = reinterpret_cast<double*>(c);
-  c += align256((size_t)p->ny * p->nz * sizeof(double));
+  p->spec32 = reinterpret_cast<Cx<float>*>(c);   // two FP32 half spectra (spec32_second)
+  c += align256(2 * spec32_bytes(p));
+  p->rowsum = reinterpret_cast<double*>(c);       // two row-sum arrays (rowsum_second)
+  c += align256(2 * (size_t)p->ny * p->nz * sizeof(double));
   p->phi00 = reinterpret_cast<double*>(c);
   c += align256((size_t)p->ny * sizeof(double));
   p->ghat = reinterpret_cast<double*>(c);
@@ -249,10 +249,19 @@ void carve_workspace(ibp_plan_s* p) {
   c += align256(sizeof(int));
   p->fctl = reinterpret_cast<int*>(c);
   c += align256((size_t)(kFctlHead + p->ny) * sizeof(int));
-  p->part = reinterpret_cast<double*>(c);   // partials, then the check's first-level sums
-  c += align256((size_t)(max_parts(p) + kCheckSplitMax) * kPartStride * sizeof(double));
+  p->part = reinterpret_cast<double*>(c);   // two partial regions (part_second), then the check's first-level sums
+  c += align256((size_t)(2 * max_parts(p) + kCheckSplitMax) * kPartStride * sizeof(double));
   p->ctl = reinterpret_cast<Ctl*>(c);
 }
+
+// The second FP32 half spectrum, row-sum array and partial region of the
+// workspace (the mixed form's direct first correction keeps the right-hand
+// side's while it builds the residual's).
+Cx<float>* spec32_second(const ibp_plan_s* p) {
+  return p->spec32 + (size_t)p->ny * spec_plane_stride<float>(p->hp, p->nz);
+}
+double* rowsum_second(const ibp_plan_s* p) { return p->rowsum + (size_t)p->ny * p->nz; }
+double* part_second(const ibp_plan_s* p) { return p->part + max_parts(p) * kPartStride; }
 
 ibp_status_t check_dims(int nx, int ny, int nz, FftPlan* fpx, FftPlan* fpz) {
   switch (dims_status(nx, ny, nz, fpx, fpz)) {
@@ -355,13 +364,14 @@ void release(ibp_plan_s* p) {
 
 enum Pass {
   P_XR2C, P_ZFWD, P_Y, P_ZINV, P_XC2R, P_XRES, P_CHECK, P_XRESONLY, P_XC2R_ADD, P_DIV,
-  P_XZF, P_ZXI, P_ZXI_ADD, P_PROJ, P_VX, P_VZ, P_VY, P_COUNT
+  P_XZF, P_ZXI, P_ZXI_ADD, P_PROJ, P_VX, P_VZ, P_VY, P_ZERO, P_ZUP, P_XRT, P_YADD, P_COUNT
 };
 const char* const kPassName[P_COUNT] = {"x_r2c",  "z_fwd",      "y_solve",    "z_inv",
                                         "x_c2r",  "x_resid_r2c", "check",      "x_resid_only",
                                         "x_c2r_add", "divergence", "xz_fwd",   "zx_inv",
                                         "zx_inv_add", "projection", "visc_x", "visc_z",
-                                        "visc_y"};
+                                        "visc_y", "zero_mode", "z_inv_up", "x_roundtrip",
+                                        "y_solve_add"};
 
 // Algorithmic bytes of one launch of each pass (each input element read
 // once, each output element written once).  N = nx ny nz cells, Nh =
@@ -390,6 +400,9 @@ double pass_bytes(const ibp_plan_s* p, int pass) {
     case P_VX:
     case P_VZ:
     case P_VY: return 16.0 * N;                    // the field in and out
+    case P_ZUP: return 24.0 * Nh;                  // FP32 spectrum in, FP64 out
+    case P_XRT: return 24.0 * Nh + 8.0 * N;        // FP64 spectrum and f in, FP32 spectrum out
+    case P_YADD: return 40.0 * Nh;                 // FP32 in, FP64 read and written
     default: return 0.0;
   }
 }
@@ -1175,7 +1188,7 @@ ZeroArgs zargs(ibp_plan_s* p, long nparts, int init, int mixed, int iter, int fi
   z.dyf = p->dyf;
   z.dyc = p->dyc;
   z.part = p->part;
-  z.part2 = p->part + max_parts(p) * kPartStride;
+  z.part2 = p->part + 2 * max_parts(p) * kPartStride;
   z.nparts = nparts;
   z.ctl = p->ctl;
   z.nx = p->nx;
@@ -1394,6 +1407,15 @@ ibp_status_t inverse_f64(ibp_plan_s* p, const double* rhs, double* phi, int cmod
   return IBP_SUCCESS;
 }
 
+// IBP_MIXED_F64INV on the register kernels (power-of-two x and z lengths
+// in their fused range), unchunked, with at least one correction allowed:
+// the first correction is computed without forming the initial iterate.
+bool direct_first_correction(const ibp_plan_s* p) {
+  const bool hx = p->h >= 32 && p->h <= 512 && p->nx == 2 * p->h;
+  const bool hz = p->nz >= 32 && p->nz <= 1024;
+  return p->xfast && p->zfast && hx && hz && !p->fused && p->chunk <= 0 && p->max_iters >= 1;
+}
+
 // Mixed forms: FP32 spectral passes wrapped in FP64 iterative refinement.
 //   pass 0: phi = solve32(f)                      (rows summed in FP64 for (0,0))
 //   pass k: r = f - m - L_h phi (FP64), stop if ||r|| <= rtol ||f - m||,
@@ -1435,13 +1457,66 @@ ibp_status_t enqueue_mixed(ibp_plan_s* p, const double* rhs, double* phi, hipStr
     }
     return launch_ytri<float, U>(p->yP, p->yK, p->ycols, ya, z, s);
   };
-  IBP_LAUNCH(P_Y, ysolve(zargs(p, np0, 1, 1, 0, 0)));
-  st = f64inv ? inverse_f64(p, rhs, phi, CM_SET, 0, 0, s) : inverse_zx<float>(p, xa, CM_SET, P_XC2R, za, s);
-  if (st != IBP_SUCCESS) return st;
+  int k0 = 1;   // first refinement pass of the loop below
+  if (f64inv && direct_first_correction(p)) {
+    // The initial iterate phi_0 = IFFT64(solve(F32)) is never formed: its
+    // residual is f - IFFT64(F32) (the rounding of the FP32 forward
+    // transform; the line solve and the FP64 inverse add only FP64
+    // rounding), so the first correction is solved from that and the two
+    // solutions are added in the spectrum, inverted once.  (0,0) mode of a
+    // singular problem: taken from the FP64 row sums as in every pass, so
+    // r0 drops the FP32 spectrum's (0,0) coefficient and subtracts the exact
+    // plane means instead.
+    ZeroArgs z0 = zargs(p, np0, 1, 1, 0, 0);
+    IBP_LAUNCH(P_ZERO, launch_zero_mode(z0, s));   // solve control, mean, (0,0) mode of f
+    const long rs64 = spec_row_stride<double>(p->hp), ps64 = spec_plane_stride<double>(p->hp, p->nz);
+    ZupArgs zu{p->spec32, rs, ps, p->spec64, rs64, ps64, p->twz, p->nz, p->hp, p->ny, p->singular() ? 1 : 0};
+    IBP_LAUNCH(P_ZUP, launch_zinv_up(zu, s));
+    RtArgs rt{};
+    rt.x = xargs<float>(p, rhs, phi, phi, spec32_second(p), p->twx32, p->rb32, 1);
+    rt.x.row_begin = 0;
+    rt.x.nrows = (long)p->ny * p->nz;
+    rt.x.rowsum = rowsum_second(p);
+    rt.x.part = part_second(p);
+    rt.t64 = p->spec64;
+    rt.trs = rs64;
+    rt.tps = ps64;
+    rt.twx64 = p->twx;
+    rt.ghat = p->ghat;
+    rt.sub_mean = p->singular() ? 1 : 0;
+    IBP_LAUNCH(P_XRT, launch_x_roundtrip(rt, s));
+    // the right-hand side's line solve (its (0,0) mode was solved above)
+    IBP_LAUNCH(P_Y, ysolve(zargs(p, np0, 0, 1, 0, 0)));
+    // record the residual of phi_0 and prepare the correction (never stops:
+    // the solution is not formed yet)
+    ZeroArgs zc = zargs(p, p->nb32, 0, 1, 1, 0);
+    zc.part = part_second(p);
+    zc.nostop = 1;
+    IBP_LAUNCH(P_CHECK, launch_check(zc, s));
+    // the correction, added to the FP64 spectrum and to the (0,0) mode
+    ZfArgs<float> zr = za;
+    zr.spec = spec32_second(p);
+    zr.plane0 = 0;
+    IBP_LAUNCH(P_ZFWD, run_zfft<float>(p, false, zr, p->ny, s));
+    YArgs<float, U> yr = ya;
+    yr.spec = spec32_second(p);
+    yr.add_iter = 1;
+    ZeroArgs zy = zargs(p, p->nb32, 0, 1, 1, 0);
+    zy.rowsum = rowsum_second(p);
+    zy.phi00_add = 1;
+    if constexpr (sizeof(U) == 8) IBP_LAUNCH(P_YADD, launch_ytri_out64(p->yP, p->yK, yr, zy, s));
+    st = inverse_f64(p, rhs, phi, CM_SET, 1, 0, s);
+    if (st != IBP_SUCCESS) return st;
+    k0 = 2;
+  } else {
+    IBP_LAUNCH(P_Y, ysolve(zargs(p, np0, 1, 1, 0, 0)));
+    st = f64inv ? inverse_f64(p, rhs, phi, CM_SET, 0, 0, s) : inverse_zx<float>(p, xa, CM_SET, P_XC2R, za, s);
+    if (st != IBP_SUCCESS) return st;
+  }
 
   za.check_done = 1;
   ya.check_done = 1;
-  for (int k = 1; k <= p->max_iters; ++k) {
+  for (int k = k0; k <= p->max_iters; ++k) {
     xa.iter = k;
     // the residual pass is not chunked: the convergence test needs all of it
     xa.row_begin = 0;

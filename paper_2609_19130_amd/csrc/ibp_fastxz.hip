@@ -291,6 +291,177 @@ __global__ __launch_bounds__(C*(NZ / kE)) void k_zfft_reg(ZfArgs<T> A) {
 }
 
 
+// ---------------------------------------------------------------- FP64 inverse of an FP32 spectrum
+// FP64 inverse z transform of kx columns [colblk C, colblk C + C) of plane
+// j of the FP32 spectrum, written to the FP64 spectrum (the first step of
+// the mixed form's direct first correction; ZupArgs).
+template <int NZ, int C>
+__global__ __launch_bounds__(C*(NZ / kE)) void k_zinv_up(ZupArgs A) {
+  constexpr int TT = NZ / kE;
+  constexpr int SS = rfft::Seq<NZ>::stride;
+  using P = rfft::Plan<NZ, true, double>;
+  constexpr int RL = P::last_radix();
+  __shared__ Cx<double> lds[C * SS];
+  const int colblk = blockIdx.x, j = blockIdx.y;
+  const int tid = threadIdx.x, c = tid % C, t = tid / C;
+  const int col = colblk * C + c;
+  const bool live = col < A.hp;
+  const Cx<float>* in = A.in + (size_t)j * A.ips;
+  Cx<double> v[kE];
+#pragma unroll
+  for (int i = 0; i < kE; ++i) {
+    const int z = t + TT * i;
+    const Cx<float> w = live ? in[(size_t)z * A.irs + col] : Cx<float>{0.0f, 0.0f};
+    v[i] = Cx<double>{double(w.x), double(w.y)};
+    if (A.zero00 && col == 0 && z == 0) v[i] = Cx<double>{0.0, 0.0};
+  }
+  P::run(v, t, lds + c * SS, A.twz, 1);
+  if (!live) return;   // no barrier follows
+  Cx<double>* out = A.out + (size_t)j * A.ops;
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const int z = t + TT * final_index<RL>(q);
+    out[(size_t)z * A.ors + col] = v[q];
+  }
+}
+
+// Per row: FP64 inverse x transform of the z-inverted FP64 spectrum, r0 =
+// f - t - (plane mean), then the FP32 forward x transform of r0 * s into the
+// FP32 half spectrum, with the row sums and norm partials of r0 (RtArgs).
+template <int H>
+__global__ __launch_bounds__(kThreads) void k_x_roundtrip(RtArgs R) {
+  constexpr int TT = H / kE;
+  constexpr int SS = rfft::Seq<H>::stride;
+  constexpr int RB = kThreads / TT;
+  using PI = rfft::Plan<H, true, double>;
+  using PF = rfft::Plan<H, false, float>;
+  constexpr int RLI = PI::last_radix();
+  constexpr int RLF = PF::last_radix();
+  __shared__ Cx<double> lds[RB * SS];
+  __shared__ double sh[(kThreads / kWave) * kPartStride];
+  const XArgs<float>& A = R.x;
+  const int tid = threadIdx.x, lr = tid / TT, t = tid % TT;
+  const long blk = blockIdx.x;
+  const long row = blk * RB + lr;
+  const bool live = row < A.nrows;
+  const int nz = A.nz, nx = A.nx;
+  const int j = live ? (int)(row / nz) : 0;
+  // the row of f, loaded with the spectrum (pair m = t + TT i in fv[i])
+  double2 fv[kE];
+  {
+    const double* frow = A.f + (live ? row : 0) * nx;
+#pragma unroll
+    for (int i = 0; i < kE; ++i)
+      fv[i] = live ? *reinterpret_cast<const double2*>(frow + 2 * (t + TT * i)) : make_double2(0.0, 0.0);
+  }
+  // inverse x transform (FP64) of the row, as in the C2R pass
+  Cx<double> v[kE];
+  {
+    const Cx<double>* trow = R.t64 + (live ? row * R.trs + (row / nz) * (R.tps - (long)nz * R.trs) : 0);
+#pragma unroll
+    for (int i = 0; i < kE; ++i) {
+      const int kk = t + TT * i;
+      Cx<double> Xk{0.0, 0.0}, Xm{0.0, 0.0};
+      if (live) {
+        Xk = trow[kk];
+        Xm = trow[H - kk];
+      }
+      if (kk == 0) {
+        Xk.y = 0.0;
+        Xm.y = 0.0;
+      }
+      const Cx<double> Xmc = cconj(Xm);
+      const Cx<double> E = cscale(cadd(Xk, Xmc), 0.5);
+      const Cx<double> D = cscale(csub(Xk, Xmc), 0.5);
+      const Cx<double> O = cmul(cconj(R.twx64[kk]), D);
+      v[i] = Cx<double>{E.x - O.y, E.y + O.x};
+    }
+  }
+  PI::run(v, t, lds + lr * SS, R.twx64, 2);
+  __syncthreads();   // the FP32 transform below reuses the LDS rows
+  const double cs = A.out_scale;
+  const double pmean = (R.sub_mean && live) ? R.ghat[j] * A.inv_nxnz : 0.0;
+  const double mean = A.ctl->removed_mean;
+  const double s = A.ctl->scale[A.iter & 1];
+  const double dyfj = live ? A.dyf[j] : 0.0;
+  Cx<float> w[kE];
+  double rs = 0.0;
+  NormAcc acc;
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const int i = final_index<RLI>(q);   // inverse output q is pair m = t + TT i
+    double r0 = 0.0, r1 = 0.0;
+    if (live) {
+      const double2 f = fv[i];
+      r0 = f.x - v[q].x * cs - pmean;
+      r1 = f.y - v[q].y * cs - pmean;
+      acc.pair(r0, r1, f.x - mean, f.y - mean, dyfj * dyfj);
+      rs += r0 + r1;
+    }
+    w[i] = Cx<float>{float(r0 * s), float(r1 * s)};
+  }
+#pragma unroll
+  for (int off = TT / 2; off > 0; off >>= 1) rs += __shfl_xor(rs, off, kWave);
+  if (live && t == 0) A.rowsum[row] = rs;
+  acc.write<kThreads, true>(A.part, blk, sh);
+  // forward x transform (FP32) of r0 * s, as in the R2C pass
+  Cx<float>* my = reinterpret_cast<Cx<float>*>(lds) + lr * SS;
+  PF::run(w, t, my, A.twx, 2);
+#pragma unroll
+  for (int q = 0; q < kE; ++q) my[pad8(t + TT * final_index<RLF>(q))] = w[q];
+  __syncthreads();
+  Cx<float>* srow = A.spec + row * A.rs + (row / nz) * (A.ps - (long)nz * A.rs);
+#pragma unroll
+  for (int i = 0; i < kE && live; ++i) {
+    const int kk = t + TT * i;
+    const Cx<float> Zk = my[pad8(kk)];
+    const Cx<float> Zc = cconj(my[pad8((H - kk) & (H - 1))]);
+    const Cx<float> E = cscale(cadd(Zk, Zc), 0.5f);
+    const Cx<float> D = csub(Zk, Zc);
+    const Cx<float> O = Cx<float>{0.5f * D.y, -0.5f * D.x};   // D / 2i
+    const Cx<float> WO = cmul(A.twx[kk], O);
+    srow[kk] = cadd(E, WO);
+    if (kk == 0) srow[H] = cconj(csub(E, WO));
+  }
+}
+
+hipError_t launch_zinv_up(const ZupArgs& a, hipStream_t s) {
+  // 16 columns per block (64-byte FP32 input segments measured 7% slower
+  // than the 128-byte ones of 16 columns), 8 for 1024-point lines (LDS)
+  auto go = [&](auto kern, int nz, int C) {
+    if (C * (nz / kE) > 1024) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((a.hp + C - 1) / C), (unsigned)a.ny);
+    hipLaunchKernelGGL(kern, grid, dim3(C * (nz / kE)), 0, s, a);
+    return hipGetLastError();
+  };
+  switch (a.nz) {
+    case 32: return go(k_zinv_up<32, 16>, 32, 16);
+    case 64: return go(k_zinv_up<64, 16>, 64, 16);
+    case 128: return go(k_zinv_up<128, 16>, 128, 16);
+    case 256: return go(k_zinv_up<256, 16>, 256, 16);
+    case 512: return go(k_zinv_up<512, 16>, 512, 16);
+    case 1024: return go(k_zinv_up<1024, 8>, 1024, 8);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_x_roundtrip(const RtArgs& a, hipStream_t s) {
+  auto go = [&](auto kern, int H) {
+    const int RB = kThreads / (H / kE);
+    const long nb = (a.x.nrows + RB - 1) / RB;
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+  };
+  switch (a.x.h) {
+    case 32: return go(k_x_roundtrip<32>, 32);
+    case 64: return go(k_x_roundtrip<64>, 64);
+    case 128: return go(k_x_roundtrip<128>, 128);
+    case 256: return go(k_x_roundtrip<256>, 256);
+    case 512: return go(k_x_roundtrip<512>, 512);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 // ---------------------------------------------------------------- fused x/z
 // Item g of the round sequence -> (stage, plane, index within the plane).
 __device__ __forceinline__ void decode_item(long g, int ny, int D, int n1, int n2, int* stage, int* plane,

@@ -237,9 +237,6 @@ struct ZfArgs {
   const Cx<T>* bc;
   const Cx<T>* bb;
   const Cx<T>* bt;
-  // XM_RESID_ONLY as a probe: runs only when the latest check predicted
-  // convergence (ctl->probe)
-  int probe = 0;
 };
 
 template <typename T, typename U>   // T: spectral storage, U: line-solve arithmetic
@@ -255,10 +252,42 @@ struct YArgs {
   int ny, hp, check_done;
   int singular;          // Neumann at both walls: column (0,0) is left to the FP64 (0,0) path
   // IBP_MIXED_F64INV: the solution goes to this FP64 half spectrum (row and
-  // plane strides out_rs, out_ps) instead of back into `spec`
+  // plane strides out_rs, out_ps) instead of back into `spec`; add_iter > 0:
+  // added to it instead, divided by the input scale ctl->scale[add_iter & 1]
   Cx<double>* out64;
   long out_rs, out_ps;
+  int add_iter = 0;
 };
+
+// IBP_MIXED_F64INV, first correction without the initial iterate: the FP64
+// inverse z transform of the FP32 right-hand-side spectrum (strides irs,
+// ips) into an FP64 half spectrum (ors, ops).  zero00: the (kx, kz) = (0, 0)
+// coefficient is dropped (the singular problem's plane means come from the
+// FP64 row sums instead).
+struct ZupArgs {
+  const Cx<float>* in;
+  long irs, ips;
+  Cx<double>* out;
+  long ors, ops;
+  const Cx<double>* twz;   // FP64 W_nz^e
+  int nz, hp, ny;
+  int zero00;
+};
+// ... and the x pass that follows it: per row, t = FP64 inverse x transform
+// of the z-inverted spectrum (x.out_scale included), r0 = f - t - ghat[j] /
+// (nx nz) (the plane mean only when zero00 was set), written as the FP32
+// half spectrum of r0 * ctl->scale[x.iter & 1] (x.spec), with the FP64 row
+// sums of r0 (x.rowsum) and its norm partials (x.part).
+struct RtArgs {
+  XArgs<float> x;
+  const Cx<double>* t64;
+  long trs, tps;
+  const Cx<double>* twx64;   // FP64 W_nx^e
+  const double* ghat;
+  int sub_mean;
+};
+hipError_t launch_zinv_up(const ZupArgs& a, hipStream_t s);
+hipError_t launch_x_roundtrip(const RtArgs& a, hipStream_t s);
 
 struct ZeroArgs {        // FP64 (0,0) mode and solve control
   const double* rowsum;
@@ -280,6 +309,8 @@ struct ZeroArgs {        // FP64 (0,0) mode and solve control
   int singular;          // Neumann at both walls: remove the mean, solve (0,0) by flux integration
   double lnorm;          // ||L_h||_inf (largest absolute row sum of the operator)
   int probe = 0;         // check of a probe pass: stops on convergence, else leaves the state to the next check
+  int nostop = 0;        // check that records the residual and prepares the next correction but never stops
+  int phi00_add = 0;     // (0,0) mode: add this solve's solution to phi00 instead of replacing it
   double* part2 = nullptr;   // [kCheckSplitMax][kPartStride]: first-level sums of the check's split reduction
 };
 // The convergence check reduces its partials in two launches once there are
@@ -491,6 +522,8 @@ hipError_t launch_ytri(int P, int K, int want, const YArgs<T, U>& a, const ZeroA
 // FP32 half spectrum in, FP64 arithmetic, FP64 half spectrum a.out64 out.
 hipError_t launch_ytri_out64(int P, int K, const YArgs<float, double>& a, const ZeroArgs& z, hipStream_t s);
 hipError_t launch_check(const ZeroArgs& z, hipStream_t s);
+// The (0,0)-mode work of a line-solve pass on its own (zero_blocks(ny) blocks).
+hipError_t launch_zero_mode(const ZeroArgs& z, hipStream_t s);
 
 // Register-FFT kernels for power-of-two lengths 32..1024 (ibp_fastxz.hip).
 template <typename T>

@@ -35,17 +35,55 @@ void k_ytri(YArgs<T, U> A, ZeroArgs Z) {
   ytri_body<T, U, M, P, K>(A, Z, blockIdx.x, tile, sizeof(T) == 8);
 }
 
-template <int M, int P, int K>
+template <int M, int P, int K, bool ADD>
 __global__ __launch_bounds__(M * P) void k_ytri_out64(YArgs<float, double> A, ZeroArgs Z) {
   __shared__ Cx<double> tile[ytile_slots<M, P, K>()];
   // kx-major column order: the FP64 inverse z pass then starts on the
   // groups written last (measured: z pass -8%, this pass +5%)
-  ytri_body<float, double, M, P, K, true>(A, Z, blockIdx.x, reinterpret_cast<Cx<float>*>(tile), true);
+  ytri_body<float, double, M, P, K, true, ADD>(A, Z, blockIdx.x, reinterpret_cast<Cx<float>*>(tile), true);
 }
 
 __global__ __launch_bounds__(kThreads) void k_check(ZeroArgs Z) {
   __shared__ double sh[(kThreads / kWave) * kPartStride];
   check_body<kThreads>(Z, sh);
+}
+
+__global__ __launch_bounds__(kThreads) void k_zero_mode(ZeroArgs Z) {
+  zero_mode_part<kThreads>(Z, blockIdx.x, gridDim.x);
+}
+
+// First level of the initial pass's partial reduction (block b sums
+// partials [b S, (b + 1) S) into Z.part2[b]); no solve state is read.
+__global__ __launch_bounds__(kThreads) void k_part_split(ZeroArgs Z, long S) {
+  __shared__ double sh[(kThreads / kWave) * kPartStride];
+  const long b0 = (long)blockIdx.x * S;
+  const long n = Z.nparts - b0 < S ? Z.nparts - b0 : S;
+  ZeroArgs z = Z;
+  z.part = Z.part + b0 * kPartStride;
+  z.nparts = n > 0 ? n : 0;
+  double v[kPartStride];
+  reduce_parts<kThreads>(z, sh, v);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < kPartStride; ++q) Z.part2[blockIdx.x * kPartStride + q] = v[q];
+  }
+}
+
+hipError_t launch_zero_mode(const ZeroArgs& z, hipStream_t s) {
+  ZeroArgs z2 = z;
+  if (z.init && z.nparts > kCheckSplitMin && z.part2 != nullptr) {   // the initial norms in two levels
+    const long G = std::min<long>(kCheckSplitMax, (z.nparts + kCheckSplitMin / 2 - 1) / (kCheckSplitMin / 2));
+    const long S = (z.nparts + G - 1) / G;
+    hipLaunchKernelGGL(k_part_split, dim3((unsigned)G), dim3(kThreads), 0, s, z, S);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    z2.part = z.part2;
+    z2.nparts = G;
+  }
+  // one wave per plane sum
+  const int nb = std::max(1, std::min(z.ny / (kThreads / kWave), 128));
+  hipLaunchKernelGGL(k_zero_mode, dim3((unsigned)nb), dim3(kThreads), 0, s, z2);
+  return hipGetLastError();
 }
 
 // First level of the split check: block b sums partials [b S, (b + 1) S)
@@ -169,7 +207,10 @@ static hipError_t launch_out64_mp(int K, const YArgs<float, double>& a, const Ze
     // only tiles within the LDS budget are instantiated
     if constexpr (ytile_slots<M, P, KK>() * (long)sizeof(Cx<double>) <= kYTileBytes) {
       const long nb = (a.Q + M - 1) / M + zero_blocks(a.ny);
-      hipLaunchKernelGGL((k_ytri_out64<M, P, KK>), dim3((unsigned)nb), dim3(M * P), 0, s, a, z);
+      if (a.add_iter)
+        hipLaunchKernelGGL((k_ytri_out64<M, P, KK, true>), dim3((unsigned)nb), dim3(M * P), 0, s, a, z);
+      else
+        hipLaunchKernelGGL((k_ytri_out64<M, P, KK, false>), dim3((unsigned)nb), dim3(M * P), 0, s, a, z);
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;

@@ -128,7 +128,8 @@ __device__ __forceinline__ void zero_mode_scans(const ZeroArgs& Z, const double 
       const double fj = flux;
       flux += Z.dyf[j] * (gh[j] - mz);
       X += j > 0 ? Z.dyc[j] * fj : 0.0;
-      Z.phi00[j] = Z.singular ? X - xbar : 0.0;
+      const double v = Z.singular ? X - xbar : 0.0;
+      Z.phi00[j] = Z.phi00_add ? Z.phi00[j] + v : v;
     }
   }
   if (Z.init && lane == 0) {
@@ -159,17 +160,19 @@ __device__ __forceinline__ void zero_mode_scans(const ZeroArgs& Z, const double 
 // for the next launch.  A handful of blocks keeps the plane sums parallel
 // while each grid pays only a handful of device-scope fences (one per
 // plane, ny per launch, measured slower on batches of short grids).
+// nzb: the number of blocks taking part (zero_blocks(ny) inside a line-solve
+// launch; more when the (0,0) mode runs on its own).
 template <int NT>
-__device__ __forceinline__ void zero_mode_part(const ZeroArgs& Z, int b) {
+__device__ __forceinline__ void zero_mode_part(const ZeroArgs& Z, int b, int nzb) {
   __shared__ double sh[(NT / kWave) * kPartStride];
   __shared__ int last;
   constexpr int NW = NT / kWave;
-  const int nzb = zero_blocks(Z.ny);
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x) / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   for (int j = b + nzb * wave; j < Z.ny; j += nzb * NW) {
     double s = 0.0;
     const double* rs = Z.rowsum + (long)j * Z.nz;
+#pragma unroll 8
     for (int k = lane; k < Z.nz; k += kWave) s += rs[k];
     s = wave_total(s);
     if (lane == 0) Z.ghat[j] = s;
@@ -268,8 +271,9 @@ __device__ __forceinline__ void ytri_stage(int ny, int lm, int row0, const Cx<T>
   }
 }
 
-template <typename T, typename U, int M, int P, int K, bool OUT64 = false>
-__device__ __forceinline__ void ytri_solve(const YArgs<T, U>& A, long q0, Cx<T>* tile);
+template <typename T, typename U, int M, int P, int K, bool OUT64 = false, bool ADD = false>
+__device__ __forceinline__ void ytri_solve(const YArgs<T, U>& A, long q0, Cx<T>* tile,
+                                           const Cx<double> (*old)[K] = nullptr);
 
 // Block `blk` of one grid's line-solve pass: blocks [0, zero_blocks(ny))
 // run the FP64 (0,0) mode, the rest own M consecutive columns each.  With
@@ -278,14 +282,14 @@ __device__ __forceinline__ void ytri_solve(const YArgs<T, U>& A, long q0, Cx<T>*
 // inverse z pass, which transforms all kz of one kx group per block and runs
 // its groups in descending order, then starts on the groups written last,
 // still in the Infinity Cache.  Every thread of the block calls it.
-template <typename T, typename U, int M, int P, int K, bool OUT64 = false>
+template <typename T, typename U, int M, int P, int K, bool OUT64 = false, bool ADD = false>
 __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& Z, long blk, Cx<T>* tile,
                                           bool kx_major = false) {
   constexpr int NT = M * P;
   if (A.check_done && __builtin_amdgcn_readfirstlane(A.ctl->done)) return;
   const int nzb = zero_blocks(A.ny);
   if (blk < nzb) {   // the first blocks: FP64 (0,0) mode
-    zero_mode_part<NT>(Z, (int)blk);
+    zero_mode_part<NT>(Z, (int)blk, nzb);
     return;
   }
   long q0 = (blk - nzb) * M;
@@ -296,17 +300,36 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
   const int lm = threadIdx.x % M, row0 = threadIdx.x / M;
   Cx<T> ld[K];
   ytri_load<T, U, M, P, K>(A, q0, lm, row0, ld);
-  ytri_stage<T, M, P, K>(A.ny, lm, row0, ld, tile);
-  __syncthreads();
-  ytri_solve<T, U, M, P, K, OUT64>(A, q0, tile);
+  if constexpr (ADD) {
+    // the FP64 values the solution is added to, loaded with the input (the
+    // store loop's rows and columns)
+    Cx<double> old[K];
+    const long qs = q0 + lm;
+    const long kz = qs / A.rs, kx = qs - kz * A.rs;
+    const bool ok = qs < A.Q && kx < A.hp;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int row = row0 + P * i;
+      old[i] = (ok && row < A.ny) ? gld(gbl(A.out64) + (long)row * A.out_ps + kz * A.out_rs + kx)
+                                  : Cx<double>{0.0, 0.0};
+    }
+    ytri_stage<T, M, P, K>(A.ny, lm, row0, ld, tile);
+    __syncthreads();
+    ytri_solve<T, U, M, P, K, OUT64, true>(A, q0, tile, &old);
+  } else {
+    ytri_stage<T, M, P, K>(A.ny, lm, row0, ld, tile);
+    __syncthreads();
+    ytri_solve<T, U, M, P, K, OUT64>(A, q0, tile);
+  }
 }
 
 // Solve of the staged columns q0 .. q0 + M - 1 and their stores.  OUT64:
 // the solution is written in FP64 to A.out64; `tile` is then the first half
 // of an LDS buffer of ytile_slots FP64 entries, re-used as their FP64 staging
 // once every lane has read its staged rows.
-template <typename T, typename U, int M, int P, int K, bool OUT64>
-__device__ __forceinline__ void ytri_solve(const YArgs<T, U>& A, long q0, Cx<T>* tile) {
+template <typename T, typename U, int M, int P, int K, bool OUT64, bool ADD>
+__device__ __forceinline__ void ytri_solve(const YArgs<T, U>& A, long q0, Cx<T>* tile,
+                                           const Cx<double> (*old)[K]) {
   constexpr int PS = K * M + 1;   // LDS slots per partition
   const int ny = A.ny;
   const long Q = A.Q;
@@ -455,11 +478,13 @@ __device__ __forceinline__ void ytri_solve(const YArgs<T, U>& A, long q0, Cx<T>*
     const long qs = q0 + mm;
     const long kz = qs / A.rs, kx = qs - kz * A.rs;
     if (qs < Q && kx < A.hp) {
+      const double inv_s = ADD ? 1.0 / A.ctl->scale[A.add_iter & 1] : 1.0;
 #pragma unroll
       for (int i = 0; i < K; ++i) {
         const int row = row0 + P * i;
         const int pp = row / K;
-        const Cx<double> v = t64[pp * PS + (row - pp * K) * M + mm];
+        Cx<double> v = t64[pp * PS + (row - pp * K) * M + mm];
+        if constexpr (ADD) v = cadd((*old)[i], cscale(v, inv_s));
         if (row < ny) gst(gbl(A.out64) + (long)row * A.out_ps + kz * A.out_rs + kx, v);
       }
     }
@@ -516,16 +541,16 @@ __device__ __forceinline__ void check_body(const ZeroArgs& Z, double* sh) {
   // Dirichlet wall the solution's mean is part of it
   c->phimean = Z.singular ? p[4] / (Z.dyf_sum * double(Z.nx) * double(Z.nz)) : 0.0;
   if (p[3] > 0.0) c->nonfinite = 1;
-  if (rel <= Z.rtol) {
+  if (rel <= Z.rtol && !Z.nostop) {
     c->done = 1;
     c->converged = 1;
-  } else if (eta <= kEtaFloor) {   // at the FP64 floor: corrections cannot lower the residual
+  } else if (eta <= kEtaFloor && !Z.nostop) {   // at the FP64 floor: corrections cannot lower the residual
     c->done = 1;
     c->converged = 2;
   } else if (Z.probe) {
     // not converged: the full residual pass of the same iterate follows and
     // its check decides the next step
-  } else if (Z.final_pass || !(rel > Z.rtol)) {   // last pass, or a NaN residual
+  } else if (!Z.nostop && (Z.final_pass || !(rel > Z.rtol))) {   // last pass, or a NaN residual
     c->done = 1;
     c->converged = 0;
   } else {
