@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 METRIC = "Poisson solves/s + HBM GB/s at 512x384x512, mixed vs FP64 at 1e-10 resid"
 HBM_PEAK_GBS = 8000.0
 SOURCES = ["ibp_api.cpp", "ibp_host.cpp", "ibp_host.hpp", "ibp_xz.hip", "ibp_xz_narrow.hip", "ibp_xz_kernels.hpp", "ibp_fastxz.hip", "ibp_ytri.hip",
-           "ibp_ytri_body.hpp", "ibp_misc.hip", "ibp_lines.hip", "ibp_persist.hip", "ibp_device.hpp",
+           "ibp_ytri_body.hpp", "ibp_misc.hip", "ibp_lines.hip", "ibp_persist.hip", "ibp_bluereg.hip", "ibp_device.hpp",
            "ibp_internal.hpp", "ibp_regfft.hpp"]
 
 

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libibpoisson.so")
 SOURCES = ["ibp_api.cpp", "ibp_host.cpp", "ibp_xz.hip", "ibp_xz_narrow.hip", "ibp_fastxz.hip", "ibp_ytri.hip", "ibp_misc.hip",
-           "ibp_lines.hip", "ibp_persist.hip"]
+           "ibp_lines.hip", "ibp_persist.hip", "ibp_bluereg.hip"]
 ARCH = os.environ.get("IBP_OFFLOAD_ARCH", "gfx950")
 
 

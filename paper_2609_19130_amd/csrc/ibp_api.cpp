@@ -52,6 +52,7 @@ struct ibp_plan_s {
   long nb64 = 1, nb32 = 1;  // x-pass blocks (transform passes)
   long nbro = 1;            // blocks of the residual-only pass
   bool xfast = false, zfast = false;   // register-FFT kernels for power-of-two lengths
+  int xbm = 0, zbm = 0;   // register Bluestein convolution lengths of the x (odd nx) and z transforms (0: off)
   bool zsmall = false;                 // general z transform in the small tile
   bool xsmall = false;                 // general x transform in the small tile
   bool xwide = true, zwide = true;     // general transform needs the wide kernel family
@@ -252,6 +253,20 @@ void carve_workspace(ibp_plan_s* p) {
   p->part = reinterpret_cast<double*>(c);   // two partial regions (part_second), then the check's first-level sums
   c += align256((size_t)(2 * max_parts(p) + kCheckSplitMax) * kPartStride * sizeof(double));
   p->ctl = reinterpret_cast<Ctl*>(c);
+}
+
+// Register Bluestein for a transform of length n: lengths up to 512 with a
+// prime factor above 11 that the LDS kernels would run as direct-sum stages
+// (the longer primes already take the LDS Bluestein path).  Returns the
+// convolution length (a power of two >= 2n - 1), or 0 for the other paths.
+// IBP_REG_BLUESTEIN=0 turns it off (comparison runs).
+int reg_bluestein_length(const FftPlan& fp, int n) {
+  if (fp.blu || !fp.any || n > 512 || n < 2) return 0;
+  if (const char* e = getenv("IBP_REG_BLUESTEIN"))
+    if (atoi(e) == 0) return 0;
+  int m = 32;
+  while (m < 2 * n - 1) m *= 2;
+  return m;
 }
 
 // The second FP32 half spectrum, row-sum array and partial region of the
@@ -532,6 +547,8 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     p->dz = Lz / nz;
     p->fpx = fpx;
     p->fpz = fpz;
+    p->xbm = (nx & 1) ? reg_bluestein_length(fpx, nx) : 0;
+    p->zbm = nz > 1 ? reg_bluestein_length(fpz, nz) : 0;
     ytri_shape(ny, &p->yP, &p->yK);
     p->xfast = rfft::supported(p->h);
     p->zfast = rfft::supported(nz);
@@ -648,6 +665,18 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     };
     if (p->fpx.blu) put_blu(p->fpx, o_bx);
     if (p->fpz.blu) put_blu(p->fpz, o_bz);
+    if (p->xbm) {   // the register Bluestein path's tables, in the same slots (fpx.blu is off)
+      FftPlan b{};
+      b.n = nx;
+      b.m = p->xbm;
+      put_blu(b, o_bx);
+    }
+    if (p->zbm) {
+      FftPlan b{};
+      b.n = nz;
+      b.m = p->zbm;
+      put_blu(b, o_bz);
+    }
 
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess && p->fused) {
@@ -694,11 +723,11 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     p->lamz32 = reinterpret_cast<const float*>(d + o_lz32);
     p->twx32 = reinterpret_cast<const Cx<float>*>(d + o_twx32);
     for (int t = 0; t < 3; ++t) {
-      if (p->fpx.blu) {
+      if (p->fpx.blu || p->xbm) {
         p->bx64[t] = reinterpret_cast<const Cx<double>*>(d + o_bx[t]);
         p->bx32[t] = reinterpret_cast<const Cx<float>*>(d + o_bx[3 + t]);
       }
-      if (p->fpz.blu) {
+      if (p->fpz.blu || p->zbm) {
         p->bz64[t] = reinterpret_cast<const Cx<double>*>(d + o_bz[t]);
         p->bz32[t] = reinterpret_cast<const Cx<float>*>(d + o_bz[3 + t]);
       }
@@ -1224,9 +1253,26 @@ ZeroArgs zargs(ibp_plan_s* p, long nparts, int init, int mixed, int iter, int fi
     if (e_ != hipSuccess) return from_hip(e_);        \
   } while (0)
 
+// The register Bluestein x path's arguments: its tables (the plan's
+// Bluestein slots hold them; fpx.blu is off so the LDS kernels ignore them).
+template <typename T>
+XArgs<T> with_xblu(const ibp_plan_s* p, const XArgs<T>& a) {
+  XArgs<T> b = a;
+  if constexpr (sizeof(T) == 8) {
+    b.bc = p->bx64[0]; b.bb = p->bx64[1]; b.bt = p->bx64[2];
+  } else {
+    b.bc = p->bx32[0]; b.bb = p->bx32[1]; b.bt = p->bx32[2];
+  }
+  return b;
+}
+
 template <typename T>
 hipError_t run_xr2c(const ibp_plan_s* p, int mode, const XArgs<T>& a, hipStream_t s) {
   if (p->xfast && mode != XM_RESID_ONLY) return launch_xr2c_fast<T>(mode, a, s);
+  // register Bluestein: the FP64 right-hand side pass (the others keep the
+  // LDS kernels, whose norm partials and residual modes it does not carry)
+  if constexpr (sizeof(T) == 8)
+    if (p->xbm && mode == XM_PLAIN && p->chunk <= 0) return launch_xblu_r2c<T>(with_xblu(p, a), p->xbm, s);
   if (mode == XM_RESID_ONLY) {
     XArgs<T> b = a;
     b.rows_per_block = x_tile_rows(p, x_tile32(p));
@@ -1241,12 +1287,22 @@ hipError_t run_xr2c(const ibp_plan_s* p, int mode, const XArgs<T>& a, hipStream_
 template <typename T>
 hipError_t run_xc2r(const ibp_plan_s* p, int mode, const XArgs<T>& a, hipStream_t s) {
   if (p->xfast) return launch_xc2r_fast<T>(mode, a, s);
+  if (p->xbm && p->chunk <= 0) return launch_xblu_c2r<T>(mode, with_xblu(p, a), p->xbm, s);
   return launch_xc2r<T>(mode, p->xsmall, p->xwide, a, s);
 }
 
 template <typename T>
 hipError_t run_zfft(const ibp_plan_s* p, bool inverse, const ZfArgs<T>& a, int nplanes, hipStream_t s) {
   if (p->zfast) return launch_zfft_fast<T>(inverse, a, nplanes, s);
+  if (p->zbm) {
+    ZfArgs<T> b = a;
+    if constexpr (sizeof(T) == 8) {
+      b.bc = p->bz64[0]; b.bb = p->bz64[1]; b.bt = p->bz64[2];
+    } else {
+      b.bc = p->bz32[0]; b.bb = p->bz32[1]; b.bt = p->bz32[2];
+    }
+    return launch_zblu_reg<T>(inverse, b, p->zbm, nplanes, s);
+  }
   return launch_zfft<T>(inverse, p->zsmall, p->zwide, a, nplanes, s);
 }
 
