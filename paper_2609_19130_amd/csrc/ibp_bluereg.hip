@@ -10,9 +10,10 @@
 // bhat (M) and W_M^e (M) in the Bluestein slots of the argument structs.
 //
 // z pass: C kx columns of one y plane per block, M / 8 threads per column.
-// x pass (odd nx only, the row as n complex values (x, 0)): M / 8 threads
-// per row; R2C keeps the first (n + 1) / 2 coefficients and the FP64 row
-// sum, C2R rebuilds X[n - k] = conj X[k] and takes the real part.
+// x pass (odd nx only): two real rows per complex line, M / 8 threads per
+// line; R2C separates the two spectra, keeps the first (n + 1) / 2
+// coefficients of each and the FP64 row sums; C2R combines the two half
+// spectra into the line's full spectrum and splits real and imaginary parts.
 #include <type_traits>
 
 #include "ibp_internal.hpp"
@@ -82,13 +83,16 @@ __global__ __launch_bounds__(C*(M / kE)) void k_zblu_reg(ZfArgs<T> A) {
   }
 }
 
-// Row sum over the TT threads of a row (TT = 64 or 128: one or two waves).
+// Sum over the TT threads of a line (TT a power of two; a line's threads are
+// TT consecutive lanes, or whole waves when TT > 64).
 template <int TT>
 __device__ __forceinline__ double row_total(double s, double* sh, int lr) {
-  s = wave_sum(s);
   if constexpr (TT <= kWave) {
+#pragma unroll
+    for (int off = TT / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
     return s;
   } else {
+    s = wave_sum(s);
     const int w = (threadIdx.x % TT) / kWave;   // wave within the row
     __syncthreads();
     if ((threadIdx.x & (kWave - 1)) == 0) sh[lr * (TT / kWave) + w] = s;
@@ -100,48 +104,81 @@ __device__ __forceinline__ double row_total(double s, double* sh, int lr) {
   }
 }
 
-// x R2C (FP64 right-hand side pass) of rows of odd length n.
+// Two real rows a, b of odd length n share one complex line z = a + i b:
+// with Z = DFT(z), A_k = (Z_k + conj Z_{n-k}) / 2 and
+// B_k = (Z_k - conj Z_{n-k}) / (2i), so one Bluestein transform serves both.
+// Rows 2p and 2p + 1 form line p; a missing second row (odd row count)
+// reads as zeros and is not stored.
+template <typename T>
+__device__ __forceinline__ Cx<T>* xblu_spec_row(const XArgs<T>& A, long row) {
+  return A.spec + row * A.rs + (row / A.nz) * (A.ps - (long)A.nz * A.rs);
+}
+
+// x R2C (FP64 right-hand side pass) of rows of odd length n, two per line.
 template <typename T, int M>
 __global__ __launch_bounds__(kThreads) void k_xblu_r2c(XArgs<T> A) {
   constexpr int TT = M / kE;
-  constexpr int RB = kThreads / TT;
+  constexpr int RB = kThreads / TT;   // lines (row pairs) per block
   constexpr int SS = rfft::Seq<M>::stride;
   constexpr int RI = rfft::Plan<M, true, T>::last_radix();
   __shared__ Cx<T> lds[RB * SS];
   __shared__ double sh[kThreads / kWave];
   const int tid = threadIdx.x, lr = tid / TT, t = tid % TT;
-  const long row = (A.row_begin / RB + blockIdx.x) * RB + lr;
-  const bool live = row < A.nrows;
+  const long r0 = 2 * ((A.row_begin / (2 * RB) + blockIdx.x) * RB + lr);
+  const bool live0 = r0 < A.nrows, live1 = r0 + 1 < A.nrows;
   const int n = A.nx;
-  const double* frow = A.f + (live ? row : 0) * n;
+  const double* fa = A.f + (live0 ? r0 : 0) * n;
+  const double* fb = A.f + (live1 ? r0 + 1 : 0) * n;
   Cx<T> v[kE];
-  double rs = 0.0;
+  double sa = 0.0, sb = 0.0;
 #pragma unroll
   for (int i = 0; i < kE; ++i) {
     const int m = t + TT * i;
     Cx<T> x{T(0), T(0)};
-    if (live && m < n) {
-      const double fv = frow[m];
-      rs += fv;
-      const Cx<T> w = A.bc[m];
-      x = Cx<T>{T(fv) * w.x, T(fv) * w.y};
+    if (m < n) {
+      const double av = live0 ? fa[m] : 0.0;
+      const double bv = live1 ? fb[m] : 0.0;
+      sa += av;
+      sb += bv;
+      x = cmul(Cx<T>{T(av), T(bv)}, A.bc[m]);
     }
     v[i] = x;
   }
-  rs = row_total<TT>(rs, sh, lr);
-  if (live && t == 0) A.rowsum[row] = rs;
-  blu_convolve<M, T>(v, t, lds + lr * SS, A.bb, A.bt);
-  if (!live) return;   // no barrier follows
-  Cx<T>* srow = A.spec + row * A.rs + (row / A.nz) * (A.ps - (long)A.nz * A.rs);
+  sa = row_total<TT>(sa, sh, lr);
+  sb = row_total<TT>(sb, sh, lr);
+  if (t == 0) {
+    if (live0) A.rowsum[r0] = sa;
+    if (live1) A.rowsum[r0 + 1] = sb;
+  }
+  Cx<T>* L = lds + lr * SS;
+  blu_convolve<M, T>(v, t, L, A.bb, A.bt);
+  // Z_k (chirp and 1/M applied) to LDS, natural order; the last LDS access
+  // of the convolution was a load followed by a barrier
   const T inv_m = T(1) / T(M);
 #pragma unroll
   for (int q = 0; q < kE; ++q) {
     const int k = t + TT * final_index<RI>(q);
-    if (k < A.hp) srow[k] = cscale(cmul(A.bc[k], v[q]), inv_m);
+    if (k < n) L[rfft::pad8(k)] = cscale(cmul(A.bc[k], v[q]), inv_m);
+  }
+  __syncthreads();
+  if (!live0) return;   // no barrier follows
+  Cx<T>* sa_row = xblu_spec_row(A, r0);
+  Cx<T>* sb_row = xblu_spec_row(A, r0 + 1);
+#pragma unroll
+  for (int i = 0; i < kE; ++i) {
+    const int k = t + TT * i;
+    if (k < A.hp) {
+      const Cx<T> z = L[rfft::pad8(k)];
+      const Cx<T> w = L[rfft::pad8(k == 0 ? 0 : n - k)];
+      sa_row[k] = Cx<T>{T(0.5) * (z.x + w.x), T(0.5) * (z.y - w.y)};
+      if (live1) sb_row[k] = Cx<T>{T(0.5) * (z.y + w.y), T(0.5) * (w.x - z.x)};
+    }
   }
 }
 
-// x C2R (set or add) of rows of odd length n.
+// x C2R (set or add) of rows of odd length n, two per line: the line's
+// spectrum is Z_k = A_k + i B_k over all k (A_{n-k} = conj A_k), its inverse
+// DFT is a + i b.
 template <typename T, int MODE, int M>
 __global__ __launch_bounds__(kThreads) void k_xblu_c2r(XArgs<T> A) {
   constexpr int TT = M / kE;
@@ -151,45 +188,60 @@ __global__ __launch_bounds__(kThreads) void k_xblu_c2r(XArgs<T> A) {
   __shared__ Cx<T> lds[RB * SS];
   if (MODE == CM_ADD && A.ctl->done) return;
   const int tid = threadIdx.x, lr = tid / TT, t = tid % TT;
-  const long row = (A.row_begin / RB + blockIdx.x) * RB + lr;
-  const bool live = row < A.nrows;
+  const long r0 = 2 * ((A.row_begin / (2 * RB) + blockIdx.x) * RB + lr);
+  const bool live0 = r0 < A.nrows, live1 = r0 + 1 < A.nrows;
   const int n = A.nx;
-  const Cx<T>* srow = A.spec + (live ? row * A.rs + (row / A.nz) * (A.ps - (long)A.nz * A.rs) : 0);
-  // conj of the full spectrum (X[n - k] = conj X[k]) times the chirp
+  const Cx<T>* sa_row = xblu_spec_row(A, live0 ? r0 : 0);
+  const Cx<T>* sb_row = xblu_spec_row(A, live1 ? r0 + 1 : 0);
+  // conj(Z_j) times the chirp (inverse DFT = conj DFT conj)
   Cx<T> v[kE];
 #pragma unroll
   for (int i = 0; i < kE; ++i) {
     const int j = t + TT * i;
     Cx<T> y{T(0), T(0)};
-    if (live && j < n) {
+    if (live0 && j < n) {
+      Cx<T> a, b{T(0), T(0)};
       if (j < A.hp) {
-        y = cconj(srow[j]);
-        if (j == 0) y.y = T(0);   // X[0] of a real sequence is real
+        a = sa_row[j];
+        if (live1) b = sb_row[j];
+        if (j == 0) a.y = b.y = T(0);   // X[0] of a real sequence is real
       } else {
-        y = srow[n - j];          // conj(conj X[n - j])
+        a = cconj(sa_row[n - j]);
+        if (live1) b = cconj(sb_row[n - j]);
       }
-      y = cmul(y, A.bc[j]);
+      // Z = a + i b; conj Z
+      y = cmul(Cx<T>{a.x - b.y, -(a.y + b.x)}, A.bc[j]);
     }
     v[i] = y;
   }
   blu_convolve<M, T>(v, t, lds + lr * SS, A.bb, A.bt);
-  if (!live) return;   // no barrier follows
+  if (!live0) return;   // no barrier follows
   double cs = A.out_scale / double(M);
   if (MODE == CM_ADD) cs = cs / A.ctl->scale[A.iter & 1];
-  const int jj = (int)(row / A.nz);
-  double c00 = A.phi00[jj] * A.inv_nxnz;
-  if (MODE == CM_ADD) c00 -= A.ctl->phimean;
-  double* orow = A.out + row * n;
+  double ca = A.phi00[(int)(r0 / A.nz)] * A.inv_nxnz;
+  double cb = live1 ? A.phi00[(int)((r0 + 1) / A.nz)] * A.inv_nxnz : 0.0;
+  if (MODE == CM_ADD) {
+    ca -= A.ctl->phimean;
+    cb -= A.ctl->phimean;
+  }
+  double* oa = A.out + r0 * n;
+  double* ob = oa + n;
 #pragma unroll
   for (int q = 0; q < kE; ++q) {
     const int j = t + TT * final_index<RI>(q);
     if (j < n) {
-      // real part of conj(w_j conv_j) = real part of w_j conv_j
+      // a + i b = conj(w_j conv_j) / M
       const Cx<T> w = A.bc[j];
-      double x = double(w.x) * double(v[q].x) - double(w.y) * double(v[q].y);
-      x = x * cs + c00;
-      if (MODE == CM_ADD) x += orow[j];
-      orow[j] = x;
+      const double re = double(w.x) * double(v[q].x) - double(w.y) * double(v[q].y);
+      const double im = double(w.x) * double(v[q].y) + double(w.y) * double(v[q].x);
+      double xa = re * cs + ca;
+      if (MODE == CM_ADD) xa += oa[j];
+      oa[j] = xa;
+      if (live1) {
+        double xb = -im * cs + cb;
+        if (MODE == CM_ADD) xb += ob[j];
+        ob[j] = xb;
+      }
     }
   }
 }
@@ -236,7 +288,7 @@ template <typename T>
 hipError_t launch_xblu_r2c(const XArgs<T>& a, int M, hipStream_t s) {
   if (!(a.nx & 1) || a.nx > 512 || 2 * a.nx - 1 > M) return hipErrorInvalidValue;
   auto go = [&](auto kern, int m) {
-    const int RB = kThreads / (m / kE);
+    const int RB = 2 * (kThreads / (m / kE));   // rows per block
     if (a.row_begin % RB) return hipErrorInvalidValue;
     const long nb = (a.nrows - a.row_begin + RB - 1) / RB;
     hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kThreads), 0, s, a);
@@ -257,7 +309,7 @@ template <typename T>
 hipError_t launch_xblu_c2r(int mode, const XArgs<T>& a, int M, hipStream_t s) {
   if (!(a.nx & 1) || a.nx > 512 || 2 * a.nx - 1 > M) return hipErrorInvalidValue;
   auto go = [&](auto kset, auto kadd, int m) {
-    const int RB = kThreads / (m / kE);
+    const int RB = 2 * (kThreads / (m / kE));   // rows per block
     if (a.row_begin % RB) return hipErrorInvalidValue;
     const long nb = (a.nrows - a.row_begin + RB - 1) / RB;
     if (mode == CM_ADD)

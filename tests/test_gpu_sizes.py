@@ -229,3 +229,54 @@ def test_bluestein_mixed_and_inverse_round_trip():
         plan.close()
     ref, _ = oracle.solve(rhs_from_velocity(u, v, w, None, g, 0.05), Lx, Lz, yf)
     assert rel(phid, ref) <= 1e-12
+
+
+# ------------------------------------------------- register Bluestein lengths
+# Lengths n <= 512 with a prime factor above 11 take the chirp convolution of
+# length M (power of two >= 2n - 1) held in registers: odd nx two rows per
+# line, z one kx column per line.  Cover every M from 32 to 1024 in x and z,
+# odd row counts (a line whose second row is missing) and the mixed form's
+# FP32 z transforms and C2R correction (add mode).
+REG_BLU = [(13, 3, 29), (29, 4, 37), (37, 5, 101), (101, 3, 13), (251, 3, 255), (481, 3, 265)]
+
+
+@pytest.mark.parametrize("nx,ny,nz", REG_BLU)
+def test_register_bluestein_lengths_fp64_match_oracle(nx, ny, nz):
+    yf = synth.tanh_faces(ny, 2.0)
+    f = np.random.default_rng(nx + 5 * ny + 3 * nz).uniform(-1, 1, (ny, nz, nx))
+    phi, info = gpu_solve(f, 1.7, 2.3, yf)
+    ref, m = oracle.solve(f, 1.7, 2.3, yf)
+    assert abs(info["removed_mean"] - m) <= 1e-12 * max(1.0, abs(m))
+    assert rel(phi, ref) <= 1e-12, rel(phi, ref)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "mixed_f64inv"])
+@pytest.mark.parametrize("nx,ny,nz", [REG_BLU[2], REG_BLU[5]])
+def test_register_bluestein_lengths_mixed_refinement(nx, ny, nz, precision):
+    Lx, Lz = 1.7, 2.3
+    yf = synth.tanh_faces(ny, 2.0)
+    g = geometry(nx, ny, nz, Lx, Lz, yf)
+    u, v, w = synth.uniform_velocity(nx, ny, nz, seed=29)
+    f = divergence(u, v, w, g)
+    phi, info = gpu_solve(f, Lx, Lz, yf, precision=precision, rtol=1e-10, max_iters=6)
+    r = residual(f, phi, Lx, Lz, yf)
+    assert info["converged"] == 1 and r <= 1e-10, (r, info)
+    ref, _ = oracle.solve(f, Lx, Lz, yf)
+    assert rel(phi, ref) <= 1e-8
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed_f64inv", 1e-9)])
+def test_paper_size_501_full_field(precision, tol):
+    """501 x 5 x 501 (the periodic directions of the paper's 501 x 501 x 1001
+    grid at reduced ny), every value against the oracle: register Bluestein
+    in x (two rows per line, 501 = 3 x 167) and z."""
+    nx, ny, nz = 501, 5, 501
+    Lx = Lz = 2 * np.pi
+    yf = synth.tanh_faces(ny, 2.0)
+    g = geometry(nx, ny, nz, Lx, Lz, yf)
+    u, v, w = synth.uniform_velocity(nx, ny, nz, seed=31)
+    f = divergence(u, v, w, g)
+    phi, info = gpu_solve(f, Lx, Lz, yf, precision=precision, rtol=1e-12, max_iters=6)
+    ref, m = oracle.solve(f, Lx, Lz, yf)
+    assert abs(info["removed_mean"] - m) <= 1e-12 * max(1.0, abs(m))
+    assert rel(phi, ref) <= tol, rel(phi, ref)
