@@ -255,13 +255,14 @@ void carve_workspace(ibp_plan_s* p) {
   p->ctl = reinterpret_cast<Ctl*>(c);
 }
 
-// Register Bluestein for a transform of length n: lengths up to 512 with a
-// prime factor above 11 that the LDS kernels would run as direct-sum stages
-// (the longer primes already take the LDS Bluestein path).  Returns the
+// Register Bluestein for a transform of length n: lengths up to nmax (512 for
+// the odd-nx x pass, 1024 for z) with a prime factor above 11 that the LDS
+// kernels would run as direct-sum stages (the longer primes already take the
+// LDS Bluestein path).  Returns the
 // convolution length (a power of two >= 2n - 1), or 0 for the other paths.
 // IBP_REG_BLUESTEIN=0 turns it off (comparison runs).
-int reg_bluestein_length(const FftPlan& fp, int n) {
-  if (fp.blu || !fp.any || n > 512 || n < 2) return 0;
+int reg_bluestein_length(const FftPlan& fp, int n, int nmax) {
+  if (fp.blu || !fp.any || n > nmax || n < 2) return 0;
   if (const char* e = getenv("IBP_REG_BLUESTEIN"))
     if (atoi(e) == 0) return 0;
   int m = 32;
@@ -547,8 +548,8 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     p->dz = Lz / nz;
     p->fpx = fpx;
     p->fpz = fpz;
-    p->xbm = (nx & 1) ? reg_bluestein_length(fpx, nx) : 0;
-    p->zbm = nz > 1 ? reg_bluestein_length(fpz, nz) : 0;
+    p->xbm = (nx & 1) ? reg_bluestein_length(fpx, nx, 512) : 0;
+    p->zbm = nz > 1 ? reg_bluestein_length(fpz, nz, 1024) : 0;
     ytri_shape(ny, &p->yP, &p->yK);
     p->xfast = rfft::supported(p->h);
     p->zfast = rfft::supported(nz);

@@ -1,9 +1,10 @@
-// Bluestein transforms held in registers, for line lengths n <= 512 with a
-// prime factor above 11 (the paper's 501-point grid: 501 = 3 x 167), where
+// Bluestein transforms held in registers, for line lengths n <= 512 (x) or
+// 1024 (z) with a prime factor above 11 (the paper's 501- and 632-point
+// grids: 501 = 3 x 167, 632 = 8 x 79), where
 // the LDS kernels would run direct-sum stages of ~170 complex multiply-adds
 // per value.  A length-n DFT is X_k = w_k sum_j (x_j w_j) conj(w_{k-j}) with
 // the chirp w_j = exp(-i pi j^2 / n): the sum is a cyclic convolution of
-// length M (a power of two >= 2n - 1, at most 1024), done as two register
+// length M (a power of two >= 2n - 1, at most 1024 in x, 2048 in z), done as two register
 // FFTs of length M (ibp_regfft.hpp) around a pointwise product with the
 // filter's transform bhat.  The inverse DFT (unnormalised) is
 // conj(DFT(conj(X))).  Tables (host, long double rounded): chirp (n values),
@@ -262,7 +263,7 @@ constexpr int blu_z_cols() {
 
 template <typename T>
 hipError_t launch_zblu_reg(bool inverse, const ZfArgs<T>& a, int M, int nplanes, hipStream_t s) {
-  if (a.nz > 512 || 2 * a.nz - 1 > M) return hipErrorInvalidValue;
+  if (a.nz > 1024 || 2 * a.nz - 1 > M) return hipErrorInvalidValue;
   auto go = [&](auto m_) {
     constexpr int m = decltype(m_)::value;
     constexpr int C = blu_z_cols<T, m>();
@@ -280,6 +281,7 @@ hipError_t launch_zblu_reg(bool inverse, const ZfArgs<T>& a, int M, int nplanes,
     case 256: return go(std::integral_constant<int, 256>{});
     case 512: return go(std::integral_constant<int, 512>{});
     case 1024: return go(std::integral_constant<int, 1024>{});
+    case 2048: return go(std::integral_constant<int, 2048>{});
     default: return hipErrorInvalidValue;
   }
 }

@@ -116,6 +116,10 @@ template <bool INV, typename T>
 struct Plan<512, INV, T> : Stages<512, 1, INV, T, 8, 8, 8> {};
 template <bool INV, typename T>
 struct Plan<1024, INV, T> : Stages<1024, 1, INV, T, 8, 8, 4, 4> {};
+// 2048: only the Bluestein convolutions of z lines up to 1024 points use it
+// (256 threads per line); not a length of the plain register transforms.
+template <bool INV, typename T>
+struct Plan<2048, INV, T> : Stages<2048, 1, INV, T, 8, 8, 8, 4> {};
 
 __host__ __device__ constexpr bool supported(int n) {
   return n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024;

@@ -232,12 +232,14 @@ def test_bluestein_mixed_and_inverse_round_trip():
 
 
 # ------------------------------------------------- register Bluestein lengths
-# Lengths n <= 512 with a prime factor above 11 take the chirp convolution of
-# length M (power of two >= 2n - 1) held in registers: odd nx two rows per
-# line, z one kx column per line.  Cover every M from 32 to 1024 in x and z,
-# odd row counts (a line whose second row is missing) and the mixed form's
-# FP32 z transforms and C2R correction (add mode).
-REG_BLU = [(13, 3, 29), (29, 4, 37), (37, 5, 101), (101, 3, 13), (251, 3, 255), (481, 3, 265)]
+# Lengths with a prime factor above 11 (odd nx up to 512, nz up to 1024) take
+# the chirp convolution of length M (power of two >= 2n - 1) held in
+# registers: odd nx two rows per line, z one kx column per line.  Cover every
+# M from 32 to 1024 in x and 32 to 2048 in z, odd row counts (a line whose
+# second row is missing) and the mixed form's FP32 z transforms and C2R
+# correction (add mode).
+REG_BLU = [(13, 3, 29), (29, 4, 37), (37, 5, 101), (101, 3, 13), (251, 3, 255), (481, 3, 265),
+           (29, 3, 632), (27, 4, 1003)]
 
 
 @pytest.mark.parametrize("nx,ny,nz", REG_BLU)
@@ -251,7 +253,7 @@ def test_register_bluestein_lengths_fp64_match_oracle(nx, ny, nz):
 
 
 @pytest.mark.parametrize("precision", ["mixed", "mixed_f64inv"])
-@pytest.mark.parametrize("nx,ny,nz", [REG_BLU[2], REG_BLU[5]])
+@pytest.mark.parametrize("nx,ny,nz", [REG_BLU[2], REG_BLU[5], REG_BLU[7]])
 def test_register_bluestein_lengths_mixed_refinement(nx, ny, nz, precision):
     Lx, Lz = 1.7, 2.3
     yf = synth.tanh_faces(ny, 2.0)
