@@ -384,6 +384,42 @@ def run_c5(args, steps=None):
     return out
 
 
+def run_paper_grids(args, steps=10, warmup=2):
+    """FP64 solves on the paper's two scaling grids (501 x 501 x 1001 and
+    632 x 632 x 1263 cells, stretched direction second): time per solve, the
+    stage model's rate and the per-pass times.  Right-hand sides are seeded
+    normal values (the direct solve's time does not depend on them)."""
+    import numpy as np
+    import torch
+
+    from paper_2609_19130_amd import ibpoisson as ibp
+    from paper_2609_19130_amd import synth
+
+    out = {}
+    for nx, ny, nz in ((501, 1001, 501), (632, 1263, 632)):
+        yf = synth.tanh_faces(ny, args.beta)
+        plan = ibp.Plan(nx, ny, nz, 2 * np.pi, 2 * np.pi, yf)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(nx)
+        f = torch.randn((ny, nz, nx), generator=g, device="cuda", dtype=torch.float64)
+        phi = torch.empty_like(f)
+        ms, _, _ = timed_solves(plan, f, phi, steps, warmup, False)
+        _, _, prof = timed_solves(plan, f, phi, steps, 0, True)
+        N = nx * ny * nz
+        Nh = (nx // 2 + 1) * ny * nz
+        model = 16.0 * N + 8 * 16.0 * Nh
+        out[f"{nx}x{ny}x{nz}"] = {
+            "ms_per_solve": ms, "solves_per_s": 1000.0 / ms,
+            "hbm_gbs_stage_model": model / (ms * 1e-3) / 1e9,
+            "roofline_frac_stage_model": model / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "passes_ms": {k: v["total_ms"] / v["launches"] for k, v in prof.items()}}
+        log(f"[bench] paper grid {nx}x{ny}x{nz}: {ms:.2f} ms")
+        del f, phi
+        plan.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -402,12 +438,13 @@ def main():
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-launch events (no per-pass breakdown or roofline)")
     ap.add_argument("--cpu-sample", choices=["full", "quarter"], default="full")
-    ap.add_argument("--config", choices=["c3", "c4", "c5"], default="c3",
+    ap.add_argument("--config", choices=["c3", "c4", "c5", "paper"], default="c3",
                     help="c3: the 512x384x512 solve (default, the headline line); "
-                         "c5: a captured graph of --seq solves at 1024x768x1024, beta 3, AR(1) right-hand sides")
+                         "c5: a captured graph of --seq solves at 1024x768x1024, beta 3, AR(1) right-hand sides; "
+                         "paper: FP64 solves on the 501x1001x501 and 632x1263x632 grids")
     ap.add_argument("--seq", type=int, default=100, help="solves per captured sequence (c5)")
     ap.add_argument("--no-extra", action="store_true",
-                    help="c3 only: skip the batched and paper-scale summaries appended to the line")
+                    help="c3 only: skip the batched, paper-scale and paper-grid summaries appended to the line")
     ap.add_argument("--extra-seq", type=int, default=20, help="solves per captured sequence of the c5 summary")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -419,6 +456,10 @@ def main():
         return
     if args.config == "c4":
         print(json.dumps(run_c4(args)), flush=True)
+        return
+    if args.config == "paper":
+        print(json.dumps({"config": "paper_grids", "beta": args.beta, "unit": "ms per FP64 solve",
+                          "grids": run_paper_grids(args, steps=args.steps, warmup=args.warmup)}), flush=True)
         return
 
     import numpy as np
@@ -620,6 +661,9 @@ def main():
         c5 = run_c5(args, steps=args.extra_seq)
         out["c5"] = {k: c5[k] for k in ("config", "value", "unit", "ms_per_step", "hbm_gbs_stage_model",
                                          "roofline_frac_stage_model", "mixed") if k in c5}
+        torch.cuda.empty_cache()
+        log("[bench] paper grids 501x1001x501 and 632x1263x632 (FP64)")
+        out["paper_grids"] = run_paper_grids(args)
     print(json.dumps(out), flush=True)
 
 
