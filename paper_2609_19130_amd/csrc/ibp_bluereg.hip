@@ -27,11 +27,17 @@ using rfft::kE;
 
 // One length-n line whose values v[i] (index t + TT i, zero past n) are
 // already multiplied by the chirp: returns in v[q] the convolution at index
-// t + TT final_index(q), unnormalised (times M).
+// t + TT final_index(q), unnormalised (times M).  As M >= 2n - 1, n <= M / 2:
+// slots i >= kE / 2 of the input are always zero and only outputs with
+// final_index(q) < kE / 2 are ever used, so a lane's chirp values (indices
+// t + TT i, i < kE / 2) serve both its loads and its stores.
+constexpr int kH = kE / 2;
 template <int M, typename T>
 __device__ __forceinline__ void blu_convolve(Cx<T> (&v)[kE], int t, Cx<T>* lds, const Cx<T>* bb, const Cx<T>* bt) {
-  using PF = rfft::Plan<M, false, T>;
-  using PI = rfft::Plan<M, true, T>;
+  // w^2 ... w^7 of each butterfly formed from w^1: the chirp and filter
+  // tables already compete with the line data for the vector cache
+  using PF = rfft::Plan<M, false, T, true>;
+  using PI = rfft::Plan<M, true, T, true>;
   constexpr int TT = M / kE;
   constexpr int RF = PF::last_radix();
   PF::run(v, t, lds, bt, 1);
@@ -58,26 +64,30 @@ __global__ __launch_bounds__(C*(M / kE)) void k_zblu_reg(ZfArgs<T> A) {
   const bool live = col < A.hp;
   const int n = A.nz;
   Cx<T>* plane = A.spec + (size_t)(A.plane0 + blockIdx.y) * A.ps;
-  Cx<T> v[kE];
+  Cx<T> v[kE], ch[kH];
 #pragma unroll
-  for (int i = 0; i < kE; ++i) {
+  for (int i = 0; i < kH; ++i) {
     const int z = t + TT * i;
     Cx<T> x{T(0), T(0)};
+    ch[i] = x;
     if (live && z < n) {
       x = plane[(size_t)z * A.rs + col];
       if (INV) x = cconj(x);
-      x = cmul(x, A.bc[z]);
+      ch[i] = A.bc[z];
+      x = cmul(x, ch[i]);
     }
     v[i] = x;
+    v[i + kH] = Cx<T>{T(0), T(0)};
   }
   blu_convolve<M, T>(v, t, lds + c * SS, A.bb, A.bt);
   if (!live) return;   // no barrier follows
   const T inv_m = T(1) / T(M);
 #pragma unroll
   for (int q = 0; q < kE; ++q) {
-    const int k = t + TT * final_index<RI>(q);
-    if (k < n) {
-      Cx<T> X = cscale(cmul(A.bc[k], v[q]), inv_m);
+    const int fi = final_index<RI>(q);
+    const int k = t + TT * fi;
+    if (fi < kH && k < n) {
+      Cx<T> X = cscale(cmul(ch[fi < kH ? fi : 0], v[q]), inv_m);
       if (INV) X = cconj(X);
       plane[(size_t)k * A.rs + col] = X;
     }
@@ -130,10 +140,13 @@ __global__ __launch_bounds__(kThreads) void k_xblu_r2c(XArgs<T> A) {
   const int n = A.nx;
   const double* fa = A.f + (live0 ? r0 : 0) * n;
   const double* fb = A.f + (live1 ? r0 + 1 : 0) * n;
+  // (the chirp is read again at the end: keeping it in registers across the
+  // convolution measured slower here, 1.95 against 1.86 ms per pass at
+  // 501 x 1001 x 501)
   Cx<T> v[kE];
   double sa = 0.0, sb = 0.0;
 #pragma unroll
-  for (int i = 0; i < kE; ++i) {
+  for (int i = 0; i < kH; ++i) {
     const int m = t + TT * i;
     Cx<T> x{T(0), T(0)};
     if (m < n) {
@@ -144,6 +157,7 @@ __global__ __launch_bounds__(kThreads) void k_xblu_r2c(XArgs<T> A) {
       x = cmul(Cx<T>{T(av), T(bv)}, A.bc[m]);
     }
     v[i] = x;
+    v[i + kH] = Cx<T>{T(0), T(0)};
   }
   sa = row_total<TT>(sa, sh, lr);
   sb = row_total<TT>(sb, sh, lr);
@@ -158,8 +172,9 @@ __global__ __launch_bounds__(kThreads) void k_xblu_r2c(XArgs<T> A) {
   const T inv_m = T(1) / T(M);
 #pragma unroll
   for (int q = 0; q < kE; ++q) {
-    const int k = t + TT * final_index<RI>(q);
-    if (k < n) L[rfft::pad8(k)] = cscale(cmul(A.bc[k], v[q]), inv_m);
+    const int fi = final_index<RI>(q);
+    const int k = t + TT * fi;
+    if (fi < kH && k < n) L[rfft::pad8(k)] = cscale(cmul(A.bc[k], v[q]), inv_m);
   }
   __syncthreads();
   if (!live0) return;   // no barrier follows
@@ -195,11 +210,12 @@ __global__ __launch_bounds__(kThreads) void k_xblu_c2r(XArgs<T> A) {
   const Cx<T>* sa_row = xblu_spec_row(A, live0 ? r0 : 0);
   const Cx<T>* sb_row = xblu_spec_row(A, live1 ? r0 + 1 : 0);
   // conj(Z_j) times the chirp (inverse DFT = conj DFT conj)
-  Cx<T> v[kE];
+  Cx<T> v[kE], ch[kH];
 #pragma unroll
-  for (int i = 0; i < kE; ++i) {
+  for (int i = 0; i < kH; ++i) {
     const int j = t + TT * i;
     Cx<T> y{T(0), T(0)};
+    ch[i] = y;
     if (live0 && j < n) {
       Cx<T> a, b{T(0), T(0)};
       if (j < A.hp) {
@@ -211,9 +227,11 @@ __global__ __launch_bounds__(kThreads) void k_xblu_c2r(XArgs<T> A) {
         if (live1) b = cconj(sb_row[n - j]);
       }
       // Z = a + i b; conj Z
-      y = cmul(Cx<T>{a.x - b.y, -(a.y + b.x)}, A.bc[j]);
+      ch[i] = A.bc[j];
+      y = cmul(Cx<T>{a.x - b.y, -(a.y + b.x)}, ch[i]);
     }
     v[i] = y;
+    v[i + kH] = Cx<T>{T(0), T(0)};
   }
   blu_convolve<M, T>(v, t, lds + lr * SS, A.bb, A.bt);
   if (!live0) return;   // no barrier follows
@@ -229,10 +247,11 @@ __global__ __launch_bounds__(kThreads) void k_xblu_c2r(XArgs<T> A) {
   double* ob = oa + n;
 #pragma unroll
   for (int q = 0; q < kE; ++q) {
-    const int j = t + TT * final_index<RI>(q);
-    if (j < n) {
+    const int fi = final_index<RI>(q);
+    const int j = t + TT * fi;
+    if (fi < kH && j < n) {
       // a + i b = conj(w_j conv_j) / M
-      const Cx<T> w = A.bc[j];
+      const Cx<T> w = ch[fi < kH ? fi : 0];
       const double re = double(w.x) * double(v[q].x) - double(w.y) * double(v[q].y);
       const double im = double(w.x) * double(v[q].y) + double(w.y) * double(v[q].x);
       double xa = re * cs + ca;
@@ -249,13 +268,16 @@ __global__ __launch_bounds__(kThreads) void k_xblu_c2r(XArgs<T> A) {
 
 // ---------------------------------------------------------------- launchers
 // kx columns per z block: 128-byte segments where the block fits 1024
-// threads.  FP64 at M = 512 takes 16 columns (1024 threads): its 8-column
-// instance (512 threads) returned wrong values on the GPU for every length
-// tried (131, 167, 255) while the 4- and 16-column instances of the same
-// code are exact; the cause was not found, so that instance is not used.
+// threads, except FP64 at M = 512 and 1024, which take 4 columns (64-byte
+// segments; two blocks per compute unit at M = 1024, so one block's loads
+// overlap another's arithmetic: 2.17 -> 1.96 ms per pass at 501 x 1001 x 501
+// against 8 columns).  The 8-column FP64 instance at M = 512 (512 threads)
+// returned wrong values on the GPU for every length tried (131, 167, 255)
+// while the 4- and 16-column instances of the same code are exact; the cause
+// was not found, and that instance is not built.
 template <typename T, int M>
 constexpr int blu_z_cols() {
-  if (sizeof(T) == 8 && M == 512) return 16;
+  if (sizeof(T) == 8 && (M == 512 || M == 1024)) return 4;
   constexpr int seg = 128 / (int)sizeof(Cx<T>);
   constexpr int maxc = 1024 / (M / kE);
   return seg < maxc ? seg : maxc;

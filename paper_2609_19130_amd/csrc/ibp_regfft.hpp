@@ -29,7 +29,10 @@ struct Seq {
   static constexpr int stride = N + N / 8 + 1;
 };
 
-template <int N, int R, int Ns, bool INV, typename T>
+// PW: read only w^1 of each butterfly from the table and form w^2 ... w^(R-1)
+// by products of depth at most 3 (one table read per butterfly instead of
+// R - 1, for kernels whose table reads compete with their data).
+template <int N, int R, int Ns, bool INV, typename T, bool PW = false>
 __device__ __forceinline__ void stage_compute(Cx<T> (&v)[kE], int t, const Cx<T>* __restrict__ tw,
                                               int twstride) {
   constexpr int TT = N / kE;
@@ -38,11 +41,27 @@ __device__ __forceinline__ void stage_compute(Cx<T> (&v)[kE], int t, const Cx<T>
     if constexpr (Ns > 1) {
       const int b = t + TT * u;
       const int k = b % Ns;
+      if constexpr (PW) {
+        Cx<T> w[R];
+        w[1] = tw[(k * (N / (Ns * R))) * twstride];
+        if (INV) w[1].y = -w[1].y;
+        if constexpr (R > 2) w[2] = cmul(w[1], w[1]);
+        if constexpr (R > 3) w[3] = cmul(w[2], w[1]);
+        if constexpr (R > 4) {
+          w[4] = cmul(w[2], w[2]);
+          w[5] = cmul(w[4], w[1]);
+          w[6] = cmul(w[4], w[2]);
+          w[7] = cmul(w[4], w[3]);
+        }
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        Cx<T> w = tw[(r * k * (N / (Ns * R))) * twstride];
-        if (INV) w.y = -w.y;
-        v[u * R + r] = cmul(v[u * R + r], w);
+        for (int r = 1; r < R; ++r) v[u * R + r] = cmul(v[u * R + r], w[r]);
+      } else {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          Cx<T> w = tw[(r * k * (N / (Ns * R))) * twstride];
+          if (INV) w.y = -w.y;
+          v[u * R + r] = cmul(v[u * R + r], w);
+        }
       }
     }
     Bfly<R, INV, T>::run(&v[u * R]);
@@ -77,49 +96,49 @@ __device__ __forceinline__ constexpr int final_index(int s) {
   return (s / RL) + (s % RL) * (kE / RL);
 }
 
-template <int N, int Ns, bool INV, typename T, int R, int... Rest>
+template <int N, int Ns, bool INV, typename T, bool PW, int R, int... Rest>
 struct Stages {
   static constexpr int last_radix() {
     if constexpr (sizeof...(Rest) == 0)
       return R;
     else
-      return Stages<N, Ns * R, INV, T, Rest...>::last_radix();
+      return Stages<N, Ns * R, INV, T, PW, Rest...>::last_radix();
   }
   // Every thread of the block must call this (it contains __syncthreads).
   __device__ __forceinline__ static void run(Cx<T> (&v)[kE], int t, Cx<T>* lds, const Cx<T>* __restrict__ tw,
                                              int twstride) {
-    stage_compute<N, R, Ns, INV, T>(v, t, tw, twstride);
+    stage_compute<N, R, Ns, INV, T, PW>(v, t, tw, twstride);
     if constexpr (sizeof...(Rest) > 0) {
-      constexpr int R2 = Stages<N, Ns * R, INV, T, Rest...>::first_radix();
+      constexpr int R2 = Stages<N, Ns * R, INV, T, PW, Rest...>::first_radix();
       stage_store<N, R, Ns, T>(v, t, lds);
       __syncthreads();
       stage_load<N, R2, T>(v, t, lds);
       __syncthreads();
-      Stages<N, Ns * R, INV, T, Rest...>::run(v, t, lds, tw, twstride);
+      Stages<N, Ns * R, INV, T, PW, Rest...>::run(v, t, lds, tw, twstride);
     }
   }
   static constexpr int first_radix() { return R; }
 };
 
 // Radix plans of the supported lengths (first radix 8: natural input layout).
-template <int N, bool INV, typename T>
+template <int N, bool INV, typename T, bool PW = false>
 struct Plan;
-template <bool INV, typename T>
-struct Plan<32, INV, T> : Stages<32, 1, INV, T, 8, 4> {};
-template <bool INV, typename T>
-struct Plan<64, INV, T> : Stages<64, 1, INV, T, 8, 8> {};
-template <bool INV, typename T>
-struct Plan<128, INV, T> : Stages<128, 1, INV, T, 8, 4, 4> {};
-template <bool INV, typename T>
-struct Plan<256, INV, T> : Stages<256, 1, INV, T, 8, 8, 4> {};
-template <bool INV, typename T>
-struct Plan<512, INV, T> : Stages<512, 1, INV, T, 8, 8, 8> {};
-template <bool INV, typename T>
-struct Plan<1024, INV, T> : Stages<1024, 1, INV, T, 8, 8, 4, 4> {};
+template <bool INV, typename T, bool PW>
+struct Plan<32, INV, T, PW> : Stages<32, 1, INV, T, PW, 8, 4> {};
+template <bool INV, typename T, bool PW>
+struct Plan<64, INV, T, PW> : Stages<64, 1, INV, T, PW, 8, 8> {};
+template <bool INV, typename T, bool PW>
+struct Plan<128, INV, T, PW> : Stages<128, 1, INV, T, PW, 8, 4, 4> {};
+template <bool INV, typename T, bool PW>
+struct Plan<256, INV, T, PW> : Stages<256, 1, INV, T, PW, 8, 8, 4> {};
+template <bool INV, typename T, bool PW>
+struct Plan<512, INV, T, PW> : Stages<512, 1, INV, T, PW, 8, 8, 8> {};
+template <bool INV, typename T, bool PW>
+struct Plan<1024, INV, T, PW> : Stages<1024, 1, INV, T, PW, 8, 8, 4, 4> {};
 // 2048: only the Bluestein convolutions of z lines up to 1024 points use it
 // (256 threads per line); not a length of the plain register transforms.
-template <bool INV, typename T>
-struct Plan<2048, INV, T> : Stages<2048, 1, INV, T, 8, 8, 8, 4> {};
+template <bool INV, typename T, bool PW>
+struct Plan<2048, INV, T, PW> : Stages<2048, 1, INV, T, PW, 8, 8, 8, 4> {};
 
 __host__ __device__ constexpr bool supported(int n) {
   return n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024;
