@@ -271,13 +271,15 @@ __global__ __launch_bounds__(kThreads) void k_xblu_c2r(XArgs<T> A) {
 // threads, except FP64 at M = 512 and 1024, which take 4 columns (64-byte
 // segments; two blocks per compute unit at M = 1024, so one block's loads
 // overlap another's arithmetic: 2.17 -> 1.96 ms per pass at 501 x 1001 x 501
-// against 8 columns).  The 8-column FP64 instance at M = 512 (512 threads)
+// against 8 columns), and FP64 at M = 2048, 2 columns (two blocks per unit:
+// 6.19 -> 5.89 ms per pass at 632 x 1263 x 632 against 4).  The 8-column FP64 instance at M = 512 (512 threads)
 // returned wrong values on the GPU for every length tried (131, 167, 255)
 // while the 4- and 16-column instances of the same code are exact; the cause
 // was not found, and that instance is not built.
 template <typename T, int M>
 constexpr int blu_z_cols() {
   if (sizeof(T) == 8 && (M == 512 || M == 1024)) return 4;
+  if (sizeof(T) == 8 && M == 2048) return 2;
   constexpr int seg = 128 / (int)sizeof(Cx<T>);
   constexpr int maxc = 1024 / (M / kE);
   return seg < maxc ? seg : maxc;
