@@ -282,3 +282,23 @@ def test_paper_size_501_full_field(precision, tol):
     ref, m = oracle.solve(f, Lx, Lz, yf)
     assert abs(info["removed_mean"] - m) <= 1e-12 * max(1.0, abs(m))
     assert rel(phi, ref) <= tol, rel(phi, ref)
+
+
+@pytest.mark.parametrize("nx,ny,nz,modes", [
+    (501, 1001, 501, MODES501),
+    (632, 1263, 632, [(0, 0), (1, 0), (0, 1), (79, 3), (316, 631), (158, 316)]),
+])
+def test_paper_grids_full_size_sampled_modes(nx, ny, nz, modes):
+    """The paper's grids at full size (501 x 501 x 1001 and 632 x 632 x 1263
+    cells, stretched direction second), as the bench times them: sampled
+    Fourier modes of the GPU solution against the oracle's 1-D solves of the
+    same modes of f."""
+    Lx = Lz = 2 * np.pi
+    yf = synth.tanh_faces(ny, 2.0)
+    f = np.random.default_rng(nx).standard_normal((ny, nz, nx))
+    plan = ibp.Plan(nx, ny, nz, Lx, Lz, yf)
+    try:
+        phi = plan.solve(to_dev(f)).cpu().numpy()
+    finally:
+        plan.close()
+    assert sampled_modes(f, phi, Lx, Lz, yf, modes) <= 1e-12
