@@ -52,18 +52,47 @@ __device__ __forceinline__ void blu_convolve(Cx<T> (&v)[kE], int t, Cx<T>* lds, 
   for (int q = 0; q < kE; ++q) v[q] = u[q];
 }
 
+// Column groups narrower than a 128-byte line: the S groups of one line
+// (S = 128 / (C * sizeof(Cx<T>)), 2 or 4) go to blocks b, b + 8, ..., which
+// the round-robin dispatch places on one XCD at about the same time, so the
+// line is fetched into that XCD's L2 once.  The launch rounds the groups per
+// plane up to a multiple of S (whole dead groups return at once); the last
+// (blocks mod 8S) blocks take the remaining sets in order.
+template <typename T, int C>
+constexpr int blu_z_siblings() {
+  constexpr int w = C * (int)sizeof(Cx<T>);
+  return w >= 128 ? 1 : 128 / w;
+}
+
 template <typename T, bool INV, int M, int C>
 __global__ __launch_bounds__(C*(M / kE)) void k_zblu_reg(ZfArgs<T> A) {
   constexpr int TT = M / kE;
   constexpr int SS = rfft::Seq<M>::stride;
   constexpr int RI = rfft::Plan<M, true, T>::last_radix();
+  constexpr int S = blu_z_siblings<T, C>();
   __shared__ Cx<T> lds[C * SS];
   if (A.check_done && A.ctl->done) return;
+  int grp = blockIdx.x, pl = blockIdx.y;
+  if constexpr (S > 1) {
+    const long G = gridDim.x, nb = G * gridDim.y, full = nb / (8 * S) * (8 * S);
+    const long b = (long)blockIdx.y * G + blockIdx.x;
+    long set, h;
+    if (b < full) {
+      set = (b / (8 * S)) * 8 + (b % 8);
+      h = (b % (8 * S)) / 8;
+    } else {
+      set = full / S + (b - full) / S;
+      h = (b - full) % S;
+    }
+    pl = (int)(set / (G / S));
+    grp = (int)((set % (G / S)) * S + h);
+    if (grp * C >= A.hp) return;   // a whole dead group (uniform)
+  }
   const int tid = threadIdx.x, c = tid % C, t = tid / C;
-  const int col = blockIdx.x * C + c;
+  const int col = grp * C + c;
   const bool live = col < A.hp;
   const int n = A.nz;
-  Cx<T>* plane = A.spec + (size_t)(A.plane0 + blockIdx.y) * A.ps;
+  Cx<T>* plane = A.spec + (size_t)(A.plane0 + pl) * A.ps;
   Cx<T> v[kE], ch[kH];
 #pragma unroll
   for (int i = 0; i < kH; ++i) {
@@ -291,7 +320,9 @@ hipError_t launch_zblu_reg(bool inverse, const ZfArgs<T>& a, int M, int nplanes,
   auto go = [&](auto m_) {
     constexpr int m = decltype(m_)::value;
     constexpr int C = blu_z_cols<T, m>();
-    const dim3 grid((unsigned)((a.hp + C - 1) / C), (unsigned)nplanes);
+    constexpr int S = blu_z_siblings<T, C>();
+    const int groups = (a.hp + C - 1) / C;
+    const dim3 grid((unsigned)((groups + S - 1) / S * S), (unsigned)nplanes);
     if (inverse)
       hipLaunchKernelGGL((k_zblu_reg<T, true, m, C>), grid, dim3(C * (m / kE)), 0, s, a);
     else
