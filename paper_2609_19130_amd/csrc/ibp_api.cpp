@@ -52,7 +52,7 @@ struct ibp_plan_s {
   long nb64 = 1, nb32 = 1;  // x-pass blocks (transform passes)
   long nbro = 1;            // blocks of the residual-only pass
   bool xfast = false, zfast = false;   // register-FFT kernels for power-of-two lengths
-  int xbm = 0, zbm = 0;   // register Bluestein convolution lengths of the x (odd nx) and z transforms (0: off)
+  int xbm = 0, zbm = 0;   // register Bluestein convolution lengths of the x and z transforms (0: off)
   bool zsmall = false;                 // general z transform in the small tile
   bool xsmall = false;                 // general x transform in the small tile
   bool xwide = true, zwide = true;     // general transform needs the wide kernel family
@@ -255,10 +255,9 @@ void carve_workspace(ibp_plan_s* p) {
   p->ctl = reinterpret_cast<Ctl*>(c);
 }
 
-// Register Bluestein for a transform of length n: lengths up to nmax (512 for
-// the odd-nx x pass, 1024 for z) with a prime factor above 11 that the LDS
-// kernels would run as direct-sum stages (the longer primes already take the
-// LDS Bluestein path).  Returns the
+// Register Bluestein for a transform of length n: lengths up to nmax (1024)
+// with a prime factor above 11 that the LDS kernels would run as direct-sum
+// stages (the longer primes already take the LDS Bluestein path).  Returns the
 // convolution length (a power of two >= 2n - 1), or 0 for the other paths.
 // IBP_REG_BLUESTEIN=0 turns it off (comparison runs).
 int reg_bluestein_length(const FftPlan& fp, int n, int nmax) {
@@ -548,7 +547,9 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     p->dz = Lz / nz;
     p->fpx = fpx;
     p->fpz = fpz;
-    p->xbm = (nx & 1) ? reg_bluestein_length(fpx, nx, 512) : 0;
+    // x: the whole row of nx points (two rows per line); fpx is the plan of
+    // the general kernels' transform length (nx/2 pairs, or nx when odd)
+    p->xbm = reg_bluestein_length(fpx, nx, 1024);
     p->zbm = nz > 1 ? reg_bluestein_length(fpz, nz, 1024) : 0;
     ytri_shape(ny, &p->yP, &p->yK);
     p->xfast = rfft::supported(p->h);

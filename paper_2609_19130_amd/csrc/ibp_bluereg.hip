@@ -1,20 +1,21 @@
-// Bluestein transforms held in registers, for line lengths n <= 512 (x) or
-// 1024 (z) with a prime factor above 11 (the paper's 501- and 632-point
-// grids: 501 = 3 x 167, 632 = 8 x 79), where
+// Bluestein transforms held in registers, for line lengths n <= 1024 with a
+// prime factor above 11 (the paper's 501- and 632-point grids: 501 = 3 x 167,
+// 632 = 8 x 79), where
 // the LDS kernels would run direct-sum stages of ~170 complex multiply-adds
 // per value.  A length-n DFT is X_k = w_k sum_j (x_j w_j) conj(w_{k-j}) with
 // the chirp w_j = exp(-i pi j^2 / n): the sum is a cyclic convolution of
-// length M (a power of two >= 2n - 1, at most 1024 in x, 2048 in z), done as two register
+// length M (a power of two >= 2n - 1, at most 2048), done as two register
 // FFTs of length M (ibp_regfft.hpp) around a pointwise product with the
 // filter's transform bhat.  The inverse DFT (unnormalised) is
 // conj(DFT(conj(X))).  Tables (host, long double rounded): chirp (n values),
 // bhat (M) and W_M^e (M) in the Bluestein slots of the argument structs.
 //
 // z pass: C kx columns of one y plane per block, M / 8 threads per column.
-// x pass (odd nx only): two real rows per complex line, M / 8 threads per
-// line; R2C separates the two spectra, keeps the first (n + 1) / 2
-// coefficients of each and the FP64 row sums; C2R combines the two half
-// spectra into the line's full spectrum and splits real and imaginary parts.
+// x pass: two real rows per complex line (the whole row of n points, odd or
+// even n), M / 8 threads per line; R2C separates the two spectra, keeps the
+// first n / 2 + 1 coefficients of each and the FP64 row sums; C2R combines
+// the two half spectra into the line's full spectrum and splits real and
+// imaginary parts.
 #include <type_traits>
 
 #include "ibp_internal.hpp"
@@ -144,7 +145,7 @@ __device__ __forceinline__ double row_total(double s, double* sh, int lr) {
   }
 }
 
-// Two real rows a, b of odd length n share one complex line z = a + i b:
+// Two real rows a, b of length n share one complex line z = a + i b:
 // with Z = DFT(z), A_k = (Z_k + conj Z_{n-k}) / 2 and
 // B_k = (Z_k - conj Z_{n-k}) / (2i), so one Bluestein transform serves both.
 // Rows 2p and 2p + 1 form line p; a missing second row (odd row count)
@@ -154,7 +155,7 @@ __device__ __forceinline__ Cx<T>* xblu_spec_row(const XArgs<T>& A, long row) {
   return A.spec + row * A.rs + (row / A.nz) * (A.ps - (long)A.nz * A.rs);
 }
 
-// x R2C (FP64 right-hand side pass) of rows of odd length n, two per line.
+// x R2C (FP64 right-hand side pass), two rows per line.
 template <typename T, int M>
 __global__ __launch_bounds__(kThreads) void k_xblu_r2c(XArgs<T> A) {
   constexpr int TT = M / kE;
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(kThreads) void k_xblu_r2c(XArgs<T> A) {
   }
 }
 
-// x C2R (set or add) of rows of odd length n, two per line: the line's
+// x C2R (set or add), two rows per line: the line's
 // spectrum is Z_k = A_k + i B_k over all k (A_{n-k} = conj A_k), its inverse
 // DFT is a + i b.
 template <typename T, int MODE, int M>
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(kThreads) void k_xblu_c2r(XArgs<T> A) {
       if (j < A.hp) {
         a = sa_row[j];
         if (live1) b = sb_row[j];
-        if (j == 0) a.y = b.y = T(0);   // X[0] of a real sequence is real
+        if (j == 0 || 2 * j == n) a.y = b.y = T(0);   // X[0] and X[n/2] of a real sequence are real
       } else {
         a = cconj(sa_row[n - j]);
         if (live1) b = cconj(sb_row[n - j]);
@@ -264,7 +265,9 @@ __global__ __launch_bounds__(kThreads) void k_xblu_c2r(XArgs<T> A) {
   }
   blu_convolve<M, T>(v, t, lds + lr * SS, A.bb, A.bt);
   if (!live0) return;   // no barrier follows
-  double cs = A.out_scale / double(M);
+  // out_scale is 1 / (h nz) with h the general kernels' transform length
+  // (nx / 2 for even nx): the whole row's inverse needs 1 / (nx nz)
+  double cs = A.out_scale * (double(A.h) / double(n)) / double(M);
   if (MODE == CM_ADD) cs = cs / A.ctl->scale[A.iter & 1];
   double ca = A.phi00[(int)(r0 / A.nz)] * A.inv_nxnz;
   double cb = live1 ? A.phi00[(int)((r0 + 1) / A.nz)] * A.inv_nxnz : 0.0;
@@ -343,7 +346,7 @@ hipError_t launch_zblu_reg(bool inverse, const ZfArgs<T>& a, int M, int nplanes,
 
 template <typename T>
 hipError_t launch_xblu_r2c(const XArgs<T>& a, int M, hipStream_t s) {
-  if (!(a.nx & 1) || a.nx > 512 || 2 * a.nx - 1 > M) return hipErrorInvalidValue;
+  if (a.nx > 1024 || 2 * a.nx - 1 > M) return hipErrorInvalidValue;
   auto go = [&](auto kern, int m) {
     const int RB = 2 * (kThreads / (m / kE));   // rows per block
     if (a.row_begin % RB) return hipErrorInvalidValue;
@@ -358,13 +361,14 @@ hipError_t launch_xblu_r2c(const XArgs<T>& a, int M, hipStream_t s) {
     case 256: return go(k_xblu_r2c<T, 256>, 256);
     case 512: return go(k_xblu_r2c<T, 512>, 512);
     case 1024: return go(k_xblu_r2c<T, 1024>, 1024);
+    case 2048: return go(k_xblu_r2c<T, 2048>, 2048);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T>
 hipError_t launch_xblu_c2r(int mode, const XArgs<T>& a, int M, hipStream_t s) {
-  if (!(a.nx & 1) || a.nx > 512 || 2 * a.nx - 1 > M) return hipErrorInvalidValue;
+  if (a.nx > 1024 || 2 * a.nx - 1 > M) return hipErrorInvalidValue;
   auto go = [&](auto kset, auto kadd, int m) {
     const int RB = 2 * (kThreads / (m / kE));   // rows per block
     if (a.row_begin % RB) return hipErrorInvalidValue;
@@ -382,6 +386,7 @@ hipError_t launch_xblu_c2r(int mode, const XArgs<T>& a, int M, hipStream_t s) {
     case 256: return go(k_xblu_c2r<T, CM_SET, 256>, k_xblu_c2r<T, CM_ADD, 256>, 256);
     case 512: return go(k_xblu_c2r<T, CM_SET, 512>, k_xblu_c2r<T, CM_ADD, 512>, 512);
     case 1024: return go(k_xblu_c2r<T, CM_SET, 1024>, k_xblu_c2r<T, CM_ADD, 1024>, 1024);
+    case 2048: return go(k_xblu_c2r<T, CM_SET, 2048>, k_xblu_c2r<T, CM_ADD, 2048>, 2048);
     default: return hipErrorInvalidValue;
   }
 }

@@ -232,14 +232,14 @@ def test_bluestein_mixed_and_inverse_round_trip():
 
 
 # ------------------------------------------------- register Bluestein lengths
-# Lengths with a prime factor above 11 (odd nx up to 512, nz up to 1024) take
-# the chirp convolution of length M (power of two >= 2n - 1) held in
-# registers: odd nx two rows per line, z one kx column per line.  Cover every
-# M from 32 to 1024 in x and 32 to 2048 in z, odd row counts (a line whose
-# second row is missing) and the mixed form's FP32 z transforms and C2R
-# correction (add mode).
+# Lengths with a prime factor above 11 (nx and nz up to 1024) take the chirp
+# convolution of length M (power of two >= 2n - 1) held in registers: x two
+# whole rows per line (odd and even nx, the even rows' real Nyquist
+# coefficient included), z one kx column per line.  Cover every M from 32 to
+# 2048 in x and z, odd row counts (a line whose second row is missing) and the
+# mixed form's FP32 z transforms and C2R correction (add mode).
 REG_BLU = [(13, 3, 29), (29, 4, 37), (37, 5, 101), (101, 3, 13), (251, 3, 255), (481, 3, 265),
-           (29, 3, 632), (27, 4, 1003)]
+           (29, 3, 632), (27, 4, 1003), (632, 3, 16), (26, 4, 7), (1001, 3, 8), (338, 5, 9)]
 
 
 @pytest.mark.parametrize("nx,ny,nz", REG_BLU)
