@@ -72,6 +72,10 @@ struct ibp_plan_s {
   const Cx<double>* bz64[3] = {nullptr, nullptr, nullptr};
   const Cx<float>* bx32[3] = {nullptr, nullptr, nullptr};
   const Cx<float>* bz32[3] = {nullptr, nullptr, nullptr};
+  // the x register Bluestein tables (whole rows of nx points), kept apart
+  // from the general x kernels' (nx/2 or nx points, primes above 256)
+  const Cx<double>* bxr64[3] = {nullptr, nullptr, nullptr};
+  const Cx<float>* bxr32[3] = {nullptr, nullptr, nullptr};
   // workspace
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -256,12 +260,13 @@ void carve_workspace(ibp_plan_s* p) {
 }
 
 // Register Bluestein for a transform of length n: lengths up to nmax (1024)
-// with a prime factor above 11 that the LDS kernels would run as direct-sum
-// stages (the longer primes already take the LDS Bluestein path).  Returns the
+// with a prime factor above 11, which the LDS kernels would run as
+// direct-sum stages (primes up to 256) or as their own Bluestein convolution
+// (larger primes); measured faster than both on every length tried.  Returns the
 // convolution length (a power of two >= 2n - 1), or 0 for the other paths.
 // IBP_REG_BLUESTEIN=0 turns it off (comparison runs).
 int reg_bluestein_length(const FftPlan& fp, int n, int nmax) {
-  if (fp.blu || !fp.any || n > nmax || n < 2) return 0;
+  if (!(fp.blu || fp.any) || n > nmax || n < 2) return 0;
   if (const char* e = getenv("IBP_REG_BLUESTEIN"))
     if (atoi(e) == 0) return 0;
   int m = 32;
@@ -648,7 +653,7 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     const size_t o_twx32 = put(cx32.data(), cx32.size() * sizeof(float));
     const size_t o_twz32 = put(cz32.data(), cz32.size() * sizeof(float));
     // Bluestein tables: chirp, filter transform, length-m twiddles; FP64 and FP32
-    size_t o_bx[6] = {0, 0, 0, 0, 0, 0}, o_bz[6] = {0, 0, 0, 0, 0, 0};
+    size_t o_bx[6] = {0, 0, 0, 0, 0, 0}, o_bz[6] = {0, 0, 0, 0, 0, 0}, o_bxr[6] = {0, 0, 0, 0, 0, 0};
     auto put_blu = [&](const FftPlan& fp, size_t* o) {
       std::vector<double> ch, bh, twr, twi;
       bluestein_tables(fp.n, fp.m, ch, bh);
@@ -667,13 +672,13 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     };
     if (p->fpx.blu) put_blu(p->fpx, o_bx);
     if (p->fpz.blu) put_blu(p->fpz, o_bz);
-    if (p->xbm) {   // the register Bluestein path's tables, in the same slots (fpx.blu is off)
+    if (p->xbm) {   // the register Bluestein x tables, beside the general kernels'
       FftPlan b{};
       b.n = nx;
       b.m = p->xbm;
-      put_blu(b, o_bx);
+      put_blu(b, o_bxr);
     }
-    if (p->zbm) {
+    if (p->zbm) {   // every z transform of such a plan takes the register path: same slots
       FftPlan b{};
       b.n = nz;
       b.m = p->zbm;
@@ -725,9 +730,13 @@ ibp_status_t ibp_plan_create(ibp_plan_t* out, int nx, int ny, int nz, double Lx,
     p->lamz32 = reinterpret_cast<const float*>(d + o_lz32);
     p->twx32 = reinterpret_cast<const Cx<float>*>(d + o_twx32);
     for (int t = 0; t < 3; ++t) {
-      if (p->fpx.blu || p->xbm) {
+      if (p->fpx.blu) {
         p->bx64[t] = reinterpret_cast<const Cx<double>*>(d + o_bx[t]);
         p->bx32[t] = reinterpret_cast<const Cx<float>*>(d + o_bx[3 + t]);
+      }
+      if (p->xbm) {
+        p->bxr64[t] = reinterpret_cast<const Cx<double>*>(d + o_bxr[t]);
+        p->bxr32[t] = reinterpret_cast<const Cx<float>*>(d + o_bxr[3 + t]);
       }
       if (p->fpz.blu || p->zbm) {
         p->bz64[t] = reinterpret_cast<const Cx<double>*>(d + o_bz[t]);
@@ -1261,9 +1270,9 @@ template <typename T>
 XArgs<T> with_xblu(const ibp_plan_s* p, const XArgs<T>& a) {
   XArgs<T> b = a;
   if constexpr (sizeof(T) == 8) {
-    b.bc = p->bx64[0]; b.bb = p->bx64[1]; b.bt = p->bx64[2];
+    b.bc = p->bxr64[0]; b.bb = p->bxr64[1]; b.bt = p->bxr64[2];
   } else {
-    b.bc = p->bx32[0]; b.bb = p->bx32[1]; b.bt = p->bx32[2];
+    b.bc = p->bxr32[0]; b.bb = p->bxr32[1]; b.bt = p->bxr32[2];
   }
   return b;
 }
