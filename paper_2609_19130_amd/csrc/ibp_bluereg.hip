@@ -33,12 +33,12 @@ using rfft::kE;
 // final_index(q) < kE / 2 are ever used, so a lane's chirp values (indices
 // t + TT i, i < kE / 2) serve both its loads and its stores.
 constexpr int kH = kE / 2;
-template <int M, typename T>
+template <int M, typename T, int SH>
 __device__ __forceinline__ void blu_convolve(Cx<T> (&v)[kE], int t, Cx<T>* lds, const Cx<T>* bb, const Cx<T>* bt) {
   // w^2 ... w^7 of each butterfly formed from w^1: the chirp and filter
   // tables already compete with the line data for the vector cache
-  using PF = rfft::Plan<M, false, T, true>;
-  using PI = rfft::Plan<M, true, T, true>;
+  using PF = rfft::Plan<M, false, T, true, SH>;
+  using PI = rfft::Plan<M, true, T, true, SH>;
   constexpr int TT = M / kE;
   constexpr int RF = PF::last_radix();
   PF::run(v, t, lds, bt, 1);
@@ -52,6 +52,15 @@ __device__ __forceinline__ void blu_convolve(Cx<T> (&v)[kE], int t, Cx<T>* lds, 
 #pragma unroll
   for (int q = 0; q < kE; ++q) v[q] = u[q];
 }
+
+// LDS layout: z regions at rfft::col_stride (adjacent columns 64 / C banks
+// apart: z passes at 501 x 1001 x 501 1.77 -> 1.59 ms against the plain
+// padded length); x lines at the plain padded length (one pad every 16
+// elements, which a bank model rates better, measured no faster).
+template <typename T, int M, int C>
+constexpr int blu_z_stride() { return rfft::col_stride<M, C, sizeof(Cx<T>)>(); }
+template <typename T, int M>
+constexpr int blu_x_shift() { return 3; }
 
 // Column groups narrower than a 128-byte line: the S groups of one line
 // (S = 128 / (C * sizeof(Cx<T>)), 2 or 4) go to blocks b, b + 8, ..., which
@@ -68,7 +77,7 @@ constexpr int blu_z_siblings() {
 template <typename T, bool INV, int M, int C>
 __global__ __launch_bounds__(C*(M / kE)) void k_zblu_reg(ZfArgs<T> A) {
   constexpr int TT = M / kE;
-  constexpr int SS = rfft::Seq<M>::stride;
+  constexpr int SS = blu_z_stride<T, M, C>();
   constexpr int RI = rfft::Plan<M, true, T>::last_radix();
   constexpr int S = blu_z_siblings<T, C>();
   __shared__ Cx<T> lds[C * SS];
@@ -109,7 +118,7 @@ __global__ __launch_bounds__(C*(M / kE)) void k_zblu_reg(ZfArgs<T> A) {
     v[i] = x;
     v[i + kH] = Cx<T>{T(0), T(0)};
   }
-  blu_convolve<M, T>(v, t, lds + c * SS, A.bb, A.bt);
+  blu_convolve<M, T, 3>(v, t, lds + c * SS, A.bb, A.bt);
   if (!live) return;   // no barrier follows
   const T inv_m = T(1) / T(M);
 #pragma unroll
@@ -160,7 +169,8 @@ template <typename T, int M>
 __global__ __launch_bounds__(kThreads) void k_xblu_r2c(XArgs<T> A) {
   constexpr int TT = M / kE;
   constexpr int RB = kThreads / TT;   // lines (row pairs) per block
-  constexpr int SS = rfft::Seq<M>::stride;
+  constexpr int SH = blu_x_shift<T, M>();
+  constexpr int SS = rfft::Seq<M, SH>::stride;
   constexpr int RI = rfft::Plan<M, true, T>::last_radix();
   __shared__ Cx<T> lds[RB * SS];
   __shared__ double sh[kThreads / kWave];
@@ -196,7 +206,7 @@ __global__ __launch_bounds__(kThreads) void k_xblu_r2c(XArgs<T> A) {
     if (live1) A.rowsum[r0 + 1] = sb;
   }
   Cx<T>* L = lds + lr * SS;
-  blu_convolve<M, T>(v, t, L, A.bb, A.bt);
+  blu_convolve<M, T, SH>(v, t, L, A.bb, A.bt);
   // Z_k (chirp and 1/M applied) to LDS, natural order; the last LDS access
   // of the convolution was a load followed by a barrier
   const T inv_m = T(1) / T(M);
@@ -204,7 +214,7 @@ __global__ __launch_bounds__(kThreads) void k_xblu_r2c(XArgs<T> A) {
   for (int q = 0; q < kE; ++q) {
     const int fi = final_index<RI>(q);
     const int k = t + TT * fi;
-    if (fi < kH && k < n) L[rfft::pad8(k)] = cscale(cmul(A.bc[k], v[q]), inv_m);
+    if (fi < kH && k < n) L[rfft::padn<SH>(k)] = cscale(cmul(A.bc[k], v[q]), inv_m);
   }
   __syncthreads();
   if (!live0) return;   // no barrier follows
@@ -214,8 +224,8 @@ __global__ __launch_bounds__(kThreads) void k_xblu_r2c(XArgs<T> A) {
   for (int i = 0; i < kE; ++i) {
     const int k = t + TT * i;
     if (k < A.hp) {
-      const Cx<T> z = L[rfft::pad8(k)];
-      const Cx<T> w = L[rfft::pad8(k == 0 ? 0 : n - k)];
+      const Cx<T> z = L[rfft::padn<SH>(k)];
+      const Cx<T> w = L[rfft::padn<SH>(k == 0 ? 0 : n - k)];
       sa_row[k] = Cx<T>{T(0.5) * (z.x + w.x), T(0.5) * (z.y - w.y)};
       if (live1) sb_row[k] = Cx<T>{T(0.5) * (z.y + w.y), T(0.5) * (w.x - z.x)};
     }
@@ -229,7 +239,8 @@ template <typename T, int MODE, int M>
 __global__ __launch_bounds__(kThreads) void k_xblu_c2r(XArgs<T> A) {
   constexpr int TT = M / kE;
   constexpr int RB = kThreads / TT;
-  constexpr int SS = rfft::Seq<M>::stride;
+  constexpr int SH = blu_x_shift<T, M>();
+  constexpr int SS = rfft::Seq<M, SH>::stride;
   constexpr int RI = rfft::Plan<M, true, T>::last_radix();
   __shared__ Cx<T> lds[RB * SS];
   if (MODE == CM_ADD && A.ctl->done) return;
@@ -263,7 +274,7 @@ __global__ __launch_bounds__(kThreads) void k_xblu_c2r(XArgs<T> A) {
     v[i] = y;
     v[i + kH] = Cx<T>{T(0), T(0)};
   }
-  blu_convolve<M, T>(v, t, lds + lr * SS, A.bb, A.bt);
+  blu_convolve<M, T, SH>(v, t, lds + lr * SS, A.bb, A.bt);
   if (!live0) return;   // no barrier follows
   // out_scale is 1 / (h nz) with h the general kernels' transform length
   // (nx / 2 for even nx): the whole row's inverse needs 1 / (nx nz)

@@ -252,7 +252,7 @@ template <typename T, bool INV, int NZ, int C>
 __device__ __forceinline__ void zfft_body(const ZfArgs<T>& A, int colblk, long plane_index, Cx<T>* lds,
                                           int tid) {
   constexpr int TT = NZ / kE;
-  constexpr int SS = rfft::Seq<NZ>::stride;
+  constexpr int SS = rfft::col_stride<NZ, C, sizeof(Cx<T>)>();
   using P = rfft::Plan<NZ, INV, T>;
   constexpr int RL = P::last_radix();
   const int c = tid % C, t = tid / C;
@@ -277,7 +277,7 @@ __device__ __forceinline__ void zfft_body(const ZfArgs<T>& A, int colblk, long p
 
 template <typename T, bool INV, int NZ, int C>
 __global__ __launch_bounds__(C*(NZ / kE)) void k_zfft_reg(ZfArgs<T> A) {
-  __shared__ Cx<T> lds[C * rfft::Seq<NZ>::stride];
+  __shared__ Cx<T> lds[C * rfft::col_stride<NZ, C, sizeof(Cx<T>)>()];
   if (A.check_done && A.ctl->done) return;
   // forward: planes in descending order (the x R2C wrote the last planes
   // last); inverse of an FP64 spectrum: grid (planes, column groups), column
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(C*(NZ / kE)) void k_zfft_reg(ZfArgs<T> A) {
 template <int NZ, int C>
 __global__ __launch_bounds__(C*(NZ / kE)) void k_zinv_up(ZupArgs A) {
   constexpr int TT = NZ / kE;
-  constexpr int SS = rfft::Seq<NZ>::stride;
+  constexpr int SS = rfft::col_stride<NZ, C, sizeof(Cx<double>)>();
   using P = rfft::Plan<NZ, true, double>;
   constexpr int RL = P::last_radix();
   __shared__ Cx<double> lds[C * SS];
@@ -527,7 +527,7 @@ template <typename T, int H, int NZ, bool FWD, int MODE>
 __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fused_xz(FusedArgs<T> F) {
   constexpr int NT = kFusedThreads;
   constexpr int RBX = NT / (H / kE), CZ = NT / (NZ / kE);
-  constexpr int LX = RBX * rfft::Seq<H>::stride, LZ = CZ * rfft::Seq<NZ>::stride;
+  constexpr int LX = RBX * rfft::Seq<H>::stride, LZ = CZ * rfft::col_stride<NZ, CZ, sizeof(Cx<T>)>();
   __shared__ Cx<T> lds[LX > LZ ? LX : LZ];
   __shared__ double sh[(NT / kWave) * kPartStride];
   __shared__ int item;
