@@ -97,10 +97,12 @@ typedef struct {
 
 /* Host-only size check (touches no GPU).  Even nx <= 4096 (transformed as
  * nx/2 complex pairs) or odd nx <= 2048 (as nx complex values); nz <= 4096;
- * 2 <= ny <= 1536.  Any prime factors are accepted (those above 11 take a
- * slower direct-sum transform stage, e.g. the paper's 632 = 8 x 79 and
- * 501 = 3 x 167 points), but then the x transform length <= 1024 or
- * nz <= 2047 for that direction.  Returns IBP_SUCCESS or
+ * 2 <= ny <= 1536.  Any prime factors are accepted, but then the x
+ * transform length <= 1024 or nz <= 2047 for that direction: lines of at
+ * most 1024 points with a prime factor above 11 (e.g. the paper's 632 = 8 x
+ * 79 and 501 = 3 x 167 points) take a chirp convolution held in registers,
+ * longer ones a slower direct-sum or convolution stage in LDS; the mixed
+ * forms' residual passes take the LDS stages.  Returns IBP_SUCCESS or
  * IBP_ERROR_UNSUPPORTED_SIZE (IBP_ERROR_INVALID_VALUE for nx, nz < 1). */
 ibp_status_t ibp_check_dims(int nx, int ny, int nz);
 
