@@ -1163,10 +1163,11 @@ ibp_status_t ibp_helmholtz(ibp_plan_t p, double* field, ibp_location_t where, hi
 
 namespace {
 
-// Bluestein z transforms: column stride m + 1 and the tables.
+// LDS Bluestein z transforms (lines the register path does not take):
+// column stride m + 1 and the tables.
 template <typename T>
 void zf_bluestein(const ibp_plan_s* p, ZfArgs<T>& z) {
-  if (!p->fpz.blu) return;
+  if (!p->fpz.blu || p->zbm) return;
   z.zss = p->fpz.m + 1;
   if constexpr (sizeof(T) == 8) {
     z.bc = p->bz64[0]; z.bb = p->bz64[1]; z.bt = p->bz64[2];
@@ -1264,8 +1265,8 @@ ZeroArgs zargs(ibp_plan_s* p, long nparts, int init, int mixed, int iter, int fi
     if (e_ != hipSuccess) return from_hip(e_);        \
   } while (0)
 
-// The register Bluestein x path's arguments: its tables (the plan's
-// Bluestein slots hold them; fpx.blu is off so the LDS kernels ignore them).
+// The register Bluestein x path's arguments: its own tables (whole rows of
+// nx points), kept apart from the LDS kernels' Bluestein tables.
 template <typename T>
 XArgs<T> with_xblu(const ibp_plan_s* p, const XArgs<T>& a) {
   XArgs<T> b = a;

@@ -288,11 +288,12 @@ struct RtArgs {
 };
 hipError_t launch_zinv_up(const ZupArgs& a, hipStream_t s);
 
-// Register Bluestein transforms (ibp_bluereg.hip) for lengths n <= 512 with
+// Register Bluestein transforms (ibp_bluereg.hip) for lengths n <= 1024 with
 // a prime factor above 11; M: the convolution length (a power of two >=
-// 2n - 1, <= 1024); tables in the args' bc (chirp), bb (filter transform)
+// 2n - 1, <= 2048); tables in the args' bc (chirp), bb (filter transform)
 // and bt (W_M).  z: forward or inverse over nplanes planes from a.plane0;
-// x: rows of odd length (R2C: FP64 right-hand side pass; C2R: set or add).
+// x: whole rows of nx points, two per line (R2C: FP64 right-hand side pass;
+// C2R: set or add).
 template <typename T>
 hipError_t launch_zblu_reg(bool inverse, const ZfArgs<T>& a, int M, int nplanes, hipStream_t s);
 template <typename T>
