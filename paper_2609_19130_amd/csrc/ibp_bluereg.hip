@@ -1,8 +1,8 @@
 // Bluestein transforms held in registers, for line lengths n <= 1024 with a
 // prime factor above 11 (the paper's 501- and 632-point grids: 501 = 3 x 167,
-// 632 = 8 x 79), where
-// the LDS kernels would run direct-sum stages of ~170 complex multiply-adds
-// per value.  A length-n DFT is X_k = w_k sum_j (x_j w_j) conj(w_{k-j}) with
+// 632 = 8 x 79), which the LDS kernels would run as direct-sum stages (up to
+// ~170 complex multiply-adds per value) or, for primes above 256, as their
+// own slower convolution.  A length-n DFT is X_k = w_k sum_j (x_j w_j) conj(w_{k-j}) with
 // the chirp w_j = exp(-i pi j^2 / n): the sum is a cyclic convolution of
 // length M (a power of two >= 2n - 1, at most 2048), done as two register
 // FFTs of length M (ibp_regfft.hpp) around a pointwise product with the
