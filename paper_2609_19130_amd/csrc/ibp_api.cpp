@@ -199,6 +199,8 @@ bool z_small(const FftPlan& fpz, int nz) {
 void set_x_split(ibp_plan_s* p) {
   const long nrows = (long)p->ny * p->nz;
   p->nbro = (nrows + x_tile_rows(p, x_tile32(p)) - 1) / x_tile_rows(p, x_tile32(p));
+  // the residual-only pass runs as the y-marching stencil kernel where it can
+  if (const long nb = resid_march_blocks(p->nx, p->ny, p->nz)) p->nbro = nb;
   if (p->xfast) {
     p->rb64 = p->rb32 = (int)fast_x_rows_per_block(p->h);
   } else {
@@ -1287,9 +1289,11 @@ hipError_t run_xr2c(const ibp_plan_s* p, int mode, const XArgs<T>& a, hipStream_
     if (p->xbm && mode == XM_PLAIN && p->chunk <= 0) return launch_xblu_r2c<T>(with_xblu(p, a), p->xbm, s);
   if (mode == XM_RESID_ONLY) {
     XArgs<T> b = a;
-    b.rows_per_block = x_tile_rows(p, x_tile32(p));
     b.row_begin = 0;
     b.nrows = (long)p->ny * p->nz;
+    if constexpr (sizeof(T) == 4)
+      if (resid_march_blocks(p->nx, p->ny, p->nz) > 0) return launch_resid_march(b, s);
+    b.rows_per_block = x_tile_rows(p, x_tile32(p));
     b.parts = 1;
     return launch_xr2c<T>(mode, p->xsmall, p->xwide, b, s);
   }

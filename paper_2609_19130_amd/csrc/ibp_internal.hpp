@@ -566,6 +566,11 @@ hipError_t launch_xcc_probe(int* out, int nblocks, hipStream_t s);
 template <typename T>
 int fast_z_cols(int nz);
 hipError_t launch_divergence(const DivArgs& a, hipStream_t s);
+// Residual-only pass (norm partials of f - m - L_h phi, no transform) by the
+// y-marching stencil kernel; resid_march_blocks: its partial records, 0 for
+// grids it does not take (nx > 4096 or nx nz >= 2^30).
+long resid_march_blocks(int nx, int ny, int nz);
+hipError_t launch_resid_march(const XArgs<float>& a, hipStream_t s);
 
 
 }  // namespace ibp

@@ -45,12 +45,12 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
-inline MarchShape march_shape(int nx, int ny, int nz, int tile) {
+inline MarchShape march_shape(int nx, int ny, int nz, int tile, int max_planes = kMarchMaxPlanes) {
   MarchShape m;
   m.kr = std::max(1, std::min(nz, tile / nx));
   m.ntk = (nz + m.kr - 1) / m.kr;
   // enough blocks to fill the device with at least 4 planes each
-  m.nj = std::max(4, std::min(kMarchMaxPlanes, (int)((long)ny * m.ntk / kMarchBlocks)));
+  m.nj = std::max(4, std::min(max_planes, (int)((long)ny * m.ntk / kMarchBlocks)));
   m.nj = std::min(m.nj, ny);
   m.nbj = (ny + m.nj - 1) / m.nj;
   return m;
@@ -212,6 +212,134 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs A, MarchShape S) {
     }
     if (j + 1 < j1) fill(j + 1, pc);
   }
+}
+
+// Residual of an iterate without a transform (the mixed forms' convergence
+// probe and final check): r = (f - m) - L_h phi at every cell, with the same
+// 7-point operator and operation order as the residual x passes, reduced to
+// the block's norm partials (one record per block, in block order).  phi
+// marches along y as in the projection: the plane's tile with its z halo
+// rows in LDS, the planes below and above in registers; f is read once.
+template <int NT, int TILE, int LDS>
+__global__ __launch_bounds__(NT) void k_resid_march(XArgs<float> A, MarchShape S) {
+  constexpr int kMarchCells = TILE / NT;
+  constexpr int kHalo = (2 * TILE + NT - 1) / NT;   // halo values per thread (2 rows of nx <= TILE)
+  __shared__ double tile[LDS];   // (kr + 2) rows of nx: z rows k0 - 1 .. k0 + kr
+  __shared__ double sh[kPartStride * (NT / kWave)];
+  if (__builtin_amdgcn_readfirstlane(A.ctl->done)) return;
+  if (A.probe && !__builtin_amdgcn_readfirstlane(A.ctl->probe)) return;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int tk = blk % S.ntk, bj = blk / S.ntk;
+  const int j0 = bj * S.nj, j1 = min(A.ny, j0 + S.nj);
+  const int k0 = tk * S.kr, nx = A.nx, nz = A.nz;
+  const int kr = min(S.kr, nz - k0);
+  const long plane = (long)nx * nz;
+  const int ncell = kr * nx;
+  const int klo = k0 == 0 ? nz - 1 : k0 - 1, khi = k0 + kr == nz ? 0 : k0 + kr;
+  int tc[kMarchCells], txm[kMarchCells], txp[kMarchCells];
+  int off[kMarchCells];
+  bool live[kMarchCells];
+#pragma unroll
+  for (int m = 0; m < kMarchCells; ++m) {
+    const int c = threadIdx.x + NT * m;
+    live[m] = c < ncell;
+    const int kk = live[m] ? c / nx : 0, i = live[m] ? c - kk * nx : 0;
+    off[m] = (k0 + kk) * nx + i;
+    tc[m] = (kk + 1) * nx + i;
+    txm[m] = (kk + 1) * nx + (i == 0 ? nx - 1 : i - 1);
+    txp[m] = (kk + 1) * nx + (i + 1 == nx ? 0 : i + 1);
+  }
+  // halo element e = threadIdx.x + NT q of the two z halo rows: its tile
+  // slot and its offset within a plane
+  int hslot[kHalo], hoff[kHalo];
+#pragma unroll
+  for (int q = 0; q < kHalo; ++q) {
+    const int e = threadIdx.x + NT * q;
+    const bool ok = e < 2 * nx;
+    const int hi = e >= nx, i = ok ? e - hi * nx : 0;
+    hslot[q] = ok ? (hi ? (kr + 1) * nx + i : i) : -1;
+    hoff[q] = (hi ? khi : klo) * nx + i;
+  }
+  // Software pipeline: while plane j is reduced, the loads of plane j + 1
+  // (f, the halo rows of phi) and of phi at plane j + 2 are in flight.
+  double pm[kMarchCells], pc[kMarchCells], pp[kMarchCells], fo[kMarchCells], hv[kHalo];
+#pragma unroll
+  for (int m = 0; m < kMarchCells; ++m) {
+    pm[m] = (live[m] && j0 > 0) ? A.phi[(long)(j0 - 1) * plane + off[m]] : 0.0;
+    pc[m] = live[m] ? A.phi[(long)j0 * plane + off[m]] : 0.0;
+    pp[m] = (live[m] && j0 + 1 < A.ny) ? A.phi[(long)(j0 + 1) * plane + off[m]] : 0.0;
+    fo[m] = live[m] ? A.f[(long)j0 * plane + off[m]] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < kHalo; ++q) hv[q] = hslot[q] >= 0 ? A.phi[(long)j0 * plane + hoff[q]] : 0.0;
+  NormAcc acc;
+  const double mean = A.ctl->removed_mean;
+  for (int j = j0; j < j1; ++j) {
+    // the tile of plane j: own cells from registers, halo rows as loaded
+#pragma unroll
+    for (int m = 0; m < kMarchCells; ++m)
+      if (live[m]) tile[tc[m]] = pc[m];
+#pragma unroll
+    for (int q = 0; q < kHalo; ++q)
+      if (hslot[q] >= 0) tile[hslot[q]] = hv[q];
+    // loads for the next plane
+    const bool more = j + 1 < j1;
+    double fn[kMarchCells], pn[kMarchCells];
+#pragma unroll
+    for (int m = 0; m < kMarchCells; ++m) {
+      fn[m] = (live[m] && more) ? A.f[(long)(j + 1) * plane + off[m]] : 0.0;
+      pn[m] = (live[m] && more && j + 2 < A.ny) ? A.phi[(long)(j + 2) * plane + off[m]] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kHalo; ++q)
+      hv[q] = (hslot[q] >= 0 && more) ? A.phi[(long)(j + 1) * plane + hoff[q]] : 0.0;
+    const double dyfj = A.dyf[j], ya = A.ya[j], yc = A.yc[j];
+    __syncthreads();   // the tile of plane j is complete
+#pragma unroll
+    for (int m = 0; m < kMarchCells; ++m) {
+      if (!live[m]) continue;
+      const double c0 = pc[m];
+      const double xm = tile[txm[m]], xp = tile[txp[m]];
+      const double zm = tile[tc[m] - nx], zp = tile[tc[m] + nx];
+      const double L0 = (xp - 2.0 * c0 + xm) * A.idx2 + (zp + zm - 2.0 * c0) * A.idz2 + ya * (pm[m] - c0) +
+                        yc * (pp[m] - c0);
+      const double f0 = fo[m] - mean;
+      acc.one(f0 - L0, f0, dyfj * dyfj);
+      acc.phi_one(c0, dyfj);
+    }
+    __syncthreads();   // every read of the tile is done
+#pragma unroll
+    for (int m = 0; m < kMarchCells; ++m) {
+      pm[m] = pc[m];
+      pc[m] = pp[m];
+      pp[m] = pn[m];
+      fo[m] = fn[m];
+    }
+  }
+  acc.write<NT, true>(A.part, blockIdx.x, sh);
+}
+
+// The residual-only pass's blocks (= its partial records), 0 when the
+// marching kernel does not take the grid.
+constexpr int kResidMaxPlanes = 32;
+long resid_march_blocks(int nx, int ny, int nz) {
+  if (nx > kMarchTileWide || (long)nx * nz >= (1L << 30)) return 0;
+  const MarchShape S = march_shape(nx, ny, nz, nx <= kMarchTile ? kMarchTile : kMarchTileWide, kResidMaxPlanes);
+  return (long)S.ntk * S.nbj;
+}
+
+hipError_t launch_resid_march(const XArgs<float>& a, hipStream_t s) {
+  if (a.nx > kMarchTileWide || (long)a.nx * a.nz >= (1L << 30)) return hipErrorInvalidValue;
+  if (a.nx <= kMarchTile) {
+    const MarchShape S = march_shape(a.nx, a.ny, a.nz, kMarchTile, kResidMaxPlanes);
+    hipLaunchKernelGGL((k_resid_march<kMarchThreads, kMarchTile, kProjLds>), dim3((unsigned)(S.ntk * S.nbj)),
+                       dim3(kMarchThreads), 0, s, a, S);
+  } else {
+    const MarchShape S = march_shape(a.nx, a.ny, a.nz, kMarchTileWide, kResidMaxPlanes);
+    hipLaunchKernelGGL((k_resid_march<kMarchThreadsWide, kMarchTileWide, kProjLdsWide>),
+                       dim3((unsigned)(S.ntk * S.nbj)), dim3(kMarchThreadsWide), 0, s, a, S);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_project(const ProjArgs& a, hipStream_t s) {
