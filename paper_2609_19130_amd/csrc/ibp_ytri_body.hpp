@@ -293,16 +293,17 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
     return;
   }
   long q0 = (blk - nzb) * M;
-  if (kx_major && A.rs % M == 0) {
-    const long lb = blk - nzb, nkz = A.Q / A.rs;
-    q0 = (lb % nkz) * A.rs + (lb / nkz) * M;
-    if constexpr (sizeof(Cx<T>) * M == 64) {
-      // Half-line column groups (64 of a row's 128 bytes): the two groups of
-      // one 128-byte line go to blocks lb and lb + 8, which the round-robin
-      // dispatch places on the same XCD at about the same time, so the line
-      // is fetched into that XCD's L2 once.  Pairs in kx-major order; the
-      // last nlb mod 16 blocks take the remaining pairs two by two.  rs is a
-      // multiple of 2M here (128-byte rows), so every group has its sibling.
+  const long lb = blk - nzb, nkz = A.Q / A.rs;
+  if (kx_major && A.rs % M == 0) q0 = (lb % nkz) * A.rs + (lb / nkz) * M;
+  if constexpr (sizeof(Cx<T>) * M == 64) {
+    // Half-line column groups (64 of a row's 128 bytes): the two groups of
+    // one 128-byte line go to blocks lb and lb + 8, which the round-robin
+    // dispatch places on the same XCD at about the same time, so the line
+    // is fetched into that XCD's L2 once.  Pairs in the block order's
+    // sequence (kx-major or plain); the last nlb mod 16 blocks take the
+    // remaining pairs two by two.  Rows of 128 bytes (rs a multiple of 2M)
+    // give every group its sibling.
+    if (A.rs % (2 * M) == 0) {
       const long nlb = A.Q / M, full = nlb / 16 * 16;
       long pair, h;
       if (lb < full) {
@@ -312,7 +313,7 @@ __device__ __forceinline__ void ytri_body(const YArgs<T, U>& A, const ZeroArgs& 
         pair = full / 2 + (lb - full) / 2;
         h = (lb - full) % 2;
       }
-      q0 = (pair % nkz) * A.rs + (2 * (pair / nkz) + h) * M;
+      q0 = kx_major ? (pair % nkz) * A.rs + (2 * (pair / nkz) + h) * M : (2 * pair + h) * M;
     }
   }
   const int lm = threadIdx.x % M, row0 = threadIdx.x / M;
