@@ -253,7 +253,7 @@ def test_register_bluestein_lengths_fp64_match_oracle(nx, ny, nz):
 
 
 @pytest.mark.parametrize("precision", ["mixed", "mixed_f64inv"])
-@pytest.mark.parametrize("nx,ny,nz", [REG_BLU[2], REG_BLU[5], REG_BLU[7]])
+@pytest.mark.parametrize("nx,ny,nz", [REG_BLU[2], REG_BLU[5], REG_BLU[7], REG_BLU[8], REG_BLU[10]])
 def test_register_bluestein_lengths_mixed_refinement(nx, ny, nz, precision):
     Lx, Lz = 1.7, 2.3
     yf = synth.tanh_faces(ny, 2.0)
